@@ -1,0 +1,371 @@
+"""ctypes wrapper of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this module.  The product path (``paper_2307_07999_amd``)
+never does.  Array layouts are the oracle's own (array-of-structures, see
+``glasma_oracle.h``); converting to the HIP library's structure-of-arrays
+layout is done by the tests with plain numpy transposes.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "glasma_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force=False):
+    """Compile the oracle with plain g++ (-O2, no fast-math, no OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared",
+                               "-o", _LIB_PATH, _SRC])
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_U32 = ctypes.POINTER(ctypes.c_uint32)
+
+
+def _declare(L):
+    c_int, c_double, c_u64 = ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+    sig = {
+        "orc_generator": (None, [c_int, _D]),
+        "orc_dsym": (c_double, [c_int, c_int, c_int]),
+        "orc_expi": (None, [_D, _D]),
+        "orc_expm": (None, [_D, _D]),
+        "orc_proj": (None, [_D, _D]),
+        "orc_philox": (None, [_U32, _U32, _U32]),
+        "orc_u53": (c_double, [ctypes.c_uint32, ctypes.c_uint32]),
+        "orc_mv_charges": (None, [c_int, c_double, c_u64, c_int, c_int, _D]),
+        "orc_fft": (c_int, [c_int, _D, c_int]),
+        "orc_poisson": (c_int, [c_int, c_double, _D, _D]),
+        "orc_wilson_line": (c_int, [c_int, c_double, c_double, c_int, c_u64, c_int, _D]),
+        "orc_nucleus_links": (None, [c_int, _D, _D]),
+        "orc_match_link": (c_int, [_D, _D, _D, c_double, c_int, _D]),
+        "orc_pi0": (None, [c_int, _D, _D, _D, _D]),
+        "orc_init_glasma": (c_int, [c_int, c_double, c_double, c_int, c_u64, c_double,
+                                    _D, _D, _D, _D, _D]),
+        "orc_forces": (None, [c_int, c_double, _D, _D, _D, _D]),
+        "orc_field_step": (None, [c_int, c_int, c_double, _D, _D, _D, _D, _D]),
+        "orc_field_step_sites": (None, [c_int, c_int, c_double, _D, _D, _D, _D, c_int, _I,
+                                        _D, _D, _D, _D, _D]),
+        "orc_energy": (None, [c_int, c_double, _D, _D, _D, _D, _D]),
+        "orc_gauss": (None, [c_int, _D, _D, _D, _D, _D]),
+        "orc_particles_init": (None, [c_int, c_u64, c_int, c_int, c_double, c_int, _I, _D,
+                                      _D, _D, _D, _D]),
+        "orc_particle_step": (None, [c_int, c_int, c_double, _D, _D, _D, c_int, _I, _D, _D,
+                                     _D, _D, _D, _I, c_int, _D, _I, _D]),
+        "orc_run": (c_int, [c_int, c_double, c_double, c_int, c_u64, c_double, c_int, c_int,
+                            _I, _D, _D, _I, _I, _D, _D, _D, _D, _I, _D, _D, _D, _D, _D,
+                            _I, _D]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _i(a):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_I)
+
+
+def _u(a):
+    assert a.dtype == np.uint32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_U32)
+
+
+# ---- matrices as numpy complex (3,3) <-> 18 doubles ------------------------
+def m2d(m):
+    return np.ascontiguousarray(np.asarray(m, np.complex128).reshape(-1, 3, 3)).view(
+        np.float64).reshape(np.shape(m)[:-2] + (18,))
+
+
+def d2m(d):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    return d.view(np.complex128).reshape(d.shape[:-1] + (3, 3))
+
+
+def generator(a):
+    out = np.zeros(18)
+    lib().orc_generator(a, _d(out))
+    return d2m(out)
+
+
+def dsym(a, b, c):
+    return lib().orc_dsym(a, b, c)
+
+
+def expi(x8):
+    x8 = np.ascontiguousarray(x8, np.float64)
+    out = np.zeros(18)
+    lib().orc_expi(_d(x8), _d(out))
+    return d2m(out)
+
+
+def expm(A):
+    a = m2d(A).copy()
+    out = np.zeros(18)
+    lib().orc_expm(_d(a), _d(out))
+    return d2m(out)
+
+
+def proj(M):
+    a = m2d(M).copy()
+    out = np.zeros(8)
+    lib().orc_proj(_d(a), _d(out))
+    return out
+
+
+def philox(key, ctr):
+    k = np.ascontiguousarray(key, np.uint32)
+    c = np.ascontiguousarray(ctr, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(_u(k), _u(c), _u(out))
+    return out
+
+
+def u53(lo, hi):
+    return lib().orc_u53(lo, hi)
+
+
+def mv_charges(N, sigma, seed, nucleus, sheet):
+    out = np.zeros((N * N, 8))
+    lib().orc_mv_charges(N, sigma, seed, nucleus, sheet, _d(out))
+    return out
+
+
+def fft(x, sign=-1):
+    d = np.ascontiguousarray(np.asarray(x, np.complex128)).view(np.float64).copy()
+    rc = lib().orc_fft(len(x), _d(d), sign)
+    assert rc == 0
+    return d.view(np.complex128)
+
+
+def poisson(N, m2, src):
+    src = np.ascontiguousarray(src, np.float64).reshape(N * N)
+    out = np.zeros(N * N)
+    assert lib().orc_poisson(N, m2, _d(src), _d(out)) == 0
+    return out
+
+
+def wilson_line(N, sigma, m2, n_sheets, seed, nucleus):
+    V = np.zeros((N * N, 18))
+    assert lib().orc_wilson_line(N, sigma, m2, n_sheets, seed, nucleus, _d(V)) == 0
+    return V
+
+
+def nucleus_links(N, V):
+    out = np.zeros((2, N * N, 18))
+    lib().orc_nucleus_links(N, _d(np.ascontiguousarray(V)), _d(out))
+    return out
+
+
+def match_link(UA, UB, tol=1e-13, max_iter=100):
+    ua, ub = m2d(UA).copy(), m2d(UB).copy()
+    out = np.zeros(18)
+    res = np.zeros(1)
+    it = lib().orc_match_link(_d(ua), _d(ub), _d(out), tol, max_iter, _d(res))
+    return d2m(out), it, float(res[0])
+
+
+def pi0(N, U, UA, UB):
+    out = np.zeros((N * N, 8))
+    lib().orc_pi0(N, _d(np.ascontiguousarray(U)), _d(np.ascontiguousarray(UA)),
+                  _d(np.ascontiguousarray(UB)), _d(out))
+    return out
+
+
+class State:
+    """Oracle field state in its own layout: U [2,N2,18], E [2,N2,8], phi/pi [N2,8]."""
+
+    def __init__(self, N):
+        self.N = N
+        n2 = N * N
+        self.U = np.zeros((2, n2, 18))
+        self.E = np.zeros((2, n2, 8))
+        self.phi = np.zeros((n2, 8))
+        self.pi = np.zeros((n2, 8))
+        self.n = 1
+
+    def copy(self):
+        s = State(self.N)
+        s.U, s.E, s.phi, s.pi, s.n = (self.U.copy(), self.E.copy(), self.phi.copy(),
+                                      self.pi.copy(), self.n)
+        return s
+
+
+def init_glasma(N, sigma, m2, n_sheets, seed, dtau):
+    s = State(N)
+    res = np.zeros(1)
+    rc = lib().orc_init_glasma(N, sigma, m2, n_sheets, seed, dtau, _d(s.U), _d(s.E),
+                               _d(s.phi), _d(s.pi), _d(res))
+    return s, rc, float(res[0])
+
+
+def forces(N, tau, U, phi):
+    FE = np.zeros((2, N * N, 8))
+    Fpi = np.zeros((N * N, 8))
+    lib().orc_forces(N, tau, _d(np.ascontiguousarray(U)), _d(np.ascontiguousarray(phi)),
+                     _d(FE), _d(Fpi))
+    return FE, Fpi
+
+
+def field_step(s, dtau, want_F=False):
+    """Advance an oracle State by one leapfrog step in place; returns F^n or None."""
+    F = np.zeros((s.N * s.N, 6, 8)) if want_F else None
+    lib().orc_field_step(s.N, s.n, dtau, _d(s.U), _d(s.E), _d(s.phi), _d(s.pi),
+                         _d(F) if want_F else None)
+    s.n += 1
+    return F
+
+
+def field_step_sites(s, dtau, sites):
+    sites = np.ascontiguousarray(sites, np.int32)
+    k = len(sites)
+    U_new = np.zeros((k, 2, 18))
+    E_new = np.zeros((k, 2, 8))
+    phi_new = np.zeros((k, 8))
+    pi_new = np.zeros((k, 8))
+    F = np.zeros((k, 6, 8))
+    lib().orc_field_step_sites(s.N, s.n, dtau, _d(s.U), _d(s.E), _d(s.phi), _d(s.pi), k,
+                               _i(sites), _d(U_new), _d(E_new), _d(phi_new), _d(pi_new),
+                               _d(F))
+    return U_new, E_new, phi_new, pi_new, F
+
+
+def energy(s, tau):
+    out = np.zeros(4)
+    lib().orc_energy(s.N, tau, _d(s.U), _d(s.E), _d(s.phi), _d(s.pi), _d(out))
+    return out
+
+
+def gauss(s):
+    G = np.zeros((s.N * s.N, 8))
+    lib().orc_gauss(s.N, _d(s.U), _d(s.E), _d(s.phi), _d(s.pi), _d(G))
+    return G
+
+
+class Particles:
+    """Oracle particle arrays (array-of-structures per quantity)."""
+
+    def __init__(self, n):
+        self.cell = np.zeros((n, 2), np.int32)
+        self.off = np.zeros((n, 2))
+        self.eta = np.zeros(n)
+        self.p = np.zeros((n, 3))
+        self.Q = np.zeros((n, 8))
+        self.p0 = np.zeros((n, 3))
+        self.species = np.zeros(n, np.int32)
+
+    @property
+    def n(self):
+        return len(self.eta)
+
+    def copy(self):
+        q = Particles(self.n)
+        for k in ("cell", "off", "eta", "p", "Q", "p0", "species"):
+            setattr(q, k, getattr(self, k).copy())
+        return q
+
+    def subset(self, idx):
+        q = Particles(len(idx))
+        for k in ("cell", "off", "eta", "p", "Q", "p0", "species"):
+            setattr(q, k, np.ascontiguousarray(getattr(self, k)[idx]))
+        return q
+
+
+def particles_init(N, seed, species_id, kind, p0, n):
+    P = Particles(n)
+    lib().orc_particles_init(N, seed, species_id, kind, p0, n, _i(P.cell), _d(P.off),
+                             _d(P.eta), _d(P.p), _d(P.Q), _d(P.p0))
+    P.species[:] = species_id
+    return P
+
+
+def particle_step(N, n, dtau, U, phi, F, P, mass, nform):
+    mass = np.ascontiguousarray(mass, np.float64)
+    nform = np.ascontiguousarray(nform, np.int32)
+    ns = len(mass)
+    series = np.zeros((ns, 4))
+    lib().orc_particle_step(N, n, dtau, _d(np.ascontiguousarray(U)),
+                            _d(np.ascontiguousarray(phi)), _d(np.ascontiguousarray(F)),
+                            P.n, _i(P.cell), _d(P.off), _d(P.eta), _d(P.p), _d(P.Q),
+                            _d(P.p0), _i(P.species), ns, _d(mass), _i(nform), _d(series))
+    return series
+
+
+def run(N, sigma, m2, n_sheets, seed, dtau, n_steps, species):
+    """species: list of dicts with kind, mass, p0, nform, n (lattice units)."""
+    ns = len(species)
+    kind = np.array([s["kind"] for s in species], np.int32)
+    mass = np.array([s["mass"] for s in species], np.float64)
+    p0 = np.array([s["p0"] for s in species], np.float64)
+    nform = np.array([s["nform"] for s in species], np.int32)
+    npart = np.array([s["n"] for s in species], np.int32)
+    tot = int(npart.sum())
+    st = State(N)
+    P = Particles(tot)
+    series = np.zeros((n_steps, ns, 4))
+    rc = lib().orc_run(N, sigma, m2, n_sheets, seed, dtau, n_steps, ns, _i(kind), _d(mass),
+                       _d(p0), _i(nform), _i(npart), _d(st.U), _d(st.E), _d(st.phi),
+                       _d(st.pi), _i(P.cell), _d(P.off), _d(P.eta), _d(P.p), _d(P.Q),
+                       _d(P.p0), _i(P.species), _d(series))
+    st.n = 1 + n_steps
+    return st, P, series, rc
+
+
+# ---- observables: the derivative of Eq. (3) on the half-step grid ----------
+HBARC_GEV_FM = 0.1973269804
+
+
+def mean_broadening(series_s):
+    """series_s [n_steps, 4] of one species -> <dp_x^2>, <dp_y^2>, <dp_z^2> per row
+    (lattice units) and the active mask; rows with no active particle are 0."""
+    series_s = np.asarray(series_s, np.float64)
+    n = series_s[:, 3]
+    mean = np.where(n[:, None] > 0, series_s[:, :3] / np.maximum(n, 1)[:, None], 0.0)
+    return mean, n > 0
+
+
+def coefficients(series_s, dtau):
+    """Instantaneous coefficients d<dp_i^2>/dtau at tau_n (lattice units) as the
+    central difference of the half-step means; the value before formation is
+    zero.  Returns (row index k of tau_n, rates [*, 3])."""
+    mean, active = mean_broadening(series_s)
+    ks, rates = [], []
+    for k in range(len(mean)):
+        if not active[k]:
+            continue
+        prev = mean[k - 1] if (k > 0 and active[k - 1]) else np.zeros(3)
+        ks.append(k)
+        rates.append((mean[k] - prev) / dtau)
+    return np.array(ks, np.int64), np.array(rates).reshape(-1, 3)
+
+
+def to_physical(a_fm):
+    """Factors turning lattice <dp^2> into GeV^2 and lattice rates into GeV^2/fm."""
+    a_gev = a_fm / HBARC_GEV_FM
+    return 1.0 / a_gev ** 2, 1.0 / (a_gev ** 2 * a_fm)
