@@ -1,0 +1,191 @@
+"""Benchmark of the Glasma + colored-particle-in-cell hot path on one MI355X.
+
+One "step" is one whole event of the 512^2 paper-scale workload: MV charges
+drawn on the device (50 sheets per nucleus), Poisson solves, Wilson lines,
+matching and pi0, 7 x 1e5 particles (charm and beauty at p_T0 in {0, 2, 5}
+GeV, massless jets at 10 GeV, tau_form = 1/(2 m_T)), then the coupled leapfrog
+to tau = 1 fm/c (409 field + particle steps after the initial half step) and
+the broadening series.  Inputs are synthetic (seeded) and generated on the
+device; nothing is read from the host inside the timed region.
+
+Prints ONE JSON line (rank 0).  `value` is lattice site-updates per second of
+the whole job; particle-steps per second is reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBARC = 0.1973269804
+PEAK_HBM_GBS = 8000.0
+
+# paper-scale workload
+N, L_FM, SHEETS, M_IR, QS = 512, 10.0, 50, 0.2, 2.0
+G2MU = QS / 0.6            # MV ratio Q_s ~ 0.6 g^2 mu (reading of the paper's "Q_s = 2 GeV")
+DTAU = 0.125
+N_PER = 100000
+SPECIES = ([(1.27, p0, 0) for p0 in (0.0, 2.0, 5.0)] + [(4.18, p0, 0) for p0 in (0.0, 2.0, 5.0)]
+           + [(0.0, 10.0, 1)])
+SEED = 2307079992
+
+
+def coupled_steps(N, L, tau_max=1.0):
+    a = L / N
+    return int(math.ceil(tau_max / (DTAU * a) - 1e-9)) - 1
+
+
+def alg_bytes(prec):
+    ts = 8 if prec == 64 else 4
+    return {
+        # U (36) E (16) phi (8) pi (8) read once and written once per site
+        "field_step": 2 * 68 * ts,
+        # U (36), phi (8), E old+new (32), pi old+new (16) read; F (48) written
+        "site_fields": (36 + 8 + 32 + 16 + 48) * ts,
+        # state read (cell 8 B, species 4 B, 17 reals), F gather 48 + phi 8 reals,
+        # state written (cell 8 B, 14 reals)
+        "push": 12 + 17 * ts + 56 * ts + 8 + 14 * ts,
+    }
+
+
+def run_event(g, torch, prec, n_per, steps, prof=False):
+    ev = g.Event(N, L_FM, DTAU, precision=prec, reunit_every=16, max_steps=steps,
+                 max_particles=n_per * len(SPECIES))
+    return ev
+
+
+def one_event(ev, g, n_per, steps):
+    ev.init_glasma(G2MU, M_IR, SHEETS, SEED)
+    for k, (m, p0, kind) in enumerate(SPECIES):
+        ev.add_species(m, p0, kind, n_per, SEED + 17 * k)
+    ev.run(steps)
+
+
+def cpu_baseline(prec_unused, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload: coupled steps
+    on the full 512^2 lattice from a seeded state, particle work on a 1e5
+    sample scaled to the 7e5 ensemble.  Single thread."""
+    import numpy as np
+    from oracle import oracle as orc
+    from tests import seeded_inputs as si
+    a_fm = L_FM / N
+    a_gev = a_fm / HBARC
+    U, E, phi, pi = si.random_state(5, N, link_kind="near", eps=0.3)
+    s = orc.State(N)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
+    P = orc.particles_init(N, SEED, 0, 0, 2.0 * a_gev, N_PER)
+    t0 = time.perf_counter()
+    U0, phi0, n = s.U.copy(), s.phi.copy(), s.n
+    F = orc.field_step(s, DTAU, want_F=True)
+    t_field = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.particle_step(N, n, DTAU, U0, phi0, F, P, [1.27 * a_gev], [1])
+    t_part = (time.perf_counter() - t0) * len(SPECIES)   # scale 1e5 -> 7e5
+    per_step = t_field + t_part
+    return {"value": N * N / per_step, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "1 coupled step on the 512^2 lattice (seeded state) with site fields; "
+                      "particle push timed on 1e5 particles and scaled x7 to the 7e5 ensemble; "
+                      "init excluded; field %.1f s + particles %.1f s" % (t_field, t_part),
+            "particle_steps_per_s": N_PER * len(SPECIES) / per_step}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
+    ap.add_argument("--particles-per-species", type=int, default=N_PER)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(events shard across GPUs without exchange; see the design notes)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2307_07999_amd as g
+    g.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    steps = coupled_steps(N, L_FM)
+    n_per = args.particles_per_species
+    ev = run_event(g, torch, args.precision, n_per, steps)
+    for _ in range(args.warmup):
+        one_event(ev, g, n_per, steps)
+        ev.close()
+        ev = run_event(g, torch, args.precision, n_per, steps)
+    torch.cuda.synchronize()
+
+    # timed region: K whole events; kernel durations from HIP events on the
+    # library's stream over the same region
+    evs = [run_event(g, torch, args.precision, n_per, steps) for _ in range(args.steps)]
+    for e in evs:
+        e.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in evs:
+        one_event(e, g, n_per, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [0.0] * 4
+    cnt = [0] * 4
+    for e in evs:
+        m, c = e.profile_read()
+        for k in range(4):
+            ms[k] += m[k]
+            cnt[k] += int(c[k])
+    kappa_ok = True
+    for e in evs:
+        d = e.diagnostics()
+        kappa_ok &= d["nonfinite"] == 0
+    for e in evs:
+        e.close()
+
+    n_part = n_per * len(SPECIES)
+    site_updates = N * N * steps * args.steps
+    particle_steps = n_part * steps * args.steps
+    ab = alg_bytes(args.precision)
+    names = ["field_step", "site_fields", "push"]
+    avg_us = {names[k]: 1e3 * ms[k] / max(cnt[k], 1) for k in range(3)}
+    units = {"field_step": N * N, "site_fields": N * N, "push": n_part}
+    dom = max(range(3), key=lambda k: ms[k])
+    dname = names[dom]
+    achieved = ab[dname] * units[dname] / (avg_us[dname] * 1e-6) / 1e9
+    out = {
+        "metric": "particle-steps/s + lattice site-updates/s (SU(3), 512^2, 1 GPU); surrogate vs solver",
+        "value": site_updates / wall,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": "glasma+cpic event: 512^2, L=10 fm, 50 MV sheets/nucleus, "
+                               "g2mu=%.3f GeV, m_IR=0.2 GeV, dtau=a/8 to 1 fm (%d coupled steps), "
+                               "7x%d particles" % (G2MU, steps, n_per),
+                   "N": N, "coupled_steps": steps, "particles": n_part,
+                   "precision": args.precision},
+        "particle_steps_per_s": particle_steps / wall,
+        "kernel_avg_us": avg_us,
+        "finite": bool(kappa_ok),
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_unit": ab[dname], "units_per_launch": units[dname]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.precision)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * glasma.h -- C-ABI of the MI355X (gfx950) library for the boost-invariant
+ * SU(3) Glasma coupled to a colored-particle-in-cell solution of Wong's
+ * equations (Avramescu et al., "Heavy quark kappa and jet qhat transport
+ * coefficients in the Glasma early stage of heavy-ion collisions", Hard
+ * Probes 2023).
+ *
+ * The calls follow the paper's statement of the problem:
+ *   gl_init_glasma          MV color sources -> Glasma at tau = 0+   (Sec. 1 "Glasma")
+ *   gl_evolve_fields        classical Yang-Mills on links, Eq. (1)    (Sec. 1 "Glasma")
+ *   gl_push_particles       Wong's equations, Eq. (2), CPIC colors    (Sec. 1 "Probes in Glasma")
+ *   gl_broadening / gl_kappa / gl_qhat   <dp_i^2>, Eq. (3)            (Sec. 2)
+ *
+ * Conventions
+ *   - Every function returns gl_status (0 = GL_OK, negative = error) and never
+ *     throws.  gl_last_error() returns a thread-local message for the last
+ *     error on the calling thread.
+ *   - Units at the boundary are GeV and fm.  Inside, a = 1 and g is absorbed
+ *     into the fields (gA -> A).
+ *   - Device memory is owned by the caller.  gl_required_bytes() gives the
+ *     size of one workspace; the caller allocates it (256-byte aligned) and
+ *     passes it to gl_event_create(); it must outlive the event.  The library
+ *     allocates no device memory of its own.
+ *   - All device work is ordered on the hipStream_t given at creation (passed
+ *     as void*).  Calls that return host data synchronise that stream.
+ *   - An event is not thread-safe; distinct events on distinct streams are
+ *     independent.
+ *
+ * Array layouts used by the host-side getters/setters (all FP64, host memory,
+ * structure of arrays, site index x = ix + N*iy):
+ *   U    [2][18][N*N]  link U_i(x), i = 0 (x) or 1 (y); 18 = row-major 3x3,
+ *                      real and imaginary parts interleaved per entry
+ *   E    [2][8][N*N]   E_i^a(x) = 2 Tr(T^a E_i(x)), T^a = lambda^a/2
+ *   phi  [8][N*N]      A_eta components
+ *   pi   [8][N*N]      E_eta components
+ *   F    [6][8][N*N]   local-frame site fields Ex, Ey, Ez, Bx, By, Bz at tau_n
+ *   particles: cell [2][n] int32, off [2][n], eta [n], p [3][n] = (px, py, P_eta
+ *   = tau^2 p^eta), Q [8][n], p0 [3][n] = (px, py, pz_lab) at formation,
+ *   species [n] int32 (grouped by species in ascending order).
+ *
+ * Time grid: tau_n = n * dtau with dtau = dtau_over_a * a.  After
+ * gl_init_glasma the state is at n = 1 (U^1, phi^1; E, pi at tau_{1/2}).
+ * One field step takes n -> n+1; one particle step does too.
+ */
+#ifndef GLASMA_H
+#define GLASMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gl_status;
+#define GL_OK        0
+#define GL_EINVAL   (-1)   /* bad argument                                 */
+#define GL_ESTATE   (-2)   /* call not allowed in the event's current state */
+#define GL_ENOTCONV (-3)   /* a link of the initial-condition matching did not converge */
+#define GL_ENUMERIC (-4)   /* non-finite value found by the diagnostics    */
+#define GL_EDEVICE  (-5)   /* a HIP runtime call failed                    */
+#define GL_ENOMEM   (-6)   /* workspace too small                          */
+
+#define GL_MAX_SPECIES 16
+
+typedef struct gl_event gl_event;
+
+/* Lattice and run description. */
+typedef struct {
+    int32_t N;              /* transverse sites per direction, 2 <= N <= 1024, N = 2^a 3^b for MV init */
+    double  L_fm;           /* transverse box size; a = L/N */
+    double  dtau_over_a;    /* leapfrog step in lattice units (the paper's runs: 1/8) */
+    int32_t precision;      /* 64 (FP64 fields/particles) or 32 (FP32 fields/particles, FP64 sums) */
+    int32_t reunit_every;   /* FP32 only: re-unitarise links when n % reunit_every == reunit_every-1; 0 = never */
+    int32_t max_steps;      /* capacity of the broadening series (rows) */
+    int64_t max_particles;  /* particle capacity over all species (padding included by the library) */
+} gl_lattice_desc;
+
+/* MV-model description (Sec. 1 "Glasma"): per-sheet charge variance
+ * (g^2 mu)^2 / (n_sheets a^2), infrared regulator m in the Poisson solve. */
+typedef struct {
+    double  g2mu_GeV;
+    double  m_ir_GeV;
+    int32_t n_sheets;
+} gl_mv_desc;
+
+/* Particle species (Sec. 2, toy initialisation). */
+#define GL_KIND_HEAVY_QUARK 0   /* |p_T| = p0 with uniform azimuth */
+#define GL_KIND_JET         1   /* p = (p0, 0, 0) along +x        */
+typedef struct {
+    double  mass_GeV;
+    double  p0_GeV;
+    int32_t kind;
+    double  tau_form_fm;    /* < 0: 1/(2 m_T) with m_T = sqrt(m^2 + p0^2) */
+} gl_species_desc;
+
+typedef struct {
+    double gauss_max;        /* max |G^a(x)| of the Gauss-law residual */
+    double gauss_rel;        /* gauss_max / max |E^a|                   */
+    double unitarity_max;    /* max |U U^dag - 1| entry                 */
+    double energy[4];        /* (E_T, E_L, B_T, B_L) per unit rapidity, lattice units, at the stored times */
+    double casimir2_dev;     /* max |Q^aQ^a - 4| over active particles  */
+    int32_t nonfinite;       /* 1 if any NaN/Inf in the fields          */
+} gl_diag;
+
+/* Workspace size for an event.  Pure function. */
+gl_status gl_required_bytes(const gl_lattice_desc *desc, size_t *bytes);
+
+/* Create an event on a caller-owned workspace and stream (hipStream_t). */
+gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t bytes,
+                          void *stream, gl_event **out);
+void gl_event_destroy(gl_event *ev);
+
+/* MV sources -> Glasma (Sec. 1): charges drawn on the device from Philox4x32-10
+ * (key = seed, counter = (site, 4*sheet + j, nucleus, 0)), Poisson solve,
+ * Wilson lines, matching of the two nuclei, initial longitudinal field and
+ * the first half step.  Returns GL_ENOTCONV if a link did not converge. */
+gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed);
+
+/* Same from caller-supplied charges rho (device, FP64) laid out
+ * [2][n_sheets][8][N*N] in lattice units. */
+gl_status gl_init_glasma_from_charges(gl_event *ev, const double *rho_dev, int32_t n_sheets,
+                                      double m_ir_GeV);
+
+/* Add n particles of one species (Sec. 2 toy model); draws from Philox with
+ * counter (i, j, 2 + species_id, 0).  Species ids are 0, 1, ... in call order. */
+gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uint64_t seed,
+                         int32_t *species_id);
+
+/* Fields only: n_steps leapfrog steps.  GL_ESTATE if particles are behind
+ * the field time (a gl_push_particles is due). */
+gl_status gl_evolve_fields(gl_event *ev, int32_t n_steps);
+/* One particle step tau_n -> tau_{n+1} with the field snapshot at tau_n;
+ * must follow gl_evolve_fields(ev, 1) when the event has particles. */
+gl_status gl_push_particles(gl_event *ev);
+/* Hot path: n_steps x (one field step + one particle step). */
+gl_status gl_run(gl_event *ev, int32_t n_steps);
+
+/* Observables of one species (Sec. 2, Eq. (3)).
+ * gl_broadening rows: (tau_fm, <dpx^2>, <dpy^2>, <dpz^2>, n_active) in GeV^2,
+ *   at the half steps tau_{n+1/2} where the species is active.
+ * gl_kappa rows: (tau_fm, tau - tau_form, kappa_T, kappa_L) in GeV^2/fm at tau_n.
+ * gl_qhat rows: (tau_fm, qhat_y, qhat_z) in GeV^2/fm at tau_n.
+ * cap is the row capacity of out; *n_rows receives the row count. */
+gl_status gl_broadening(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows);
+gl_status gl_kappa(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows);
+gl_status gl_qhat(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows);
+/* Raw FP64 series [rows][GL_MAX_SPECIES][4] = (sum dpx^2, sum dpy^2, sum dpz^2,
+ * n_active) in lattice units; row k holds tau_{k+1+1/2}. */
+gl_status gl_series(gl_event *ev, double *out, int32_t cap_rows, int32_t *n_rows);
+
+/* Same derivative as gl_kappa on a host series of one species, for callers
+ * that hold their own series: series [rows][4] (lattice units), rate out
+ * [rows][3] (lattice units); rows before formation are set to 0. */
+gl_status gl_rates_from_series(const double *series, int32_t rows, double dtau,
+                               double *rates);
+
+/* Diagnostics of the current state (FP64 reductions on the device). */
+gl_status gl_diagnostics(gl_event *ev, gl_diag *out);
+
+/* Host <-> device state transfer in the layouts above (tests, checkpoints). */
+gl_status gl_set_state(gl_event *ev, const double *U, const double *E, const double *phi,
+                       const double *pi, int64_t n);
+gl_status gl_get_state(gl_event *ev, double *U, double *E, double *phi, double *pi,
+                       int64_t *n);
+/* Site fields F^n of the last field step (valid while a particle step is due
+ * or right after it). */
+gl_status gl_get_site_fields(gl_event *ev, double *F);
+/* Replace all particles; species table given as desc + per-particle species
+ * (grouped ascending).  nform per species is derived from tau_form. */
+gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_desc *sp,
+                           int64_t n, const int32_t *cell, const double *off,
+                           const double *eta, const double *p, const double *Q,
+                           const double *p0, const int32_t *species);
+gl_status gl_get_particles(gl_event *ev, int64_t cap, int64_t *n, int32_t *cell, double *off,
+                           double *eta, double *p, double *Q, double *p0, int32_t *species);
+/* Per-species formation step index and mass in lattice units. */
+gl_status gl_species_info(gl_event *ev, int32_t species, int32_t *nform, double *mass_lat);
+
+/* Wilson line V of one nucleus after gl_init_glasma: [18][N*N], FP64. */
+gl_status gl_get_wilson_line(gl_event *ev, int32_t nucleus, double *V);
+/* MV charges of one (nucleus, sheet) drawn exactly as gl_init_glasma draws
+ * them: [8][N*N] FP64, lattice units, for standard deviation sigma. */
+gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t sheet,
+                          double sigma, double *rho);
+
+/* Kernel timing with HIP events recorded on the event's stream around every
+ * launch of the hot-path kernels while enabled.  gl_profile_read synchronises
+ * the stream and returns, per kernel class (0 field step, 1 site fields,
+ * 2 particle push, 3 series reduction), the summed milliseconds and the
+ * launch counts since the last read, then clears them.  Creates HIP events
+ * only (no device memory). */
+#define GL_PROF_KERNELS 4
+gl_status gl_profile_enable(gl_event *ev, int32_t on);
+gl_status gl_profile_read(gl_event *ev, double *ms, int64_t *launches);
+
+/* Lattice spacing in fm and GeV^-1, and the current step index. */
+gl_status gl_event_info(gl_event *ev, double *a_fm, double *dtau_lat, int64_t *n);
+/* Block until the event's stream is idle. */
+gl_status gl_sync(gl_event *ev);
+
+const char *gl_status_string(gl_status s);
+const char *gl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLASMA_H */

@@ -1,0 +1,877 @@
+// event.hip -- runtime behind the C-ABI of include/glasma.h: one event holds
+// a caller-owned workspace carved into ping-pong field buffers, the site-field
+// planes, the padded particle arrays, the FP64 broadening series and the
+// initial-condition scratch, and orders every launch on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/glasma.h"
+#include "internal.hpp"
+
+using namespace gl;
+
+namespace {
+
+thread_local std::string g_err;
+constexpr double kHbarC = 0.1973269804;   // GeV fm
+
+gl_status fail(gl_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(GL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t field[2], F, part, partials, block_start, series, diag, VA, VB, planes, U0, pi0, status,
+        total;
+    int64_t slots;         // particle capacity in slots (padding included)
+    size_t n_diag_blocks;  // workgroups of the diagnostics kernel
+};
+
+bool valid_N_for_fft(int N) {
+    int m = N;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1;
+}
+
+gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
+    if (!d) return fail(GL_EINVAL, "null lattice description");
+    if (d->N < 2 || d->N > 1024) return fail(GL_EINVAL, "N must be in [2, 1024]");
+    if (!(d->L_fm > 0) || !(d->dtau_over_a > 0) || d->dtau_over_a > 0.5)
+        return fail(GL_EINVAL, "L_fm must be > 0 and 0 < dtau_over_a <= 0.5");
+    if (d->precision != 64 && d->precision != 32) return fail(GL_EINVAL, "precision must be 64 or 32");
+    if (d->max_steps < 0 || d->max_particles < 0 || d->reunit_every < 0)
+        return fail(GL_EINVAL, "negative capacity");
+    const size_t n2 = (size_t)d->N * d->N, ts = d->precision == 64 ? 8 : 4;
+    L.slots = ((d->max_particles + kPushBlock - 1) / kPushBlock + kMaxSpecies) * kPushBlock;
+    if (d->max_particles == 0) L.slots = 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    for (int b = 0; b < 2; b++) L.field[b] = take(68 * n2 * ts);
+    L.F = take(48 * n2 * ts);
+    L.part = take((size_t)L.slots * (17 * ts + 12));
+    L.partials = take(std::max<int64_t>(1, L.slots / kPushBlock) * 4 * sizeof(double));
+    L.block_start = take((kMaxSpecies + 1) * sizeof(int32_t));
+    L.series = take(std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double));
+    L.n_diag_blocks = (size_t)((d->N + 31) / 32) * ((d->N + 7) / 8);
+    size_t cas_blocks = (size_t)std::max<int64_t>(1, (L.slots + 255) / 256);
+    L.diag = take(std::max(L.n_diag_blocks * 8, cas_blocks) * sizeof(double));
+    L.VA = take(18 * n2 * sizeof(double));
+    L.VB = take(18 * n2 * sizeof(double));
+    L.planes = take(4 * n2 * sizeof(double2));
+    L.U0 = take(36 * n2 * sizeof(double));
+    L.pi0 = take(8 * n2 * sizeof(double));
+    L.status = take(256);
+    L.total = off;
+    return GL_OK;
+}
+
+struct SpeciesInfo {
+    gl_species_desc desc;
+    int64_t n, slot0, cap;
+    int32_t nform;
+    double mass_lat, p0_lat, tau_form_fm;
+};
+
+}  // namespace
+
+struct gl_event {
+    gl_lattice_desc desc;
+    Layout L;
+    int N;
+    size_t n2;
+    double a_fm, a_gev, dtau;   // dtau in lattice units
+    hipStream_t stream;
+    char *ws;
+    int cur = 0;
+    int64_t n = 0;
+    bool ready = false, push_due = false;
+    int64_t rows = 0;           // series rows written
+    int64_t slots_used = 0;
+    std::vector<SpeciesInfo> species;
+    int32_t block_start_host[kMaxSpecies + 1];
+
+    // kernel timing: pairs of events per launch, grouped by kernel class
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> prof_marks;   // (class, index of start event)
+
+    bool fp64() const { return desc.precision == 64; }
+    template <typename T>
+    FieldPtrs<T> fields(int b) const {
+        T *base = (T *)(ws + L.field[b]);
+        return FieldPtrs<T>{base, base + 36 * n2, base + 52 * n2, base + 60 * n2};
+    }
+    template <typename T>
+    PartPtrs<T> parts() const {
+        PartPtrs<T> p;
+        int64_t c = L.slots;
+        char *b = ws + L.part;
+        p.cx = (int32_t *)b;
+        p.cy = p.cx + c;
+        p.species = p.cy + c;
+        T *t = (T *)(b + 12 * c);
+        p.ox = t;
+        p.oy = t + c;
+        p.eta = t + 2 * c;
+        p.px = t + 3 * c;
+        p.py = t + 4 * c;
+        p.peta = t + 5 * c;
+        p.px0 = t + 6 * c;
+        p.py0 = t + 7 * c;
+        p.pz0 = t + 8 * c;
+        p.Q = t + 9 * c;
+        p.cap = c;
+        return p;
+    }
+    template <typename T>
+    SpeciesTab<T> tab() const {
+        SpeciesTab<T> t;
+        for (int s = 0; s < kMaxSpecies; s++) {
+            t.mass[s] = s < (int)species.size() ? (T)species[s].mass_lat : T(0);
+            t.nform[s] = s < (int)species.size() ? species[s].nform : 0x7fffffff;
+        }
+        return t;
+    }
+    double *series() const { return (double *)(ws + L.series); }
+    double *partials() const { return (double *)(ws + L.partials); }
+};
+
+namespace {
+
+gl_status check_ev(gl_event *ev) {
+    if (!ev) return fail(GL_EINVAL, "null event");
+    return GL_OK;
+}
+
+// start/stop marks around one launch of kernel class k (no-ops when disabled)
+gl_status prof_begin(gl_event *ev, int k, size_t *idx) {
+    if (!ev->prof) return GL_OK;
+    while (ev->ev_pool.size() < ev->ev_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ev->ev_pool.push_back(e);
+    }
+    *idx = ev->ev_used;
+    ev->ev_used += 2;
+    ev->prof_marks.push_back({k, *idx});
+    HIP_TRY(hipEventRecord(ev->ev_pool[*idx], ev->stream));
+    return GL_OK;
+}
+
+gl_status prof_end(gl_event *ev, size_t idx) {
+    if (!ev->prof) return GL_OK;
+    HIP_TRY(hipEventRecord(ev->ev_pool[idx + 1], ev->stream));
+    return GL_OK;
+}
+
+#define PROF(ev, k, call)                                       \
+    do {                                                        \
+        size_t pidx_ = 0;                                       \
+        gl_status ps_ = prof_begin(ev, k, &pidx_);              \
+        if (ps_) return ps_;                                    \
+        HIP_TRY(call);                                          \
+        ps_ = prof_end(ev, pidx_);                              \
+        if (ps_) return ps_;                                    \
+    } while (0)
+
+// one field step n -> n+1; site fields F^n when the event has particles
+template <typename T>
+gl_status field_step(gl_event *ev, bool site_fields) {
+    const int nxt = 1 - ev->cur;
+    const double tau = ev->n * ev->dtau;
+    int reunit = 0;
+    if (!ev->fp64() && ev->desc.reunit_every > 0 &&
+        ev->n % ev->desc.reunit_every == ev->desc.reunit_every - 1)
+        reunit = 1;
+    PROF(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt), tau,
+                                      ev->dtau, reunit)));
+    if (site_fields)
+        PROF(ev, 1, (launch_site_fields<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
+                                           (T *)(ev->ws + ev->L.F), tau)));
+    ev->cur = nxt;
+    ev->n += 1;
+    return GL_OK;
+}
+
+template <typename T>
+gl_status push(gl_event *ev) {
+    const int64_t n_prev = ev->n - 1;   // particles advance n_prev -> n
+    const int64_t row = n_prev - 1;
+    if (row >= ev->desc.max_steps) return fail(GL_EINVAL, "series capacity (max_steps) exhausted");
+    PROF(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used, ev->fields<T>(1 - ev->cur),
+                                (const T *)(ev->ws + ev->L.F), ev->tab<T>(), (int)n_prev, ev->dtau,
+                                ev->partials())));
+    PROF(ev, 3, (launch_series_reduce(ev->stream, ev->partials(), (const int32_t *)(ev->ws + ev->L.block_start),
+                                      (int)ev->species.size(), ev->series() + row * kMaxSpecies * 4)));
+    ev->rows = std::max<int64_t>(ev->rows, row + 1);
+    ev->push_due = false;
+    return GL_OK;
+}
+
+gl_status do_field_step(gl_event *ev, bool sf) {
+    return ev->fp64() ? field_step<double>(ev, sf) : field_step<float>(ev, sf);
+}
+gl_status do_push(gl_event *ev) { return ev->fp64() ? push<double>(ev) : push<float>(ev); }
+
+int32_t nform_of(double tau_form_fm, double dtau_fm) {
+    double r = std::ceil(tau_form_fm / dtau_fm);
+    if (!(r >= 1.0)) r = 1.0;
+    if (r > 2e9) r = 2e9;
+    return (int32_t)r;
+}
+
+gl_status fill_species(gl_event *ev, const gl_species_desc *sp, SpeciesInfo &si) {
+    if (!(sp->mass_GeV >= 0) || !(sp->p0_GeV >= 0)) return fail(GL_EINVAL, "mass and p0 must be >= 0");
+    if (sp->kind != GL_KIND_HEAVY_QUARK && sp->kind != GL_KIND_JET) return fail(GL_EINVAL, "unknown kind");
+    double tf = sp->tau_form_fm;
+    if (tf < 0) {
+        double mT = std::sqrt(sp->mass_GeV * sp->mass_GeV + sp->p0_GeV * sp->p0_GeV);
+        if (!(mT > 0)) return fail(GL_EINVAL, "tau_form = 1/(2 m_T) needs m_T > 0");
+        tf = kHbarC / (2.0 * mT);
+    }
+    if (sp->mass_GeV == 0 && sp->p0_GeV == 0) return fail(GL_EINVAL, "massless particle needs p0 > 0");
+    si.desc = *sp;
+    si.tau_form_fm = tf;
+    si.nform = nform_of(tf, ev->dtau * ev->a_fm);
+    si.mass_lat = sp->mass_GeV * ev->a_gev;
+    si.p0_lat = sp->p0_GeV * ev->a_gev;
+    return GL_OK;
+}
+
+gl_status upload_block_start(gl_event *ev) {
+    for (int s = 0; s <= kMaxSpecies; s++) ev->block_start_host[s] = (int32_t)(ev->slots_used / kPushBlock);
+    for (size_t s = 0; s < ev->species.size(); s++) {
+        ev->block_start_host[s] = (int32_t)(ev->species[s].slot0 / kPushBlock);
+        ev->block_start_host[s + 1] = (int32_t)((ev->species[s].slot0 + ev->species[s].cap) / kPushBlock);
+    }
+    HIP_TRY(hipMemcpyAsync(ev->ws + ev->L.block_start, ev->block_start_host, sizeof(ev->block_start_host),
+                           hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+template <typename T>
+gl_status init_particles(gl_event *ev, const SpeciesInfo &si, int sid, uint64_t seed) {
+    PartPtrs<T> p = ev->parts<T>();
+    HIP_TRY(hipMemsetAsync(p.species + si.slot0, 0xFF, si.cap * sizeof(int32_t), ev->stream));
+    HIP_TRY(launch_particles_init<T>(ev->stream, ev->N, p, si.slot0, si.n, seed, sid, si.desc.kind,
+                                     si.p0_lat));
+    return GL_OK;
+}
+
+template <typename T>
+gl_status finish_init(gl_event *ev) {
+    int *status = (int *)(ev->ws + ev->L.status);
+    HIP_TRY(hipMemsetAsync(status, 0, sizeof(int), ev->stream));
+    HIP_TRY(launch_match_pi0(ev->stream, ev->N, (double *)(ev->ws + ev->L.VA), (double *)(ev->ws + ev->L.VB),
+                             (double *)(ev->ws + ev->L.U0), (double *)(ev->ws + ev->L.pi0), status, 100, 1e-13));
+    ev->cur = 0;
+    HIP_TRY(launch_first_half_step<T>(ev->stream, ev->N, (double *)(ev->ws + ev->L.U0),
+                                      (double *)(ev->ws + ev->L.pi0), ev->fields<T>(0), ev->dtau));
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    ev->n = 1;
+    ev->ready = true;
+    ev->push_due = false;
+    ev->rows = 0;
+    if (ev->desc.max_steps > 0)
+        HIP_TRY(hipMemsetAsync(ev->series(), 0, (size_t)ev->desc.max_steps * kMaxSpecies * 4 * sizeof(double),
+                               ev->stream));
+    if (h) return fail(GL_ENOTCONV, "matching Newton iteration did not converge on some link");
+    return GL_OK;
+}
+
+template <typename T>
+void to_T(const double *src, std::vector<T> &dst, size_t n) {
+    dst.resize(n);
+    for (size_t i = 0; i < n; i++) dst[i] = (T)src[i];
+}
+
+template <typename T>
+gl_status copy_in(gl_event *ev, void *dev, const double *host, size_t n) {
+    if (sizeof(T) == 8) {
+        HIP_TRY(hipMemcpyAsync(dev, host, n * 8, hipMemcpyHostToDevice, ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+    } else {
+        std::vector<T> tmp;
+        to_T(host, tmp, n);
+        HIP_TRY(hipMemcpyAsync(dev, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+    }
+    return GL_OK;
+}
+
+template <typename T>
+gl_status copy_out(gl_event *ev, double *host, const void *dev, size_t n) {
+    std::vector<T> tmp(n);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), dev, n * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    for (size_t i = 0; i < n; i++) host[i] = (double)tmp[i];
+    return GL_OK;
+}
+
+template <typename T>
+gl_status set_state_t(gl_event *ev, const double *U, const double *E, const double *phi, const double *pi) {
+    FieldPtrs<T> f = ev->fields<T>(ev->cur);
+    gl_status s;
+    if ((s = copy_in<T>(ev, f.U, U, 36 * ev->n2))) return s;
+    if ((s = copy_in<T>(ev, f.E, E, 16 * ev->n2))) return s;
+    if ((s = copy_in<T>(ev, f.phi, phi, 8 * ev->n2))) return s;
+    return copy_in<T>(ev, f.pi, pi, 8 * ev->n2);
+}
+
+template <typename T>
+gl_status get_state_t(gl_event *ev, double *U, double *E, double *phi, double *pi) {
+    FieldPtrs<T> f = ev->fields<T>(ev->cur);
+    gl_status s;
+    if (U && (s = copy_out<T>(ev, U, f.U, 36 * ev->n2))) return s;
+    if (E && (s = copy_out<T>(ev, E, f.E, 16 * ev->n2))) return s;
+    if (phi && (s = copy_out<T>(ev, phi, f.phi, 8 * ev->n2))) return s;
+    if (pi && (s = copy_out<T>(ev, pi, f.pi, 8 * ev->n2))) return s;
+    return GL_OK;
+}
+
+template <typename T>
+gl_status set_particles_t(gl_event *ev, int64_t n, const int32_t *cell, const double *off, const double *eta,
+                          const double *p, const double *Q, const double *p0, const int32_t *species) {
+    const int64_t c = ev->L.slots;
+    std::vector<int32_t> cx(c, 0), cy(c, 0), sp(c, -1);
+    std::vector<T> f(17 * (size_t)c, T(0));
+    int64_t i = 0;
+    for (size_t s = 0; s < ev->species.size(); s++) {
+        const SpeciesInfo &si = ev->species[s];
+        for (int64_t k = 0; k < si.n; k++, i++) {
+            int64_t j = si.slot0 + k;
+            cx[j] = cell[i];
+            cy[j] = cell[n + i];
+            sp[j] = species[i];
+            f[0 * c + j] = (T)off[i];
+            f[1 * c + j] = (T)off[n + i];
+            f[2 * c + j] = (T)eta[i];
+            f[3 * c + j] = (T)p[i];
+            f[4 * c + j] = (T)p[n + i];
+            f[5 * c + j] = (T)p[2 * n + i];
+            f[6 * c + j] = (T)p0[i];
+            f[7 * c + j] = (T)p0[n + i];
+            f[8 * c + j] = (T)p0[2 * n + i];
+            for (int a = 0; a < 8; a++) f[(9 + a) * c + j] = (T)Q[a * n + i];
+        }
+    }
+    PartPtrs<T> P = ev->parts<T>();
+    HIP_TRY(hipMemcpyAsync(P.cx, cx.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipMemcpyAsync(P.cy, cy.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipMemcpyAsync(P.species, sp.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipMemcpyAsync(P.ox, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+template <typename T>
+gl_status get_particles_t(gl_event *ev, int64_t n, int32_t *cell, double *off, double *eta, double *p,
+                          double *Q, double *p0, int32_t *species) {
+    const int64_t c = ev->L.slots;
+    std::vector<int32_t> cx(c), cy(c), sp(c);
+    std::vector<T> f(17 * (size_t)c);
+    PartPtrs<T> P = ev->parts<T>();
+    if (c > 0) {
+        HIP_TRY(hipMemcpyAsync(cx.data(), P.cx, c * 4, hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipMemcpyAsync(cy.data(), P.cy, c * 4, hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipMemcpyAsync(sp.data(), P.species, c * 4, hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipMemcpyAsync(f.data(), P.ox, f.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+    }
+    int64_t i = 0;
+    for (size_t s = 0; s < ev->species.size(); s++) {
+        const SpeciesInfo &si = ev->species[s];
+        for (int64_t k = 0; k < si.n; k++, i++) {
+            int64_t j = si.slot0 + k;
+            if (cell) { cell[i] = cx[j]; cell[n + i] = cy[j]; }
+            if (species) species[i] = sp[j];
+            if (off) { off[i] = f[0 * c + j]; off[n + i] = f[1 * c + j]; }
+            if (eta) eta[i] = f[2 * c + j];
+            if (p) { p[i] = f[3 * c + j]; p[n + i] = f[4 * c + j]; p[2 * n + i] = f[5 * c + j]; }
+            if (p0) { p0[i] = f[6 * c + j]; p0[n + i] = f[7 * c + j]; p0[2 * n + i] = f[8 * c + j]; }
+            if (Q)
+                for (int a = 0; a < 8; a++) Q[a * n + i] = f[(9 + a) * c + j];
+        }
+    }
+    return GL_OK;
+}
+
+int64_t total_particles(const gl_event *ev) {
+    int64_t t = 0;
+    for (auto &s : ev->species) t += s.n;
+    return t;
+}
+
+gl_status read_series_species(gl_event *ev, int32_t species, std::vector<double> &rows4) {
+    if (species < 0 || species >= (int32_t)ev->species.size()) return fail(GL_EINVAL, "no such species");
+    std::vector<double> all((size_t)ev->rows * kMaxSpecies * 4);
+    if (ev->rows > 0) {
+        HIP_TRY(hipMemcpyAsync(all.data(), ev->series(), all.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+    }
+    rows4.resize((size_t)ev->rows * 4);
+    for (int64_t k = 0; k < ev->rows; k++)
+        for (int c = 0; c < 4; c++) rows4[k * 4 + c] = all[(k * kMaxSpecies + species) * 4 + c];
+    return GL_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char *gl_last_error(void) { return g_err.c_str(); }
+
+const char *gl_status_string(gl_status s) {
+    switch (s) {
+        case GL_OK: return "ok";
+        case GL_EINVAL: return "invalid argument";
+        case GL_ESTATE: return "call not allowed in the current state";
+        case GL_ENOTCONV: return "matching did not converge";
+        case GL_ENUMERIC: return "non-finite values";
+        case GL_EDEVICE: return "HIP runtime error";
+        case GL_ENOMEM: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+gl_status gl_required_bytes(const gl_lattice_desc *desc, size_t *bytes) {
+    Layout L;
+    gl_status s = make_layout(desc, L);
+    if (s) return s;
+    if (!bytes) return fail(GL_EINVAL, "null output");
+    *bytes = L.total;
+    return GL_OK;
+}
+
+gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t bytes, void *stream,
+                          gl_event **out) {
+    if (!out) return fail(GL_EINVAL, "null output");
+    *out = nullptr;
+    Layout L;
+    gl_status s = make_layout(desc, L);
+    if (s) return s;
+    if (!workspace) return fail(GL_EINVAL, "null workspace");
+    if (((uintptr_t)workspace & 255) != 0) return fail(GL_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < L.total) return fail(GL_ENOMEM, "workspace smaller than gl_required_bytes()");
+    gl_event *ev = new (std::nothrow) gl_event();
+    if (!ev) return fail(GL_ENOMEM, "host allocation failed");
+    ev->desc = *desc;
+    ev->L = L;
+    ev->N = desc->N;
+    ev->n2 = (size_t)desc->N * desc->N;
+    ev->a_fm = desc->L_fm / desc->N;
+    ev->a_gev = ev->a_fm / kHbarC;
+    ev->dtau = desc->dtau_over_a;
+    ev->stream = (hipStream_t)stream;
+    ev->ws = (char *)workspace;
+    for (int k = 0; k <= kMaxSpecies; k++) ev->block_start_host[k] = 0;
+    *out = ev;
+    return GL_OK;
+}
+
+void gl_event_destroy(gl_event *ev) {
+    if (!ev) return;
+    for (hipEvent_t e : ev->ev_pool) (void)hipEventDestroy(e);
+    delete ev;
+}
+
+static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, const double *rho_dev, double sigma,
+                             uint64_t seed) {
+    const int N = ev->N;
+    double m2 = (m_ir_GeV * ev->a_gev) * (m_ir_GeV * ev->a_gev);
+    if (!(m2 > 0)) return fail(GL_EINVAL, "infrared regulator must be > 0");
+    if (!valid_N_for_fft(N)) return fail(GL_EINVAL, "MV initialisation needs N = 2^a 3^b");
+    double *V[2] = {(double *)(ev->ws + ev->L.VA), (double *)(ev->ws + ev->L.VB)};
+    double2 *planes = (double2 *)(ev->ws + ev->L.planes);
+    for (int nuc = 0; nuc < 2; nuc++) {
+        HIP_TRY(launch_wilson_init(ev->stream, N, V[nuc]));
+        for (int sh = 0; sh < n_sheets; sh++) {
+            if (rho_dev)
+                HIP_TRY(launch_charges_to_planes(ev->stream, N, rho_dev + ((size_t)nuc * n_sheets + sh) * 8 * ev->n2,
+                                                 planes));
+            else
+                HIP_TRY(launch_mv_charges(ev->stream, N, sigma, seed, nuc, sh, planes));
+            HIP_TRY(launch_poisson(ev->stream, N, m2, planes, nullptr));
+            HIP_TRY(launch_wilson_accum(ev->stream, N, planes, V[nuc]));
+        }
+    }
+    return ev->fp64() ? finish_init<double>(ev) : finish_init<float>(ev);
+}
+
+gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed) {
+    if (check_ev(ev) || !mv) return fail(GL_EINVAL, "null argument");
+    if (mv->n_sheets < 1) return fail(GL_EINVAL, "n_sheets must be >= 1");
+    if (!(mv->g2mu_GeV >= 0)) return fail(GL_EINVAL, "g2mu must be >= 0");
+    double sigma = mv->g2mu_GeV * ev->a_gev / std::sqrt((double)mv->n_sheets);
+    return init_common(ev, mv->n_sheets, mv->m_ir_GeV, nullptr, sigma, seed);
+}
+
+gl_status gl_init_glasma_from_charges(gl_event *ev, const double *rho_dev, int32_t n_sheets, double m_ir_GeV) {
+    if (check_ev(ev) || !rho_dev) return fail(GL_EINVAL, "null argument");
+    if (n_sheets < 1) return fail(GL_EINVAL, "n_sheets must be >= 1");
+    return init_common(ev, n_sheets, m_ir_GeV, rho_dev, 0.0, 0);
+}
+
+gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uint64_t seed, int32_t *species_id) {
+    if (check_ev(ev) || !sp) return fail(GL_EINVAL, "null argument");
+    if (n < 1) return fail(GL_EINVAL, "n must be >= 1");
+    if ((int)ev->species.size() >= kMaxSpecies) return fail(GL_EINVAL, "too many species");
+    if (ev->push_due) return fail(GL_ESTATE, "a particle step is due");
+    SpeciesInfo si;
+    gl_status s = fill_species(ev, sp, si);
+    if (s) return s;
+    si.n = n;
+    si.slot0 = ev->slots_used;
+    si.cap = (n + kPushBlock - 1) / kPushBlock * kPushBlock;
+    if (si.slot0 + si.cap > ev->L.slots) return fail(GL_ENOMEM, "particle capacity exceeded");
+    int sid = (int)ev->species.size();
+    ev->species.push_back(si);
+    ev->slots_used += si.cap;
+    s = ev->fp64() ? init_particles<double>(ev, si, sid, seed) : init_particles<float>(ev, si, sid, seed);
+    if (s) return s;
+    s = upload_block_start(ev);
+    if (s) return s;
+    if (species_id) *species_id = sid;
+    return GL_OK;
+}
+
+gl_status gl_evolve_fields(gl_event *ev, int32_t n_steps) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    if (n_steps < 0) return fail(GL_EINVAL, "n_steps must be >= 0");
+    bool has_particles = ev->slots_used > 0;
+    if (has_particles && (ev->push_due || n_steps > 1))
+        return fail(GL_ESTATE, "particles are not at the field time: push them first, one field step at a time");
+    for (int32_t k = 0; k < n_steps; k++) {
+        gl_status s = do_field_step(ev, has_particles);
+        if (s) return s;
+        if (has_particles) ev->push_due = true;
+    }
+    return GL_OK;
+}
+
+gl_status gl_push_particles(gl_event *ev) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (!ev->push_due) return fail(GL_ESTATE, "no particle step is due: call gl_evolve_fields(ev, 1) first");
+    return do_push(ev);
+}
+
+gl_status gl_run(gl_event *ev, int32_t n_steps) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    if (ev->push_due) return fail(GL_ESTATE, "a particle step is due");
+    if (n_steps < 0) return fail(GL_EINVAL, "n_steps must be >= 0");
+    bool has_particles = ev->slots_used > 0;
+    if (has_particles && ev->n - 1 + n_steps > ev->desc.max_steps)
+        return fail(GL_EINVAL, "series capacity (max_steps) too small for this run");
+    for (int32_t k = 0; k < n_steps; k++) {
+        gl_status s = do_field_step(ev, has_particles);
+        if (s) return s;
+        if (has_particles) {
+            ev->push_due = true;
+            s = do_push(ev);
+            if (s) return s;
+        }
+    }
+    return GL_OK;
+}
+
+gl_status gl_series(gl_event *ev, double *out, int32_t cap_rows, int32_t *n_rows) {
+    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
+    *n_rows = (int32_t)ev->rows;
+    if (!out || ev->rows == 0) return GL_OK;
+    if (cap_rows < ev->rows) return fail(GL_EINVAL, "output too small");
+    HIP_TRY(hipMemcpyAsync(out, ev->series(), (size_t)ev->rows * kMaxSpecies * 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+gl_status gl_rates_from_series(const double *series, int32_t rows, double dtau, double *rates) {
+    if (!series || !rates || rows < 0 || !(dtau > 0)) return fail(GL_EINVAL, "bad argument");
+    double prev[3] = {0, 0, 0};
+    bool prev_active = false;
+    for (int32_t k = 0; k < rows; k++) {
+        double cnt = series[k * 4 + 3];
+        if (!(cnt > 0)) {
+            rates[k * 3] = rates[k * 3 + 1] = rates[k * 3 + 2] = 0.0;
+            prev_active = false;
+            continue;
+        }
+        for (int c = 0; c < 3; c++) {
+            double m = series[k * 4 + c] / cnt;
+            rates[k * 3 + c] = (m - (prev_active ? prev[c] : 0.0)) / dtau;
+            prev[c] = m;
+        }
+        prev_active = true;
+    }
+    return GL_OK;
+}
+
+gl_status gl_broadening(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows) {
+    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
+    std::vector<double> s4;
+    gl_status s = read_series_species(ev, species, s4);
+    if (s) return s;
+    const double f2 = 1.0 / (ev->a_gev * ev->a_gev), dt_fm = ev->dtau * ev->a_fm;
+    int32_t r = 0;
+    for (int64_t k = 0; k < ev->rows; k++) {
+        double cnt = s4[k * 4 + 3];
+        if (!(cnt > 0)) continue;
+        if (out) {
+            if (r >= cap) return fail(GL_EINVAL, "output too small");
+            out[r * 5 + 0] = (k + 1.5) * dt_fm;
+            for (int c = 0; c < 3; c++) out[r * 5 + 1 + c] = s4[k * 4 + c] / cnt * f2;
+            out[r * 5 + 4] = cnt;
+        }
+        r++;
+    }
+    *n_rows = r;
+    return GL_OK;
+}
+
+static gl_status coeff_rows(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows, bool kappa) {
+    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
+    std::vector<double> s4;
+    gl_status s = read_series_species(ev, species, s4);
+    if (s) return s;
+    std::vector<double> rates(ev->rows * 3);
+    if (ev->rows > 0) {
+        s = gl_rates_from_series(s4.data(), (int32_t)ev->rows, ev->dtau, rates.data());
+        if (s) return s;
+    }
+    const double fk = 1.0 / (ev->a_gev * ev->a_gev * ev->a_fm), dt_fm = ev->dtau * ev->a_fm;
+    const double tf = ev->species[species].tau_form_fm;
+    int32_t r = 0;
+    const int w = kappa ? 4 : 3;
+    for (int64_t k = 0; k < ev->rows; k++) {
+        if (!(s4[k * 4 + 3] > 0)) continue;
+        if (out) {
+            if (r >= cap) return fail(GL_EINVAL, "output too small");
+            double tau = (k + 1) * dt_fm;
+            if (kappa) {
+                out[r * w + 0] = tau;
+                out[r * w + 1] = tau - tf;
+                out[r * w + 2] = (rates[k * 3] + rates[k * 3 + 1]) * fk;
+                out[r * w + 3] = rates[k * 3 + 2] * fk;
+            } else {
+                out[r * w + 0] = tau;
+                out[r * w + 1] = rates[k * 3 + 1] * fk;
+                out[r * w + 2] = rates[k * 3 + 2] * fk;
+            }
+        }
+        r++;
+    }
+    *n_rows = r;
+    return GL_OK;
+}
+
+gl_status gl_kappa(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows) {
+    return coeff_rows(ev, species, out, cap, n_rows, true);
+}
+
+gl_status gl_qhat(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows) {
+    return coeff_rows(ev, species, out, cap, n_rows, false);
+}
+
+gl_status gl_diagnostics(gl_event *ev, gl_diag *out) {
+    if (check_ev(ev) || !out) return fail(GL_EINVAL, "null argument");
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    double *part = (double *)(ev->ws + ev->L.diag);
+    int nb = 0;
+    double tau = ev->n * ev->dtau;
+    if (tau <= 0) tau = ev->dtau;
+    if (ev->fp64()) HIP_TRY(launch_diag<double>(ev->stream, ev->N, ev->fields<double>(ev->cur), tau, part, &nb));
+    else HIP_TRY(launch_diag<float>(ev->stream, ev->N, ev->fields<float>(ev->cur), tau, part, &nb));
+    std::vector<double> h((size_t)nb * 8);
+    HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; b++)
+        for (int k = 0; k < 8; k++) v[k] = k < 3 ? std::max(v[k], h[b * 8 + k]) : v[k] + h[b * 8 + k];
+    out->gauss_max = v[0];
+    out->gauss_rel = v[1] > 0 ? v[0] / v[1] : v[0];
+    out->unitarity_max = v[2];
+    for (int k = 0; k < 4; k++) out->energy[k] = v[3 + k];
+    out->nonfinite = v[7] > 0 ? 1 : 0;
+    out->casimir2_dev = 0.0;
+    if (ev->slots_used > 0) {
+        int cb = 0;
+        if (ev->fp64()) HIP_TRY(launch_casimir<double>(ev->stream, ev->parts<double>(), ev->slots_used, part, &cb));
+        else HIP_TRY(launch_casimir<float>(ev->stream, ev->parts<float>(), ev->slots_used, part, &cb));
+        std::vector<double> c(cb);
+        HIP_TRY(hipMemcpyAsync(c.data(), part, cb * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+        for (double x : c) out->casimir2_dev = std::max(out->casimir2_dev, x);
+    }
+    if (out->nonfinite) return fail(GL_ENUMERIC, "non-finite values in the fields");
+    return GL_OK;
+}
+
+gl_status gl_set_state(gl_event *ev, const double *U, const double *E, const double *phi, const double *pi,
+                       int64_t n) {
+    if (check_ev(ev) || !U || !E || !phi || !pi) return fail(GL_EINVAL, "null argument");
+    if (n < 1) return fail(GL_EINVAL, "time index must be >= 1");
+    gl_status s = ev->fp64() ? set_state_t<double>(ev, U, E, phi, pi) : set_state_t<float>(ev, U, E, phi, pi);
+    if (s) return s;
+    ev->n = n;
+    ev->ready = true;
+    ev->push_due = false;
+    return GL_OK;
+}
+
+gl_status gl_get_state(gl_event *ev, double *U, double *E, double *phi, double *pi, int64_t *n) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    gl_status s = ev->fp64() ? get_state_t<double>(ev, U, E, phi, pi) : get_state_t<float>(ev, U, E, phi, pi);
+    if (s) return s;
+    if (n) *n = ev->n;
+    return GL_OK;
+}
+
+gl_status gl_get_site_fields(gl_event *ev, double *F) {
+    if (check_ev(ev) || !F) return fail(GL_EINVAL, "null argument");
+    if (ev->slots_used == 0) return fail(GL_ESTATE, "site fields are only computed when the event has particles");
+    return ev->fp64() ? copy_out<double>(ev, F, ev->ws + ev->L.F, 48 * ev->n2)
+                      : copy_out<float>(ev, F, ev->ws + ev->L.F, 48 * ev->n2);
+}
+
+gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_desc *sp, int64_t n,
+                           const int32_t *cell, const double *off, const double *eta, const double *p,
+                           const double *Q, const double *p0, const int32_t *species) {
+    if (check_ev(ev) || !sp || !cell || !off || !eta || !p || !Q || !p0 || !species)
+        return fail(GL_EINVAL, "null argument");
+    if (n_species < 1 || n_species > kMaxSpecies || n < 1) return fail(GL_EINVAL, "bad counts");
+    if (ev->push_due) return fail(GL_ESTATE, "a particle step is due");
+    std::vector<int64_t> count(n_species, 0);
+    for (int64_t i = 0; i < n; i++) {
+        if (species[i] < 0 || species[i] >= n_species) return fail(GL_EINVAL, "species id out of range");
+        if (i > 0 && species[i] < species[i - 1]) return fail(GL_EINVAL, "particles must be grouped by species");
+        if (cell[i] < 0 || cell[i] >= ev->N || cell[n + i] < 0 || cell[n + i] >= ev->N)
+            return fail(GL_EINVAL, "cell out of range");
+        count[species[i]]++;
+    }
+    std::vector<SpeciesInfo> tab;
+    int64_t used = 0;
+    for (int s = 0; s < n_species; s++) {
+        SpeciesInfo si;
+        gl_status st = fill_species(ev, &sp[s], si);
+        if (st) return st;
+        si.n = count[s];
+        si.slot0 = used;
+        si.cap = (count[s] + kPushBlock - 1) / kPushBlock * kPushBlock;
+        used += si.cap;
+        tab.push_back(si);
+    }
+    if (used > ev->L.slots) return fail(GL_ENOMEM, "particle capacity exceeded");
+    ev->species = tab;
+    ev->slots_used = used;
+    gl_status s = ev->fp64() ? set_particles_t<double>(ev, n, cell, off, eta, p, Q, p0, species)
+                             : set_particles_t<float>(ev, n, cell, off, eta, p, Q, p0, species);
+    if (s) return s;
+    return upload_block_start(ev);
+}
+
+gl_status gl_get_particles(gl_event *ev, int64_t cap, int64_t *n, int32_t *cell, double *off, double *eta,
+                           double *p, double *Q, double *p0, int32_t *species) {
+    if (check_ev(ev) || !n) return fail(GL_EINVAL, "null argument");
+    int64_t tot = total_particles(ev);
+    *n = tot;
+    if (!cell && !off && !eta && !p && !Q && !p0 && !species) return GL_OK;
+    if (cap < tot) return fail(GL_EINVAL, "output too small");
+    return ev->fp64() ? get_particles_t<double>(ev, tot, cell, off, eta, p, Q, p0, species)
+                      : get_particles_t<float>(ev, tot, cell, off, eta, p, Q, p0, species);
+}
+
+gl_status gl_species_info(gl_event *ev, int32_t species, int32_t *nform, double *mass_lat) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (species < 0 || species >= (int32_t)ev->species.size()) return fail(GL_EINVAL, "no such species");
+    if (nform) *nform = ev->species[species].nform;
+    if (mass_lat) *mass_lat = ev->species[species].mass_lat;
+    return GL_OK;
+}
+
+gl_status gl_get_wilson_line(gl_event *ev, int32_t nucleus, double *V) {
+    if (check_ev(ev) || !V || (nucleus != 0 && nucleus != 1)) return fail(GL_EINVAL, "bad argument");
+    HIP_TRY(hipMemcpyAsync(V, ev->ws + (nucleus == 0 ? ev->L.VA : ev->L.VB), 18 * ev->n2 * sizeof(double),
+                           hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t sheet, double sigma, double *rho) {
+    if (check_ev(ev) || !rho || sheet < 0 || nucleus < 0) return fail(GL_EINVAL, "bad argument");
+    double2 *planes = (double2 *)(ev->ws + ev->L.planes);
+    double *tmp = (double *)(ev->ws + ev->L.U0);
+    HIP_TRY(launch_mv_charges(ev->stream, ev->N, sigma, seed, nucleus, sheet, planes));
+    HIP_TRY(launch_planes_to_charges(ev->stream, ev->N, planes, tmp));
+    HIP_TRY(hipMemcpyAsync(rho, tmp, 8 * ev->n2 * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+gl_status gl_profile_enable(gl_event *ev, int32_t on) {
+    if (check_ev(ev)) return GL_EINVAL;
+    ev->prof = on != 0;
+    return GL_OK;
+}
+
+gl_status gl_profile_read(gl_event *ev, double *ms, int64_t *launches) {
+    if (check_ev(ev) || !ms || !launches) return fail(GL_EINVAL, "null argument");
+    for (int k = 0; k < GL_PROF_KERNELS; k++) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    for (auto &m : ev->prof_marks) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, ev->ev_pool[m.second], ev->ev_pool[m.second + 1]));
+        ms[m.first] += t;
+        launches[m.first] += 1;
+    }
+    ev->prof_marks.clear();
+    ev->ev_used = 0;
+    return GL_OK;
+}
+
+gl_status gl_event_info(gl_event *ev, double *a_fm, double *dtau_lat, int64_t *n) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (a_fm) *a_fm = ev->a_fm;
+    if (dtau_lat) *dtau_lat = ev->dtau;
+    if (n) *n = ev->n;
+    return GL_OK;
+}
+
+gl_status gl_sync(gl_event *ev) {
+    if (check_ev(ev)) return GL_EINVAL;
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+}  // extern "C"

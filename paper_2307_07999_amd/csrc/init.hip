@@ -1,0 +1,493 @@
+// init.hip -- MV-model initial conditions of the Glasma (Sec. 1, "Glasma"),
+// computed in FP64 on the device:
+//   1. Gaussian color charges rho^a per (nucleus, sheet, site) from Philox,
+//      packed two colors per complex plane (rho^{2j} + i rho^{2j+1}).
+//   2. Poisson solve (-Lap + m^2) Lambda = rho with the 5-point Laplacian,
+//      exact in Fourier space: 2-D FFT by LDS-resident mixed-radix (4, 2, 3)
+//      Stockham line transforms, one workgroup per line.  The kernel is real
+//      and even, so the packed pair separates again after the inverse.
+//   3. Wilson lines V = prod_s exp(-i Lambda_s), sheet 1 leftmost.
+//   4. Matching of the nuclei's pure-gauge links U^n_i(x) = V_n(x) V_n^dag(x+i)
+//      to the forward light cone: [(U^A + U^B)(1 + U^dag)]_X = 0 per link by
+//      damped Newton with the analytic Jacobian J_ab = -2 Re Tr(T^a W U^dag T^b),
+//      started from the SU(3) projection of W (W^dag)^{-1}, W = U^A + U^B.
+//   5. pi0(x) = 1/2 sum_i { [(U_i(x) - 1)(U^B_i(x)^dag - U^A_i(x)^dag)]_X
+//                         + [(U_i(x-i)^dag - 1)(U^B_i(x-i) - U^A_i(x-i))]_X },
+//      and the first half step E^{1/2} = 0, pi^{1/2} = pi0, U^1 = U^0,
+//      phi^1 = dtau * tau_{1/2} * pi0.
+#include "internal.hpp"
+#include "philox.hpp"
+#include "su3.hpp"
+
+namespace gl {
+
+// ---- 1. charges ---------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_mv_charges(int N, double sigma, uint64_t seed, int nucleus, int sheet, double2 *planes) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        U4 w = draw(seed, (uint32_t)x, (uint32_t)(4 * sheet + j), (uint32_t)nucleus);
+        double g0, g1;
+        box_muller(w, g0, g1);
+        planes[(size_t)j * n2 + x] = make_double2(sigma * g0, sigma * g1);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_pack(int N, const double *rho, double2 *planes) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        planes[(size_t)j * n2 + x] = make_double2(rho[(size_t)(2 * j) * n2 + x], rho[(size_t)(2 * j + 1) * n2 + x]);
+}
+
+__global__ void __launch_bounds__(256)
+k_unpack(int N, const double2 *planes, double *rho) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        double2 v = planes[(size_t)j * n2 + x];
+        rho[(size_t)(2 * j) * n2 + x] = v.x;
+        rho[(size_t)(2 * j + 1) * n2 + x] = v.y;
+    }
+}
+
+// ---- 2. FFT ------------------------------------------------------------------
+constexpr int kFftThreads = 256;
+constexpr int kFftMaxN = 1024;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// radix sequence of N: 4s, then a 2, then 3s (N = 2^a 3^b)
+struct Radices {
+    int r[24];
+    int n;
+};
+
+__host__ __device__ inline bool radices_of(int N, Radices &rs) {
+    rs.n = 0;
+    int m = N;
+    while (m % 4 == 0) { rs.r[rs.n++] = 4; m /= 4; }
+    while (m % 2 == 0) { rs.r[rs.n++] = 2; m /= 2; }
+    while (m % 3 == 0) { rs.r[rs.n++] = 3; m /= 3; }
+    return m == 1;
+}
+
+// In-place transform of n_lines lines: line l of plane p starts at
+// p * plane_stride + l * line_stride and has N elements elem_stride apart.
+// sign = -1 forward, +1 inverse (unnormalised).
+__global__ void __launch_bounds__(kFftThreads)
+k_fft_lines(double2 *data, int N, size_t elem_stride, size_t line_stride, size_t plane_stride,
+            int lines_per_plane, int sign, Radices rs) {
+    __shared__ double2 buf[2][kFftMaxN];
+    const int line = blockIdx.x % lines_per_plane, plane = blockIdx.x / lines_per_plane;
+    double2 *base = data + (size_t)plane * plane_stride + (size_t)line * line_stride;
+    for (int k = threadIdx.x; k < N; k += kFftThreads) buf[0][k] = base[(size_t)k * elem_stride];
+    __syncthreads();
+    int src = 0, Ns = 1;
+    for (int st = 0; st < rs.n; st++) {
+        const int R = rs.r[st];
+        const int nb = N / R;
+        for (int j = threadIdx.x; j < nb; j += kFftThreads) {
+            const int k = j % Ns;
+            double2 v[4];
+            for (int r = 0; r < R; r++) v[r] = buf[src][j + r * nb];
+            // twiddles exp(sign 2 pi i r k / (Ns R))
+            for (int r = 1; r < R; r++) {
+                double s, c;
+                sincospi(2.0 * sign * (double)(r * k) / (double)(Ns * R), &s, &c);
+                v[r] = cmul(v[r], make_double2(c, s));
+            }
+            double2 o[4];
+            if (R == 2) {
+                o[0] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+                o[1] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+            } else if (R == 4) {
+                double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+                double2 b = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+                double2 c = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+                double2 d = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+                // multiply d by sign*i
+                double2 di = make_double2(-sign * d.y, sign * d.x);
+                o[0] = make_double2(a.x + c.x, a.y + c.y);
+                o[2] = make_double2(a.x - c.x, a.y - c.y);
+                o[1] = make_double2(b.x + di.x, b.y + di.y);
+                o[3] = make_double2(b.x - di.x, b.y - di.y);
+            } else {   // R == 3
+                const double c3 = -0.5, s3 = 0.86602540378443864676 * sign;
+                double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
+                double2 u = make_double2(v[1].x - v[2].x, v[1].y - v[2].y);
+                o[0] = make_double2(v[0].x + t.x, v[0].y + t.y);
+                double2 m = make_double2(v[0].x + c3 * t.x, v[0].y + c3 * t.y);
+                // s3 * i * u
+                double2 iu = make_double2(-s3 * u.y, s3 * u.x);
+                o[1] = make_double2(m.x + iu.x, m.y + iu.y);
+                o[2] = make_double2(m.x - iu.x, m.y - iu.y);
+            }
+            const int idx = (j / Ns) * Ns * R + k;
+            for (int r = 0; r < R; r++) buf[src ^ 1][idx + r * Ns] = o[r];
+        }
+        __syncthreads();
+        src ^= 1;
+        Ns *= R;
+    }
+    for (int k = threadIdx.x; k < N; k += kFftThreads) base[(size_t)k * elem_stride] = buf[src][k];
+}
+
+// multiply by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2)) on all 4 planes
+__global__ void __launch_bounds__(256)
+k_poisson_kernel(int N, double m2, double2 *planes) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+    int kx = (int)(x % N), ky = (int)(x / N);
+    double sx = sinpi((double)kx / N), sy = sinpi((double)ky / N);
+    double g = 1.0 / (((double)N * N) * (4.0 * sx * sx + 4.0 * sy * sy + m2));
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        double2 v = planes[(size_t)j * n2 + x];
+        planes[(size_t)j * n2 + x] = make_double2(v.x * g, v.y * g);
+    }
+}
+
+// ---- 3. Wilson lines --------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_wilson_init(int N, double *V) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+    store_m(V, n2, x, m_ident<double>());
+}
+
+__global__ void __launch_bounds__(256)
+k_wilson_accum(int N, const double2 *planes, double *V) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+    double lam[8];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        double2 v = planes[(size_t)j * n2 + x];
+        lam[2 * j] = v.x;
+        lam[2 * j + 1] = v.y;
+    }
+    M3<double> v = load_m(V, n2, x);
+    store_m(V, n2, x, mul(v, expi_alg(lam, -1.0)));
+}
+
+// ---- 4. matching ------------------------------------------------------------
+__device__ inline void cdiv(double ar, double ai, double br, double bi, double &cr, double &ci) {
+    double d = br * br + bi * bi;
+    cr = (ar * br + ai * bi) / d;
+    ci = (ai * br - ar * bi) / d;
+}
+
+__device__ inline void det3(const M3<double> &a, double &dr, double &di) {
+    auto cm = [](double xr, double xi, double yr, double yi, double &zr, double &zi) {
+        zr = xr * yr - xi * yi;
+        zi = xr * yi + xi * yr;
+    };
+    double r = 0, i = 0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        double m1r, m1i, m2r, m2i;
+        cm(a.re[1][c1], a.im[1][c1], a.re[2][c2], a.im[2][c2], m1r, m1i);
+        cm(a.re[1][c2], a.im[1][c2], a.re[2][c1], a.im[2][c1], m2r, m2i);
+        double cofr = m1r - m2r, cofi = m1i - m2i;
+        double tr, ti;
+        cm(a.re[0][c], a.im[0][c], cofr, cofi, tr, ti);
+        r += tr;
+        i += ti;
+    }
+    dr = r;
+    di = i;
+}
+
+// inverse by cofactors
+__device__ inline M3<double> inv3(const M3<double> &a) {
+    double dr, di;
+    det3(a, dr, di);
+    M3<double> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            double pr = a.re[i1][j1] * a.re[i2][j2] - a.im[i1][j1] * a.im[i2][j2];
+            double pi = a.re[i1][j1] * a.im[i2][j2] + a.im[i1][j1] * a.re[i2][j2];
+            double qr = a.re[i1][j2] * a.re[i2][j1] - a.im[i1][j2] * a.im[i2][j1];
+            double qi = a.re[i1][j2] * a.im[i2][j1] + a.im[i1][j2] * a.re[i2][j1];
+            double cr, ci;
+            cdiv(pr - qr, pi - qi, dr, di, cr, ci);
+            r.re[j][i] = cr;
+            r.im[j][i] = ci;
+        }
+    return r;
+}
+
+__device__ inline M3<double> dagger(const M3<double> &a) {
+    M3<double> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) { r.re[i][j] = a.re[j][i]; r.im[i][j] = -a.im[j][i]; }
+    return r;
+}
+
+// unitary polar factor by X <- (X + X^{-dag})/2, then principal cube root of det removed
+__device__ inline M3<double> su3_project(M3<double> X) {
+    for (int it = 0; it < 100; it++) {
+        M3<double> Y = add(X, dagger(inv3(X)));
+        double ch = 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                Y.re[i][j] *= 0.5;
+                Y.im[i][j] *= 0.5;
+                double a = Y.re[i][j] - X.re[i][j], b = Y.im[i][j] - X.im[i][j];
+                ch += a * a + b * b;
+            }
+        X = Y;
+        if (sqrt(ch) < 1e-15) break;
+    }
+    double dr, di;
+    det3(X, dr, di);
+    double th = atan2(di, dr) / 3.0;
+    double s, c;
+    sincos(-th, &s, &c);
+    M3<double> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            r.re[i][j] = X.re[i][j] * c - X.im[i][j] * s;
+            r.im[i][j] = X.re[i][j] * s + X.im[i][j] * c;
+        }
+    return r;
+}
+
+__device__ inline double match_residual(const M3<double> &W, const M3<double> &U, double *R) {
+    M3<double> M = add(W, mul_nd(W, U));   // W (1 + U^dag)
+    alg_proj(M, R);
+    double m = 0;
+#pragma unroll
+    for (int a = 0; a < 8; a++) m = fmax(m, fabs(R[a]));
+    return m;
+}
+
+__device__ inline bool solve8(double J[8][8], double *b) {
+    for (int c = 0; c < 8; c++) {
+        int piv = c;
+        for (int r = c + 1; r < 8; r++)
+            if (fabs(J[r][c]) > fabs(J[piv][c])) piv = r;
+        if (J[piv][c] == 0.0) return false;
+        if (piv != c) {
+            for (int k = 0; k < 8; k++) { double t = J[c][k]; J[c][k] = J[piv][k]; J[piv][k] = t; }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < 8; r++) {
+            double f = J[r][c] / J[c][c];
+            for (int k = c; k < 8; k++) J[r][k] -= f * J[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int i = 7; i >= 0; i--) {
+        double s = b[i];
+        for (int k = i + 1; k < 8; k++) s -= J[i][k] * b[k];
+        b[i] = s / J[i][i];
+    }
+    return true;
+}
+
+__device__ inline M3<double> nucleus_link(const double *V, size_t n2, size_t x, size_t xp) {
+    return mul_nd(load_m(V, n2, x), load_m(V, n2, xp));
+}
+
+// one thread per link (d, x)
+__global__ void __launch_bounds__(128)
+k_match(int N, const double *VA, const double *VB, double *U0, int *status, int max_iter,
+        double tol) {
+    size_t n2 = (size_t)N * N;
+    size_t t = (size_t)blockIdx.x * 128 + threadIdx.x;
+    if (t >= 2 * n2) return;
+    int d = (int)(t / n2);
+    size_t x = t % n2;
+    int ix = (int)(x % N), iy = (int)(x / N);
+    size_t xp = d == 0 ? (size_t)(ix + 1 == N ? 0 : ix + 1) + (size_t)N * iy
+                       : (size_t)ix + (size_t)N * (iy + 1 == N ? 0 : iy + 1);
+    M3<double> W = add(nucleus_link(VA, n2, x, xp), nucleus_link(VB, n2, x, xp));
+    M3<double> U = su3_project(mul(W, inv3(dagger(W))));
+    double R[8];
+    double rn = match_residual(W, U, R);
+    int it = 0;
+    while (rn >= tol && it < max_iter) {
+        M3<double> M = mul_nd(W, U);
+        double J[8][8];
+        for (int b = 0; b < 8; b++) {
+            double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            e[b] = 1.0;
+            double col[8];
+            alg_from_herm(mul(M, herm_from_alg(e)), col);   // 2 Re Tr(T^a M T^b)
+            for (int a = 0; a < 8; a++) J[a][b] = -col[a];
+        }
+        double dl[8];
+        for (int a = 0; a < 8; a++) dl[a] = -R[a];
+        if (!solve8(J, dl)) break;
+        double step = 1.0, rnn = rn, Rn[8];
+        M3<double> Un = U;
+        for (int h = 0; h < 40; h++) {
+            Un = mul(expi_alg(dl, step), U);
+            rnn = match_residual(W, Un, Rn);
+            if (rnn < rn) break;
+            step *= 0.5;
+        }
+        U = Un;
+        for (int a = 0; a < 8; a++) R[a] = Rn[a];
+        rn = rnn;
+        it++;
+    }
+    store_m(U0 + (size_t)d * 18 * n2, n2, x, U);
+    if (!(rn < tol)) atomicOr(status, 1);
+}
+
+// ---- 5. pi0 -------------------------------------------------------------------
+__global__ void __launch_bounds__(128)
+k_pi0(int N, const double *VA, const double *VB, const double *U0, double *pi0) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 128 + threadIdx.x;
+    if (x >= n2) return;
+    int ix = (int)(x % N), iy = (int)(x / N);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 2; d++) {
+        int pxi = d == 0 ? (ix + 1 == N ? 0 : ix + 1) : ix, pyi = d == 0 ? iy : (iy + 1 == N ? 0 : iy + 1);
+        int mxi = d == 0 ? (ix == 0 ? N - 1 : ix - 1) : ix, myi = d == 0 ? iy : (iy == 0 ? N - 1 : iy - 1);
+        size_t xp = (size_t)pxi + (size_t)N * pyi, xm = (size_t)mxi + (size_t)N * myi;
+        M3<double> one = m_ident<double>();
+        {
+            M3<double> u = load_m(U0 + (size_t)d * 18 * n2, n2, x);
+            M3<double> ua = nucleus_link(VA, n2, x, xp), ub = nucleus_link(VB, n2, x, xp);
+            M3<double> m = mul(sub(u, one), sub(dagger(ub), dagger(ua)));
+            double v[8];
+            alg_proj(m, v);
+            for (int a = 0; a < 8; a++) acc[a] += v[a];
+        }
+        {
+            M3<double> u = load_m(U0 + (size_t)d * 18 * n2, n2, xm);
+            M3<double> ua = nucleus_link(VA, n2, xm, x), ub = nucleus_link(VB, n2, xm, x);
+            M3<double> m = mul(sub(dagger(u), one), sub(ub, ua));
+            double v[8];
+            alg_proj(m, v);
+            for (int a = 0; a < 8; a++) acc[a] += v[a];
+        }
+    }
+    for (int a = 0; a < 8; a++) pi0[(size_t)a * n2 + x] = 0.5 * acc[a];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_first_half_step(int N, const double *U0, const double *pi0, FieldPtrs<T> out, double dtau) {
+    size_t n2 = (size_t)N * N;
+    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n2) return;
+    for (int c = 0; c < 36; c++) out.U[(size_t)c * n2 + x] = (T)U0[(size_t)c * n2 + x];
+    for (int c = 0; c < 16; c++) out.E[(size_t)c * n2 + x] = T(0);
+    const double th = 0.5 * dtau;
+    for (int a = 0; a < 8; a++) {
+        double p = pi0[(size_t)a * n2 + x];
+        out.pi[(size_t)a * n2 + x] = (T)p;
+        out.phi[(size_t)a * n2 + x] = (T)(dtau * th * p);
+    }
+}
+
+// ---- launchers ----------------------------------------------------------------
+static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed, int nucleus,
+                             int sheet, double2 *planes) {
+    hipLaunchKernelGGL(k_mv_charges, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, sigma,
+                       seed, nucleus, sheet, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_charges_to_planes(hipStream_t st, int N, const double *rho, double2 *planes) {
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, rho, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes, double *rho) {
+    hipLaunchKernelGGL(k_unpack, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, planes, rho);
+    return hipGetLastError();
+}
+
+static hipError_t fft2(hipStream_t st, int N, double2 *planes, int sign) {
+    Radices rs;
+    if (N > kFftMaxN || !radices_of(N, rs)) return hipErrorInvalidValue;
+    size_t n2 = (size_t)N * N;
+    // rows: contiguous elements
+    hipLaunchKernelGGL(k_fft_lines, dim3(4 * N), dim3(kFftThreads), 0, st, planes, N, (size_t)1,
+                       (size_t)N, n2, N, sign, rs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // columns: elements N apart
+    hipLaunchKernelGGL(k_fft_lines, dim3(4 * N), dim3(kFftThreads), 0, st, planes, N, (size_t)N,
+                       (size_t)1, n2, N, sign, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double2 *planes, double2 *) {
+    hipError_t e = fft2(st, N, planes, -1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_poisson_kernel, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, m2,
+                       planes);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return fft2(st, N, planes, +1);
+}
+
+hipError_t launch_wilson_init(hipStream_t st, int N, double *V) {
+    hipLaunchKernelGGL(k_wilson_init, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, double *V) {
+    hipLaunchKernelGGL(k_wilson_accum, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N,
+                       planes, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_match_pi0(hipStream_t st, int N, const double *VA, const double *VB, double *U0,
+                           double *pi0, int *status, int max_iter, double tol) {
+    size_t n2 = (size_t)N * N;
+    hipLaunchKernelGGL(k_match, dim3(blocks_for(2 * n2, 128)), dim3(128), 0, st, N, VA, VB, U0, status,
+                       max_iter, tol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pi0, dim3(blocks_for(n2, 128)), dim3(128), 0, st, N, VA, VB, U0, pi0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_first_half_step(hipStream_t st, int N, const double *U0, const double *pi0,
+                                  FieldPtrs<T> out, double dtau) {
+    hipLaunchKernelGGL(k_first_half_step<T>, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N,
+                       U0, pi0, out, dtau);
+    return hipGetLastError();
+}
+
+template hipError_t launch_first_half_step<double>(hipStream_t, int, const double *, const double *,
+                                                   FieldPtrs<double>, double);
+template hipError_t launch_first_half_step<float>(hipStream_t, int, const double *, const double *,
+                                                  FieldPtrs<float>, double);
+
+}  // namespace gl

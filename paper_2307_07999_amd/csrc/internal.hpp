@@ -1,0 +1,79 @@
+// internal.hpp -- device-side data descriptions shared by the kernels and the
+// runtime of the Glasma + colored-particle-in-cell library (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gl {
+
+constexpr int kMaxSpecies = 16;
+constexpr int kPushBlock = 256;   // particles per push workgroup; species are padded to it
+
+// One field state in structure-of-arrays planes of n2 = N*N values:
+//   U   [2][18][n2], E [2][8][n2], phi [8][n2], pi [8][n2]
+template <typename T>
+struct FieldPtrs {
+    T *U;
+    T *E;
+    T *phi;
+    T *pi;
+};
+
+// Particle arrays, capacity cap (padded per species to kPushBlock).
+template <typename T>
+struct PartPtrs {
+    int32_t *cx, *cy;
+    T *ox, *oy, *eta;
+    T *px, *py, *peta;   // p_x, p_y and P_eta = tau^2 p^eta
+    T *Q;                // [8][cap]
+    T *px0, *py0, *pz0;  // momenta at formation (pz0 in the lab frame)
+    int32_t *species;    // -1 for padding
+    int64_t cap;
+};
+
+template <typename T>
+struct SpeciesTab {
+    T mass[kMaxSpecies];
+    int32_t nform[kMaxSpecies];
+};
+
+// ---- launchers (stream-ordered, no synchronisation) --------------------------
+template <typename T>
+hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out,
+                             double tau, double dtau, int reunit);
+template <typename T>
+hipError_t launch_site_fields(hipStream_t st, int N, FieldPtrs<T> old_, FieldPtrs<T> new_,
+                              T *F, double tau);
+template <typename T>
+hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
+                       const T *F, SpeciesTab<T> tab, int n, double dtau, double *partials);
+hipError_t launch_series_reduce(hipStream_t st, const double *partials, const int32_t *block_start,
+                                int n_species, double *row);
+template <typename T>
+hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
+                       int *n_blocks_out);
+
+// initial conditions (always FP64 internally)
+hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed, int nucleus,
+                             int sheet, double2 *planes /* [4][n2] */);
+hipError_t launch_charges_to_planes(hipStream_t st, int N, const double *rho /* [8][n2] */,
+                                 double2 *planes);
+hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes, double *rho);
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double2 *planes /* [4][n2] in place */,
+                          double2 *tmp);
+hipError_t launch_wilson_init(hipStream_t st, int N, double *V);
+hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, double *V);
+hipError_t launch_match_pi0(hipStream_t st, int N, const double *VA, const double *VB,
+                           double *U0 /* [2][18][n2] FP64 */, double *pi0 /* [8][n2] */,
+                           int *status, int max_iter, double tol);
+template <typename T>
+hipError_t launch_casimir(hipStream_t st, PartPtrs<T> p, int64_t n_slots, double *partials,
+                          int *n_blocks_out);
+template <typename T>
+hipError_t launch_first_half_step(hipStream_t st, int N, const double *U0, const double *pi0,
+                                  FieldPtrs<T> out, double dtau);
+template <typename T>
+hipError_t launch_particles_init(hipStream_t st, int N, PartPtrs<T> p, int64_t slot0, int64_t n,
+                                 uint64_t seed, int species_id, int kind, double p0);
+
+}  // namespace gl

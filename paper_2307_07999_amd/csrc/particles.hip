@@ -1,0 +1,343 @@
+// particles.hip -- colored particles in the Glasma: initialisation, the push
+// of Wong's equations (Eq. (2)) and the FP64 momentum-broadening sums.
+//
+// Push (one thread per particle, reading the site fields F^n of its cell):
+//   e_k = Q^a E_k^a, b_k = Q^a B_k^a in the local frame at tau_n
+//   Boris kick of dp/dtau = e + v x b on (p_x, p_y, P_eta/tau_n), P_eta = tau^2 p^eta
+//   drift with velocities at tau_{n+1/2}; rapidity step d_eta
+//   color: Q <- W Q W^dag, W = exp(-i phi^n(cell) d_eta) (eta component of the
+//   Wilson line), then on a cell crossing Q <- U^dag Q U (forward) or
+//   U Q U^dag (backward) with the crossed link: the link-built particle
+//   Wilson line of the colored-particle-in-cell method, which conserves the
+//   Casimirs of Q.
+//   broadening at tau_{n+1/2}: dp_x^2, dp_y^2 and the lab-frame dp_z^2.
+// Each workgroup holds particles of one species (the runtime pads species to
+// kPushBlock) and writes one FP64 partial row; a second kernel sums the rows
+// of each species in a fixed order, so the series is deterministic.
+#include "internal.hpp"
+#include "philox.hpp"
+#include "su3.hpp"
+
+namespace gl {
+
+template <typename T>
+__global__ void __launch_bounds__(kPushBlock)
+k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restrict__ F,
+       SpeciesTab<T> tab, int n, T dtau, double *__restrict__ partials) {
+    const int64_t i = (int64_t)blockIdx.x * kPushBlock + threadIdx.x;
+    const size_t n2 = (size_t)N * N;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int s = i < n_slots ? P.species[i] : -1;
+    if (s >= 0 && n >= tab.nform[s]) {
+        const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
+        const T m = tab.mass[s];
+        int cx = P.cx[i], cy = P.cy[i];
+        size_t x = (size_t)cx + (size_t)N * cy;
+        T q[8];
+#pragma unroll
+        for (int a = 0; a < 8; a++) q[a] = P.Q[(size_t)a * P.cap + i];
+        T e[3], b[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            T se = T(0), sb = T(0);
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                se = fma(q[a], F[(size_t)(8 * k + a) * n2 + x], se);
+                sb = fma(q[a], F[(size_t)(8 * (3 + k) + a) * n2 + x], sb);
+            }
+            e[k] = se;
+            b[k] = sb;
+        }
+        // Boris kick at tau_n
+        T pl[3] = {P.px[i], P.py[i], P.peta[i] / tau};
+        T pm[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) pm[k] = pl[k] + T(0.5) * dtau * e[k];
+        T g = sqrt(m * m + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2]);
+        T h = dtau / (T(2) * g);
+        T t[3] = {b[0] * h, b[1] * h, b[2] * h};
+        T t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+        T sf = T(2) / (T(1) + t2);
+        T sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
+        T pp[3] = {pm[0] + (pm[1] * t[2] - pm[2] * t[1]), pm[1] + (pm[2] * t[0] - pm[0] * t[2]),
+                   pm[2] + (pm[0] * t[1] - pm[1] * t[0])};
+        T pq[3] = {pm[0] + (pp[1] * sv[2] - pp[2] * sv[1]), pm[1] + (pp[2] * sv[0] - pp[0] * sv[2]),
+                   pm[2] + (pp[0] * sv[1] - pp[1] * sv[0])};
+#pragma unroll
+        for (int k = 0; k < 3; k++) pl[k] = pq[k] + T(0.5) * dtau * e[k];
+        const T peta = tau * pl[2];
+        // drift
+        const T pzh = peta / th;
+        const T ptau = sqrt(m * m + pl[0] * pl[0] + pl[1] * pl[1] + pzh * pzh);
+        T ox = P.ox[i] + dtau * pl[0] / ptau;
+        T oy = P.oy[i] + dtau * pl[1] / ptau;
+        const T deta = dtau * peta / (th * th * ptau);
+        const T eta_old = P.eta[i];
+        const T eta_new = eta_old + deta;
+        // color rotation along eta with phi^n at the old cell
+        M3<T> Qm = herm_from_alg(q);
+        {
+            T ph[8];
+            load_a(f.phi, n2, x, ph);
+            M3<T> W = expi_alg(ph, -deta);
+            Qm = mul_nd(mul(W, Qm), W);
+        }
+        // crossings, x first then y
+        if (ox >= T(0.5)) {
+            M3<T> u = load_m(f.U, n2, x);
+            Qm = mul(mul_dn(u, Qm), u);
+            ox -= T(1);
+            cx = cx + 1 == N ? 0 : cx + 1;
+        } else if (ox < T(-0.5)) {
+            int cm = cx == 0 ? N - 1 : cx - 1;
+            M3<T> u = load_m(f.U, n2, (size_t)cm + (size_t)N * cy);
+            Qm = mul_nd(mul(u, Qm), u);
+            ox += T(1);
+            cx = cm;
+        }
+        if (oy >= T(0.5)) {
+            M3<T> u = load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cy);
+            Qm = mul(mul_dn(u, Qm), u);
+            oy -= T(1);
+            cy = cy + 1 == N ? 0 : cy + 1;
+        } else if (oy < T(-0.5)) {
+            int cm = cy == 0 ? N - 1 : cy - 1;
+            M3<T> u = load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cm);
+            Qm = mul_nd(mul(u, Qm), u);
+            oy += T(1);
+            cy = cm;
+        }
+        alg_from_herm(Qm, q);
+        P.cx[i] = cx;
+        P.cy[i] = cy;
+        P.ox[i] = ox;
+        P.oy[i] = oy;
+        P.eta[i] = eta_new;
+        P.px[i] = pl[0];
+        P.py[i] = pl[1];
+        P.peta[i] = peta;
+#pragma unroll
+        for (int a = 0; a < 8; a++) P.Q[(size_t)a * P.cap + i] = q[a];
+        // broadening at tau_{n+1/2}, accumulated in FP64
+        const double etab = 0.5 * ((double)eta_old + (double)eta_new);
+        const double pzlab = (double)ptau * sinh(etab) + (double)pzh * cosh(etab);
+        const double x0 = P.px0[i], y0 = P.py0[i], z0 = P.pz0[i];
+        acc[0] = (double)pl[0] * pl[0] - x0 * x0;
+        acc[1] = (double)pl[1] * pl[1] - y0 * y0;
+        acc[2] = pzlab * pzlab - z0 * z0;
+        acc[3] = 1.0;
+    }
+    // workgroup reduction: wave64 butterflies, then across the four waves
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    __shared__ double red[kPushBlock / 64][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) red[wave][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kPushBlock / 64; w++) v += red[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+// series row [kMaxSpecies][4]: species s sums partial rows
+// [block_start[s], block_start[s+1]) in a fixed order.
+__global__ void __launch_bounds__(256)
+k_series_reduce(const double *__restrict__ partials, const int32_t *__restrict__ block_start,
+                int n_species, double *__restrict__ row) {
+    const int s = blockIdx.x;
+    __shared__ double red[256][4];
+    double acc[4] = {0, 0, 0, 0};
+    if (s < n_species) {
+        for (int b = block_start[s] + threadIdx.x; b < block_start[s + 1]; b += 256)
+#pragma unroll
+            for (int k = 0; k < 4; k++) acc[k] += partials[(size_t)b * 4 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) row[s * 4 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+// Particle initialisation (Sec. 2 toy model, Sec. 1 color charges): counter
+// (i, j, 2 + species, 0) with j = 0 position, j = 1 azimuth, j = 2..10 the nine
+// Gaussian pairs of a complex matrix whose Gram-Schmidt factor is Haar on U(3)
+// (Mezzadri 2007); Q = U Q0 U^dag with Q0 = diag of the roots of
+// l^3 - l - 5/18 (q2 = 4, q3 = 10/3).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, int species,
+                 int kind, double p0) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = slot0 + i;
+    const uint32_t stream = 2u + (uint32_t)species;
+    U4 w = draw(seed, (uint32_t)i, 0u, stream);
+    double X = uniform53(w.v[0], w.v[1]) * N, Y = uniform53(w.v[2], w.v[3]) * N;
+    double fx = floor(X + 0.5), fy = floor(Y + 0.5);
+    int cx = (int)fx, cy = (int)fy;
+    P.cx[j] = cx >= N ? cx - N : cx;
+    P.cy[j] = cy >= N ? cy - N : cy;
+    P.ox[j] = (T)(X - fx);
+    P.oy[j] = (T)(Y - fy);
+    P.eta[j] = T(0);
+    w = draw(seed, (uint32_t)i, 1u, stream);
+    double az = 6.283185307179586476925286766559 * uniform53(w.v[0], w.v[1]);
+    double px, py;
+    if (kind == 0) {
+        double sa, ca;
+        sincos(az, &sa, &ca);
+        px = p0 * ca;
+        py = p0 * sa;
+    } else {
+        px = p0;
+        py = 0.0;
+    }
+    P.px[j] = (T)px; P.py[j] = (T)py; P.peta[j] = T(0);
+    P.px0[j] = (T)px; P.py0[j] = (T)py; P.pz0[j] = T(0);
+    P.species[j] = species;
+    // Gaussian complex matrix, columns orthonormalised in order
+    double zr[3][3], zi[3][3];
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        U4 v = draw(seed, (uint32_t)i, (uint32_t)(2 + k), stream);
+        double g0, g1;
+        box_muller(v, g0, g1);
+        zr[k / 3][k % 3] = g0;
+        zi[k / 3][k % 3] = g1;
+    }
+    double ur[3][3], ui[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        double vr[3], vi[3];
+#pragma unroll
+        for (int r = 0; r < 3; r++) { vr[r] = zr[r][c]; vi[r] = zi[r][c]; }
+#pragma unroll
+        for (int q = 0; q < c; q++) {
+            // (u_q^dag v) u_q, modified Gram-Schmidt
+            double dr = 0, di = 0;
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                dr += ur[r][q] * vr[r] + ui[r][q] * vi[r];
+                di += ur[r][q] * vi[r] - ui[r][q] * vr[r];
+            }
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                vr[r] -= dr * ur[r][q] - di * ui[r][q];
+                vi[r] -= dr * ui[r][q] + di * ur[r][q];
+            }
+        }
+        double nr = sqrt(vr[0] * vr[0] + vi[0] * vi[0] + vr[1] * vr[1] + vi[1] * vi[1] +
+                         vr[2] * vr[2] + vi[2] * vi[2]);
+#pragma unroll
+        for (int r = 0; r < 3; r++) { ur[r][c] = vr[r] / nr; ui[r][c] = vi[r] / nr; }
+    }
+    // roots of l^3 - l - 5/18 = 0 (trigonometric form of the depressed cubic)
+    const double qd[3] = {1.1174041524913475, -0.30659898226164492, -0.81080517022970258};
+    // Q = U diag(qd) U^dag, hermitian; components x^a = 2 Re Tr(T^a Q)
+    M3<double> Qm;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            double sr = 0, si = 0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // U[r][k] qd[k] conj(U[c][k])
+                sr += qd[k] * (ur[r][k] * ur[c][k] + ui[r][k] * ui[c][k]);
+                si += qd[k] * (ui[r][k] * ur[c][k] - ur[r][k] * ui[c][k]);
+            }
+            Qm.re[r][c] = sr;
+            Qm.im[r][c] = si;
+        }
+    double q[8];
+    alg_from_herm(Qm, q);
+#pragma unroll
+    for (int a = 0; a < 8; a++) P.Q[(size_t)a * P.cap + j] = (T)q[a];
+}
+
+// max |Q^a Q^a - 4| per workgroup over particles (padding excluded)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_casimir(PartPtrs<T> P, int64_t n_slots, double *partials) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < n_slots && P.species[i] >= 0) {
+        double q2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            double q = P.Q[(size_t)a * P.cap + i];
+            q2 += q * q;
+        }
+        v = fabs(q2 - 4.0);
+        if (!isfinite(v)) v = 1e300;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+template <typename T>
+hipError_t launch_casimir(hipStream_t st, PartPtrs<T> p, int64_t n_slots, double *partials,
+                          int *n_blocks_out) {
+    unsigned blocks = (unsigned)((n_slots + 255) / 256);
+    *n_blocks_out = (int)blocks;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_casimir<T>, dim3(blocks), dim3(256), 0, st, p, n_slots, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
+                       const T *F, SpeciesTab<T> tab, int n, double dtau, double *partials) {
+    if (n_slots <= 0) return hipSuccess;
+    unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
+    hipLaunchKernelGGL(k_push<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, n_slots, f, F, tab,
+                       n, (T)dtau, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_series_reduce(hipStream_t st, const double *partials, const int32_t *block_start,
+                                int n_species, double *row) {
+    hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies), dim3(256), 0, st, partials, block_start,
+                       n_species, row);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particles_init(hipStream_t st, int N, PartPtrs<T> p, int64_t slot0, int64_t n,
+                                 uint64_t seed, int species_id, int kind, double p0) {
+    if (n <= 0) return hipSuccess;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_particles_init<T>, dim3(blocks), dim3(256), 0, st, N, p, slot0, n, seed,
+                       species_id, kind, p0);
+    return hipGetLastError();
+}
+
+#define GL_INST(T)                                                                               \
+    template hipError_t launch_push<T>(hipStream_t, int, PartPtrs<T>, int64_t, FieldPtrs<T>,      \
+                                       const T *, SpeciesTab<T>, int, double, double *);         \
+    template hipError_t launch_particles_init<T>(hipStream_t, int, PartPtrs<T>, int64_t, int64_t, \
+                                                 uint64_t, int, int, double);                    \
+    template hipError_t launch_casimir<T>(hipStream_t, PartPtrs<T>, int64_t, double *, int *);
+GL_INST(double)
+GL_INST(float)
+#undef GL_INST
+
+}  // namespace gl

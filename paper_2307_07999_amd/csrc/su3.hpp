@@ -1,0 +1,360 @@
+// su3.hpp -- register-resident SU(3) arithmetic for gfx950 kernels.
+//
+// Matrices are 3x3 complex held as separate real and imaginary 3x3 arrays so
+// that every entry is its own register; all loops are unrolled.  Algebra
+// elements X = X^a T^a (T^a = lambda^a/2) travel as 8 reals.  T is float or
+// double; the same code serves both precisions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gl {
+
+template <typename T>
+struct M3 {
+    T re[3][3];
+    T im[3][3];
+};
+
+template <typename T>
+__device__ __forceinline__ M3<T> m_zero() {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) { r.re[i][j] = T(0); r.im[i][j] = T(0); }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ M3<T> m_ident() {
+    M3<T> r = m_zero<T>();
+    r.re[0][0] = r.re[1][1] = r.re[2][2] = T(1);
+    return r;
+}
+
+// A B
+template <typename T>
+__device__ __forceinline__ M3<T> mul(const M3<T> &a, const M3<T> &b) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                sr = fma(a.re[i][k], b.re[k][j], sr);
+                sr = fma(-a.im[i][k], b.im[k][j], sr);
+                si = fma(a.re[i][k], b.im[k][j], si);
+                si = fma(a.im[i][k], b.re[k][j], si);
+            }
+            r.re[i][j] = sr;
+            r.im[i][j] = si;
+        }
+    return r;
+}
+
+// A B^dag
+template <typename T>
+__device__ __forceinline__ M3<T> mul_nd(const M3<T> &a, const M3<T> &b) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // a[i][k] * conj(b[j][k])
+                sr = fma(a.re[i][k], b.re[j][k], sr);
+                sr = fma(a.im[i][k], b.im[j][k], sr);
+                si = fma(a.im[i][k], b.re[j][k], si);
+                si = fma(-a.re[i][k], b.im[j][k], si);
+            }
+            r.re[i][j] = sr;
+            r.im[i][j] = si;
+        }
+    return r;
+}
+
+// A^dag B
+template <typename T>
+__device__ __forceinline__ M3<T> mul_dn(const M3<T> &a, const M3<T> &b) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // conj(a[k][i]) * b[k][j]
+                sr = fma(a.re[k][i], b.re[k][j], sr);
+                sr = fma(a.im[k][i], b.im[k][j], sr);
+                si = fma(a.re[k][i], b.im[k][j], si);
+                si = fma(-a.im[k][i], b.re[k][j], si);
+            }
+            r.re[i][j] = sr;
+            r.im[i][j] = si;
+        }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ M3<T> add(const M3<T> &a, const M3<T> &b) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            r.re[i][j] = a.re[i][j] + b.re[i][j];
+            r.im[i][j] = a.im[i][j] + b.im[i][j];
+        }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ M3<T> sub(const M3<T> &a, const M3<T> &b) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            r.re[i][j] = a.re[i][j] - b.re[i][j];
+            r.im[i][j] = a.im[i][j] - b.im[i][j];
+        }
+    return r;
+}
+
+// ---- algebra <-> matrix -----------------------------------------------------
+// Hermitian X = x^a T^a written out from the Gell-Mann matrices.
+template <typename T>
+__device__ __forceinline__ M3<T> herm_from_alg(const T *x) {
+    const T h = T(0.5);
+    const T s3 = T(0.57735026918962576451);   // 1/sqrt(3)
+    M3<T> r;
+    r.re[0][0] = h * (x[2] + s3 * x[7]);
+    r.re[1][1] = h * (-x[2] + s3 * x[7]);
+    r.re[2][2] = -s3 * x[7];
+    r.im[0][0] = r.im[1][1] = r.im[2][2] = T(0);
+    r.re[0][1] = h * x[0];  r.im[0][1] = -h * x[1];
+    r.re[1][0] = h * x[0];  r.im[1][0] = h * x[1];
+    r.re[0][2] = h * x[3];  r.im[0][2] = -h * x[4];
+    r.re[2][0] = h * x[3];  r.im[2][0] = h * x[4];
+    r.re[1][2] = h * x[5];  r.im[1][2] = -h * x[6];
+    r.re[2][1] = h * x[5];  r.im[2][1] = h * x[6];
+    return r;
+}
+
+// x^a = 2 Re Tr(T^a H) of a hermitian H (only its hermitian part counts).
+template <typename T>
+__device__ __forceinline__ void alg_from_herm(const M3<T> &H, T *x) {
+    const T s3 = T(0.57735026918962576451);
+    x[0] = H.re[0][1] + H.re[1][0];
+    x[1] = H.im[1][0] - H.im[0][1];
+    x[2] = H.re[0][0] - H.re[1][1];
+    x[3] = H.re[0][2] + H.re[2][0];
+    x[4] = H.im[2][0] - H.im[0][2];
+    x[5] = H.re[1][2] + H.re[2][1];
+    x[6] = H.im[2][1] - H.im[1][2];
+    x[7] = s3 * (H.re[0][0] + H.re[1][1] - T(2) * H.re[2][2]);
+}
+
+// Components of [M]_X = (M - M^dag)/(2i) - trace/3:  x^a = 2 Im Tr(T^a M).
+template <typename T>
+__device__ __forceinline__ void alg_proj(const M3<T> &M, T *x) {
+    const T s3 = T(0.57735026918962576451);
+    x[0] = M.im[0][1] + M.im[1][0];
+    x[1] = M.re[0][1] - M.re[1][0];
+    x[2] = M.im[0][0] - M.im[1][1];
+    x[3] = M.im[0][2] + M.im[2][0];
+    x[4] = M.re[0][2] - M.re[2][0];
+    x[5] = M.im[1][2] + M.im[2][1];
+    x[6] = M.re[1][2] - M.re[2][1];
+    x[7] = s3 * (M.im[0][0] + M.im[1][1] - T(2) * M.im[2][2]);
+}
+
+// Tr(A B) real part for hermitian A, B
+template <typename T>
+__device__ __forceinline__ T re_tr_mul(const M3<T> &a, const M3<T> &b) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) s += a.re[i][k] * b.re[k][i] - a.im[i][k] * b.im[k][i];
+    return s;
+}
+
+// ---- exponential of i Q for hermitian traceless Q ---------------------------
+// Cayley-Hamilton form exp(iQ) = f0 + f1 Q + f2 Q^2 with the f_j of
+// C. Morningstar and M. Peardon, Phys. Rev. D 69 (2004) 054501, Sec. III.
+// For tiny Q the f_j come from the power series reduced with Q^3 = c1 Q + c0.
+template <typename T>
+__device__ __forceinline__ M3<T> expi_herm(const M3<T> &Q) {
+    M3<T> Q2 = mul(Q, Q);
+    T c1 = T(0.5) * (Q2.re[0][0] + Q2.re[1][1] + Q2.re[2][2]);
+    // det of hermitian traceless Q = Tr(Q^3)/3
+    T c0 = re_tr_mul(Q, Q2) * T(1.0 / 3.0);
+    T f0r, f0i, f1r, f1i, f2r, f2i;
+    const T small = T(1e-4);
+    if (c1 < small) {
+        // sum_k (iQ)^k / k! through k = 6
+        f0r = T(1) - c0 * c0 * T(1.0 / 720.0);
+        f0i = -c0 * T(1.0 / 6.0) + c0 * c1 * T(1.0 / 120.0);
+        f1r = c0 * T(1.0 / 24.0) - c0 * c1 * T(2.0 / 720.0);
+        f1i = T(1) - c1 * T(1.0 / 6.0) + c1 * c1 * T(1.0 / 120.0);
+        f2r = T(-0.5) + c1 * T(1.0 / 24.0) - c1 * c1 * T(1.0 / 720.0);
+        f2i = c0 * T(1.0 / 120.0);
+    } else {
+        bool neg = c0 < T(0);
+        T c0a = neg ? -c0 : c0;
+        T c1o3 = c1 * T(1.0 / 3.0);
+        T sq = sqrt(c1o3);
+        T c0max = T(2) * c1o3 * sq;
+        T ratio = c0a / c0max;
+        ratio = ratio > T(1) ? T(1) : ratio;
+        T theta = acos(ratio);
+        T u = sq * cos(theta * T(1.0 / 3.0));
+        T w = sqrt(c1) * sin(theta * T(1.0 / 3.0));
+        T u2 = u * u, w2 = w * w;
+        T xi0;
+        if (w < T(0.05)) xi0 = T(1) - w2 * T(1.0 / 6.0) * (T(1) - w2 * T(1.0 / 20.0) * (T(1) - w2 * T(1.0 / 42.0)));
+        else xi0 = sin(w) / w;
+        T cw = cos(w);
+        T c2u = cos(T(2) * u), s2u = sin(T(2) * u);
+        T cu = cos(u), su = sin(u);   // e^{-iu} = cu - i su
+        // h0 = (u^2 - w^2) e^{2iu} + e^{-iu} [8u^2 cos w + 2iu(3u^2 + w^2) xi0]
+        T a_r = T(8) * u2 * cw, a_i = T(2) * u * (T(3) * u2 + w2) * xi0;
+        T h0r = (u2 - w2) * c2u + (cu * a_r + su * a_i);
+        T h0i = (u2 - w2) * s2u + (cu * a_i - su * a_r);
+        // h1 = 2u e^{2iu} - e^{-iu} [2u cos w - i(3u^2 - w^2) xi0]
+        T b_r = T(2) * u * cw, b_i = -(T(3) * u2 - w2) * xi0;
+        T h1r = T(2) * u * c2u - (cu * b_r + su * b_i);
+        T h1i = T(2) * u * s2u - (cu * b_i - su * b_r);
+        // h2 = e^{2iu} - e^{-iu} [cos w + 3iu xi0]
+        T d_r = cw, d_i = T(3) * u * xi0;
+        T h2r = c2u - (cu * d_r + su * d_i);
+        T h2i = s2u - (cu * d_i - su * d_r);
+        T inv = T(1) / (T(9) * u2 - w2);
+        f0r = h0r * inv; f0i = h0i * inv;
+        f1r = h1r * inv; f1i = h1i * inv;
+        f2r = h2r * inv; f2i = h2i * inv;
+        if (neg) {   // f_j(-c0) = (-1)^j conj(f_j(c0))
+            f0i = -f0i;
+            f1r = -f1r;
+            f2i = -f2i;
+        }
+    }
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            // f1 Q + f2 Q^2 with Q, Q^2 hermitian (complex entries)
+            T qr = Q.re[i][j], qi = Q.im[i][j], pr = Q2.re[i][j], pi = Q2.im[i][j];
+            T rr = f1r * qr - f1i * qi + f2r * pr - f2i * pi;
+            T ri = f1r * qi + f1i * qr + f2r * pi + f2i * pr;
+            if (i == j) { rr += f0r; ri += f0i; }
+            r.re[i][j] = rr;
+            r.im[i][j] = ri;
+        }
+    return r;
+}
+
+// exp(i s x^a T^a)
+template <typename T>
+__device__ __forceinline__ M3<T> expi_alg(const T *x, T s) {
+    T y[8];
+#pragma unroll
+    for (int a = 0; a < 8; a++) y[a] = s * x[a];
+    return expi_herm(herm_from_alg(y));
+}
+
+// Gram-Schmidt on rows 0 and 1, row 2 = conj(r0 x r1): nearest-by-construction SU(3)
+template <typename T>
+__device__ __forceinline__ M3<T> reunitarize(const M3<T> &m) {
+    M3<T> r;
+    T n0 = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) n0 += m.re[0][k] * m.re[0][k] + m.im[0][k] * m.im[0][k];
+    T in0 = T(1) / sqrt(n0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) { r.re[0][k] = m.re[0][k] * in0; r.im[0][k] = m.im[0][k] * in0; }
+    // <r0, m1> = sum conj(r0_k) m1_k
+    T dr = T(0), di = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        dr += r.re[0][k] * m.re[1][k] + r.im[0][k] * m.im[1][k];
+        di += r.re[0][k] * m.im[1][k] - r.im[0][k] * m.re[1][k];
+    }
+    T v_r[3], v_i[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        v_r[k] = m.re[1][k] - (dr * r.re[0][k] - di * r.im[0][k]);
+        v_i[k] = m.im[1][k] - (dr * r.im[0][k] + di * r.re[0][k]);
+    }
+    T n1 = v_r[0] * v_r[0] + v_i[0] * v_i[0] + v_r[1] * v_r[1] + v_i[1] * v_i[1] + v_r[2] * v_r[2] + v_i[2] * v_i[2];
+    T in1 = T(1) / sqrt(n1);
+#pragma unroll
+    for (int k = 0; k < 3; k++) { r.re[1][k] = v_r[k] * in1; r.im[1][k] = v_i[k] * in1; }
+    // row2 = conj(r0 x r1)
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        int a = (k + 1) % 3, b = (k + 2) % 3;
+        T cr = r.re[0][a] * r.re[1][b] - r.im[0][a] * r.im[1][b] - (r.re[0][b] * r.re[1][a] - r.im[0][b] * r.im[1][a]);
+        T ci = r.re[0][a] * r.im[1][b] + r.im[0][a] * r.re[1][b] - (r.re[0][b] * r.im[1][a] + r.im[0][b] * r.re[1][a]);
+        r.re[2][k] = cr;
+        r.im[2][k] = -ci;
+    }
+    return r;
+}
+
+// U^dag X U and U X U^dag of a hermitian X, returned as algebra components
+template <typename T>
+__device__ __forceinline__ void transport_dn(const M3<T> &U, const M3<T> &X, T *out) {
+    alg_from_herm(mul(mul_dn(U, X), U), out);
+}
+template <typename T>
+__device__ __forceinline__ void transport_nd(const M3<T> &U, const M3<T> &X, T *out) {
+    alg_from_herm(mul_nd(mul(U, X), U), out);
+}
+
+// ---- structure-of-arrays loads/stores ---------------------------------------
+// A link plane set: 18 planes of n2 values, entry (i,j) real at plane 2(3i+j).
+template <typename T>
+__device__ __forceinline__ M3<T> load_m(const T *__restrict__ base, size_t n2, size_t x) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            r.re[i][j] = base[(size_t)(2 * (3 * i + j)) * n2 + x];
+            r.im[i][j] = base[(size_t)(2 * (3 * i + j) + 1) * n2 + x];
+        }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_m(T *__restrict__ base, size_t n2, size_t x, const M3<T> &m) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            base[(size_t)(2 * (3 * i + j)) * n2 + x] = m.re[i][j];
+            base[(size_t)(2 * (3 * i + j) + 1) * n2 + x] = m.im[i][j];
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_a(const T *__restrict__ base, size_t n2, size_t x, T *v) {
+#pragma unroll
+    for (int a = 0; a < 8; a++) v[a] = base[(size_t)a * n2 + x];
+}
+
+template <typename T>
+__device__ __forceinline__ void store_a(T *__restrict__ base, size_t n2, size_t x, const T *v) {
+#pragma unroll
+    for (int a = 0; a < 8; a++) base[(size_t)a * n2 + x] = v[a];
+}
+
+}  // namespace gl

@@ -1,0 +1,322 @@
+"""Thin Python binding of the C-ABI in include/glasma.h.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libglasma.so.  PyTorch provides the device workspace and the stream.  The
+library must be built (``python paper_2307_07999_amd/build.py``); loading
+fails loudly otherwise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglasma.so")
+HBARC_GEV_FM = 0.1973269804
+
+GL_OK, GL_EINVAL, GL_ESTATE, GL_ENOTCONV, GL_ENUMERIC, GL_EDEVICE, GL_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+GL_MAX_SPECIES = 16
+KIND_HEAVY_QUARK, KIND_JET = 0, 1
+
+
+class GlasmaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("glasma status %d: %s" % (status, msg))
+        self.status = status
+
+
+class LatticeDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("L_fm", ctypes.c_double), ("dtau_over_a", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("reunit_every", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("max_particles", ctypes.c_int64)]
+
+
+class MVDesc(ctypes.Structure):
+    _fields_ = [("g2mu_GeV", ctypes.c_double), ("m_ir_GeV", ctypes.c_double),
+                ("n_sheets", ctypes.c_int32)]
+
+
+class SpeciesDesc(ctypes.Structure):
+    _fields_ = [("mass_GeV", ctypes.c_double), ("p0_GeV", ctypes.c_double), ("kind", ctypes.c_int32),
+                ("tau_form_fm", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("gauss_max", ctypes.c_double), ("gauss_rel", ctypes.c_double),
+                ("unitarity_max", ctypes.c_double), ("energy", ctypes.c_double * 4),
+                ("casimir2_dev", ctypes.c_double), ("nonfinite", ctypes.c_int32)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_VP = ctypes.c_void_p
+
+_SIGS = {
+    "gl_required_bytes": [ctypes.POINTER(LatticeDesc), ctypes.POINTER(ctypes.c_size_t)],
+    "gl_event_create": [ctypes.POINTER(LatticeDesc), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)],
+    "gl_init_glasma": [_VP, ctypes.POINTER(MVDesc), ctypes.c_uint64],
+    "gl_init_glasma_from_charges": [_VP, _VP, ctypes.c_int32, ctypes.c_double],
+    "gl_add_species": [_VP, ctypes.POINTER(SpeciesDesc), ctypes.c_int64, ctypes.c_uint64, _I32],
+    "gl_evolve_fields": [_VP, ctypes.c_int32],
+    "gl_push_particles": [_VP],
+    "gl_run": [_VP, ctypes.c_int32],
+    "gl_broadening": [_VP, ctypes.c_int32, _D, ctypes.c_int32, _I32],
+    "gl_kappa": [_VP, ctypes.c_int32, _D, ctypes.c_int32, _I32],
+    "gl_qhat": [_VP, ctypes.c_int32, _D, ctypes.c_int32, _I32],
+    "gl_series": [_VP, _D, ctypes.c_int32, _I32],
+    "gl_rates_from_series": [_D, ctypes.c_int32, ctypes.c_double, _D],
+    "gl_diagnostics": [_VP, ctypes.POINTER(Diag)],
+    "gl_set_state": [_VP, _D, _D, _D, _D, ctypes.c_int64],
+    "gl_get_state": [_VP, _D, _D, _D, _D, _I64],
+    "gl_get_site_fields": [_VP, _D],
+    "gl_set_particles": [_VP, ctypes.c_int32, ctypes.POINTER(SpeciesDesc), ctypes.c_int64, _I32, _D, _D,
+                         _D, _D, _D, _I32],
+    "gl_get_particles": [_VP, ctypes.c_int64, _I64, _I32, _D, _D, _D, _D, _D, _I32],
+    "gl_species_info": [_VP, ctypes.c_int32, _I32, _D],
+    "gl_get_wilson_line": [_VP, ctypes.c_int32, _D],
+    "gl_draw_charges": [_VP, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _D],
+    "gl_event_info": [_VP, _D, _D, _I64],
+    "gl_sync": [_VP],
+    "gl_profile_enable": [_VP, ctypes.c_int32],
+    "gl_profile_read": [_VP, _D, _I64],
+}
+
+_lib = None
+
+
+def lib():
+    """Load libglasma.so (never a fallback: raise if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libglasma.so is not built; run `python paper_2307_07999_amd/build.py` "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.gl_event_destroy.argtypes = [_VP]
+        L.gl_event_destroy.restype = None
+        L.gl_status_string.argtypes = [ctypes.c_int32]
+        L.gl_status_string.restype = ctypes.c_char_p
+        L.gl_last_error.argtypes = []
+        L.gl_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != GL_OK:
+        raise GlasmaError(status, lib().gl_last_error().decode())
+    return status
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _i(a):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_I32)
+
+
+def lattice_spacing(N, L_fm):
+    a_fm = L_fm / N
+    return a_fm, a_fm / HBARC_GEV_FM
+
+
+def required_bytes(N, L_fm, dtau_over_a=0.125, precision=64, reunit_every=16, max_steps=512,
+                   max_particles=0):
+    d = LatticeDesc(N, L_fm, dtau_over_a, precision, reunit_every, max_steps, max_particles)
+    out = ctypes.c_size_t(0)
+    check(lib().gl_required_bytes(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
+
+
+def rates_from_series(series_s, dtau):
+    s = np.ascontiguousarray(series_s, np.float64)
+    rates = np.zeros((s.shape[0], 3))
+    check(lib().gl_rates_from_series(_d(s), s.shape[0], dtau, _d(rates)))
+    return rates
+
+
+class Event:
+    """One Glasma event with its particles, on a torch-allocated workspace."""
+
+    def __init__(self, N, L_fm, dtau_over_a=0.125, precision=64, reunit_every=16, max_steps=512,
+                 max_particles=0, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.N, self.L_fm, self.precision = N, L_fm, precision
+        self.desc = LatticeDesc(N, L_fm, dtau_over_a, precision, reunit_every, max_steps, max_particles)
+        nbytes = ctypes.c_size_t(0)
+        check(lib().gl_required_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
+        self.nbytes = nbytes.value
+        self.device = torch.device(device)
+        self._ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _VP()
+        check(lib().gl_event_create(ctypes.byref(self.desc), _VP(self._ws_ptr), self.nbytes,
+                                    _VP(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n2 = N * N
+        self.a_fm, self.a_gev = lattice_spacing(N, L_fm)
+        self.dtau = dtau_over_a
+        self.species = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_event_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- initial conditions ------------------------------------------------
+    def init_glasma(self, g2mu_GeV, m_ir_GeV, n_sheets, seed):
+        mv = MVDesc(g2mu_GeV, m_ir_GeV, n_sheets)
+        return check(lib().gl_init_glasma(self._h, ctypes.byref(mv), seed))
+
+    def init_glasma_from_charges(self, rho, m_ir_GeV):
+        """rho: torch float64 device tensor [2, n_sheets, 8, N*N] (lattice units)."""
+        assert rho.dtype == self.torch.float64 and rho.is_contiguous() and rho.device.type == "cuda"
+        return check(lib().gl_init_glasma_from_charges(self._h, _VP(rho.data_ptr()), rho.shape[1], m_ir_GeV))
+
+    def add_species(self, mass_GeV, p0_GeV, kind, n, seed, tau_form_fm=-1.0):
+        sp = SpeciesDesc(mass_GeV, p0_GeV, kind, tau_form_fm)
+        sid = ctypes.c_int32(-1)
+        check(lib().gl_add_species(self._h, ctypes.byref(sp), n, seed, ctypes.byref(sid)))
+        self.species.append(dict(mass_GeV=mass_GeV, p0_GeV=p0_GeV, kind=kind, n=n,
+                                 tau_form_fm=tau_form_fm))
+        return sid.value
+
+    # ---- evolution -----------------------------------------------------------
+    def evolve_fields(self, n_steps):
+        return check(lib().gl_evolve_fields(self._h, n_steps))
+
+    def push_particles(self):
+        return check(lib().gl_push_particles(self._h))
+
+    def run(self, n_steps):
+        return check(lib().gl_run(self._h, n_steps))
+
+    def sync(self):
+        return check(lib().gl_sync(self._h))
+
+    # ---- observables ---------------------------------------------------------
+    def _rows(self, fn, species, width):
+        n = ctypes.c_int32(0)
+        check(fn(self._h, species, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), width))
+        check(fn(self._h, species, _d(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
+
+    def broadening(self, species):
+        return self._rows(lib().gl_broadening, species, 5)
+
+    def kappa(self, species):
+        return self._rows(lib().gl_kappa, species, 4)
+
+    def qhat(self, species):
+        return self._rows(lib().gl_qhat, species, 3)
+
+    def series(self):
+        n = ctypes.c_int32(0)
+        check(lib().gl_series(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), GL_MAX_SPECIES, 4))
+        check(lib().gl_series(self._h, _d(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
+
+    def diagnostics(self):
+        d = Diag()
+        st = lib().gl_diagnostics(self._h, ctypes.byref(d))
+        if st not in (GL_OK, GL_ENUMERIC):
+            check(st)
+        return dict(gauss_max=d.gauss_max, gauss_rel=d.gauss_rel, unitarity_max=d.unitarity_max,
+                    energy=list(d.energy), casimir2_dev=d.casimir2_dev, nonfinite=d.nonfinite,
+                    status=st)
+
+    # ---- host transfers (tests, checkpoints) ---------------------------------
+    def set_state(self, U, E, phi, pi, n):
+        arrs = [np.ascontiguousarray(a, np.float64) for a in (U, E, phi, pi)]
+        assert arrs[0].size == 36 * self.n2 and arrs[1].size == 16 * self.n2
+        assert arrs[2].size == 8 * self.n2 and arrs[3].size == 8 * self.n2
+        return check(lib().gl_set_state(self._h, *[_d(a) for a in arrs], n))
+
+    def get_state(self):
+        U = np.zeros((2, 18, self.n2))
+        E = np.zeros((2, 8, self.n2))
+        phi = np.zeros((8, self.n2))
+        pi = np.zeros((8, self.n2))
+        n = ctypes.c_int64(0)
+        check(lib().gl_get_state(self._h, _d(U), _d(E), _d(phi), _d(pi), ctypes.byref(n)))
+        return U, E, phi, pi, n.value
+
+    def site_fields(self):
+        F = np.zeros((6, 8, self.n2))
+        check(lib().gl_get_site_fields(self._h, _d(F)))
+        return F
+
+    def set_particles(self, species_descs, cell, off, eta, p, Q, p0, species):
+        n = len(species)
+        sp = (SpeciesDesc * len(species_descs))(*[SpeciesDesc(*d) for d in species_descs])
+        arr = lambda a, t: np.ascontiguousarray(a, t)
+        check(lib().gl_set_particles(self._h, len(species_descs), sp, n, _i(arr(cell, np.int32)),
+                                     _d(arr(off, np.float64)), _d(arr(eta, np.float64)),
+                                     _d(arr(p, np.float64)), _d(arr(Q, np.float64)),
+                                     _d(arr(p0, np.float64)), _i(arr(species, np.int32))))
+
+    def get_particles(self):
+        n = ctypes.c_int64(0)
+        check(lib().gl_get_particles(self._h, 0, ctypes.byref(n), None, None, None, None, None, None,
+                                     None))
+        k = n.value
+        out = dict(cell=np.zeros((2, k), np.int32), off=np.zeros((2, k)), eta=np.zeros(k),
+                   p=np.zeros((3, k)), Q=np.zeros((8, k)), p0=np.zeros((3, k)),
+                   species=np.zeros(k, np.int32))
+        if k:
+            check(lib().gl_get_particles(self._h, k, ctypes.byref(n), _i(out["cell"]), _d(out["off"]),
+                                         _d(out["eta"]), _d(out["p"]), _d(out["Q"]), _d(out["p0"]),
+                                         _i(out["species"])))
+        return out
+
+    def species_info(self, s):
+        nf = ctypes.c_int32(0)
+        m = ctypes.c_double(0)
+        check(lib().gl_species_info(self._h, s, ctypes.byref(nf), ctypes.byref(m)))
+        return nf.value, m.value
+
+    def wilson_line(self, nucleus):
+        V = np.zeros((18, self.n2))
+        check(lib().gl_get_wilson_line(self._h, nucleus, _d(V)))
+        return V
+
+    def draw_charges(self, seed, nucleus, sheet, sigma):
+        rho = np.zeros((8, self.n2))
+        check(lib().gl_draw_charges(self._h, seed, nucleus, sheet, sigma, _d(rho)))
+        return rho
+
+    def profile(self, on=True):
+        return check(lib().gl_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(ms[4], launches[4]) per kernel class: field step, site fields, push, reduction."""
+        ms = np.zeros(4)
+        cnt = np.zeros(4, np.int64)
+        check(lib().gl_profile_read(self._h, _d(ms), cnt.ctypes.data_as(_I64)))
+        return ms, cnt
+
+    def info(self):
+        a = ctypes.c_double(0)
+        dt = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        check(lib().gl_event_info(self._h, ctypes.byref(a), ctypes.byref(dt), ctypes.byref(n)))
+        return a.value, dt.value, n.value

@@ -1,0 +1,252 @@
+"""GPU parity: every stage of the HIP path against the FP64 CPU oracle on the
+same seeded inputs, through the C-ABI.
+
+Tolerances (FP64 path): the two sides differ only by rounding order (the GPU
+uses Cayley-Hamilton exponentials, fused multiply-adds and tree reductions,
+the oracle power-series exponentials and sequential sums), so single steps
+agree to ~1e-15 relative; a full 63-step coupled run amplifies that by the
+chaotic growth of classical Yang-Mills over tau <= 1 fm, and we bound the
+relative error at 1e-9.  FP32 (configuration with FP32 links and fields): the
+target is 1e-3 relative on the observables, err(f) = max|f32 - f64| / max|f64|.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests import gpu_helpers as H
+from tests import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_07999_amd as g
+    g.lib()
+    return g
+
+
+def _event(gl, N, L=4.0, prec=64, max_particles=0, max_steps=128, reunit=16):
+    return gl.Event(N, L, 0.125, precision=prec, reunit_every=reunit, max_steps=max_steps,
+                    max_particles=max_particles)
+
+
+def test_charges_match_oracle(gl, orc):
+    N = 16
+    ev = _event(gl, N)
+    for nuc, sheet in ((0, 0), (1, 3)):
+        got = ev.draw_charges(77, nuc, sheet, 0.6)
+        want = orc.mv_charges(N, 0.6, 77, nuc, sheet)
+        assert H.rel_err(got, want.T) < 1e-14
+
+
+@pytest.mark.parametrize("N,sheets", [(32, 2), (48, 2), (6, 1)])
+def test_wilson_lines_match_oracle(gl, orc, N, sheets):
+    cfg = dict(H.C1, N=N, sheets=sheets)
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    ev = _event(gl, N, cfg["L"])
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], sheets, cfg["seed"])
+    for nuc in (0, 1):
+        want = orc.wilson_line(N, sigma, m2, sheets, cfg["seed"], nuc)
+        got = ev.wilson_line(nuc)
+        assert np.abs(got - want.T).max() < 1e-12
+
+
+@pytest.mark.parametrize("N", [32, 24])
+def test_initial_state_matches_oracle(gl, orc, N):
+    cfg = dict(H.C1, N=N)
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    ev = _event(gl, N, cfg["L"])
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], 1, cfg["seed"])
+    U, E, phi, pi, n = ev.get_state()
+    s, rc, res = orc.init_glasma(N, sigma, m2, 1, cfg["seed"], 0.125)
+    assert rc == 0 and n == 1
+    Uo, Eo, phio, pio = H.state_oracle_to_soa(s)
+    assert np.abs(U - Uo).max() < 1e-12
+    assert np.abs(E).max() == 0
+    assert np.abs(pi - pio).max() < 1e-12
+    assert np.abs(phi - phio).max() < 1e-14
+
+
+@pytest.mark.parametrize("N", [8, 40, 64])
+def test_field_steps_match_oracle(gl, orc, N):
+    U, E, phi, pi = si.random_state(100 + N, N, link_kind="near", eps=0.5)
+    s = orc.State(N)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 3
+    ev = _event(gl, N)
+    ev.set_state(*H.state_oracle_to_soa(s), 3)
+    ev.evolve_fields(5)
+    for _ in range(5):
+        orc.field_step(s, 0.125)
+    got = ev.get_state()
+    assert got[4] == s.n
+    for g, w in zip(got[:4], H.state_oracle_to_soa(s)):
+        assert np.abs(g - w).max() < 1e-12
+
+
+def _oracle_particles(orc, N, seed, specs):
+    parts = []
+    for sid, (kind, p0, n) in enumerate(specs):
+        P = orc.particles_init(N, seed, sid, kind, p0, n)
+        parts.append(P)
+    tot = sum(p.n for p in parts)
+    Pall = orc.Particles(tot)
+    for k in ("cell", "off", "eta", "p", "Q", "p0", "species"):
+        setattr(Pall, k, np.ascontiguousarray(np.concatenate([getattr(p, k) for p in parts])))
+    return Pall
+
+
+def test_particle_init_matches_oracle(gl, orc):
+    N, seed = 32, 4242
+    cfg = dict(H.C1)
+    a_fm, a_gev, _, _ = H.lattice(cfg)
+    ev = _event(gl, N, max_particles=3000)
+    ev.init_glasma(1.0, 0.2, 1, seed)
+    ev.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, 1000, seed)
+    ev.add_species(0.0, 10.0, gl.KIND_JET, 700, seed)
+    got = ev.get_particles()
+    want = _oracle_particles(orc, N, seed, [(0, 2.0 * a_gev, 1000), (1, 10.0 * a_gev, 700)])
+    w = H.particles_oracle_to_gpu(want)
+    assert np.array_equal(got["cell"], w["cell"])
+    assert np.array_equal(got["off"], w["off"])
+    assert np.array_equal(got["species"], w["species"])
+    assert np.abs(got["p0"] - w["p0"]).max() < 1e-15
+    assert np.abs(got["Q"] - w["Q"]).max() < 1e-13
+
+
+def _setup_coupled(gl, orc, N, prec, seed, specs, cfg):
+    """GPU and oracle events with identical fields (oracle init) and particles."""
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    s, rc, _ = orc.init_glasma(N, sigma, m2, cfg["sheets"], seed, 0.125)
+    ev = _event(gl, N, cfg["L"], prec=prec, max_particles=sum(n for *_, n in specs) + 10, max_steps=256)
+    ev.set_state(*H.state_oracle_to_soa(s), 1)
+    descs = []
+    lat = []
+    for kind, m, p0, n in specs:
+        descs.append((m, p0, kind, -1.0))
+        lat.append((kind, p0 * a_gev, n))
+    P = _oracle_particles(orc, N, seed, lat)
+    d = H.particles_oracle_to_gpu(P)
+    ev.set_particles(descs, d["cell"], d["off"], d["eta"], d["p"], d["Q"], d["p0"], d["species"])
+    mass = [ev.species_info(k)[1] for k in range(len(specs))]
+    nform = [ev.species_info(k)[0] for k in range(len(specs))]
+    return s, P, ev, mass, nform
+
+
+def test_site_fields_and_one_push_match_oracle(gl, orc):
+    N = 24
+    cfg = dict(H.C1, N=N, L=3.0)
+    s, P, ev, mass, nform = _setup_coupled(gl, orc, N, 64, 9, [(0, 1.27, 2.0, 300), (1, 0.0, 10.0, 200)], cfg)
+    # advance both to n = 6 so that every species is formed and fields are generic
+    for _ in range(5):
+        ev.evolve_fields(1)
+        ev.push_particles()
+    for _ in range(5):
+        U0, phi0, n = s.U.copy(), s.phi.copy(), s.n
+        F = orc.field_step(s, 0.125, want_F=True)
+        orc.particle_step(N, n, 0.125, U0, phi0, F, P, mass, nform)
+    U0, phi0, n = s.U.copy(), s.phi.copy(), s.n
+    F = orc.field_step(s, 0.125, want_F=True)
+    ev.evolve_fields(1)
+    Fg = ev.site_fields()
+    assert np.abs(Fg - np.transpose(F, (1, 2, 0))).max() < 1e-12 * max(1.0, np.abs(F).max())
+    orc.particle_step(N, n, 0.125, U0, phi0, F, P, mass, nform)
+    ev.push_particles()
+    got = ev.get_particles()
+    w = H.particles_oracle_to_gpu(P)
+    assert np.array_equal(got["cell"], w["cell"])
+    for k in ("off", "eta", "p", "Q"):
+        assert np.abs(got[k] - w[k]).max() < 1e-12, k
+
+
+def test_c1_full_run_matches_oracle(gl, orc):
+    """The 32^2 parity configuration end to end: MV init on the device,
+    1000 charm quarks, 63 coupled steps to tau = 1 fm, series and kappa."""
+    cfg = H.C1
+    N = cfg["N"]
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    steps = H.n_steps(cfg)
+    assert steps == 63
+    ev = _event(gl, N, cfg["L"], max_particles=1000, max_steps=steps)
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
+    sid = ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 1000, cfg["seed"])
+    nform, mass = ev.species_info(sid)
+    assert nform == 5
+    ev.run(steps)
+    ser = ev.series()[:, :1, :]
+    st, P, ser_o, rc = orc.run(N, sigma, m2, 1, cfg["seed"], 0.125, steps,
+                               [dict(kind=0, mass=mass, p0=0.0, nform=nform, n=1000)])
+    assert rc == 0
+    assert np.array_equal(ser[:, 0, 3], ser_o[:, 0, 3])
+    for c in range(3):
+        assert H.rel_err(ser[:, 0, c], ser_o[:, 0, c]) < 1e-9
+    # kappa rows from the library against the oracle's derivative
+    kap = ev.kappa(sid)
+    ks, rates = orc.coefficients(ser_o[:, 0, :], 0.125)
+    f2, fk = orc.to_physical(a_fm)
+    assert len(kap) == len(ks)
+    assert H.rel_err(kap[:, 2], (rates[:, 0] + rates[:, 1]) * fk) < 1e-9
+    assert H.rel_err(kap[:, 3], rates[:, 2] * fk) < 1e-9
+    assert np.allclose(kap[:, 0], (ks + 1) * 0.125 * a_fm)
+    d = ev.diagnostics()
+    assert d["gauss_max"] < 1e-12 and d["unitarity_max"] < 1e-12
+    assert d["casimir2_dev"] < 1e-12 and d["nonfinite"] == 0
+    U, E, phi, pi, n = ev.get_state()
+    for g, w in zip((U, E, phi, pi), H.state_oracle_to_soa(st)):
+        assert H.rel_err(g, w) < 1e-9
+
+
+def test_fp32_observables_within_target(gl, orc):
+    """FP32 links/fields (re-unitarised every 16 steps) with FP64 sums against
+    the FP64 oracle on the 32^2 configuration with charm quarks and jets."""
+    cfg = H.C1
+    N = cfg["N"]
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    steps = H.n_steps(cfg)
+    ev = _event(gl, N, cfg["L"], prec=32, max_particles=2000, max_steps=steps)
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], 1, cfg["seed"])
+    c = ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 1000, cfg["seed"])
+    j = ev.add_species(0.0, 10.0, gl.KIND_JET, 1000, cfg["seed"])
+    ev.run(steps)
+    sp = [dict(kind=0, mass=ev.species_info(c)[1], p0=0.0, nform=ev.species_info(c)[0], n=1000),
+          dict(kind=1, mass=0.0, p0=10.0 * a_gev, nform=ev.species_info(j)[0], n=1000)]
+    st, P, ser_o, rc = orc.run(N, sigma, m2, 1, cfg["seed"], 0.125, steps, sp)
+    ser = ev.series()
+    f2, fk = orc.to_physical(a_fm)
+    errs = {}
+    mean_o, _ = orc.mean_broadening(ser_o[:, 0])
+    mean_g, _ = orc.mean_broadening(ser[:, 0])
+    errs["dpT2"] = H.rel_err(mean_g[:, 0] + mean_g[:, 1], mean_o[:, 0] + mean_o[:, 1])
+    _, ro = orc.coefficients(ser_o[:, 0], 0.125)
+    _, rg = orc.coefficients(ser[:, 0], 0.125)
+    errs["kappa_T"] = H.rel_err(rg[:, 0] + rg[:, 1], ro[:, 0] + ro[:, 1])
+    errs["kappa_L"] = H.rel_err(rg[:, 2], ro[:, 2])
+    _, ro = orc.coefficients(ser_o[:, 1], 0.125)
+    _, rg = orc.coefficients(ser[:, 1], 0.125)
+    errs["qhat_y"] = H.rel_err(rg[:, 1], ro[:, 1])
+    errs["qhat_z"] = H.rel_err(rg[:, 2], ro[:, 2])
+    print("FP32 vs FP64 oracle errors:", errs)
+    for k, v in errs.items():
+        assert v < 1e-3, (k, v)
+
+
+def test_call_order_errors(gl):
+    ev = _event(gl, 8, max_particles=10)
+    with pytest.raises(gl.GlasmaError) as e:
+        ev.evolve_fields(1)
+    assert e.value.status == -2
+    ev.init_glasma(1.0, 0.2, 1, 1)
+    ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 10, 1)
+    with pytest.raises(gl.GlasmaError):
+        ev.push_particles()
+    with pytest.raises(gl.GlasmaError):
+        ev.evolve_fields(2)
+    ev.evolve_fields(1)
+    with pytest.raises(gl.GlasmaError):
+        ev.evolve_fields(1)
+    ev.push_particles()
+    ev.run(3)
