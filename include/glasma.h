@@ -36,7 +36,7 @@
  *   F    [6][8][N*N]   local-frame site fields Ex, Ey, Ez, Bx, By, Bz at tau_n
  *   particles: cell [2][n] int32, off [2][n], eta [n], p [3][n] = (px, py, P_eta
  *   = tau^2 p^eta), Q [8][n], p0 [3][n] = (px, py, pz_lab) at formation,
- *   species [n] int32 (grouped by species in ascending order).
+ *   species [n] int32, in creation order.
  *
  * Time grid: tau_n = n * dtau with dtau = dtau_over_a * a.  After
  * gl_init_glasma the state is at n = 1 (U^1, phi^1; E, pi at tau_{1/2}).
@@ -167,13 +167,21 @@ gl_status gl_get_state(gl_event *ev, double *U, double *E, double *phi, double *
  * or right after it). */
 gl_status gl_get_site_fields(gl_event *ev, double *F);
 /* Replace all particles; species table given as desc + per-particle species
- * (grouped ascending).  nform per species is derived from tau_form. */
+ * (any order; the getters return this order).  nform per species is derived
+ * from tau_form. */
 gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_desc *sp,
                            int64_t n, const int32_t *cell, const double *off,
                            const double *eta, const double *p, const double *Q,
                            const double *p0, const int32_t *species);
 gl_status gl_get_particles(gl_event *ev, int64_t cap, int64_t *n, int32_t *cell, double *off,
                            double *eta, double *p, double *Q, double *p0, int32_t *species);
+/* Particles are kept ordered by cell in device memory so that the push
+ * gathers neighbouring site fields; they are re-sorted (stable, so the result
+ * is deterministic) after every `every` particle steps and whenever particles
+ * are added.  0 disables the periodic re-sort.  Default 16.  The host getters
+ * always return particles in creation order. */
+gl_status gl_set_sort_period(gl_event *ev, int32_t every);
+
 /* Per-species formation step index and mass in lattice units. */
 gl_status gl_species_info(gl_event *ev, int32_t species, int32_t *nform, double *mass_lat);
 

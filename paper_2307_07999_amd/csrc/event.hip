@@ -36,8 +36,8 @@ gl_status fail(gl_status s, const std::string &msg) {
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t field[2], F, part, partials, block_start, series, diag, VA, VB, planes, U0, pi0, status,
-        total;
+    size_t field[2], F, part[2], id[2], sort_keys[2], sort_vals[2], sort_counts, sort_totals, partials,
+        series, diag, VA, VB, planes, U0, pi0, status, total;
     int64_t slots;         // particle capacity in slots (padding included)
     size_t n_diag_blocks;  // workgroups of the diagnostics kernel
 };
@@ -58,7 +58,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     if (d->max_steps < 0 || d->max_particles < 0 || d->reunit_every < 0)
         return fail(GL_EINVAL, "negative capacity");
     const size_t n2 = (size_t)d->N * d->N, ts = d->precision == 64 ? 8 : 4;
-    L.slots = ((d->max_particles + kPushBlock - 1) / kPushBlock + kMaxSpecies) * kPushBlock;
+    L.slots = (d->max_particles + kPushBlock - 1) / kPushBlock * kPushBlock;
     if (d->max_particles == 0) L.slots = 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -67,10 +67,14 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
         return o;
     };
     for (int b = 0; b < 2; b++) L.field[b] = take(68 * n2 * ts);
-    L.F = take(48 * n2 * ts);
-    L.part = take((size_t)L.slots * (17 * ts + 12));
-    L.partials = take(std::max<int64_t>(1, L.slots / kPushBlock) * 4 * sizeof(double));
-    L.block_start = take((kMaxSpecies + 1) * sizeof(int32_t));
+    L.F = take((size_t)kSiteRec * n2 * ts);
+    for (int b = 0; b < 2; b++) L.part[b] = take((size_t)L.slots * (17 * ts + 12));
+    for (int b = 0; b < 2; b++) L.id[b] = take((size_t)L.slots * sizeof(int32_t));
+    for (int b = 0; b < 2; b++) L.sort_keys[b] = take((size_t)L.slots * sizeof(uint32_t));
+    for (int b = 0; b < 2; b++) L.sort_vals[b] = take((size_t)L.slots * sizeof(int32_t));
+    L.sort_counts = take((size_t)256 * std::max<int64_t>(1, sort_tiles(L.slots)) * sizeof(uint32_t));
+    L.sort_totals = take(256 * sizeof(uint32_t));
+    L.partials = take(std::max<int64_t>(1, L.slots / kPushBlock) * kMaxSpecies * 4 * sizeof(double));
     L.series = take(std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double));
     L.n_diag_blocks = (size_t)((d->N + 31) / 32) * ((d->N + 7) / 8);
     size_t cas_blocks = (size_t)std::max<int64_t>(1, (L.slots + 255) / 256);
@@ -87,7 +91,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
 
 struct SpeciesInfo {
     gl_species_desc desc;
-    int64_t n, slot0, cap;
+    int64_t n;
     int32_t nform;
     double mass_lat, p0_lat, tau_form_fm;
 };
@@ -108,7 +112,9 @@ struct gl_event {
     int64_t rows = 0;           // series rows written
     int64_t slots_used = 0;
     std::vector<SpeciesInfo> species;
-    int32_t block_start_host[kMaxSpecies + 1];
+    int pbuf = 0;               // which particle buffer is current
+    int32_t sort_every = 16;    // re-sort particles by cell every this many pushes (0: never)
+    int64_t since_sort = 0;
 
     // kernel timing: pairs of events per launch, grouped by kernel class
     bool prof = false;
@@ -123,10 +129,10 @@ struct gl_event {
         return FieldPtrs<T>{base, base + 36 * n2, base + 52 * n2, base + 60 * n2};
     }
     template <typename T>
-    PartPtrs<T> parts() const {
+    PartPtrs<T> parts(int buf = -1) const {
         PartPtrs<T> p;
         int64_t c = L.slots;
-        char *b = ws + L.part;
+        char *b = ws + L.part[buf < 0 ? pbuf : buf];
         p.cx = (int32_t *)b;
         p.cy = p.cx + c;
         p.species = p.cy + c;
@@ -152,6 +158,17 @@ struct gl_event {
             t.nform[s] = s < (int)species.size() ? species[s].nform : 0x7fffffff;
         }
         return t;
+    }
+    int32_t *ids(int buf = -1) const { return (int32_t *)(ws + L.id[buf < 0 ? pbuf : buf]); }
+    SortScratch scratch() const {
+        SortScratch sc;
+        for (int b = 0; b < 2; b++) {
+            sc.keys[b] = (uint32_t *)(ws + L.sort_keys[b]);
+            sc.vals[b] = (int32_t *)(ws + L.sort_vals[b]);
+        }
+        sc.counts = (uint32_t *)(ws + L.sort_counts);
+        sc.totals = (uint32_t *)(ws + L.sort_totals);
+        return sc;
     }
     double *series() const { return (double *)(ws + L.series); }
     double *partials() const { return (double *)(ws + L.partials); }
@@ -219,20 +236,44 @@ gl_status push(gl_event *ev) {
     const int64_t n_prev = ev->n - 1;   // particles advance n_prev -> n
     const int64_t row = n_prev - 1;
     if (row >= ev->desc.max_steps) return fail(GL_EINVAL, "series capacity (max_steps) exhausted");
+    const int ns = (int)ev->species.size();
     PROF(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used, ev->fields<T>(1 - ev->cur),
-                                (const T *)(ev->ws + ev->L.F), ev->tab<T>(), (int)n_prev, ev->dtau,
+                                (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev, ev->dtau,
                                 ev->partials())));
-    PROF(ev, 3, (launch_series_reduce(ev->stream, ev->partials(), (const int32_t *)(ev->ws + ev->L.block_start),
-                                      (int)ev->species.size(), ev->series() + row * kMaxSpecies * 4)));
+    PROF(ev, 3, (launch_series_reduce(ev->stream, ev->partials(), (int)(ev->slots_used / kPushBlock), ns,
+                                      ev->series() + row * kMaxSpecies * 4)));
     ev->rows = std::max<int64_t>(ev->rows, row + 1);
     ev->push_due = false;
+    ev->since_sort++;
     return GL_OK;
+}
+
+template <typename T>
+gl_status sort_t(gl_event *ev) {
+    const int nb = 1 - ev->pbuf;
+    HIP_TRY(launch_sort_particles<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->parts<T>(nb), ev->slots_used,
+                                     ev->scratch(), ev->ids(ev->pbuf), ev->ids(nb)));
+    ev->pbuf = nb;
+    ev->since_sort = 0;
+    return GL_OK;
+}
+
+gl_status sort_particles(gl_event *ev) {
+    if (ev->slots_used == 0) return GL_OK;
+    return ev->fp64() ? sort_t<double>(ev) : sort_t<float>(ev);
 }
 
 gl_status do_field_step(gl_event *ev, bool sf) {
     return ev->fp64() ? field_step<double>(ev, sf) : field_step<float>(ev, sf);
 }
-gl_status do_push(gl_event *ev) { return ev->fp64() ? push<double>(ev) : push<float>(ev); }
+gl_status sort_particles(gl_event *ev);
+
+gl_status do_push(gl_event *ev) {
+    gl_status s = ev->fp64() ? push<double>(ev) : push<float>(ev);
+    if (s) return s;
+    if (ev->sort_every > 0 && ev->since_sort >= ev->sort_every) return sort_particles(ev);
+    return GL_OK;
+}
 
 int32_t nform_of(double tau_form_fm, double dtau_fm) {
     double r = std::ceil(tau_form_fm / dtau_fm);
@@ -259,24 +300,15 @@ gl_status fill_species(gl_event *ev, const gl_species_desc *sp, SpeciesInfo &si)
     return GL_OK;
 }
 
-gl_status upload_block_start(gl_event *ev) {
-    for (int s = 0; s <= kMaxSpecies; s++) ev->block_start_host[s] = (int32_t)(ev->slots_used / kPushBlock);
-    for (size_t s = 0; s < ev->species.size(); s++) {
-        ev->block_start_host[s] = (int32_t)(ev->species[s].slot0 / kPushBlock);
-        ev->block_start_host[s + 1] = (int32_t)((ev->species[s].slot0 + ev->species[s].cap) / kPushBlock);
-    }
-    HIP_TRY(hipMemcpyAsync(ev->ws + ev->L.block_start, ev->block_start_host, sizeof(ev->block_start_host),
-                           hipMemcpyHostToDevice, ev->stream));
-    HIP_TRY(hipStreamSynchronize(ev->stream));
-    return GL_OK;
-}
-
+// new particles of one species occupy slots [slot0, slot0 + n); the slots up
+// to the next multiple of the push workgroup are padding (species -1)
 template <typename T>
-gl_status init_particles(gl_event *ev, const SpeciesInfo &si, int sid, uint64_t seed) {
+gl_status init_particles(gl_event *ev, const SpeciesInfo &si, int sid, uint64_t seed, int64_t slot0,
+                         int64_t slots_end) {
     PartPtrs<T> p = ev->parts<T>();
-    HIP_TRY(hipMemsetAsync(p.species + si.slot0, 0xFF, si.cap * sizeof(int32_t), ev->stream));
-    HIP_TRY(launch_particles_init<T>(ev->stream, ev->N, p, si.slot0, si.n, seed, sid, si.desc.kind,
-                                     si.p0_lat));
+    HIP_TRY(hipMemsetAsync(p.species + slot0, 0xFF, (slots_end - slot0) * sizeof(int32_t), ev->stream));
+    HIP_TRY(launch_particles_init<T>(ev->stream, ev->N, p, slot0, si.n, seed, sid, si.desc.kind, si.p0_lat));
+    HIP_TRY(launch_iota(ev->stream, ev->ids() + slot0, slots_end - slot0, si.n, (int32_t)slot0));
     return GL_OK;
 }
 
@@ -357,29 +389,26 @@ template <typename T>
 gl_status set_particles_t(gl_event *ev, int64_t n, const int32_t *cell, const double *off, const double *eta,
                           const double *p, const double *Q, const double *p0, const int32_t *species) {
     const int64_t c = ev->L.slots;
-    std::vector<int32_t> cx(c, 0), cy(c, 0), sp(c, -1);
+    std::vector<int32_t> cx(c, 0), cy(c, 0), sp(c, -1), id(c, -1);
     std::vector<T> f(17 * (size_t)c, T(0));
-    int64_t i = 0;
-    for (size_t s = 0; s < ev->species.size(); s++) {
-        const SpeciesInfo &si = ev->species[s];
-        for (int64_t k = 0; k < si.n; k++, i++) {
-            int64_t j = si.slot0 + k;
-            cx[j] = cell[i];
-            cy[j] = cell[n + i];
-            sp[j] = species[i];
-            f[0 * c + j] = (T)off[i];
-            f[1 * c + j] = (T)off[n + i];
-            f[2 * c + j] = (T)eta[i];
-            f[3 * c + j] = (T)p[i];
-            f[4 * c + j] = (T)p[n + i];
-            f[5 * c + j] = (T)p[2 * n + i];
-            f[6 * c + j] = (T)p0[i];
-            f[7 * c + j] = (T)p0[n + i];
-            f[8 * c + j] = (T)p0[2 * n + i];
-            for (int a = 0; a < 8; a++) f[(9 + a) * c + j] = (T)Q[a * n + i];
-        }
+    for (int64_t i = 0; i < n; i++) {
+        id[i] = (int32_t)i;
+        cx[i] = cell[i];
+        cy[i] = cell[n + i];
+        sp[i] = species[i];
+        f[0 * c + i] = (T)off[i];
+        f[1 * c + i] = (T)off[n + i];
+        f[2 * c + i] = (T)eta[i];
+        f[3 * c + i] = (T)p[i];
+        f[4 * c + i] = (T)p[n + i];
+        f[5 * c + i] = (T)p[2 * n + i];
+        f[6 * c + i] = (T)p0[i];
+        f[7 * c + i] = (T)p0[n + i];
+        f[8 * c + i] = (T)p0[2 * n + i];
+        for (int a = 0; a < 8; a++) f[(9 + a) * c + i] = (T)Q[a * n + i];
     }
     PartPtrs<T> P = ev->parts<T>();
+    HIP_TRY(hipMemcpyAsync(ev->ids(), id.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipMemcpyAsync(P.cx, cx.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipMemcpyAsync(P.cy, cy.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipMemcpyAsync(P.species, sp.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
@@ -392,21 +421,22 @@ template <typename T>
 gl_status get_particles_t(gl_event *ev, int64_t n, int32_t *cell, double *off, double *eta, double *p,
                           double *Q, double *p0, int32_t *species) {
     const int64_t c = ev->L.slots;
-    std::vector<int32_t> cx(c), cy(c), sp(c);
+    std::vector<int32_t> cx(c), cy(c), sp(c), id(c);
     std::vector<T> f(17 * (size_t)c);
     PartPtrs<T> P = ev->parts<T>();
     if (c > 0) {
+        HIP_TRY(hipMemcpyAsync(id.data(), ev->ids(), c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(cx.data(), P.cx, c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(cy.data(), P.cy, c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(sp.data(), P.species, c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(f.data(), P.ox, f.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipStreamSynchronize(ev->stream));
     }
-    int64_t i = 0;
-    for (size_t s = 0; s < ev->species.size(); s++) {
-        const SpeciesInfo &si = ev->species[s];
-        for (int64_t k = 0; k < si.n; k++, i++) {
-            int64_t j = si.slot0 + k;
+    for (int64_t j = 0; j < ev->slots_used; j++) {
+        {
+            if (id[j] < 0) continue;
+            int64_t i = id[j];
+            if (i >= n) return fail(GL_EDEVICE, "corrupt particle id");
             if (cell) { cell[i] = cx[j]; cell[n + i] = cy[j]; }
             if (species) species[i] = sp[j];
             if (off) { off[i] = f[0 * c + j]; off[n + i] = f[1 * c + j]; }
@@ -490,7 +520,6 @@ gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t b
     ev->dtau = desc->dtau_over_a;
     ev->stream = (hipStream_t)stream;
     ev->ws = (char *)workspace;
-    for (int k = 0; k <= kMaxSpecies; k++) ev->block_start_host[k] = 0;
     *out = ev;
     return GL_OK;
 }
@@ -547,15 +576,16 @@ gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uin
     gl_status s = fill_species(ev, sp, si);
     if (s) return s;
     si.n = n;
-    si.slot0 = ev->slots_used;
-    si.cap = (n + kPushBlock - 1) / kPushBlock * kPushBlock;
-    if (si.slot0 + si.cap > ev->L.slots) return fail(GL_ENOMEM, "particle capacity exceeded");
+    const int64_t slot0 = total_particles(ev);   // valid particles occupy [0, total) (padding sorts last)
+    const int64_t end = (slot0 + n + kPushBlock - 1) / kPushBlock * kPushBlock;
+    if (end > ev->L.slots) return fail(GL_ENOMEM, "particle capacity exceeded");
     int sid = (int)ev->species.size();
     ev->species.push_back(si);
-    ev->slots_used += si.cap;
-    s = ev->fp64() ? init_particles<double>(ev, si, sid, seed) : init_particles<float>(ev, si, sid, seed);
+    ev->slots_used = end;
+    s = ev->fp64() ? init_particles<double>(ev, si, sid, seed, slot0, end)
+                   : init_particles<float>(ev, si, sid, seed, slot0, end);
     if (s) return s;
-    s = upload_block_start(ev);
+    s = sort_particles(ev);
     if (s) return s;
     if (species_id) *species_id = sid;
     return GL_OK;
@@ -758,6 +788,7 @@ gl_status gl_get_state(gl_event *ev, double *U, double *E, double *phi, double *
 gl_status gl_get_site_fields(gl_event *ev, double *F) {
     if (check_ev(ev) || !F) return fail(GL_EINVAL, "null argument");
     if (ev->slots_used == 0) return fail(GL_ESTATE, "site fields are only computed when the event has particles");
+    // the first 48 planes are [6][8][n2]
     return ev->fp64() ? copy_out<double>(ev, F, ev->ws + ev->L.F, 48 * ev->n2)
                       : copy_out<float>(ev, F, ev->ws + ev->L.F, 48 * ev->n2);
 }
@@ -772,21 +803,17 @@ gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_des
     std::vector<int64_t> count(n_species, 0);
     for (int64_t i = 0; i < n; i++) {
         if (species[i] < 0 || species[i] >= n_species) return fail(GL_EINVAL, "species id out of range");
-        if (i > 0 && species[i] < species[i - 1]) return fail(GL_EINVAL, "particles must be grouped by species");
         if (cell[i] < 0 || cell[i] >= ev->N || cell[n + i] < 0 || cell[n + i] >= ev->N)
             return fail(GL_EINVAL, "cell out of range");
         count[species[i]]++;
     }
     std::vector<SpeciesInfo> tab;
-    int64_t used = 0;
+    const int64_t used = (n + kPushBlock - 1) / kPushBlock * kPushBlock;
     for (int s = 0; s < n_species; s++) {
         SpeciesInfo si;
         gl_status st = fill_species(ev, &sp[s], si);
         if (st) return st;
         si.n = count[s];
-        si.slot0 = used;
-        si.cap = (count[s] + kPushBlock - 1) / kPushBlock * kPushBlock;
-        used += si.cap;
         tab.push_back(si);
     }
     if (used > ev->L.slots) return fail(GL_ENOMEM, "particle capacity exceeded");
@@ -795,7 +822,14 @@ gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_des
     gl_status s = ev->fp64() ? set_particles_t<double>(ev, n, cell, off, eta, p, Q, p0, species)
                              : set_particles_t<float>(ev, n, cell, off, eta, p, Q, p0, species);
     if (s) return s;
-    return upload_block_start(ev);
+    return sort_particles(ev);
+}
+
+gl_status gl_set_sort_period(gl_event *ev, int32_t every) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (every < 0) return fail(GL_EINVAL, "sort period must be >= 0");
+    ev->sort_every = every;
+    return GL_OK;
 }
 
 gl_status gl_get_particles(gl_event *ev, int64_t cap, int64_t *n, int32_t *cell, double *off, double *eta,

@@ -27,6 +27,11 @@ namespace gl {
 
 constexpr int TX = 32, TY = 8;
 
+template <typename T>
+__device__ __forceinline__ void store_rec(T *__restrict__ F, size_t n2, size_t x, int slot, const T *v) {
+    store_a(F + (size_t)slot * n2, n2, x, v);
+}
+
 struct Nbr {
     size_t x, xp1, xm1, xp2, xm2, xp1m2, xm1p2, xm1m2;
 };
@@ -190,7 +195,10 @@ k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T tau, T dtau, T tau_h, i
 // Local-frame site fields at tau_n (NGP reading of the colored particle-in-cell
 // coupling): E_i from the time- and link-averaged E_i, E_z = pi averaged in
 // time, B_x = -D_2 phi / tau, B_y = D_1 phi / tau (central, covariant), and
-// B_z = -(clover of the four plaquettes at x).  Written as F [6][8][n2].
+// B_z = -(clover of the four plaquettes at x).  Written as planes
+// F [56][n2] = (Ex, Ey, Ez, Bx, By, Bz, phi^n) x 8 components (coalesced
+// stores); the particles are kept sorted by cell so that their gathers from
+// these planes are coalesced too.
 template <typename T>
 __global__ void __launch_bounds__(TX *TY)
 k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) {
@@ -221,7 +229,7 @@ k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) 
         transport_dn(um, herm_from_alg(cm), t);
 #pragma unroll
         for (int k = 0; k < 8; k++) out[k] = T(0.5) * inv_tau * (c[k] + t[k]);
-        store_a(F + (size_t)(8 * d) * n2, n2, nb.x, out);
+        store_rec(F, n2, nb.x, 8 * d, out);
     }
     {
         T a[8], b[8];
@@ -229,7 +237,7 @@ k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) 
         load_a(nw.pi, n2, nb.x, b);
 #pragma unroll
         for (int k = 0; k < 8; k++) out[k] = T(0.5) * (a[k] + b[k]);
-        store_a(F + (size_t)16 * n2, n2, nb.x, out);
+        store_rec(F, n2, nb.x, 16, out);
     }
     // magnetic from phi: D_i phi = 1/2 (Phi_{+i} - Phi_{-i})
     M3<T> u1x = load_m(U1, n2, nb.x), u2x = load_m(U2, n2, nb.x);
@@ -249,7 +257,7 @@ k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) 
         T sgn = d == 0 ? T(0.5) : T(-0.5);
 #pragma unroll
         for (int k = 0; k < 8; k++) out[k] = sgn * inv_tau * dphi[k];
-        store_a(F + (size_t)(8 * (d == 0 ? 4 : 3)) * n2, n2, nb.x, out);
+        store_rec(F, n2, nb.x, 8 * (d == 0 ? 4 : 3), out);
     }
     // clover
     T cl[8];
@@ -287,7 +295,9 @@ k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) 
     }
 #pragma unroll
     for (int k = 0; k < 8; k++) out[k] = T(-0.25) * cl[k];
-    store_a(F + (size_t)40 * n2, n2, nb.x, out);
+    store_rec(F, n2, nb.x, 40, out);
+    load_a(o.phi, n2, nb.x, out);
+    store_rec(F, n2, nb.x, 48, out);
 }
 
 // Diagnostics per site, reduced per workgroup in FP64:

@@ -7,7 +7,8 @@
 namespace gl {
 
 constexpr int kMaxSpecies = 16;
-constexpr int kPushBlock = 256;   // particles per push workgroup; species are padded to it
+constexpr int kPushBlock = 256;   // particles per push workgroup
+constexpr int kSiteRec = 56;      // site-field planes: Ex, Ey, Ez, Bx, By, Bz, phi (8 reals each)
 
 // One field state in structure-of-arrays planes of n2 = N*N values:
 //   U   [2][18][n2], E [2][8][n2], phi [8][n2], pi [8][n2]
@@ -31,6 +32,19 @@ struct PartPtrs {
     int64_t cap;
 };
 
+// radix-sort scratch: double-buffered keys and values, per-(digit, tile)
+// counts and per-digit totals
+struct SortScratch {
+    uint32_t *keys[2];
+    int32_t *vals[2];
+    uint32_t *counts;
+    uint32_t *totals;
+};
+int64_t sort_tiles(int64_t n);
+template <typename T>
+hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtrs<T> dst, int64_t n,
+                                 SortScratch s, int32_t *id_src, int32_t *id_dst);
+
 template <typename T>
 struct SpeciesTab {
     T mass[kMaxSpecies];
@@ -46,9 +60,11 @@ hipError_t launch_site_fields(hipStream_t st, int N, FieldPtrs<T> old_, FieldPtr
                               T *F, double tau);
 template <typename T>
 hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
-                       const T *F, SpeciesTab<T> tab, int n, double dtau, double *partials);
-hipError_t launch_series_reduce(hipStream_t st, const double *partials, const int32_t *block_start,
-                                int n_species, double *row);
+                       const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
+                       double *partials);
+hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, int32_t base);
+hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
+                                double *row);
 template <typename T>
 hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
                        int *n_blocks_out);

@@ -1,7 +1,9 @@
 // particles.hip -- colored particles in the Glasma: initialisation, the push
 // of Wong's equations (Eq. (2)) and the FP64 momentum-broadening sums.
 //
-// Push (one thread per particle, reading the site fields F^n of its cell):
+// Push (one thread per particle, reading the site-field planes F^n at its
+// cell: the six local-frame fields and phi^n; the particles are kept sorted by
+// cell so that a wave's gathers hit neighbouring addresses):
 //   e_k = Q^a E_k^a, b_k = Q^a B_k^a in the local frame at tau_n
 //   Boris kick of dp/dtau = e + v x b on (p_x, p_y, P_eta/tau_n), P_eta = tau^2 p^eta
 //   drift with velocities at tau_{n+1/2}; rapidity step d_eta
@@ -11,9 +13,9 @@
 //   Wilson line of the colored-particle-in-cell method, which conserves the
 //   Casimirs of Q.
 //   broadening at tau_{n+1/2}: dp_x^2, dp_y^2 and the lab-frame dp_z^2.
-// Each workgroup holds particles of one species (the runtime pads species to
-// kPushBlock) and writes one FP64 partial row; a second kernel sums the rows
-// of each species in a fixed order, so the series is deterministic.
+// Each workgroup writes one FP64 partial row per species; a second kernel
+// sums the rows of each species in a fixed order, so the series is
+// deterministic for a given particle order.
 #include "internal.hpp"
 #include "philox.hpp"
 #include "su3.hpp"
@@ -23,7 +25,7 @@ namespace gl {
 template <typename T>
 __global__ void __launch_bounds__(kPushBlock)
 k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restrict__ F,
-       SpeciesTab<T> tab, int n, T dtau, double *__restrict__ partials) {
+       SpeciesTab<T> tab, int n_species, int n, T dtau, double *__restrict__ partials) {
     const int64_t i = (int64_t)blockIdx.x * kPushBlock + threadIdx.x;
     const size_t n2 = (size_t)N * N;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -78,7 +80,8 @@ k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restric
         M3<T> Qm = herm_from_alg(q);
         {
             T ph[8];
-            load_a(f.phi, n2, x, ph);
+#pragma unroll
+            for (int a = 0; a < 8; a++) ph[a] = F[(size_t)(48 + a) * n2 + x];
             M3<T> W = expi_alg(ph, -deta);
             Qm = mul_nd(mul(W, Qm), W);
         }
@@ -127,38 +130,47 @@ k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restric
         acc[2] = pzlab * pzlab - z0 * z0;
         acc[3] = 1.0;
     }
-    // workgroup reduction: wave64 butterflies, then across the four waves
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    // per-species workgroup reduction (particles of several species share a
+    // workgroup once they are sorted by cell): for each species, wave64
+    // butterflies, then the four waves in order -- a fixed order, so the
+    // partial sums are deterministic
     __shared__ double red[kPushBlock / 64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
+    for (int sp = 0; sp < n_species; sp++) {
+        double v[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) red[wave][k] = acc[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        double v = 0.0;
+        for (int k = 0; k < 4; k++) v[k] = s == sp ? acc[k] : 0.0;
 #pragma unroll
-        for (int w = 0; w < kPushBlock / 64; w++) v += red[w][threadIdx.x];
-        partials[(size_t)blockIdx.x * 4 + threadIdx.x] = v;
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[wave][k] = v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kPushBlock / 64; w++) t += red[w][threadIdx.x];
+            partials[((size_t)blockIdx.x * n_species + sp) * 4 + threadIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 
-// series row [kMaxSpecies][4]: species s sums partial rows
-// [block_start[s], block_start[s+1]) in a fixed order.
+// series row [kMaxSpecies][4]: species s sums the partial rows of all push
+// workgroups in a fixed order.
 __global__ void __launch_bounds__(256)
-k_series_reduce(const double *__restrict__ partials, const int32_t *__restrict__ block_start,
-                int n_species, double *__restrict__ row) {
+k_series_reduce(const double *__restrict__ partials, int n_blocks, int n_species,
+                double *__restrict__ row) {
     const int s = blockIdx.x;
     __shared__ double red[256][4];
     double acc[4] = {0, 0, 0, 0};
     if (s < n_species) {
-        for (int b = block_start[s] + threadIdx.x; b < block_start[s + 1]; b += 256)
+        for (int b = threadIdx.x; b < n_blocks; b += 256)
 #pragma unroll
-            for (int k = 0; k < 4; k++) acc[k] += partials[(size_t)b * 4 + k];
+            for (int k = 0; k < 4; k++) acc[k] += partials[((size_t)b * n_species + s) * 4 + k];
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) red[threadIdx.x][k] = acc[k];
@@ -303,19 +315,31 @@ hipError_t launch_casimir(hipStream_t st, PartPtrs<T> p, int64_t n_slots, double
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
-                       const T *F, SpeciesTab<T> tab, int n, double dtau, double *partials) {
-    if (n_slots <= 0) return hipSuccess;
-    unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
-    hipLaunchKernelGGL(k_push<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, n_slots, f, F, tab,
-                       n, (T)dtau, partials);
+__global__ void __launch_bounds__(256)
+k_iota(int32_t *__restrict__ id, int64_t n, int64_t n_valid, int32_t base) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) id[i] = i < n_valid ? base + (int32_t)i : -1;
+}
+
+hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, int32_t base) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, id, n, n_valid, base);
     return hipGetLastError();
 }
 
-hipError_t launch_series_reduce(hipStream_t st, const double *partials, const int32_t *block_start,
-                                int n_species, double *row) {
-    hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies), dim3(256), 0, st, partials, block_start,
+template <typename T>
+hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
+                       const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau, double *partials) {
+    if (n_slots <= 0) return hipSuccess;
+    unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
+    hipLaunchKernelGGL(k_push<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, n_slots, f, F, tab,
+                       n_species, n, (T)dtau, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
+                                double *row) {
+    hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies), dim3(256), 0, st, partials, n_blocks,
                        n_species, row);
     return hipGetLastError();
 }
@@ -332,7 +356,7 @@ hipError_t launch_particles_init(hipStream_t st, int N, PartPtrs<T> p, int64_t s
 
 #define GL_INST(T)                                                                               \
     template hipError_t launch_push<T>(hipStream_t, int, PartPtrs<T>, int64_t, FieldPtrs<T>,      \
-                                       const T *, SpeciesTab<T>, int, double, double *);         \
+                                       const T *, SpeciesTab<T>, int, int, double, double *);    \
     template hipError_t launch_particles_init<T>(hipStream_t, int, PartPtrs<T>, int64_t, int64_t, \
                                                  uint64_t, int, int, double);                    \
     template hipError_t launch_casimir<T>(hipStream_t, PartPtrs<T>, int64_t, double *, int *);

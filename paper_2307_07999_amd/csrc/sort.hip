@@ -1,0 +1,184 @@
+// sort.hip -- keeps the particle arrays ordered by cell so that the particles
+// of one workgroup gather site fields of neighbouring cells (a few cache
+// lines per plane per wave, L2 reuse).  Stable LSD radix sort on 20-bit cell
+// keys (padding slots get 0xFFFFF and stay at the end), three 8-bit digit
+// passes, deterministic: counts per (digit, workgroup), a per-digit scan over
+// workgroups, and a stable scatter whose in-workgroup ranks come from wave64
+// ballots.
+#include "internal.hpp"
+
+namespace gl {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 4;                              // keys per thread
+constexpr int kSortTile = kSortThreads * kSortItems;       // keys per workgroup
+constexpr int kDigits = 256;
+
+int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_keys(PartPtrs<T> P, int64_t n, int N, uint32_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = P.species[i] >= 0 ? (uint32_t)(P.cx[i] + N * P.cy[i]) : 0xFFFFFu;
+    vals[i] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_count(const uint32_t *__restrict__ keys, int64_t n, int shift, int64_t tiles,
+              uint32_t *__restrict__ counts) {
+    __shared__ uint32_t h[kDigits];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) {
+        int64_t i = base + k;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    counts[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// per digit d (one workgroup each): exclusive scan of counts[d][0..tiles) in
+// place, and the digit's total
+__global__ void __launch_bounds__(256)
+k_scan_rows(uint32_t *__restrict__ counts, int64_t tiles, uint32_t *__restrict__ totals) {
+    __shared__ uint32_t part[256];
+    const int t = threadIdx.x;
+    uint32_t *row = counts + (size_t)blockIdx.x * tiles;
+    int64_t chunk = (tiles + 255) / 256;
+    int64_t lo = t * chunk, hi = lo + chunk < tiles ? lo + chunk : tiles;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; i++) s += row[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+    for (int64_t i = lo; i < hi; i++) {
+        uint32_t v = row[i];
+        row[i] = run;
+        run += v;
+    }
+    if (t == 255) totals[blockIdx.x] = part[255];
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n,
+                int shift, int64_t tiles, const uint32_t *__restrict__ offs,
+                const uint32_t *__restrict__ totals, uint32_t *__restrict__ kout,
+                int32_t *__restrict__ vout) {
+    __shared__ uint32_t wcount[kSortThreads / 64][kDigits];
+    __shared__ uint32_t running[kDigits];
+    __shared__ uint32_t gstart[kDigits];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    // exclusive scan of the digit totals gives each digit's base
+    gstart[t] = totals[t];
+    __syncthreads();
+    for (int off = 1; off < kDigits; off <<= 1) {
+        uint32_t v = t >= off ? gstart[t - off] : 0u;
+        __syncthreads();
+        gstart[t] += v;
+        __syncthreads();
+    }
+    uint32_t base = (t > 0 ? gstart[t - 1] : 0u) + offs[(size_t)t * tiles + blockIdx.x];
+    __syncthreads();
+    gstart[t] = base;
+    running[t] = 0;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kSortItems; r++) {
+#pragma unroll
+        for (int w = 0; w < kSortThreads / 64; w++) wcount[w][t] = 0;
+        __syncthreads();
+        int64_t i = (int64_t)blockIdx.x * kSortTile + (int64_t)r * kSortThreads + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        uint32_t d = (key >> shift) & 0xFF;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t m = __ballot(valid && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t before = running[d];
+            for (int w = 0; w < wave; w++) before += wcount[w][d];
+            uint32_t pos = gstart[d] + before + rank;
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kSortThreads / 64; w++) add += wcount[w][t];
+        running[t] += add;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_permute(PartPtrs<T> src, PartPtrs<T> dst, const int32_t *__restrict__ perm, int64_t n,
+          int32_t *__restrict__ id_src, int32_t *__restrict__ id_dst) {
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    int64_t i = perm[j];
+    dst.cx[j] = src.cx[i];
+    dst.cy[j] = src.cy[i];
+    dst.species[j] = src.species[i];
+    dst.ox[j] = src.ox[i];
+    dst.oy[j] = src.oy[i];
+    dst.eta[j] = src.eta[i];
+    dst.px[j] = src.px[i];
+    dst.py[j] = src.py[i];
+    dst.peta[j] = src.peta[i];
+    dst.px0[j] = src.px0[i];
+    dst.py0[j] = src.py0[i];
+    dst.pz0[j] = src.pz0[i];
+#pragma unroll
+    for (int a = 0; a < 8; a++) dst.Q[(size_t)a * dst.cap + j] = src.Q[(size_t)a * src.cap + i];
+    id_dst[j] = id_src[i];
+}
+
+template <typename T>
+hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtrs<T> dst, int64_t n,
+                                 SortScratch s, int32_t *id_src, int32_t *id_dst) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = sort_tiles(n);
+    unsigned b256 = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_sort_keys<T>, dim3(b256), dim3(256), 0, st, src, n, N, s.keys[0], s.vals[0]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    for (int pass = 0; pass < 3; pass++) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, s.keys[cur], n,
+                           shift, tiles, s.counts);
+        hipLaunchKernelGGL(k_scan_rows, dim3(kDigits), dim3(256), 0, st, s.counts, tiles, s.totals);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, s.keys[cur],
+                           s.vals[cur], n, shift, tiles, s.counts, s.totals, s.keys[cur ^ 1],
+                           s.vals[cur ^ 1]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_permute<T>, dim3(b256), dim3(256), 0, st, src, dst, s.vals[cur], n, id_src, id_dst);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sort_particles<double>(hipStream_t, int, PartPtrs<double>, PartPtrs<double>,
+                                                  int64_t, SortScratch, int32_t *, int32_t *);
+template hipError_t launch_sort_particles<float>(hipStream_t, int, PartPtrs<float>, PartPtrs<float>,
+                                                 int64_t, SortScratch, int32_t *, int32_t *);
+
+}  // namespace gl

@@ -80,6 +80,7 @@ _SIGS = {
     "gl_sync": [_VP],
     "gl_profile_enable": [_VP, ctypes.c_int32],
     "gl_profile_read": [_VP, _D, _I64],
+    "gl_set_sort_period": [_VP, ctypes.c_int32],
 }
 
 _lib = None
@@ -303,6 +304,9 @@ class Event:
         rho = np.zeros((8, self.n2))
         check(lib().gl_draw_charges(self._h, seed, nucleus, sheet, sigma, _d(rho)))
         return rho
+
+    def set_sort_period(self, every):
+        return check(lib().gl_set_sort_period(self._h, every))
 
     def profile(self, on=True):
         return check(lib().gl_profile_enable(self._h, 1 if on else 0))

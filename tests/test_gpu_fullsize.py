@@ -1,0 +1,90 @@
+"""Parity at the paper-scale size (512^2, L = 10 fm, 7 x 1e5 particles) in the
+launch configuration the benchmark times, on outputs the oracle computes one
+by one: sampled sites of one field step (with site fields) and sampled
+particles of one push.  Sample sites include the lattice edges and corners."""
+import numpy as np
+import pytest
+
+from tests import gpu_helpers as H
+from tests import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+N, L = 512, 10.0
+HB = 0.1973269804
+
+
+@pytest.fixture(scope="module")
+def gl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_07999_amd as g
+    g.lib()
+    return g
+
+
+def _sites(seed, k):
+    g = np.random.default_rng(seed)
+    edge = [0, N - 1, N * (N - 1), N * N - 1, N // 2, N * 7 + N - 1, N * (N - 1) + 5]
+    return np.array(sorted(set(edge) | set(g.integers(0, N * N, k).tolist())), np.int32)
+
+
+SPECIES = [(1.27, 0.0, 0), (1.27, 2.0, 0), (1.27, 5.0, 0), (4.18, 0.0, 0), (4.18, 2.0, 0),
+           (4.18, 5.0, 0), (0.0, 10.0, 1)]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_field_step_and_site_fields_sampled(gl, orc, prec):
+    U, E, phi, pi = si.random_state(512, N, link_kind="near", eps=0.3, e_scale=0.1,
+                                    phi_scale=0.1, pi_scale=0.1)
+    s = orc.State(N)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
+    ev = gl.Event(N, L, 0.125, precision=prec, max_steps=64, max_particles=1000)
+    ev.set_state(*H.state_oracle_to_soa(s), 40)
+    ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 1000, 3)     # so that site fields are made
+    ev.evolve_fields(1)
+    Ug, Eg, phig, pig, n = ev.get_state()
+    Fg = ev.site_fields()
+    sites = _sites(prec, 300)
+    Un, En, phin, pin, F = orc.field_step_sites(s, 0.125, sites)
+    tol = 1e-12 if prec == 64 else 2e-5
+    assert np.abs(Ug[:, :, sites] - np.transpose(Un, (1, 2, 0))).max() < tol
+    assert np.abs(Eg[:, :, sites] - np.transpose(En, (1, 2, 0))).max() < tol
+    assert np.abs(phig[:, sites] - phin.T).max() < tol
+    assert np.abs(pig[:, sites] - pin.T).max() < tol
+    scale = max(1.0, np.abs(F).max())
+    assert np.abs(Fg[:, :, sites] - np.transpose(F, (1, 2, 0))).max() < tol * scale
+
+
+def test_push_sampled_paper_scale(gl, orc):
+    """One coupled step of the 7 x 1e5 ensemble on 512^2 (FP64); 3000
+    particles of all species recomputed by the oracle."""
+    U, E, phi, pi = si.random_state(513, N, link_kind="near", eps=0.3, e_scale=0.1,
+                                    phi_scale=0.1, pi_scale=0.1)
+    s = orc.State(N)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
+    ev = gl.Event(N, L, 0.125, precision=64, max_steps=64, max_particles=700000)
+    ev.set_state(*H.state_oracle_to_soa(s), 40)
+    for k, (m, p0, kind) in enumerate(SPECIES):
+        ev.add_species(m, p0, kind, 100000, 1000 + k)
+    before = ev.get_particles()
+    mass = [ev.species_info(k)[1] for k in range(len(SPECIES))]
+    nform = [ev.species_info(k)[0] for k in range(len(SPECIES))]
+    assert max(nform) <= 40
+    ev.evolve_fields(1)
+    ev.push_particles()
+    after = ev.get_particles()
+    g = np.random.default_rng(5)
+    pick = np.sort(g.choice(700000, 3000, replace=False))
+    P = H.particles_gpu_to_oracle(orc, before).subset(pick)
+    cells = np.unique(P.cell[:, 0] + N * P.cell[:, 1]).astype(np.int32)
+    _, _, _, _, Fs = orc.field_step_sites(s, 0.125, cells)
+    Ffull = np.zeros((N * N, 6, 8))
+    Ffull[cells] = Fs
+    ser = orc.particle_step(N, 40, 0.125, s.U, s.phi, Ffull, P, mass, nform)
+    A = H.particles_gpu_to_oracle(orc, after).subset(pick)
+    assert np.array_equal(A.cell, P.cell)
+    for k in ("off", "eta", "p", "Q"):
+        assert np.abs(getattr(A, k) - getattr(P, k)).max() < 1e-12, k
+    assert ser[:, 3].sum() == 3000

@@ -250,3 +250,29 @@ def test_call_order_errors(gl):
         ev.evolve_fields(1)
     ev.push_particles()
     ev.run(3)
+
+
+def test_particle_sort_is_transparent_and_deterministic(gl, orc):
+    """Re-sorting particles by cell changes only their storage order: the
+    particles returned in creation order and the series are the same with
+    sorting every step, every 16 steps, and never, up to FP64 summation order,
+    and two identical runs are bitwise equal."""
+    N = 32
+    results = []
+    for every in (1, 16, 0, 1):
+        ev = _event(gl, N, 4.0, max_particles=3000, max_steps=40)
+        ev.set_sort_period(every)
+        ev.init_glasma(1.0, 0.2, 1, 7)
+        ev.add_species(1.27, 5.0, gl.KIND_HEAVY_QUARK, 1000, 7)
+        ev.add_species(0.0, 10.0, gl.KIND_JET, 1500, 8)
+        ev.run(40)
+        results.append((ev.get_particles(), ev.series()))
+    ref_p, ref_s = results[0]
+    for parts, ser in results[1:]:
+        assert np.array_equal(parts["cell"], ref_p["cell"])
+        for k in ("off", "p", "Q", "eta"):
+            assert np.abs(parts[k] - ref_p[k]).max() < 1e-13
+        assert H.rel_err(ser, ref_s) < 1e-13
+    # identical configuration -> bitwise identical series and particles
+    assert np.array_equal(results[3][1], results[0][1])
+    assert np.array_equal(results[3][0]["p"], results[0][0]["p"])
