@@ -207,6 +207,38 @@ gl_status gl_event_info(gl_event *ev, double *a_fm, double *dtau_lat, int64_t *n
 /* Block until the event's stream is idle. */
 gl_status gl_sync(gl_event *ev);
 
+/* ---- batches of events (many uneven events in one launch per phase) ------
+ * A batch steps events of equal precision, dtau and step index in lock-step
+ * with flattened multi-event kernels: one launch per phase walks a table of
+ * (event, tile) or (event, particle block) work items.  The step loop is
+ * captured once into a hipGraph (graph_steps steps, default 32 = two particle
+ * sort periods, so that the ping-pong parities return) and replayed; steps
+ * that do not fill a graph run as ordinary launches.  The batch snapshots the
+ * events: do not add particles to or step its events individually while the
+ * batch exists (gl_batch_run keeps their step index, buffers and series up
+ * to date, so they can be read and used again afterwards).  The caller owns
+ * the batch workspace (gl_batch_required_bytes, 256-byte aligned). */
+typedef struct gl_batch gl_batch;
+gl_status gl_batch_required_bytes(gl_event *const *evs, int32_t n_events, size_t *bytes);
+gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspace, size_t bytes,
+                          void *stream, gl_batch **out);
+void gl_batch_destroy(gl_batch *b);
+/* Pick the field-kernel tile shape (0: 32x8, 1: 64x4, 2: 16x16) and the
+ * persistent grid (0: one workgroup per tile, k: k workgroups per compute
+ * unit) by timing the field phases on this batch (they are idempotent, so
+ * the state does not change), or read the choice from cache_json when it
+ * holds this batch's key (device, precision, lattice sizes, particle count);
+ * the choice is written back to cache_json.  cache_json may be NULL. */
+gl_status gl_batch_autotune(gl_batch *b, const char *cache_json);
+/* Set the configuration by hand (sort_every 0: never sort; graph_steps 0: no
+ * graph; graph_steps must be even and a multiple of 2*sort_every). */
+gl_status gl_batch_config(gl_batch *b, int32_t shape, int32_t grid_mult, int32_t sort_every,
+                          int32_t graph_steps);
+gl_status gl_batch_info(gl_batch *b, int32_t *shape, int32_t *tile_x, int32_t *tile_y,
+                        int32_t *grid_mult, int32_t *graph_steps);
+/* n_steps coupled steps of every event of the batch. */
+gl_status gl_batch_run(gl_batch *b, int32_t n_steps);
+
 const char *gl_status_string(gl_status s);
 const char *gl_last_error(void);
 

@@ -1,0 +1,36 @@
+// batch_internal.hpp -- device descriptors of a batch of events stepped in
+// lock-step by the flattened multi-event kernels (batch_kernels.hip).
+#pragma once
+#include "internal.hpp"
+
+namespace gl {
+
+template <typename T>
+struct BatchEv {
+    int N;
+    int reunit_every;
+    int n_species;
+    int max_steps;
+    int64_t n_slots;
+    FieldPtrs<T> f[2];     // f[p] and f[p ^ 1]: state at step n and at n + 1 for parity p
+    PartPtrs<T> P[2];      // particle buffers; the current one alternates at each sort
+    T *F;                  // site-field planes
+    double *partials;      // [n_slots / kPushBlock][n_species][4]
+    double *series;        // [max_steps][kMaxSpecies][4]
+    SpeciesTab<T> tab;
+};
+
+struct BatchCtl {
+    int64_t n;             // common step index of all events
+};
+
+constexpr int kBatchShapes = 3;   // field-kernel tiles 32x8, 64x4, 16x16
+
+template <typename T>
+hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs, const int2 *tiles, int64_t total,
+                               int fpar, const BatchCtl *ctl, double dtau, int grid, bool site_fields);
+template <typename T>
+hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *blocks, int64_t total, int fpar,
+                             int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events);
+
+}  // namespace gl

@@ -1,0 +1,160 @@
+// batch_kernels.hip -- many events of uneven lattice and ensemble size in one
+// launch per phase.  Work is flattened over events: the field phases walk a
+// table of (event, tile) entries, the push a table of (event, particle block)
+// entries.  Kernels are persistent: a grid sized to the chip walks its table
+// with a stride, and the table is split into eight contiguous chunks, one per
+// XCD (workgroup b runs on XCD b mod 8), so that neighbouring tiles of one
+// lattice share an XCD's L2.  The step index lives in device memory (the
+// batch control block), so one captured hipGraph of the step loop can be
+// replayed without changing kernel arguments.
+#include "batch_internal.hpp"
+#include "fields_dev.hpp"
+#include "push_dev.hpp"
+
+namespace gl {
+
+// First entry, stride and end of workgroup b's walk: the table is cut into
+// nx = 8 contiguous chunks; chunk x is shared by the workgroups b = x mod 8
+// (there are per = ceil((g - x) / 8) of them, j = b / 8 numbers them), so
+// every entry is visited by exactly one workgroup for any grid size g.
+__device__ __forceinline__ int64_t xcd_first(int64_t total, int64_t &stride, int64_t &end) {
+    const int64_t g = gridDim.x, b = blockIdx.x;
+    const int64_t nx = g >= 8 ? 8 : 1;
+    const int64_t x = b % nx, j = b / nx, per = (g - x + nx - 1) / nx;
+    const int64_t chunk = (total + nx - 1) / nx;
+    const int64_t lo = x * chunk;
+    end = lo + chunk < total ? lo + chunk : total;
+    stride = per;
+    return lo + j;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total, int fpar,
+              const BatchCtl *__restrict__ ctl, T dtau) {
+    const int64_t n = ctl->n;
+    const T tau = dtau * (T)n, tau_h = dtau * ((T)n + T(0.5));
+    int64_t stride, end;
+    for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
+        const int2 w = tiles[t];
+        const BatchEv<T> &e = evs[w.x];
+        const int tx = (e.N + TX - 1) / TX;
+        const int ix = (w.y % tx) * TX + threadIdx.x, iy = (w.y / tx) * TY + threadIdx.y;
+        if (ix < e.N && iy < e.N) {
+            int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
+            field_step_site<T>(e.N, e.f[fpar], e.f[fpar ^ 1], ix, iy, tau, dtau, tau_h, reunit);
+        }
+    }
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+k_batch_site_fields(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total,
+                    int fpar, const BatchCtl *__restrict__ ctl, T dtau) {
+    const T tau = dtau * (T)ctl->n;
+    int64_t stride, end;
+    for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
+        const int2 w = tiles[t];
+        const BatchEv<T> &e = evs[w.x];
+        if (e.n_species == 0) continue;
+        const int tx = (e.N + TX - 1) / TX;
+        const int ix = (w.y % tx) * TX + threadIdx.x, iy = (w.y / tx) * TY + threadIdx.y;
+        if (ix < e.N && iy < e.N) site_fields_site<T>(e.N, e.f[fpar], e.f[fpar ^ 1], e.F, ix, iy, tau);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPushBlock)
+k_batch_push(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks, int64_t total, int fpar,
+             int ppar, const BatchCtl *__restrict__ ctl, T dtau) {
+    const int n = (int)ctl->n;
+    int64_t stride, end;
+    for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
+        const int2 w = blocks[t];
+        const BatchEv<T> &e = evs[w.x];
+        const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int s = -1;
+        if (i < e.n_slots) s = push_particle<T>(e.N, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+        block_species_reduce(s, acc, e.n_species, e.partials + (size_t)w.y * e.n_species * 4);
+    }
+}
+
+// one workgroup per (event, species): fixed-order sum of the event's partial
+// rows into its series row n - 1, n taken from the control block
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_batch_reduce(const BatchEv<T> *__restrict__ evs, const BatchCtl *__restrict__ ctl) {
+    const BatchEv<T> &e = evs[blockIdx.x];
+    const int s = blockIdx.y;
+    if (s >= e.n_species) return;
+    const int64_t row = ctl->n - 1;
+    if (row < 0 || row >= e.max_steps) return;
+    const int nb = (int)(e.n_slots / kPushBlock);
+    __shared__ double red[256][4];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[k] += e.partials[((size_t)b * e.n_species + s) * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; k++) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) e.series[((size_t)row * kMaxSpecies + s) * 4 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ void k_batch_advance(BatchCtl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->n = ctl->n + 1;
+}
+
+template <typename T>
+hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs, const int2 *tiles, int64_t total,
+                               int fpar, const BatchCtl *ctl, double dtau, int grid, bool site_fields) {
+    if (total <= 0) return hipSuccess;
+    unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
+#define GL_SHAPE(TXv, TYv)                                                                                    \
+    {                                                                                                         \
+        hipLaunchKernelGGL((k_batch_field<T, TXv, TYv>), dim3(g), dim3(TXv, TYv), 0, st, evs, tiles, total,   \
+                           fpar, ctl, (T)dtau);                                                               \
+        if (site_fields)                                                                                      \
+            hipLaunchKernelGGL((k_batch_site_fields<T, TXv, TYv>), dim3(g), dim3(TXv, TYv), 0, st, evs, tiles, \
+                               total, fpar, ctl, (T)dtau);                                                    \
+    }
+    switch (shape) {
+        case 0: GL_SHAPE(32, 8) break;
+        case 1: GL_SHAPE(64, 4) break;
+        case 2: GL_SHAPE(16, 16) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GL_SHAPE
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *blocks, int64_t total, int fpar,
+                             int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events) {
+    if (total > 0) {
+        unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
+        hipLaunchKernelGGL(k_batch_push<T>, dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, fpar, ppar, ctl,
+                           (T)dtau);
+        hipLaunchKernelGGL(k_batch_reduce<T>, dim3(n_events, kMaxSpecies), dim3(256), 0, st, evs, ctl);
+    }
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, st, (BatchCtl *)ctl);
+    return hipGetLastError();
+}
+
+#define GL_INST(T)                                                                                          \
+    template hipError_t launch_batch_fields<T>(hipStream_t, int, const BatchEv<T> *, const int2 *, int64_t, int, \
+                                               const BatchCtl *, double, int, bool);                         \
+    template hipError_t launch_batch_push<T>(hipStream_t, const BatchEv<T> *, const int2 *, int64_t, int, int,  \
+                                             const BatchCtl *, double, int, int);
+GL_INST(double)
+GL_INST(float)
+#undef GL_INST
+
+}  // namespace gl

@@ -909,3 +909,439 @@ gl_status gl_sync(gl_event *ev) {
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Batches: many events stepped in lock-step by the flattened kernels of
+// batch_kernels.hip, the step loop captured once into a hipGraph.
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "batch_internal.hpp"
+
+struct gl_batch {
+    std::vector<gl_event *> evs;
+    std::vector<int> cur0, pbuf0;      // event buffers that parity 0 maps to
+    bool fp64 = true;
+    double dtau = 0.125;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t desc = 0, tiles[kBatchShapes] = {0, 0, 0}, pblocks = 0, ctl = 0;
+    int64_t total_tiles[kBatchShapes] = {0, 0, 0}, total_pblocks = 0;
+    int shape = 0, grid_mult = 4, cus = 256;
+    int fpar = 0, ppar = 0;
+    int64_t since_sort = 0;
+    int sort_every = 16;
+    int graph_steps = 32;             // two sort periods: both parities return
+    bool any_particles = false;
+    std::map<int, hipGraphExec_t> graphs;
+    std::map<int, hipGraph_t> graph_defs;
+};
+
+namespace {
+
+struct BatchSizes {
+    size_t desc, tiles[kBatchShapes], pblocks, ctl, total;
+    int64_t n_tiles[kBatchShapes], n_pblocks;
+};
+
+const int kShapeTX[kBatchShapes] = {32, 64, 16}, kShapeTY[kBatchShapes] = {8, 4, 16};
+
+gl_status batch_sizes(gl_event *const *evs, int n, BatchSizes &z) {
+    if (!evs || n < 1) return fail(GL_EINVAL, "empty batch");
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align256(off + b);
+        return o;
+    };
+    z.desc = take((size_t)n * std::max(sizeof(BatchEv<double>), sizeof(BatchEv<float>)));
+    for (int s = 0; s < kBatchShapes; s++) {
+        z.n_tiles[s] = 0;
+        for (int e = 0; e < n; e++) {
+            if (!evs[e]) return fail(GL_EINVAL, "null event in batch");
+            int N = evs[e]->N;
+            z.n_tiles[s] += (int64_t)((N + kShapeTX[s] - 1) / kShapeTX[s]) * ((N + kShapeTY[s] - 1) / kShapeTY[s]);
+        }
+        z.tiles[s] = take((size_t)z.n_tiles[s] * sizeof(int2));
+    }
+    z.n_pblocks = 0;
+    for (int e = 0; e < n; e++) z.n_pblocks += evs[e]->L.slots / kPushBlock;
+    z.pblocks = take((size_t)std::max<int64_t>(1, z.n_pblocks) * sizeof(int2));
+    z.ctl = take(sizeof(BatchCtl));
+    z.total = off;
+    return GL_OK;
+}
+
+template <typename T>
+BatchEv<T> batch_desc(const gl_batch *b, int e) {
+    gl_event *ev = b->evs[e];
+    BatchEv<T> d;
+    d.N = ev->N;
+    d.reunit_every = ev->fp64() ? 0 : ev->desc.reunit_every;
+    d.n_species = (int)ev->species.size();
+    d.max_steps = ev->desc.max_steps;
+    d.n_slots = ev->slots_used;
+    d.f[0] = ev->fields<T>(b->cur0[e]);
+    d.f[1] = ev->fields<T>(1 - b->cur0[e]);
+    d.P[0] = ev->parts<T>(b->pbuf0[e]);
+    d.P[1] = ev->parts<T>(1 - b->pbuf0[e]);
+    d.F = (T *)(ev->ws + ev->L.F);
+    d.partials = ev->partials();
+    d.series = ev->series();
+    d.tab = ev->tab<T>();
+    return d;
+}
+
+template <typename T>
+gl_status batch_step(gl_batch *b) {
+    const int grid = b->grid_mult > 0 ? b->grid_mult * b->cus : 0;
+    const BatchEv<T> *d = (const BatchEv<T> *)(b->ws + b->desc);
+    const BatchCtl *ctl = (const BatchCtl *)(b->ws + b->ctl);
+    HIP_TRY(launch_batch_fields<T>(b->stream, b->shape, d, (const int2 *)(b->ws + b->tiles[b->shape]),
+                                   b->total_tiles[b->shape], b->fpar, ctl, b->dtau, grid, b->any_particles));
+    HIP_TRY(launch_batch_push<T>(b->stream, d, (const int2 *)(b->ws + b->pblocks), b->total_pblocks, b->fpar,
+                                 b->ppar, ctl, b->dtau, grid, (int)b->evs.size()));
+    b->fpar ^= 1;
+    b->since_sort++;
+    if (b->any_particles && b->sort_every > 0 && b->since_sort >= b->sort_every) {
+        for (size_t e = 0; e < b->evs.size(); e++) {
+            gl_event *ev = b->evs[e];
+            if (ev->slots_used == 0) continue;
+            int src = b->pbuf0[e] ^ b->ppar;
+            HIP_TRY(launch_sort_particles<T>(b->stream, ev->N, ev->parts<T>(src), ev->parts<T>(1 - src),
+                                             ev->slots_used, ev->scratch(), ev->ids(src), ev->ids(1 - src)));
+        }
+        b->ppar ^= 1;
+        b->since_sort = 0;
+    }
+    return GL_OK;
+}
+
+gl_status batch_step_any(gl_batch *b) { return b->fp64 ? batch_step<double>(b) : batch_step<float>(b); }
+
+void batch_drop_graphs(gl_batch *b) {
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &g : b->graph_defs) (void)hipGraphDestroy(g.second);
+    b->graphs.clear();
+    b->graph_defs.clear();
+}
+
+// capture graph_steps steps starting at a sort boundary with parities (fpar, ppar)
+gl_status batch_graph(gl_batch *b, hipGraphExec_t *out) {
+    int key = b->fpar * 2 + b->ppar;
+    auto it = b->graphs.find(key);
+    if (it != b->graphs.end()) {
+        *out = it->second;
+        return GL_OK;
+    }
+    int f0 = b->fpar, p0 = b->ppar;
+    int64_t s0 = b->since_sort;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    gl_status st = GL_OK;
+    for (int k = 0; k < b->graph_steps && st == GL_OK; k++) st = batch_step_any(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    b->fpar = f0;
+    b->ppar = p0;
+    b->since_sort = s0;
+    if (st) return st;
+    if (e != hipSuccess) return fail(GL_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    HIP_TRY(hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+    b->graph_defs[key] = g;
+    b->graphs[key] = x;
+    *out = x;
+    return GL_OK;
+}
+
+std::string batch_key(const gl_batch *b) {
+    std::vector<int> Ns;
+    int64_t parts = 0;
+    for (auto *ev : b->evs) {
+        Ns.push_back(ev->N);
+        parts += total_particles(ev);
+    }
+    std::sort(Ns.begin(), Ns.end());
+    std::ostringstream k;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    k << arch << "|p" << (b->fp64 ? 64 : 32) << "|N";
+    for (int N : Ns) k << "," << N;
+    k << "|parts" << parts;
+    return k.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, int *shape, int *mult) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string s = ss.str(), pat = "\"" + key + "\": [";
+    size_t p = s.find(pat);
+    if (p == std::string::npos) return false;
+    return std::sscanf(s.c_str() + p + pat.size(), "%d, %d", shape, mult) == 2 && *shape >= 0 &&
+           *shape < kBatchShapes && *mult >= 0;
+}
+
+void cache_store(const char *path, const std::string &key, int shape, int mult) {
+    if (!path) return;
+    std::map<std::string, std::pair<int, int>> entries;
+    std::ifstream f(path);
+    if (f) {
+        std::string line;
+        while (std::getline(f, line)) {
+            size_t a = line.find('"'), bq = line.find("\": [");
+            if (a == std::string::npos || bq == std::string::npos) continue;
+            int s = 0, m = 0;
+            if (std::sscanf(line.c_str() + bq + 4, "%d, %d", &s, &m) == 2) entries[line.substr(a + 1, bq - a - 1)] = {s, m};
+        }
+    }
+    entries[key] = {shape, mult};
+    std::ofstream o(path);
+    o << "{\n";
+    size_t i = 0;
+    for (auto &kv : entries)
+        o << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+          << (++i < entries.size() ? "," : "") << "\n";
+    o << "}\n";
+}
+
+template <typename T>
+gl_status time_fields(gl_batch *b, int shape, int mult, float *ms) {
+    const int grid = mult > 0 ? mult * b->cus : 0;
+    const BatchEv<T> *d = (const BatchEv<T> *)(b->ws + b->desc);
+    const BatchCtl *ctl = (const BatchCtl *)(b->ws + b->ctl);
+    const int2 *tiles = (const int2 *)(b->ws + b->tiles[shape]);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    // the field phases read the state at parity fpar and only write the
+    // next-step buffer and the site fields: repeating them changes nothing
+    HIP_TRY(launch_batch_fields<T>(b->stream, shape, d, tiles, b->total_tiles[shape], b->fpar, ctl, b->dtau, grid,
+                                   b->any_particles));
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    const int reps = 3;
+    for (int r = 0; r < reps; r++)
+        HIP_TRY(launch_batch_fields<T>(b->stream, shape, d, tiles, b->total_tiles[shape], b->fpar, ctl, b->dtau,
+                                       grid, b->any_particles));
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    *ms /= reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return GL_OK;
+}
+
+// order the batch stream after the events' own streams (and the reverse at the end)
+gl_status batch_fence(gl_batch *b) {
+    for (auto *ev : b->evs)
+        if (ev->stream != b->stream) HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+void batch_sync_events(gl_batch *b, int64_t steps) {
+    for (size_t e = 0; e < b->evs.size(); e++) {
+        gl_event *ev = b->evs[e];
+        ev->cur = b->cur0[e] ^ b->fpar;
+        ev->pbuf = b->pbuf0[e] ^ b->ppar;
+        ev->n += steps;
+        if (ev->slots_used > 0) ev->rows = std::max<int64_t>(ev->rows, std::min<int64_t>(ev->n - 1, ev->desc.max_steps));
+        ev->since_sort = b->since_sort;
+        ev->push_due = false;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_batch_required_bytes(gl_event *const *evs, int32_t n_events, size_t *bytes) {
+    if (!bytes) return fail(GL_EINVAL, "null output");
+    BatchSizes z;
+    gl_status s = batch_sizes(evs, n_events, z);
+    if (s) return s;
+    *bytes = z.total;
+    return GL_OK;
+}
+
+gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspace, size_t bytes, void *stream,
+                          gl_batch **out) {
+    if (!out) return fail(GL_EINVAL, "null output");
+    *out = nullptr;
+    BatchSizes z;
+    gl_status s = batch_sizes(evs, n_events, z);
+    if (s) return s;
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(GL_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < z.total) return fail(GL_ENOMEM, "workspace smaller than gl_batch_required_bytes()");
+    gl_event *e0 = evs[0];
+    for (int e = 0; e < n_events; e++) {
+        gl_event *ev = evs[e];
+        if (!ev->ready) return fail(GL_ESTATE, "every event must be initialised");
+        if (ev->push_due) return fail(GL_ESTATE, "an event has a particle step due");
+        if (ev->desc.precision != e0->desc.precision || ev->dtau != e0->dtau || ev->n != e0->n)
+            return fail(GL_EINVAL, "events of a batch share precision, dtau and the step index");
+        for (int f = 0; f < e; f++)
+            if (evs[f] == ev) return fail(GL_EINVAL, "an event appears twice");
+    }
+    gl_batch *b = new (std::nothrow) gl_batch();
+    if (!b) return fail(GL_ENOMEM, "host allocation failed");
+    b->evs.assign(evs, evs + n_events);
+    b->fp64 = e0->fp64();
+    b->dtau = e0->dtau;
+    b->stream = (hipStream_t)stream;
+    b->ws = (char *)workspace;
+    b->desc = z.desc;
+    for (int k = 0; k < kBatchShapes; k++) {
+        b->tiles[k] = z.tiles[k];
+        b->total_tiles[k] = z.n_tiles[k];
+    }
+    b->pblocks = z.pblocks;
+    b->ctl = z.ctl;
+    for (auto *ev : b->evs) {
+        b->cur0.push_back(ev->cur);
+        b->pbuf0.push_back(ev->pbuf);
+        b->any_particles |= ev->slots_used > 0;
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        b->cus = cus;
+    // descriptors and work tables
+    std::vector<char> dbuf((size_t)n_events * std::max(sizeof(BatchEv<double>), sizeof(BatchEv<float>)));
+    for (int e = 0; e < n_events; e++) {
+        if (b->fp64) ((BatchEv<double> *)dbuf.data())[e] = batch_desc<double>(b, e);
+        else ((BatchEv<float> *)dbuf.data())[e] = batch_desc<float>(b, e);
+    }
+    auto cleanup = [&](gl_status st) {
+        delete b;
+        return st;
+    };
+    if (hipMemcpyAsync(b->ws + b->desc, dbuf.data(), dbuf.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return cleanup(fail(GL_EDEVICE, "descriptor upload failed"));
+    for (int k = 0; k < kBatchShapes; k++) {
+        std::vector<int2> t;
+        for (int e = 0; e < n_events; e++) {
+            int N = evs[e]->N, nt = ((N + kShapeTX[k] - 1) / kShapeTX[k]) * ((N + kShapeTY[k] - 1) / kShapeTY[k]);
+            for (int j = 0; j < nt; j++) t.push_back(make_int2(e, j));
+        }
+        if (!t.empty() && hipMemcpyAsync(b->ws + b->tiles[k], t.data(), t.size() * sizeof(int2),
+                                         hipMemcpyHostToDevice, b->stream) != hipSuccess)
+            return cleanup(fail(GL_EDEVICE, "tile table upload failed"));
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return cleanup(fail(GL_EDEVICE, "sync failed"));
+    }
+    std::vector<int2> pb;
+    for (int e = 0; e < n_events; e++)
+        for (int64_t j = 0; j < evs[e]->slots_used / kPushBlock; j++) pb.push_back(make_int2(e, (int)j));
+    b->total_pblocks = (int64_t)pb.size();
+    BatchCtl c;
+    c.n = e0->n;
+    if ((!pb.empty() && hipMemcpyAsync(b->ws + b->pblocks, pb.data(), pb.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                       b->stream) != hipSuccess) ||
+        hipMemcpyAsync(b->ws + b->ctl, &c, sizeof(c), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return cleanup(fail(GL_EDEVICE, "table upload failed"));
+    *out = b;
+    return GL_OK;
+}
+
+void gl_batch_destroy(gl_batch *b) {
+    if (!b) return;
+    batch_drop_graphs(b);
+    delete b;
+}
+
+gl_status gl_batch_autotune(gl_batch *b, const char *cache_json) {
+    if (!b) return fail(GL_EINVAL, "null batch");
+    gl_status fs = batch_fence(b);
+    if (fs) return fs;
+    std::string key = batch_key(b);
+    int shape = 0, mult = 0;
+    if (!cache_lookup(cache_json, key, &shape, &mult)) {
+        float best = 1e30f;
+        const int mults[] = {0, 2, 4, 8};
+        for (int s = 0; s < kBatchShapes; s++)
+            for (int m : mults) {
+                float ms = 0;
+                gl_status st = b->fp64 ? time_fields<double>(b, s, m, &ms) : time_fields<float>(b, s, m, &ms);
+                if (st) return st;
+                if (ms < best) {
+                    best = ms;
+                    shape = s;
+                    mult = m;
+                }
+            }
+        cache_store(cache_json, key, shape, mult);
+    }
+    if (shape != b->shape || mult != b->grid_mult) batch_drop_graphs(b);
+    b->shape = shape;
+    b->grid_mult = mult;
+    return GL_OK;
+}
+
+gl_status gl_batch_config(gl_batch *b, int32_t shape, int32_t grid_mult, int32_t sort_every, int32_t graph_steps) {
+    if (!b) return fail(GL_EINVAL, "null batch");
+    if (shape < 0 || shape >= kBatchShapes || grid_mult < 0 || sort_every < 0 || graph_steps < 0)
+        return fail(GL_EINVAL, "bad batch configuration");
+    if (graph_steps > 0 && sort_every > 0 && graph_steps % (2 * sort_every) != 0)
+        return fail(GL_EINVAL, "graph_steps must be a multiple of 2*sort_every");
+    if (graph_steps > 0 && graph_steps % 2 != 0) return fail(GL_EINVAL, "graph_steps must be even");
+    batch_drop_graphs(b);
+    b->shape = shape;
+    b->grid_mult = grid_mult;
+    b->sort_every = sort_every;
+    b->graph_steps = graph_steps;
+    return GL_OK;
+}
+
+gl_status gl_batch_info(gl_batch *b, int32_t *shape, int32_t *tile_x, int32_t *tile_y, int32_t *grid_mult,
+                        int32_t *graph_steps) {
+    if (!b) return fail(GL_EINVAL, "null batch");
+    if (shape) *shape = b->shape;
+    if (tile_x) *tile_x = kShapeTX[b->shape];
+    if (tile_y) *tile_y = kShapeTY[b->shape];
+    if (grid_mult) *grid_mult = b->grid_mult;
+    if (graph_steps) *graph_steps = b->graph_steps;
+    return GL_OK;
+}
+
+gl_status gl_batch_run(gl_batch *b, int32_t n_steps) {
+    if (!b) return fail(GL_EINVAL, "null batch");
+    if (n_steps < 0) return fail(GL_EINVAL, "n_steps must be >= 0");
+    for (auto *ev : b->evs)
+        if (ev->slots_used > 0 && ev->n - 1 + n_steps > ev->desc.max_steps)
+            return fail(GL_EINVAL, "series capacity (max_steps) too small for this run");
+    gl_status fs = batch_fence(b);
+    if (fs) return fs;
+    int64_t left = n_steps;
+    while (left > 0) {
+        bool aligned = b->since_sort == 0 || !b->any_particles || b->sort_every == 0;
+        if (b->graph_steps > 0 && aligned && left >= b->graph_steps) {
+            hipGraphExec_t g;
+            gl_status s = batch_graph(b, &g);
+            if (s) return s;
+            HIP_TRY(hipGraphLaunch(g, b->stream));
+            // a whole graph returns both parities to where they started
+            left -= b->graph_steps;
+            continue;
+        }
+        gl_status s = batch_step_any(b);
+        if (s) return s;
+        left--;
+    }
+    batch_sync_events(b, n_steps);
+    for (auto *ev : b->evs)
+        if (ev->stream != b->stream) {
+            HIP_TRY(hipStreamSynchronize(b->stream));
+            break;
+        }
+    return GL_OK;
+}
+
+}  // extern "C"

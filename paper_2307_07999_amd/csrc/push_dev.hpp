@@ -1,0 +1,154 @@
+// push_dev.hpp -- per-particle device function of the push of Wong's
+// equations and the per-species workgroup reduction, shared by the
+// single-event and the batched kernels.  The scheme is described in
+// particles.hip.
+#pragma once
+#include "internal.hpp"
+#include "su3.hpp"
+
+namespace gl {
+
+// one particle step of slot i (i < number of slots); returns the species of
+// an active particle (-1 otherwise) and its broadening terms in acc
+template <typename T>
+__device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const FieldPtrs<T> &f,
+                                             const T *__restrict__ F, const SpeciesTab<T> &tab, int n,
+                                             T dtau, double *acc) {
+    const size_t n2 = (size_t)N * N;
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+    int s = P.species[i];
+    if (s >= 0 && n >= tab.nform[s]) {
+        const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
+        const T m = tab.mass[s];
+        int cx = P.cx[i], cy = P.cy[i];
+        size_t x = (size_t)cx + (size_t)N * cy;
+        T q[8];
+#pragma unroll
+        for (int a = 0; a < 8; a++) q[a] = P.Q[(size_t)a * P.cap + i];
+        T e[3], b[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            T se = T(0), sb = T(0);
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                se = fma(q[a], F[(size_t)(8 * k + a) * n2 + x], se);
+                sb = fma(q[a], F[(size_t)(8 * (3 + k) + a) * n2 + x], sb);
+            }
+            e[k] = se;
+            b[k] = sb;
+        }
+        // Boris kick at tau_n
+        T pl[3] = {P.px[i], P.py[i], P.peta[i] / tau};
+        T pm[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) pm[k] = pl[k] + T(0.5) * dtau * e[k];
+        T g = sqrt(m * m + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2]);
+        T h = dtau / (T(2) * g);
+        T t[3] = {b[0] * h, b[1] * h, b[2] * h};
+        T t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+        T sf = T(2) / (T(1) + t2);
+        T sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
+        T pp[3] = {pm[0] + (pm[1] * t[2] - pm[2] * t[1]), pm[1] + (pm[2] * t[0] - pm[0] * t[2]),
+                   pm[2] + (pm[0] * t[1] - pm[1] * t[0])};
+        T pq[3] = {pm[0] + (pp[1] * sv[2] - pp[2] * sv[1]), pm[1] + (pp[2] * sv[0] - pp[0] * sv[2]),
+                   pm[2] + (pp[0] * sv[1] - pp[1] * sv[0])};
+#pragma unroll
+        for (int k = 0; k < 3; k++) pl[k] = pq[k] + T(0.5) * dtau * e[k];
+        const T peta = tau * pl[2];
+        // drift
+        const T pzh = peta / th;
+        const T ptau = sqrt(m * m + pl[0] * pl[0] + pl[1] * pl[1] + pzh * pzh);
+        T ox = P.ox[i] + dtau * pl[0] / ptau;
+        T oy = P.oy[i] + dtau * pl[1] / ptau;
+        const T deta = dtau * peta / (th * th * ptau);
+        const T eta_old = P.eta[i];
+        const T eta_new = eta_old + deta;
+        // color rotation along eta with phi^n at the old cell
+        M3<T> Qm = herm_from_alg(q);
+        {
+            T ph[8];
+#pragma unroll
+            for (int a = 0; a < 8; a++) ph[a] = F[(size_t)(48 + a) * n2 + x];
+            M3<T> W = expi_alg(ph, -deta);
+            Qm = mul_nd(mul(W, Qm), W);
+        }
+        // crossings, x first then y
+        if (ox >= T(0.5)) {
+            M3<T> u = load_m(f.U, n2, x);
+            Qm = mul(mul_dn(u, Qm), u);
+            ox -= T(1);
+            cx = cx + 1 == N ? 0 : cx + 1;
+        } else if (ox < T(-0.5)) {
+            int cm = cx == 0 ? N - 1 : cx - 1;
+            M3<T> u = load_m(f.U, n2, (size_t)cm + (size_t)N * cy);
+            Qm = mul_nd(mul(u, Qm), u);
+            ox += T(1);
+            cx = cm;
+        }
+        if (oy >= T(0.5)) {
+            M3<T> u = load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cy);
+            Qm = mul(mul_dn(u, Qm), u);
+            oy -= T(1);
+            cy = cy + 1 == N ? 0 : cy + 1;
+        } else if (oy < T(-0.5)) {
+            int cm = cy == 0 ? N - 1 : cy - 1;
+            M3<T> u = load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cm);
+            Qm = mul_nd(mul(u, Qm), u);
+            oy += T(1);
+            cy = cm;
+        }
+        alg_from_herm(Qm, q);
+        P.cx[i] = cx;
+        P.cy[i] = cy;
+        P.ox[i] = ox;
+        P.oy[i] = oy;
+        P.eta[i] = eta_new;
+        P.px[i] = pl[0];
+        P.py[i] = pl[1];
+        P.peta[i] = peta;
+#pragma unroll
+        for (int a = 0; a < 8; a++) P.Q[(size_t)a * P.cap + i] = q[a];
+        // broadening at tau_{n+1/2}, accumulated in FP64
+        const double etab = 0.5 * ((double)eta_old + (double)eta_new);
+        const double pzlab = (double)ptau * sinh(etab) + (double)pzh * cosh(etab);
+        const double x0 = P.px0[i], y0 = P.py0[i], z0 = P.pz0[i];
+        acc[0] = (double)pl[0] * pl[0] - x0 * x0;
+        acc[1] = (double)pl[1] * pl[1] - y0 * y0;
+        acc[2] = pzlab * pzlab - z0 * z0;
+        acc[3] = 1.0;
+    }
+    return s >= 0 && n >= tab.nform[s] ? s : -1;
+}
+
+// Per-species workgroup reduction of kPushBlock threads (particles of
+// several species share a workgroup once they are sorted by cell): for each
+// species, wave64 butterflies, then the four waves in order -- a fixed order,
+// so the partial sums are deterministic.  Writes out[sp * 4 + k].
+__device__ __forceinline__ void block_species_reduce(int s, const double *acc, int n_species,
+                                                     double *__restrict__ out) {
+    __shared__ double red[kPushBlock / 64][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int sp = 0; sp < n_species; sp++) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[k] = s == sp ? acc[k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[wave][k] = v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kPushBlock / 64; w++) t += red[w][threadIdx.x];
+            out[sp * 4 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace gl

@@ -81,6 +81,12 @@ _SIGS = {
     "gl_profile_enable": [_VP, ctypes.c_int32],
     "gl_profile_read": [_VP, _D, _I64],
     "gl_set_sort_period": [_VP, ctypes.c_int32],
+    "gl_batch_required_bytes": [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "gl_batch_create": [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)],
+    "gl_batch_autotune": [_VP, ctypes.c_char_p],
+    "gl_batch_config": [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "gl_batch_info": [_VP, _I32, _I32, _I32, _I32, _I32],
+    "gl_batch_run": [_VP, ctypes.c_int32],
 }
 
 _lib = None
@@ -100,6 +106,8 @@ def lib():
             fn.restype = ctypes.c_int32
         L.gl_event_destroy.argtypes = [_VP]
         L.gl_event_destroy.restype = None
+        L.gl_batch_destroy.argtypes = [_VP]
+        L.gl_batch_destroy.restype = None
         L.gl_status_string.argtypes = [ctypes.c_int32]
         L.gl_status_string.restype = ctypes.c_char_p
         L.gl_last_error.argtypes = []
@@ -324,3 +332,52 @@ class Event:
         n = ctypes.c_int64(0)
         check(lib().gl_event_info(self._h, ctypes.byref(a), ctypes.byref(dt), ctypes.byref(n)))
         return a.value, dt.value, n.value
+
+
+class Batch:
+    """Events stepped in lock-step by the flattened multi-event kernels, with
+    the step loop replayed from a captured hipGraph."""
+
+    def __init__(self, events, stream=None):
+        import torch
+        self.events = list(events)
+        arr = (_VP * len(self.events))(*[e._h for e in self.events])
+        self._arr = arr
+        nbytes = ctypes.c_size_t(0)
+        check(lib().gl_batch_required_bytes(arr, len(self.events), ctypes.byref(nbytes)))
+        dev = self.events[0].device
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        # a stream of its own (default priority): the legacy default stream
+        # cannot be captured into a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        h = _VP()
+        check(lib().gl_batch_create(arr, len(self.events), _VP(ptr), nbytes.value,
+                                    _VP(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def autotune(self, cache_json=None):
+        return check(lib().gl_batch_autotune(self._h, cache_json.encode() if cache_json else None))
+
+    def config(self, shape=0, grid_mult=4, sort_every=16, graph_steps=32):
+        return check(lib().gl_batch_config(self._h, shape, grid_mult, sort_every, graph_steps))
+
+    def info(self):
+        v = [ctypes.c_int32(0) for _ in range(5)]
+        check(lib().gl_batch_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(shape=v[0].value, tile=(v[1].value, v[2].value), grid_mult=v[3].value,
+                    graph_steps=v[4].value)
+
+    def run(self, n_steps):
+        return check(lib().gl_batch_run(self._h, n_steps))

@@ -1,0 +1,83 @@
+"""Batched events: the flattened multi-event kernels, replayed from a captured
+hipGraph, reproduce events run one by one bitwise (same per-site and
+per-particle arithmetic, same fixed-order reductions), for every tile shape
+and grid choice; the autotuner writes and then reads its cache."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(32, 700), (48, 300), (24, 0), (64, 1500)]
+
+
+@pytest.fixture(scope="module")
+def gl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_07999_amd as g
+    g.lib()
+    return g
+
+
+def _make(gl, prec, steps):
+    evs = []
+    for k, (N, npart) in enumerate(SIZES):
+        ev = gl.Event(N, N * 0.125, 0.125, precision=prec, max_steps=steps + 2,
+                      max_particles=max(npart, 1))
+        ev.init_glasma(1.0, 0.2, 1, 100 + k)
+        if npart:
+            ev.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, npart // 2, 200 + k)
+            ev.add_species(0.0, 10.0, gl.KIND_JET, npart - npart // 2, 300 + k)
+        evs.append(ev)
+    return evs
+
+
+@pytest.mark.parametrize("prec,shape,mult", [(64, 0, 4), (32, 1, 0), (64, 2, 2)])
+def test_batch_equals_single_events(gl, prec, shape, mult):
+    steps = 45          # one 32-step graph plus 13 ordinary steps
+    single = _make(gl, prec, steps)
+    for ev in single:
+        ev.run(steps)
+    batched = _make(gl, prec, steps)
+    b = gl.Batch(batched)
+    b.config(shape=shape, grid_mult=mult, sort_every=16, graph_steps=32)
+    b.run(steps)
+    for s, t, (N, npart) in zip(single, batched, SIZES):
+        Us, Es, phs, pis, ns = s.get_state()
+        Ub, Eb, phb, pib, nb = t.get_state()
+        assert ns == nb
+        for a, c in ((Us, Ub), (Es, Eb), (phs, phb), (pis, pib)):
+            assert np.array_equal(a, c)
+        if npart:
+            assert np.array_equal(s.series(), t.series())
+            ps, pb = s.get_particles(), t.get_particles()
+            for k in ("cell", "p", "Q"):
+                assert np.array_equal(ps[k], pb[k])
+    # the events keep working on their own after the batch
+    for t, (N, npart) in zip(batched, SIZES):
+        if npart:
+            t.evolve_fields(1)
+            t.push_particles()
+
+
+def test_autotune_cache_roundtrip(gl, tmp_path):
+    evs = _make(gl, 32, 4)
+    b = gl.Batch(evs)
+    path = str(tmp_path / "tune.json")
+    b.autotune(path)
+    first = b.info()
+    data = json.load(open(path))
+    assert len(data) == 1
+    (key, val), = data.items()
+    assert key.startswith("gfx") and "|p32|" in key
+    assert val == [first["shape"], first["grid_mult"]]
+    b2 = gl.Batch(evs)
+    b2.autotune(path)
+    assert b2.info() == first
+    b2.run(4)
