@@ -239,6 +239,40 @@ gl_status gl_batch_info(gl_batch *b, int32_t *shape, int32_t *tile_x, int32_t *t
 /* n_steps coupled steps of every event of the batch. */
 gl_status gl_batch_run(gl_batch *b, int32_t n_steps);
 
+/* ---- learned surrogate ------------------------------------------------------
+ * Fully connected network n_in -> width (x depth hidden layers, SiLU) -> n_out
+ * with BF16 weights and activations, FP32 accumulation on the matrix cores
+ * (MFMA), FP32 master weights and Adam.  Inputs are scaled to [-1, 1] with
+ * (in_lo, in_hi), outputs standardised with (out_mean, out_std), both inside
+ * the kernels.  Parameters are one flat FP32 vector: W_1 [out][in], ...,
+ * W_L, then b_1, ..., b_L.  X, Y are device FP32 arrays [n][n_in], [n][n_out].
+ * The caller owns the workspace (gl_mlp_required_bytes; max_samples bounds n
+ * of gl_mlp_train). */
+typedef struct gl_mlp gl_mlp;
+typedef struct {
+    int32_t n_in, width, depth, n_out;
+    int32_t max_batch;
+} gl_mlp_desc;
+gl_status gl_mlp_required_bytes(const gl_mlp_desc *d, int64_t max_samples, size_t *bytes);
+gl_status gl_mlp_create(const gl_mlp_desc *d, int64_t max_samples, void *workspace, size_t bytes,
+                        void *stream, uint64_t seed, gl_mlp **out);
+void gl_mlp_destroy(gl_mlp *m);
+gl_status gl_mlp_set_scaling(gl_mlp *m, const float *in_lo, const float *in_hi,
+                             const float *out_mean, const float *out_std);
+/* Minibatch Adam (beta 0.9, 0.999) for `epochs` passes over n samples in
+ * shuffled whole batches; loss_per_epoch (host, may be NULL) receives the
+ * mean standardised MSE of each epoch. */
+gl_status gl_mlp_train(gl_mlp *m, const float *X, const float *Y, int64_t n, int32_t epochs,
+                       int32_t batch, float lr, uint64_t seed, float *loss_per_epoch);
+gl_status gl_mlp_infer(gl_mlp *m, const float *X, float *Y, int64_t n);
+/* One forward/backward pass on n <= max_batch samples (no update): gradients
+ * of the standardised MSE to host grads [n_params], loss to *loss. */
+gl_status gl_mlp_grads(gl_mlp *m, const float *X, const float *Y, int32_t n, float *grads,
+                       float *loss);
+/* Read (get) and/or write (set) the FP32 parameters (host arrays). */
+gl_status gl_mlp_params(gl_mlp *m, float *get, const float *set, int64_t *n_params);
+const char *gl_mlp_last_error(void);
+
 const char *gl_status_string(gl_status s);
 const char *gl_last_error(void);
 

@@ -381,3 +381,121 @@ class Batch:
 
     def run(self, n_steps):
         return check(lib().gl_batch_run(self._h, n_steps))
+
+
+class MLPDesc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+def _mlp_check(status):
+    if status != GL_OK:
+        raise GlasmaError(status, lib().gl_mlp_last_error().decode())
+    return status
+
+
+def _mlp_declare(L):
+    _F = ctypes.POINTER(ctypes.c_float)
+    sig = {
+        "gl_mlp_required_bytes": [ctypes.POINTER(MLPDesc), ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+        "gl_mlp_create": [ctypes.POINTER(MLPDesc), ctypes.c_int64, _VP, ctypes.c_size_t, _VP, ctypes.c_uint64,
+                          ctypes.POINTER(_VP)],
+        "gl_mlp_set_scaling": [_VP, _F, _F, _F, _F],
+        "gl_mlp_train": [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                         ctypes.c_uint64, _F],
+        "gl_mlp_infer": [_VP, _VP, _VP, ctypes.c_int64],
+        "gl_mlp_grads": [_VP, _VP, _VP, ctypes.c_int32, _F, _F],
+        "gl_mlp_params": [_VP, _F, _F, _I64],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    L.gl_mlp_destroy.argtypes = [_VP]
+    L.gl_mlp_destroy.restype = None
+    L.gl_mlp_last_error.argtypes = []
+    L.gl_mlp_last_error.restype = ctypes.c_char_p
+
+
+def _f(a):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """The surrogate network on a torch-allocated workspace (see gl_mlp_* in glasma.h)."""
+
+    def __init__(self, n_in=5, width=256, depth=3, n_out=2, max_batch=4096, max_samples=1 << 20,
+                 seed=1, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        L = lib()
+        if not getattr(L, "_mlp_declared", False):
+            _mlp_declare(L)
+            L._mlp_declared = True
+        self.desc = MLPDesc(n_in, width, depth, n_out, max_batch)
+        nbytes = ctypes.c_size_t(0)
+        _mlp_check(L.gl_mlp_required_bytes(ctypes.byref(self.desc), max_samples, ctypes.byref(nbytes)))
+        self.device = torch.device(device)
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _VP()
+        _mlp_check(L.gl_mlp_create(ctypes.byref(self.desc), max_samples, _VP(ptr), nbytes.value,
+                                   _VP(self.stream.cuda_stream), seed, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64(0)
+        _mlp_check(L.gl_mlp_params(h, None, None, ctypes.byref(n)))
+        self.n_params = n.value
+        self.n_in, self.n_out = n_in, n_out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scaling(self, in_lo, in_hi, out_mean, out_std):
+        a = [np.ascontiguousarray(v, np.float32) for v in (in_lo, in_hi, out_mean, out_std)]
+        _mlp_check(lib().gl_mlp_set_scaling(self._h, *[_f(x) for x in a]))
+
+    def _dev(self, a, cols):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, np.float32)).reshape(-1, cols)
+        return t.to(self.device).contiguous()
+
+    def train(self, X, Y, epochs, batch, lr, seed=0):
+        """X, Y: host arrays or torch device tensors (float32)."""
+        Xd = X if hasattr(X, "data_ptr") else self._dev(X, self.n_in)
+        Yd = Y if hasattr(Y, "data_ptr") else self._dev(Y, self.n_out)
+        losses = np.zeros(max(epochs, 1), np.float32)
+        _mlp_check(lib().gl_mlp_train(self._h, _VP(Xd.data_ptr()), _VP(Yd.data_ptr()), Xd.shape[0], epochs,
+                                      batch, lr, seed, _f(losses)))
+        return losses[:epochs]
+
+    def infer(self, X):
+        Xd = X if hasattr(X, "data_ptr") else self._dev(X, self.n_in)
+        Yd = self.torch.empty((Xd.shape[0], self.n_out), dtype=self.torch.float32, device=self.device)
+        _mlp_check(lib().gl_mlp_infer(self._h, _VP(Xd.data_ptr()), _VP(Yd.data_ptr()), Xd.shape[0]))
+        return Yd
+
+    def grads(self, X, Y):
+        Xd, Yd = self._dev(X, self.n_in), self._dev(Y, self.n_out)
+        g = np.zeros(self.n_params, np.float32)
+        loss = np.zeros(1, np.float32)
+        _mlp_check(lib().gl_mlp_grads(self._h, _VP(Xd.data_ptr()), _VP(Yd.data_ptr()), Xd.shape[0], _f(g),
+                                      _f(loss)))
+        return g, float(loss[0])
+
+    def params(self, set_to=None):
+        if set_to is not None:
+            v = np.ascontiguousarray(set_to, np.float32)
+            assert v.size == self.n_params
+            _mlp_check(lib().gl_mlp_params(self._h, None, _f(v), None))
+        out = np.zeros(self.n_params, np.float32)
+        _mlp_check(lib().gl_mlp_params(self._h, _f(out), None, None))
+        return out
