@@ -77,11 +77,16 @@ typedef struct {
 } gl_lattice_desc;
 
 /* MV-model description (Sec. 1 "Glasma"): per-sheet charge variance
- * (g^2 mu)^2 / (n_sheets a^2), infrared regulator m in the Poisson solve. */
+ * (g^2 mu)^2 / (n_sheets a^2), infrared regulator m in the Poisson solve, and
+ * an optional UV regulator: Fourier modes whose lattice momentum
+ * 2 sqrt(sin^2(pi kx/N) + sin^2(pi ky/N)) / a exceeds uv_cut_GeV are dropped
+ * (0: no cut), which makes the initial fields independent of the lattice
+ * spacing once a is fine enough. */
 typedef struct {
     double  g2mu_GeV;
     double  m_ir_GeV;
     int32_t n_sheets;
+    double  uv_cut_GeV;
 } gl_mv_desc;
 
 /* Particle species (Sec. 2, toy initialisation). */
@@ -118,7 +123,7 @@ void gl_event_destroy(gl_event *ev);
 gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed);
 
 /* Same from caller-supplied charges rho (device, FP64) laid out
- * [2][n_sheets][8][N*N] in lattice units. */
+ * [2][n_sheets][8][N*N] in lattice units (no UV cut). */
 gl_status gl_init_glasma_from_charges(gl_event *ev, const double *rho_dev, int32_t n_sheets,
                                       double m_ir_GeV);
 

@@ -361,8 +361,10 @@ void fft2(int N, std::vector<cd> &a, int sign) {
 
 // Reading of the MV-model Poisson step: (-Lap + m^2) Lambda = rho with the
 // 5-point lattice Laplacian, solved exactly in Fourier space
-// (denominator 4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2), no UV cut.
-void poisson(int N, double m2, const double *src, size_t src_stride, double *out,
+// (denominator 4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2).  An optional UV
+// regulator removes the modes whose lattice momentum squared exceeds uv2
+// (uv2 <= 0: no cut).
+void poisson(int N, double m2, double uv2, const double *src, size_t src_stride, double *out,
              size_t out_stride) {
     std::vector<cd> a((size_t)N * N);
     for (size_t x = 0; x < (size_t)N * N; x++) a[x] = src[x * src_stride];
@@ -371,8 +373,9 @@ void poisson(int N, double m2, const double *src, size_t src_stride, double *out
     for (int ky = 0; ky < N; ky++)
         for (int kx = 0; kx < N; kx++) {
             double sx = std::sin(pi * kx / N), sy = std::sin(pi * ky / N);
-            double den = 4.0 * sx * sx + 4.0 * sy * sy + m2;
-            a[(size_t)kx + (size_t)N * ky] /= den;
+            double k2 = 4.0 * sx * sx + 4.0 * sy * sy;
+            if (uv2 > 0.0 && k2 > uv2) a[(size_t)kx + (size_t)N * ky] = 0.0;
+            else a[(size_t)kx + (size_t)N * ky] /= (k2 + m2);
         }
     fft2(N, a, +1);
     double inv = 1.0 / ((double)N * N);
@@ -503,7 +506,13 @@ int orc_fft(int n, double *data, int sign) {
 
 int orc_poisson(int N, double m2, const double *src, double *out) {
     if (N < 1 || m2 <= 0.0) return -1;
-    poisson(N, m2, src, 1, out, 1);
+    poisson(N, m2, 0.0, src, 1, out, 1);
+    return 0;
+}
+
+int orc_poisson_uv(int N, double m2, double uv2, const double *src, double *out) {
+    if (N < 1 || m2 <= 0.0) return -1;
+    poisson(N, m2, uv2, src, 1, out, 1);
     return 0;
 }
 
@@ -511,13 +520,18 @@ int orc_poisson(int N, double m2, const double *src, double *out) {
 // sheet 1 leftmost, where L_s solves the Poisson equation for sheet s.
 int orc_wilson_line(int N, double sigma, double m2, int n_sheets, uint64_t seed,
                     int nucleus, double *V) {
+    return orc_wilson_line_uv(N, sigma, m2, 0.0, n_sheets, seed, nucleus, V);
+}
+
+int orc_wilson_line_uv(int N, double sigma, double m2, double uv2, int n_sheets, uint64_t seed,
+                       int nucleus, double *V) {
     if (N < 1 || n_sheets < 1 || m2 <= 0.0) return -1;
     size_t N2 = (size_t)N * N;
     std::vector<Mat> v(N2, ident());
     std::vector<double> rho(N2 * 8), lam(N2 * 8);
     for (int s = 0; s < n_sheets; s++) {
         orc_mv_charges(N, sigma, seed, nucleus, s, rho.data());
-        for (int a = 0; a < 8; a++) poisson(N, m2, rho.data() + a, 8, lam.data() + a, 8);
+        for (int a = 0; a < 8; a++) poisson(N, m2, uv2, rho.data() + a, 8, lam.data() + a, 8);
         for (size_t x = 0; x < N2; x++) {
             double ml[8];
             for (int a = 0; a < 8; a++) ml[a] = -lam[x * 8 + a];
@@ -618,11 +632,17 @@ void orc_pi0(int N, const double *U, const double *UA, const double *UB, double 
 int orc_init_glasma(int N, double sigma, double m2, int n_sheets, uint64_t seed,
                     double dtau, double *U, double *E, double *phi, double *pi,
                     double *max_res_out) {
+    return orc_init_glasma_uv(N, sigma, m2, 0.0, n_sheets, seed, dtau, U, E, phi, pi, max_res_out);
+}
+
+int orc_init_glasma_uv(int N, double sigma, double m2, double uv2, int n_sheets, uint64_t seed,
+                       double dtau, double *U, double *E, double *phi, double *pi,
+                       double *max_res_out) {
     size_t N2 = (size_t)N * N;
     std::vector<double> VA(N2 * 18), VB(N2 * 18), UA(2 * N2 * 18), UB(2 * N2 * 18);
-    int rc = orc_wilson_line(N, sigma, m2, n_sheets, seed, 0, VA.data());
+    int rc = orc_wilson_line_uv(N, sigma, m2, uv2, n_sheets, seed, 0, VA.data());
     if (rc) return rc;
-    rc = orc_wilson_line(N, sigma, m2, n_sheets, seed, 1, VB.data());
+    rc = orc_wilson_line_uv(N, sigma, m2, uv2, n_sheets, seed, 1, VB.data());
     if (rc) return rc;
     orc_nucleus_links(N, VA.data(), UA.data());
     orc_nucleus_links(N, VB.data(), UB.data());

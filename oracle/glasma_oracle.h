@@ -51,9 +51,14 @@ void orc_mv_charges(int N, double sigma, uint64_t seed, int nucleus, int sheet,
 int orc_fft(int n, double *data_re_im, int sign);
 /* Solve (-Lap + m2) out = src on the periodic N x N lattice (one real plane). */
 int orc_poisson(int N, double m2, const double *src, double *out);
+/* Same with a UV regulator: Fourier modes with lattice momentum squared
+ * 4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) > uv2 are removed (uv2 <= 0: none). */
+int orc_poisson_uv(int N, double m2, double uv2, const double *src, double *out);
 /* Wilson line of one nucleus, V = prod_s exp(-i Lambda_s), V [N*N][18]. */
 int orc_wilson_line(int N, double sigma, double m2, int n_sheets, uint64_t seed,
                     int nucleus, double *V);
+int orc_wilson_line_uv(int N, double sigma, double m2, double uv2, int n_sheets, uint64_t seed,
+                       int nucleus, double *V);
 /* Pure-gauge nucleus links U_i(x) = V(x) V^dag(x+i), Un [2][N*N][18]. */
 void orc_nucleus_links(int N, const double *V, double *Un);
 /* Solve [(UA+UB)(1+U^dag)]_X = 0 for one link; returns iterations or -3. */
@@ -66,6 +71,9 @@ void orc_pi0(int N, const double *U, const double *UA, const double *UB,
 int orc_init_glasma(int N, double sigma, double m2, int n_sheets, uint64_t seed,
                     double dtau, double *U, double *E, double *phi, double *pi,
                     double *max_res_out);
+int orc_init_glasma_uv(int N, double sigma, double m2, double uv2, int n_sheets, uint64_t seed,
+                       double dtau, double *U, double *E, double *phi, double *pi,
+                       double *max_res_out);
 
 /* ---- field evolution --------------------------------------------------- */
 /* Forces at time tau: dE/dtau [2][N*N][8], dpi/dtau [N*N][8]. */

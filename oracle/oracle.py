@@ -57,6 +57,10 @@ def _declare(L):
         "orc_fft": (c_int, [c_int, _D, c_int]),
         "orc_poisson": (c_int, [c_int, c_double, _D, _D]),
         "orc_wilson_line": (c_int, [c_int, c_double, c_double, c_int, c_u64, c_int, _D]),
+        "orc_poisson_uv": (c_int, [c_int, c_double, c_double, _D, _D]),
+        "orc_wilson_line_uv": (c_int, [c_int, c_double, c_double, c_double, c_int, c_u64, c_int, _D]),
+        "orc_init_glasma_uv": (c_int, [c_int, c_double, c_double, c_double, c_int, c_u64, c_double,
+                                       _D, _D, _D, _D, _D]),
         "orc_nucleus_links": (None, [c_int, _D, _D]),
         "orc_match_link": (c_int, [_D, _D, _D, c_double, c_int, _D]),
         "orc_pi0": (None, [c_int, _D, _D, _D, _D]),
@@ -171,10 +175,17 @@ def poisson(N, m2, src):
     return out
 
 
-def wilson_line(N, sigma, m2, n_sheets, seed, nucleus):
+def wilson_line(N, sigma, m2, n_sheets, seed, nucleus, uv2=0.0):
     V = np.zeros((N * N, 18))
-    assert lib().orc_wilson_line(N, sigma, m2, n_sheets, seed, nucleus, _d(V)) == 0
+    assert lib().orc_wilson_line_uv(N, sigma, m2, uv2, n_sheets, seed, nucleus, _d(V)) == 0
     return V
+
+
+def poisson_uv(N, m2, uv2, src):
+    src = np.ascontiguousarray(src, np.float64).reshape(N * N)
+    out = np.zeros(N * N)
+    assert lib().orc_poisson_uv(N, m2, uv2, _d(src), _d(out)) == 0
+    return out
 
 
 def nucleus_links(N, V):
@@ -217,11 +228,11 @@ class State:
         return s
 
 
-def init_glasma(N, sigma, m2, n_sheets, seed, dtau):
+def init_glasma(N, sigma, m2, n_sheets, seed, dtau, uv2=0.0):
     s = State(N)
     res = np.zeros(1)
-    rc = lib().orc_init_glasma(N, sigma, m2, n_sheets, seed, dtau, _d(s.U), _d(s.E),
-                               _d(s.phi), _d(s.pi), _d(res))
+    rc = lib().orc_init_glasma_uv(N, sigma, m2, uv2, n_sheets, seed, dtau, _d(s.U), _d(s.E),
+                                  _d(s.phi), _d(s.pi), _d(res))
     return s, rc, float(res[0])
 
 

@@ -530,10 +530,11 @@ void gl_event_destroy(gl_event *ev) {
     delete ev;
 }
 
-static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, const double *rho_dev, double sigma,
-                             uint64_t seed) {
+static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, double uv_GeV, const double *rho_dev,
+                             double sigma, uint64_t seed) {
     const int N = ev->N;
     double m2 = (m_ir_GeV * ev->a_gev) * (m_ir_GeV * ev->a_gev);
+    double uv2 = uv_GeV > 0 ? (uv_GeV * ev->a_gev) * (uv_GeV * ev->a_gev) : 0.0;
     if (!(m2 > 0)) return fail(GL_EINVAL, "infrared regulator must be > 0");
     if (!valid_N_for_fft(N)) return fail(GL_EINVAL, "MV initialisation needs N = 2^a 3^b");
     double *V[2] = {(double *)(ev->ws + ev->L.VA), (double *)(ev->ws + ev->L.VB)};
@@ -546,7 +547,7 @@ static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, const 
                                                  planes));
             else
                 HIP_TRY(launch_mv_charges(ev->stream, N, sigma, seed, nuc, sh, planes));
-            HIP_TRY(launch_poisson(ev->stream, N, m2, planes, nullptr));
+            HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes));
             HIP_TRY(launch_wilson_accum(ev->stream, N, planes, V[nuc]));
         }
     }
@@ -557,14 +558,15 @@ gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed) {
     if (check_ev(ev) || !mv) return fail(GL_EINVAL, "null argument");
     if (mv->n_sheets < 1) return fail(GL_EINVAL, "n_sheets must be >= 1");
     if (!(mv->g2mu_GeV >= 0)) return fail(GL_EINVAL, "g2mu must be >= 0");
+    if (!(mv->uv_cut_GeV >= 0)) return fail(GL_EINVAL, "uv_cut_GeV must be >= 0");
     double sigma = mv->g2mu_GeV * ev->a_gev / std::sqrt((double)mv->n_sheets);
-    return init_common(ev, mv->n_sheets, mv->m_ir_GeV, nullptr, sigma, seed);
+    return init_common(ev, mv->n_sheets, mv->m_ir_GeV, mv->uv_cut_GeV, nullptr, sigma, seed);
 }
 
 gl_status gl_init_glasma_from_charges(gl_event *ev, const double *rho_dev, int32_t n_sheets, double m_ir_GeV) {
     if (check_ev(ev) || !rho_dev) return fail(GL_EINVAL, "null argument");
     if (n_sheets < 1) return fail(GL_EINVAL, "n_sheets must be >= 1");
-    return init_common(ev, n_sheets, m_ir_GeV, rho_dev, 0.0, 0);
+    return init_common(ev, n_sheets, m_ir_GeV, 0.0, rho_dev, 0.0, 0);
 }
 
 gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uint64_t seed, int32_t *species_id) {

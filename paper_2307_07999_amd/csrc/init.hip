@@ -143,15 +143,17 @@ k_fft_lines(double2 *data, int N, size_t elem_stride, size_t line_stride, size_t
     for (int k = threadIdx.x; k < N; k += kFftThreads) base[(size_t)k * elem_stride] = buf[src][k];
 }
 
-// multiply by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2)) on all 4 planes
+// multiply by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2)) on all 4
+// planes; modes with lattice momentum squared above uv2 > 0 are set to zero
 __global__ void __launch_bounds__(256)
-k_poisson_kernel(int N, double m2, double2 *planes) {
+k_poisson_kernel(int N, double m2, double uv2, double2 *planes) {
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
     int kx = (int)(x % N), ky = (int)(x / N);
     double sx = sinpi((double)kx / N), sy = sinpi((double)ky / N);
-    double g = 1.0 / (((double)N * N) * (4.0 * sx * sx + 4.0 * sy * sy + m2));
+    double k2 = 4.0 * sx * sx + 4.0 * sy * sy;
+    double g = (uv2 > 0.0 && k2 > uv2) ? 0.0 : 1.0 / (((double)N * N) * (k2 + m2));
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         double2 v = planes[(size_t)j * n2 + x];
@@ -445,11 +447,11 @@ static hipError_t fft2(hipStream_t st, int N, double2 *planes, int sign) {
     return hipGetLastError();
 }
 
-hipError_t launch_poisson(hipStream_t st, int N, double m2, double2 *planes, double2 *) {
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes) {
     hipError_t e = fft2(st, N, planes, -1);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_poisson_kernel, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, m2,
-                       planes);
+                       uv2, planes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return fft2(st, N, planes, +1);

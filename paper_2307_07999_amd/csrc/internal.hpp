@@ -75,8 +75,8 @@ hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed,
 hipError_t launch_charges_to_planes(hipStream_t st, int N, const double *rho /* [8][n2] */,
                                  double2 *planes);
 hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes, double *rho);
-hipError_t launch_poisson(hipStream_t st, int N, double m2, double2 *planes /* [4][n2] in place */,
-                          double2 *tmp);
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2,
+                          double2 *planes /* [4][n2] in place */);
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V);
 hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, double *V);
 hipError_t launch_match_pi0(hipStream_t st, int N, const double *VA, const double *VB,

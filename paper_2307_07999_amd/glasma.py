@@ -33,7 +33,7 @@ class LatticeDesc(ctypes.Structure):
 
 class MVDesc(ctypes.Structure):
     _fields_ = [("g2mu_GeV", ctypes.c_double), ("m_ir_GeV", ctypes.c_double),
-                ("n_sheets", ctypes.c_int32)]
+                ("n_sheets", ctypes.c_int32), ("uv_cut_GeV", ctypes.c_double)]
 
 
 class SpeciesDesc(ctypes.Structure):
@@ -190,8 +190,8 @@ class Event:
             pass
 
     # ---- initial conditions ------------------------------------------------
-    def init_glasma(self, g2mu_GeV, m_ir_GeV, n_sheets, seed):
-        mv = MVDesc(g2mu_GeV, m_ir_GeV, n_sheets)
+    def init_glasma(self, g2mu_GeV, m_ir_GeV, n_sheets, seed, uv_cut_GeV=0.0):
+        mv = MVDesc(g2mu_GeV, m_ir_GeV, n_sheets, uv_cut_GeV)
         return check(lib().gl_init_glasma(self._h, ctypes.byref(mv), seed))
 
     def init_glasma_from_charges(self, rho, m_ir_GeV):

@@ -75,7 +75,7 @@ def _curve(ev, jet):
 
 
 def solver_curves(params, N, L_fm, n_particles, seed, precision=32, sheets=50, batch=64,
-                  tune_cache=None):
+                  tune_cache=None, uv_cut=0.0):
     """Run the solver for each (Q_s, m, p_T0); returns a list of curves
     (tau, kappa, dpT2) and the GPU wall time spent per curve."""
     import torch
@@ -89,7 +89,7 @@ def solver_curves(params, N, L_fm, n_particles, seed, precision=32, sheets=50, b
         for k, (qs, m, pt) in enumerate(chunk):
             ev = G.Event(N, L_fm, 0.125, precision=precision, max_steps=steps,
                          max_particles=n_particles)
-            ev.init_glasma(qs / QS_OVER_G2MU, M_IR, sheets, seed + c0 + k)
+            ev.init_glasma(qs / QS_OVER_G2MU, M_IR, sheets, seed + c0 + k, uv_cut)
             ev.add_species(m, pt, G.KIND_JET if m == 0 else G.KIND_HEAVY_QUARK, n_particles,
                            seed + 7919 * (c0 + k) + 1)
             evs.append(ev)

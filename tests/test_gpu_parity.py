@@ -56,6 +56,19 @@ def test_wilson_lines_match_oracle(gl, orc, N, sheets):
         assert np.abs(got - want.T).max() < 1e-12
 
 
+def test_wilson_lines_with_uv_cut_match_oracle(gl, orc):
+    N, sheets, uv = 48, 2, 3.0
+    cfg = dict(H.C1, N=N, sheets=sheets)
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    ev = _event(gl, N, cfg["L"])
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], sheets, cfg["seed"], uv_cut_GeV=uv)
+    for nuc in (0, 1):
+        want = orc.wilson_line(N, sigma, m2, sheets, cfg["seed"], nuc, uv2=(uv * a_gev) ** 2)
+        assert np.abs(ev.wilson_line(nuc) - want.T).max() < 1e-12
+        nocut = orc.wilson_line(N, sigma, m2, sheets, cfg["seed"], nuc)
+        assert np.abs(want - nocut).max() > 1e-3
+
+
 @pytest.mark.parametrize("N", [32, 24])
 def test_initial_state_matches_oracle(gl, orc, N):
     cfg = dict(H.C1, N=N)

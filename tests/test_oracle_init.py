@@ -175,3 +175,17 @@ def test_init_glasma_invariants(orc):
     assert np.abs(s.E).max() == 0.0
     assert np.abs(s.phi - 0.5 * dt * dt * s.pi).max() < 1e-17
     assert np.abs(orc.gauss(s)).max() < 1e-14
+
+
+def test_poisson_uv_cut_keeps_low_and_removes_high_modes(orc):
+    N, m2 = 32, 0.01
+    xs = np.arange(N)
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    low = np.cos(2 * np.pi * (2 * X + 1 * Y) / N).reshape(-1)
+    high = np.cos(2 * np.pi * (12 * X + 9 * Y) / N).reshape(-1)
+    k2 = lambda kx, ky: 4 * np.sin(np.pi * kx / N) ** 2 + 4 * np.sin(np.pi * ky / N) ** 2
+    uv2 = 0.5 * (k2(2, 1) + k2(12, 9))
+    out = orc.poisson_uv(N, m2, uv2, low + high)
+    assert np.abs(out - low / (k2(2, 1) + m2)).max() < 1e-13
+    # no cut reproduces the plain solve
+    assert np.abs(orc.poisson_uv(N, m2, 0.0, low + high) - orc.poisson(N, m2, low + high)).max() < 1e-15
