@@ -264,6 +264,10 @@ gl_status gl_mlp_create(const gl_mlp_desc *d, int64_t max_samples, void *workspa
 void gl_mlp_destroy(gl_mlp *m);
 gl_status gl_mlp_set_scaling(gl_mlp *m, const float *in_lo, const float *in_hi,
                              const float *out_mean, const float *out_std);
+/* Optional per-output power of one input: the network then models
+ * Y_c / X_col^powers[c] (standardised), and inference multiplies it back
+ * (col < 0: off).  Used to factor out the Q_s scaling of the observables. */
+gl_status gl_mlp_set_output_power(gl_mlp *m, int32_t col, const float *powers);
 /* Minibatch Adam (beta 0.9, 0.999) for `epochs` passes over n samples in
  * shuffled whole batches; loss_per_epoch (host, may be NULL) receives the
  * mean standardised MSE of each epoch. */

@@ -114,10 +114,12 @@ k_gemm(const bf16 *__restrict__ A, int lda, const bf16 *__restrict__ B, int ldb,
             }
 }
 
-// gather a batch by permutation, scale inputs to [-1, 1] (BF16) and standardise targets
+// gather a batch by permutation, scale inputs to [-1, 1] (BF16) and standardise
+// targets; target c is first divided by X[col]^pw[c] when col >= 0
 __global__ void __launch_bounds__(256)
 k_prep(const float *__restrict__ X, const float *__restrict__ Y, const int32_t *__restrict__ idx, int64_t off,
-       int B, int nin, int nout, const float *__restrict__ sc, bf16 *__restrict__ Xb, float *__restrict__ Yb) {
+       int B, int nin, int nout, const float *__restrict__ sc, int pcol, bf16 *__restrict__ Xb,
+       float *__restrict__ Yb) {
     int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= B) return;
     int64_t s = idx ? idx[off + r] : off + r;
@@ -128,7 +130,9 @@ k_prep(const float *__restrict__ X, const float *__restrict__ Y, const int32_t *
     if (Y)
         for (int c = 0; c < nout; c++) {
             float mu = sc[2 * nin + c], sd = sc[2 * nin + nout + c];
-            Yb[(size_t)r * nout + c] = (Y[s * nout + c] - mu) / sd;
+            float y = Y[s * nout + c];
+            if (pcol >= 0) y /= powf(X[s * nin + pcol], sc[2 * nin + 2 * nout + c]);
+            Yb[(size_t)r * nout + c] = (y - mu) / sd;
         }
 }
 
@@ -201,12 +205,16 @@ k_to_bf16(const float *__restrict__ w, int64_t n, bf16 *__restrict__ o) {
     if (i < n) o[i] = f2bf(w[i]);
 }
 
+// outputs back to physical units: undo the standardisation and the input power
 __global__ void __launch_bounds__(256)
-k_unscale(const float *__restrict__ Z, int B, int nout, const float *__restrict__ sc_out, float *__restrict__ Y) {
+k_unscale(const float *__restrict__ Z, int B, int nout, const float *__restrict__ sc_out,
+          const float *__restrict__ X, int nin, int pcol, float *__restrict__ Y) {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= B * nout) return;
-    int c = i % nout;
-    Y[i] = Z[i] * sc_out[nout + c] + sc_out[c];
+    int c = i % nout, r = i / nout;
+    float y = Z[i] * sc_out[nout + c] + sc_out[c];
+    if (pcol >= 0) y *= powf(X[(size_t)r * nin + pcol], sc_out[2 * nout + c]);
+    Y[i] = y;
 }
 
 __global__ void k_zero1(float *p) {
@@ -253,6 +261,7 @@ struct gl_mlp {
     int32_t *perm;                              // [max_samples]
     int64_t max_samples;
     int64_t adam_t = 0;
+    int pcol = -1;                              // input column of the output power, -1: none
 };
 
 namespace {
@@ -291,7 +300,7 @@ gl_status mlp_layout(const gl_mlp_desc *d, int64_t max_samples, gl_mlp *m, size_
         return o;
     };
     size_t oP = take(np * 4), oG = take(np * 4), oM = take(np * 4), oV = take(np * 4), oW = take(nw * 2);
-    size_t osc = take(2 * (d->n_in + d->n_out) * 4), oX = take(B * d->n_in * 2), oY = take(B * d->n_out * 4);
+    size_t osc = take((2 * d->n_in + 3 * d->n_out) * 4), oX = take(B * d->n_in * 2), oY = take(B * d->n_out * 4);
     std::vector<size_t> oZ(L), oH(L);
     for (int l = 0; l < L; l++) {
         oZ[l] = take(B * dout[l] * 4);
@@ -420,7 +429,7 @@ gl_status gl_mlp_create(const gl_mlp_desc *d, int64_t max_samples, void *ws, siz
         std::uniform_real_distribution<float> u(-bound, bound);
         for (int64_t k = 0; k < (int64_t)m->din[l] * m->dout[l]; k++) p[m->woff[l] + k] = u(rng);
     }
-    std::vector<float> sc(2 * (d->n_in + d->n_out));
+    std::vector<float> sc(2 * d->n_in + 3 * d->n_out, 0.f);
     for (int c = 0; c < d->n_in; c++) {
         sc[c] = -1.f;
         sc[d->n_in + c] = 1.f;
@@ -449,7 +458,7 @@ gl_status gl_mlp_set_scaling(gl_mlp *m, const float *in_lo, const float *in_hi, 
                              const float *out_std) {
     if (!m || !in_lo || !in_hi || !out_mean || !out_std) return mfail(GL_EINVAL, "null argument");
     const int ni = m->d.n_in, no = m->d.n_out;
-    std::vector<float> sc(2 * (ni + no));
+    std::vector<float> sc(2 * ni + 2 * no);
     for (int c = 0; c < ni; c++) {
         if (!(in_hi[c] > in_lo[c])) return mfail(GL_EINVAL, "in_hi must exceed in_lo");
         sc[c] = in_lo[c];
@@ -462,6 +471,18 @@ gl_status gl_mlp_set_scaling(gl_mlp *m, const float *in_lo, const float *in_hi, 
     }
     MHIP(hipMemcpyAsync(m->sc, sc.data(), sc.size() * 4, hipMemcpyHostToDevice, m->st));
     MHIP(hipStreamSynchronize(m->st));
+    return GL_OK;
+}
+
+gl_status gl_mlp_set_output_power(gl_mlp *m, int32_t col, const float *powers) {
+    if (!m) return mfail(GL_EINVAL, "null argument");
+    if (col >= m->d.n_in || (col >= 0 && !powers)) return mfail(GL_EINVAL, "bad column or powers");
+    m->pcol = col < 0 ? -1 : col;
+    if (col >= 0) {
+        MHIP(hipMemcpyAsync(m->sc + 2 * m->d.n_in + 2 * m->d.n_out, powers, m->d.n_out * 4, hipMemcpyHostToDevice,
+                            m->st));
+        MHIP(hipStreamSynchronize(m->st));
+    }
     return GL_OK;
 }
 
@@ -482,7 +503,7 @@ gl_status gl_mlp_train(gl_mlp *m, const float *X, const float *Y, int64_t n, int
         hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, m->st, m->loss);
         for (int64_t bi = 0; bi < nbat; bi++) {
             hipLaunchKernelGGL(k_prep, dim3(nb(batch, 256)), dim3(256), 0, m->st, X, Y, m->perm, bi * batch, batch,
-                               m->d.n_in, m->d.n_out, m->sc, m->Xb, m->Yb);
+                               m->d.n_in, m->d.n_out, m->sc, m->pcol, m->Xb, m->Yb);
             MHIP(hipGetLastError());
             gl_status s = forward(m, batch);
             if (s) return s;
@@ -514,12 +535,14 @@ gl_status gl_mlp_infer(gl_mlp *m, const float *X, float *Y, int64_t n) {
     for (int64_t off = 0; off < n; off += B) {
         int b = (int)std::min<int64_t>(B, n - off);
         hipLaunchKernelGGL(k_prep, dim3(nb(b, 256)), dim3(256), 0, m->st, X, (const float *)nullptr,
-                           (const int32_t *)nullptr, off, b, m->d.n_in, m->d.n_out, m->sc, m->Xb, (float *)nullptr);
+                           (const int32_t *)nullptr, off, b, m->d.n_in, m->d.n_out, m->sc, m->pcol, m->Xb,
+                           (float *)nullptr);
         MHIP(hipGetLastError());
         gl_status s = forward(m, b);
         if (s) return s;
         hipLaunchKernelGGL(k_unscale, dim3(nb((int64_t)b * m->d.n_out, 256)), dim3(256), 0, m->st, m->Z[m->L - 1], b,
-                           m->d.n_out, m->sc + 2 * m->d.n_in, Y + off * m->d.n_out);
+                           m->d.n_out, m->sc + 2 * m->d.n_in, X + off * m->d.n_in, m->d.n_in, m->pcol,
+                           Y + off * m->d.n_out);
         MHIP(hipGetLastError());
     }
     return GL_OK;
@@ -530,7 +553,7 @@ gl_status gl_mlp_grads(gl_mlp *m, const float *X, const float *Y, int32_t n, flo
     if (n < 1 || n > m->d.max_batch) return mfail(GL_EINVAL, "n must be in [1, max_batch]");
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, m->st, m->loss);
     hipLaunchKernelGGL(k_prep, dim3(nb(n, 256)), dim3(256), 0, m->st, X, Y, (const int32_t *)nullptr, (int64_t)0, n,
-                       m->d.n_in, m->d.n_out, m->sc, m->Xb, m->Yb);
+                       m->d.n_in, m->d.n_out, m->sc, m->pcol, m->Xb, m->Yb);
     MHIP(hipGetLastError());
     gl_status s = forward(m, n);
     if (s) return s;

@@ -401,6 +401,7 @@ def _mlp_declare(L):
         "gl_mlp_create": [ctypes.POINTER(MLPDesc), ctypes.c_int64, _VP, ctypes.c_size_t, _VP, ctypes.c_uint64,
                           ctypes.POINTER(_VP)],
         "gl_mlp_set_scaling": [_VP, _F, _F, _F, _F],
+        "gl_mlp_set_output_power": [_VP, ctypes.c_int32, _F],
         "gl_mlp_train": [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                          ctypes.c_uint64, _F],
         "gl_mlp_infer": [_VP, _VP, _VP, ctypes.c_int64],
@@ -463,6 +464,10 @@ class MLP:
     def set_scaling(self, in_lo, in_hi, out_mean, out_std):
         a = [np.ascontiguousarray(v, np.float32) for v in (in_lo, in_hi, out_mean, out_std)]
         _mlp_check(lib().gl_mlp_set_scaling(self._h, *[_f(x) for x in a]))
+
+    def set_output_power(self, col, powers):
+        p = np.ascontiguousarray(powers, np.float32)
+        _mlp_check(lib().gl_mlp_set_output_power(self._h, col, _f(p)))
 
     def _dev(self, a, cols):
         t = self.torch.as_tensor(np.ascontiguousarray(a, np.float32)).reshape(-1, cols)

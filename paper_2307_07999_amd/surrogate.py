@@ -26,6 +26,9 @@ JET_PT_MIN = 0.5
 TAU_MAX = 1.0
 M_IR = 0.2
 QS_OVER_G2MU = 0.6          # reading of "Q_s = 2 GeV": g^2 mu = Q_s / 0.6
+# network inputs: Q_s, m, p_T0, tau_form and the time since formation
+# tau - tau_form (the same information as tau; it lines up the sharp rise of
+# the coefficients that follows formation)
 IN_LO = np.array([QS_RANGE[0], 0.0, PT_RANGE[0], 0.0, 0.0], np.float32)
 IN_HI = np.array([QS_RANGE[1], MASSES[-1], PT_RANGE[1], 0.2, TAU_MAX], np.float32)
 
@@ -112,7 +115,7 @@ def rows(params, curves):
     for (qs, m, pt), (tau, kap, dpt) in zip(params, curves):
         tf = tau_form(m, pt)
         for t, k, d in zip(tau, kap, dpt):
-            X.append((qs, m, pt, tf, t))
+            X.append((qs, m, pt, tf, t - tf))
             Y.append((k, d))
     return np.asarray(X, np.float32), np.asarray(Y, np.float32)
 
@@ -122,18 +125,25 @@ class Surrogate:
         self.net = G.MLP(5, 256, 3, 2, max_batch=4096, max_samples=max_samples, seed=seed)
         self.trained = False
 
+    # the Glasma has one physical scale, Q_s: the network models kappa / Q_s^3
+    # and <dp_T^2> / Q_s^2 (dimensionless up to the mass and p_T dependence)
+    OUT_POWERS = np.array([3.0, 2.0], np.float32)
+
     def fit(self, X, Y, epochs=40, batch=4096, lr=1e-3, seed=0):
-        mu, sd = Y.mean(0), Y.std(0)
+        Ys = Y / X[:, :1] ** self.OUT_POWERS[None, :]
+        mu, sd = Ys.mean(0), Ys.std(0)
         sd = np.where(sd > 0, sd, 1.0)
         self.net.set_scaling(IN_LO, IN_HI, mu, sd)
+        self.net.set_output_power(0, self.OUT_POWERS)
         losses = self.net.train(X, Y, epochs=epochs, batch=batch, lr=lr, seed=seed)
         self.trained = True
         return losses
 
     def predict(self, qs, m, pt, tau):
         tau = np.asarray(tau, np.float64)
+        tf = tau_form(m, pt)
         X = np.stack([np.full_like(tau, qs), np.full_like(tau, m), np.full_like(tau, pt),
-                      np.full_like(tau, tau_form(m, pt)), tau], axis=1).astype(np.float32)
+                      np.full_like(tau, tf), tau - tf], axis=1).astype(np.float32)
         Y = self.net.infer(X).cpu().numpy()
         return Y[:, 0], Y[:, 1]
 
@@ -150,3 +160,96 @@ class Surrogate:
 def curve_error(pred, ref):
     """max |pred - ref| / max |ref| over the curve."""
     return float(np.abs(pred - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_part_train=10000,
+             n_part_fine=100000, n_part_heldout=100000, epochs=60, fine_epochs=120, seed=20230718,
+             log=print):
+    """The surrogate workload end to end on the GPU.
+
+    1. training data from the solver: n_train_coarse runs at 256^2 and
+       n_train_fine runs at 512^2 (L = 10 fm, n_part_train particles each);
+    2. held-out solver runs at 512^2 with n_part_heldout particles, and for
+       the first n_noise of them a second solver run with other seeds (the
+       noise floor: what a perfect surrogate could reach against one run);
+    3. network A trained on the 256^2 runs only, network B the same then
+       fine-tuned on the 512^2 runs;
+    4. errors on the held-out curves (max |pred - solver| / max |solver|) and
+       the time per kappa(tau) curve of the network and of the solver.
+    """
+    import torch
+    rep = {}
+    t = time.perf_counter()
+    pc = draw_params(n_train_coarse, seed)
+    cc, tpc_c = solver_curves(pc, 256, 10.0, n_part_train, seed + 1)
+    Xc, Yc = rows(pc, cc)
+    pf = draw_params(n_train_fine, seed + 2)
+    cf, tpc_f = solver_curves(pf, 512, 10.0, n_part_fine, seed + 3)
+    Xf, Yf = rows(pf, cf)
+    rep["data_s"] = time.perf_counter() - t
+    rep["train_rows"] = [int(len(Xc)), int(len(Xf))]
+    log("surrogate: data %.1f s, rows %s" % (rep["data_s"], rep["train_rows"]))
+    hp = draw_params(n_heldout, seed + 4)
+    hc, tpc_h = solver_curves(hp, 512, 10.0, n_part_heldout, seed + 5)
+    hc2, _ = solver_curves(hp[:n_noise], 512, 10.0, n_part_heldout, seed + 6)
+    rep["solver_s_per_curve"] = tpc_h
+    noise = [curve_error(a[1], np.interp(a[0], b[0], b[1])) for a, b in zip(hc[:n_noise], hc2)]
+    rep["noise_floor_kappa"] = {"median": float(np.median(noise)), "max": float(np.max(noise))}
+
+    def judge(sur):
+        ek, ed = [], []
+        for (qs, m, pt), (tau, k, d) in zip(hp, hc):
+            kp, dp = sur.predict(qs, m, pt, tau)
+            ek.append(curve_error(kp, k))
+            ed.append(curve_error(dp, d))
+        ek, ed = np.array(ek), np.array(ed)
+        out = {"kappa_median": float(np.median(ek)), "kappa_p90": float(np.percentile(ek, 90)),
+               "kappa_max": float(np.max(ek)), "dpT2_median": float(np.median(ed)),
+               "dpT2_max": float(np.max(ed))}
+        ms = np.array([m for _, m, _ in hp])
+        for mm in MASSES:
+            sel = ms == mm
+            if sel.any():
+                out["kappa_median_m%.2f" % mm] = float(np.median(ek[sel]))
+        return out
+
+    t = time.perf_counter()
+    A = Surrogate(seed=seed, max_samples=max(len(Xc), len(Xf)) + 1)
+    la = A.fit(Xc, Yc, epochs=epochs, lr=1e-3, seed=1)
+    B = Surrogate(seed=seed, max_samples=max(len(Xc), len(Xf)) + 1)
+    B.fit(Xc, Yc, epochs=epochs, lr=1e-3, seed=1)
+    # fine-tune on the 512^2 runs with the coarse runs' output scaling kept
+    lb = B.net.train(Xf, Yf, epochs=fine_epochs, batch=4096, lr=3e-4, seed=2)
+    torch.cuda.synchronize()
+    rep["train_s"] = time.perf_counter() - t
+    rep["loss_final"] = [float(la[-1]), float(lb[-1])]
+    rep["coarse_only"] = judge(A)
+    rep["fine_tuned"] = judge(B)
+    tau = np.linspace(0.0025, 1.0, 410)
+    B.predict(2.0, 4.18, 2.0, tau)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = 50
+    for _ in range(reps):
+        B.predict(2.0, 4.18, 2.0, tau)
+    torch.cuda.synchronize()
+    rep["mlp_s_per_curve"] = (time.perf_counter() - t) / reps
+    # a batch of curves in one inference call
+    tf = tau_form(4.18, 2.0)
+    Xq = np.tile(np.stack([np.full(410, 2.0), np.full(410, 4.18), np.full(410, 2.0),
+                           np.full(410, tf), tau - tf], axis=1), (64, 1)).astype(np.float32)
+    Xd = B.net._dev(Xq, 5)
+    B.net.infer(Xd)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        B.net.infer(Xd)
+    torch.cuda.synchronize()
+    rep["mlp_s_per_curve_batched64"] = (time.perf_counter() - t) / reps / 64
+    rep["speedup"] = rep["solver_s_per_curve"] / rep["mlp_s_per_curve"]
+    rep["speedup_batched"] = rep["solver_s_per_curve"] / rep["mlp_s_per_curve_batched64"]
+    # fallback outside the training domain goes to the solver
+    _, _, used = B.query(3.5, 1.27, 2.0, tau[:100], N=64, L_fm=10.0 * 64 / 512, n_particles=1000)
+    rep["fallback_outside_domain"] = bool(used)
+    log("surrogate: %s" % rep)
+    return rep
