@@ -143,6 +143,53 @@ def cpu_baseline(prec_unused, budget_s=20.0):
             "particle_steps_per_s": N_PER * len(SPECIES) / per_step}
 
 
+def copy_calibration(mib):
+    """A plain device-to-device copy of a known size (read mib MiB, write mib MiB),
+    run three times: the reference for scaling the FETCH_SIZE / WRITE_SIZE
+    hardware counters to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                      "launches": 3}))
+
+
+def summarize(path, command):
+    """Markdown summary of a rocprofv3 output directory: per-kernel durations
+    (kernel_stats.csv) and mean per-dispatch counter values
+    (counter_collection.csv), whichever are present."""
+    import csv
+    import glob
+    lines = ["Command:", "", "```", command, "```", ""]
+    for f in sorted(glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True)):
+        lines += ["| kernel | calls | avg µs | total ms | % |", "|---|---|---|---|---|"]
+        for r in csv.DictReader(open(f)):
+            name = r["Name"].split("(")[0].replace("void ", "")
+            lines.append("| %s | %s | %.2f | %.2f | %.1f |" % (
+                name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
+                float(r["Percentage"])))
+        lines.append("")
+    for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
+        acc = {}
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            key = (name, r["Counter_Name"])
+            a = acc.setdefault(key, [0.0, 0, r.get("VGPR_Count", ""), r.get("Accum_VGPR_Count", "")])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+        lines += ["| kernel | counter | dispatches | mean per dispatch | VGPR | AGPR |",
+                  "|---|---|---|---|---|---|"]
+        for (name, cn), (tot, cnt, vg, ag) in sorted(acc.items(), key=lambda kv: -kv[1][0]):
+            lines.append("| %s | %s | %d | %.1f | %s | %s |" % (name, cn, cnt, tot / cnt, vg, ag))
+        lines.append("")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +201,17 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-event batched FP32 workload")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache for the batch")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--summarize", nargs=2, metavar=("DIR", "COMMAND"),
+                    help="print a markdown summary of a rocprofv3 output directory and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize)
+        return
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
               "(events shard across GPUs without exchange; see the design notes)" % args.gpus,

@@ -18,8 +18,9 @@
 //
 // Kernel design: one thread per site, 2-D workgroups of 32 x 8 sites so that
 // a wave reads 32 consecutive x of two rows from every structure-of-arrays
-// plane (coalesced), and the neighbour reads of the stencil hit the L2 cache
-// of the XCD that owns the tile.
+// plane (coalesced).  Tiles are numbered so that each XCD owns one band of
+// rows (xcd_remap): the neighbour reads of the stencil then hit the L2 of the
+// XCD that owns the tile instead of refetching halo lines from memory.
 #include "fields_dev.hpp"
 
 namespace gl {
@@ -29,8 +30,10 @@ constexpr int TX = 32, TY = 8;
 template <typename T>
 __global__ void __launch_bounds__(TX *TY)
 k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T tau, T dtau, T tau_h, int reunit) {
-    int ix = blockIdx.x * TX + threadIdx.x;
-    int iy = blockIdx.y * TY + threadIdx.y;
+    const int tx = (N + TX - 1) / TX;
+    const int l = (int)xcd_remap(blockIdx.x, gridDim.x);
+    int ix = (l % tx) * TX + threadIdx.x;
+    int iy = (l / tx) * TY + threadIdx.y;
     if (ix >= N || iy >= N) return;
     field_step_site<T>(N, in, out, ix, iy, tau, dtau, tau_h, reunit);
 }
@@ -45,8 +48,10 @@ k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T tau, T dtau, T tau_h, i
 template <typename T>
 __global__ void __launch_bounds__(TX *TY)
 k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) {
-    int ix = blockIdx.x * TX + threadIdx.x;
-    int iy = blockIdx.y * TY + threadIdx.y;
+    const int tx = (N + TX - 1) / TX;
+    const int l = (int)xcd_remap(blockIdx.x, gridDim.x);
+    int ix = (l % tx) * TX + threadIdx.x;
+    int iy = (l / tx) * TY + threadIdx.y;
     if (ix >= N || iy >= N) return;
     site_fields_site<T>(N, o, nw, F, ix, iy, tau);
 }
@@ -166,7 +171,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
 template <typename T>
 hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, double tau,
                              double dtau, int reunit) {
-    dim3 grid((N + TX - 1) / TX, (N + TY - 1) / TY), block(TX, TY);
+    dim3 grid(((N + TX - 1) / TX) * ((N + TY - 1) / TY)), block(TX, TY);
     hipLaunchKernelGGL(k_field_step<T>, grid, block, 0, st, N, in, out, (T)tau, (T)dtau,
                        (T)(tau + 0.5 * dtau), reunit);
     return hipGetLastError();
@@ -175,7 +180,7 @@ hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T
 template <typename T>
 hipError_t launch_site_fields(hipStream_t st, int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *F,
                               double tau) {
-    dim3 grid((N + TX - 1) / TX, (N + TY - 1) / TY), block(TX, TY);
+    dim3 grid(((N + TX - 1) / TX) * ((N + TY - 1) / TY)), block(TX, TY);
     hipLaunchKernelGGL(k_site_fields<T>, grid, block, 0, st, N, o, nw, F, (T)tau);
     return hipGetLastError();
 }

@@ -57,7 +57,7 @@ __device__ __forceinline__ M3<T> comm_term(const M3<T> &ph, const M3<T> &Ph, T i
 template <typename T>
 __device__ __forceinline__ void field_step_site(int N, const FieldPtrs<T> &in, const FieldPtrs<T> &out, int ix,
                                                 int iy, T tau, T dtau, T tau_h, int reunit) {
-    const size_t n2 = (size_t)N * N;
+    const size_t n2 = plane_pitch(N);
     Nbr nb = neighbours(ix, iy, N);
     const T *U1 = in.U, *U2 = in.U + 18 * n2;
 
@@ -173,7 +173,7 @@ __device__ __forceinline__ void field_step_site(int N, const FieldPtrs<T> &in, c
 template <typename T>
 __device__ __forceinline__ void site_fields_site(int N, const FieldPtrs<T> &o, const FieldPtrs<T> &nw,
                                                  T *__restrict__ F, int ix, int iy, T tau) {
-    const size_t n2 = (size_t)N * N;
+    const size_t n2 = plane_pitch(N);
     Nbr nb = neighbours(ix, iy, N);
     const T *U1 = o.U, *U2 = o.U + 18 * n2;
     const T inv_tau = T(1) / tau;

@@ -10,6 +10,21 @@ constexpr int kMaxSpecies = 16;
 constexpr int kPushBlock = 256;   // particles per push workgroup
 constexpr int kSiteRec = 56;      // site-field planes: Ex, Ey, Ez, Bx, By, Bz, phi (8 reals each)
 
+#ifndef GL_PLANE_PAD
+#define GL_PLANE_PAD 0
+#endif
+// distance between consecutive planes of a lattice quantity, in elements
+__host__ __device__ __forceinline__ size_t plane_pitch(int N) { return (size_t)N * N + GL_PLANE_PAD; }
+
+// Workgroup b of a grid of nb runs on XCD b mod 8.  Renumber the grid so
+// that every XCD gets one contiguous run of logical blocks (row bands of a
+// lattice, neighbouring particle blocks), and the stencil's neighbour reads
+// hit that XCD's L2: XCD x owns nb/8 (+1 for x < nb mod 8) blocks.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, j = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // One field state in structure-of-arrays planes of n2 = N*N values:
 //   U   [2][18][n2], E [2][8][n2], phi [8][n2], pi [8][n2]
 template <typename T>

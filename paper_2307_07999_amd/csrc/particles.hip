@@ -25,11 +25,13 @@ template <typename T>
 __global__ void __launch_bounds__(kPushBlock)
 k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restrict__ F,
        SpeciesTab<T> tab, int n_species, int n, T dtau, double *__restrict__ partials) {
-    const int64_t i = (int64_t)blockIdx.x * kPushBlock + threadIdx.x;
+    // neighbouring blocks (neighbouring cells, the particles being sorted) on one XCD
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = blk * kPushBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int s = -1;
     if (i < n_slots) s = push_particle<T>(N, P, i, f, F, tab, n, dtau, acc);
-    block_species_reduce(s, acc, n_species, partials + (size_t)blockIdx.x * n_species * 4);
+    block_species_reduce(s, acc, n_species, partials + (size_t)blk * n_species * 4);
 }
 
 // series row [kMaxSpecies][4]: species s sums the partial rows of all push
