@@ -199,8 +199,9 @@ gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t 
 
 /* Kernel timing with HIP events recorded on the event's stream around every
  * launch of the hot-path kernels while enabled.  gl_profile_read synchronises
- * the stream and returns, per kernel class (0 field step, 1 site fields,
- * 2 particle push, 3 series reduction), the summed milliseconds and the
+ * the stream and returns, per kernel class (0 field step, which also writes
+ * the site fields when the event has particles, 1 unused, 2 particle push,
+ * 3 series reduction), the summed milliseconds and the
  * launch counts since the last read, then clears them.  Creates HIP events
  * only (no device memory). */
 #define GL_PROF_KERNELS 4

@@ -14,7 +14,7 @@ struct BatchEv {
     int64_t n_slots;
     FieldPtrs<T> f[2];     // f[p] and f[p ^ 1]: state at step n and at n + 1 for parity p
     PartPtrs<T> P[2];      // particle buffers; the current one alternates at each sort
-    T *F;                  // site-field planes
+    T *F;                  // site-field planes, written by the field phase when n_species > 0
     double *partials;      // [n_slots / kPushBlock][n_species][4]
     double *series;        // [max_steps][kMaxSpecies][4]
     SpeciesTab<T> tab;
@@ -28,7 +28,7 @@ constexpr int kBatchShapes = 3;   // field-kernel tiles 32x8, 64x4, 16x16
 
 template <typename T>
 hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs, const int2 *tiles, int64_t total,
-                               int fpar, const BatchCtl *ctl, double dtau, int grid, bool site_fields);
+                               int fpar, const BatchCtl *ctl, double dtau, int grid);
 template <typename T>
 hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *blocks, int64_t total, int fpar,
                              int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events);

@@ -42,24 +42,9 @@ k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles
         const int ix = (w.y % tx) * TX + threadIdx.x, iy = (w.y / tx) * TY + threadIdx.y;
         if (ix < e.N && iy < e.N) {
             int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
-            field_step_site<T>(e.N, e.f[fpar], e.f[fpar ^ 1], ix, iy, tau, dtau, tau_h, reunit);
+            field_step_site<T>(e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, ix, iy, tau,
+                               dtau, tau_h, reunit);
         }
-    }
-}
-
-template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY)
-k_batch_site_fields(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total,
-                    int fpar, const BatchCtl *__restrict__ ctl, T dtau) {
-    const T tau = dtau * (T)ctl->n;
-    int64_t stride, end;
-    for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
-        const int2 w = tiles[t];
-        const BatchEv<T> &e = evs[w.x];
-        if (e.n_species == 0) continue;
-        const int tx = (e.N + TX - 1) / TX;
-        const int ix = (w.y % tx) * TX + threadIdx.x, iy = (w.y / tx) * TY + threadIdx.y;
-        if (ix < e.N && iy < e.N) site_fields_site<T>(e.N, e.f[fpar], e.f[fpar ^ 1], e.F, ix, iy, tau);
     }
 }
 
@@ -114,16 +99,13 @@ __global__ void k_batch_advance(BatchCtl *ctl) {
 
 template <typename T>
 hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs, const int2 *tiles, int64_t total,
-                               int fpar, const BatchCtl *ctl, double dtau, int grid, bool site_fields) {
+                               int fpar, const BatchCtl *ctl, double dtau, int grid) {
     if (total <= 0) return hipSuccess;
     unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
 #define GL_SHAPE(TXv, TYv)                                                                                    \
     {                                                                                                         \
         hipLaunchKernelGGL((k_batch_field<T, TXv, TYv>), dim3(g), dim3(TXv, TYv), 0, st, evs, tiles, total,   \
                            fpar, ctl, (T)dtau);                                                               \
-        if (site_fields)                                                                                      \
-            hipLaunchKernelGGL((k_batch_site_fields<T, TXv, TYv>), dim3(g), dim3(TXv, TYv), 0, st, evs, tiles, \
-                               total, fpar, ctl, (T)dtau);                                                    \
     }
     switch (shape) {
         case 0: GL_SHAPE(32, 8) break;
@@ -150,7 +132,7 @@ hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *
 
 #define GL_INST(T)                                                                                          \
     template hipError_t launch_batch_fields<T>(hipStream_t, int, const BatchEv<T> *, const int2 *, int64_t, int, \
-                                               const BatchCtl *, double, int, bool);                         \
+                                               const BatchCtl *, double, int);                               \
     template hipError_t launch_batch_push<T>(hipStream_t, const BatchEv<T> *, const int2 *, int64_t, int, int,  \
                                              const BatchCtl *, double, int, int);
 GL_INST(double)

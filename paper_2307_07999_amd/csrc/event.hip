@@ -212,7 +212,8 @@ gl_status prof_end(gl_event *ev, size_t idx) {
         if (ps_) return ps_;                                    \
     } while (0)
 
-// one field step n -> n+1; site fields F^n when the event has particles
+// one field step n -> n+1; site fields F^n in the same pass when the event
+// has particles
 template <typename T>
 gl_status field_step(gl_event *ev, bool site_fields) {
     const int nxt = 1 - ev->cur;
@@ -221,11 +222,8 @@ gl_status field_step(gl_event *ev, bool site_fields) {
     if (!ev->fp64() && ev->desc.reunit_every > 0 &&
         ev->n % ev->desc.reunit_every == ev->desc.reunit_every - 1)
         reunit = 1;
-    PROF(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt), tau,
-                                      ev->dtau, reunit)));
-    if (site_fields)
-        PROF(ev, 1, (launch_site_fields<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
-                                           (T *)(ev->ws + ev->L.F), tau)));
+    PROF(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
+                                      site_fields ? (T *)(ev->ws + ev->L.F) : nullptr, tau, ev->dtau, reunit)));
     ev->cur = nxt;
     ev->n += 1;
     return GL_OK;
@@ -361,6 +359,18 @@ gl_status copy_out(gl_event *ev, double *host, const void *dev, size_t n) {
     HIP_TRY(hipMemcpyAsync(tmp.data(), dev, n * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
     for (size_t i = 0; i < n; i++) host[i] = (double)tmp[i];
+    return GL_OK;
+}
+
+template <typename T>
+gl_status get_site_fields_t(gl_event *ev, double *F) {
+    // planes [6][8][n2]; E_x and E_y are the sums of their two stored halves
+    const size_t n2 = ev->n2;
+    std::vector<T> tmp((size_t)kSiteRec * n2);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), ev->ws + ev->L.F, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    for (size_t i = 0; i < 48 * n2; i++) F[i] = (double)tmp[i];
+    for (size_t i = 0; i < 16 * n2; i++) F[i] += (double)tmp[48 * n2 + i];
     return GL_OK;
 }
 
@@ -790,9 +800,7 @@ gl_status gl_get_state(gl_event *ev, double *U, double *E, double *phi, double *
 gl_status gl_get_site_fields(gl_event *ev, double *F) {
     if (check_ev(ev) || !F) return fail(GL_EINVAL, "null argument");
     if (ev->slots_used == 0) return fail(GL_ESTATE, "site fields are only computed when the event has particles");
-    // the first 48 planes are [6][8][n2]
-    return ev->fp64() ? copy_out<double>(ev, F, ev->ws + ev->L.F, 48 * ev->n2)
-                      : copy_out<float>(ev, F, ev->ws + ev->L.F, 48 * ev->n2);
+    return ev->fp64() ? get_site_fields_t<double>(ev, F) : get_site_fields_t<float>(ev, F);
 }
 
 gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_desc *sp, int64_t n,
@@ -1001,7 +1009,7 @@ gl_status batch_step(gl_batch *b) {
     const BatchEv<T> *d = (const BatchEv<T> *)(b->ws + b->desc);
     const BatchCtl *ctl = (const BatchCtl *)(b->ws + b->ctl);
     HIP_TRY(launch_batch_fields<T>(b->stream, b->shape, d, (const int2 *)(b->ws + b->tiles[b->shape]),
-                                   b->total_tiles[b->shape], b->fpar, ctl, b->dtau, grid, b->any_particles));
+                                   b->total_tiles[b->shape], b->fpar, ctl, b->dtau, grid));
     HIP_TRY(launch_batch_push<T>(b->stream, d, (const int2 *)(b->ws + b->pblocks), b->total_pblocks, b->fpar,
                                  b->ppar, ctl, b->dtau, grid, (int)b->evs.size()));
     b->fpar ^= 1;
@@ -1125,13 +1133,12 @@ gl_status time_fields(gl_batch *b, int shape, int mult, float *ms) {
     HIP_TRY(hipEventCreate(&e1));
     // the field phases read the state at parity fpar and only write the
     // next-step buffer and the site fields: repeating them changes nothing
-    HIP_TRY(launch_batch_fields<T>(b->stream, shape, d, tiles, b->total_tiles[shape], b->fpar, ctl, b->dtau, grid,
-                                   b->any_particles));
+    HIP_TRY(launch_batch_fields<T>(b->stream, shape, d, tiles, b->total_tiles[shape], b->fpar, ctl, b->dtau, grid));
     HIP_TRY(hipEventRecord(e0, b->stream));
     const int reps = 3;
     for (int r = 0; r < reps; r++)
         HIP_TRY(launch_batch_fields<T>(b->stream, shape, d, tiles, b->total_tiles[shape], b->fpar, ctl, b->dtau,
-                                       grid, b->any_particles));
+                                       grid));
     HIP_TRY(hipEventRecord(e1, b->stream));
     HIP_TRY(hipEventSynchronize(e1));
     HIP_TRY(hipEventElapsedTime(ms, e0, e1));

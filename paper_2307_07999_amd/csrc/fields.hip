@@ -29,31 +29,13 @@ constexpr int TX = 32, TY = 8;
 
 template <typename T>
 __global__ void __launch_bounds__(TX *TY)
-k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T tau, T dtau, T tau_h, int reunit) {
+k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T *__restrict__ F, T tau, T dtau, T tau_h, int reunit) {
     const int tx = (N + TX - 1) / TX;
     const int l = (int)xcd_remap(blockIdx.x, gridDim.x);
     int ix = (l % tx) * TX + threadIdx.x;
     int iy = (l / tx) * TY + threadIdx.y;
     if (ix >= N || iy >= N) return;
-    field_step_site<T>(N, in, out, ix, iy, tau, dtau, tau_h, reunit);
-}
-
-// Local-frame site fields at tau_n (NGP reading of the colored particle-in-cell
-// coupling): E_i from the time- and link-averaged E_i, E_z = pi averaged in
-// time, B_x = -D_2 phi / tau, B_y = D_1 phi / tau (central, covariant), and
-// B_z = -(clover of the four plaquettes at x).  Written as planes
-// F [56][n2] = (Ex, Ey, Ez, Bx, By, Bz, phi^n) x 8 components (coalesced
-// stores); the particles are kept sorted by cell so that their gathers from
-// these planes are coalesced too.
-template <typename T>
-__global__ void __launch_bounds__(TX *TY)
-k_site_fields(int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *__restrict__ F, T tau) {
-    const int tx = (N + TX - 1) / TX;
-    const int l = (int)xcd_remap(blockIdx.x, gridDim.x);
-    int ix = (l % tx) * TX + threadIdx.x;
-    int iy = (l / tx) * TY + threadIdx.y;
-    if (ix >= N || iy >= N) return;
-    site_fields_site<T>(N, o, nw, F, ix, iy, tau);
+    field_step_site<T>(N, in, out, F, ix, iy, tau, dtau, tau_h, reunit);
 }
 
 // Diagnostics per site, reduced per workgroup in FP64:
@@ -169,19 +151,11 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
 }
 
 template <typename T>
-hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, double tau,
+hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F, double tau,
                              double dtau, int reunit) {
     dim3 grid(((N + TX - 1) / TX) * ((N + TY - 1) / TY)), block(TX, TY);
-    hipLaunchKernelGGL(k_field_step<T>, grid, block, 0, st, N, in, out, (T)tau, (T)dtau,
+    hipLaunchKernelGGL(k_field_step<T>, grid, block, 0, st, N, in, out, F, (T)tau, (T)dtau,
                        (T)(tau + 0.5 * dtau), reunit);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_site_fields(hipStream_t st, int N, FieldPtrs<T> o, FieldPtrs<T> nw, T *F,
-                              double tau) {
-    dim3 grid(((N + TX - 1) / TX) * ((N + TY - 1) / TY)), block(TX, TY);
-    hipLaunchKernelGGL(k_site_fields<T>, grid, block, 0, st, N, o, nw, F, (T)tau);
     return hipGetLastError();
 }
 
@@ -195,10 +169,8 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
 }
 
 #define GL_INST(T)                                                                           \
-    template hipError_t launch_field_step<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, double, \
-                                             double, int);                                   \
-    template hipError_t launch_site_fields<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, T *,  \
-                                              double);                                       \
+    template hipError_t launch_field_step<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, T *,    \
+                                             double, double, int);                           \
     template hipError_t launch_diag<T>(hipStream_t, int, FieldPtrs<T>, double, double *, int *);
 GL_INST(double)
 GL_INST(float)

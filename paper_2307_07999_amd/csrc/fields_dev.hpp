@@ -53,219 +53,182 @@ __device__ __forceinline__ M3<T> comm_term(const M3<T> &ph, const M3<T> &Ph, T i
     return r;
 }
 
-// one site of the leapfrog step; (ix, iy) must lie on the lattice
+// One site of the leapfrog step n -> n+1; (ix, iy) must lie on the lattice.
+// If F is non-null the same pass writes the local-frame site fields at tau_n
+// that the particle push reads (NGP reading of the colored particle-in-cell
+// coupling), reusing the plaquettes and transported scalars of the forces:
+//   E_i = 1/2 [Ebar_i(x) + U_i^dag(x-i) Ebar_i(x-i) U_i(x-i)] / tau,
+//         Ebar = (E^{n-1/2} + E^{n+1/2}) / 2,
+//   E_z = (pi^{n-1/2} + pi^{n+1/2}) / 2,
+//   B_x = -D_2 phi / tau, B_y = D_1 phi / tau, D_i phi = (Phi_{+i} - Phi_{-i}) / 2,
+//   B_z = -(1/4) (sum of the four plaquettes at x, each transported to x).
+// The second half of E_i belongs to the site x+i; this thread owns the link
+// U_i(x) and Ebar_i(x) it needs, so it stores that half at x+i in a plane of
+// its own (slots 48..63) and the push adds the two halves.
+// Keeps the instruction scheduler from hoisting the next phase's loads above
+// this point: with every load of the step in flight at once the kernel needs
+// more than twice the registers, and the lost occupancy costs more than the
+// overlap gains.
+__device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// E_i^{n+1/2}(x) and U_i^{n+1}(x) from the force fe; with F, also this
+// site's half of the electric site field and the transported half of x+i
 template <typename T>
-__device__ __forceinline__ void field_step_site(int N, const FieldPtrs<T> &in, const FieldPtrs<T> &out, int ix,
-                                                int iy, T tau, T dtau, T tau_h, int reunit) {
-    const size_t n2 = plane_pitch(N);
-    Nbr nb = neighbours(ix, iy, N);
-    const T *U1 = in.U, *U2 = in.U + 18 * n2;
-
-    const T inv_tau = T(1) / tau;
-    M3<T> ph = [&] { T v[8]; load_a(in.phi, n2, nb.x, v); return herm_from_alg(v); }();
-
-    T fe1[8], fe2[8], fpi[8];
-    {
-        M3<T> u1x = load_m(U1, n2, nb.x);
-        M3<T> u2x = load_m(U2, n2, nb.x);
-        M3<T> Px;
-        {
-            M3<T> u2xp1 = load_m(U2, n2, nb.xp1);
-            M3<T> u1xp2 = load_m(U1, n2, nb.xp2);
-            M3<T> P = plaq(u1x, u2xp1, u1xp2, u2x);
-            T pa[8];
-            alg_proj(P, pa);
-            Px = herm_from_alg(pa);
-        }
-        // E_1 force: -tau([P(x)] - U_2^dag(x-2)[P(x-2)]U_2(x-2))
-        {
-            M3<T> u2m = load_m(U2, n2, nb.xm2);
-            M3<T> u1m = load_m(U1, n2, nb.xm2);
-            M3<T> u2pm = load_m(U2, n2, nb.xp1m2);
-            M3<T> P = plaq(u1m, u2pm, u1x, u2m);
-            T pa[8];
-            alg_proj(P, pa);
-            T t[8];
-            transport_dn(u2m, herm_from_alg(pa), t);
-            T px[8];
-            alg_from_herm(Px, px);
-#pragma unroll
-            for (int a = 0; a < 8; a++) fe1[a] = -tau * (px[a] - t[a]);
-        }
-        // E_2 force: -tau(U_1^dag(x-1)[P(x-1)]U_1(x-1) - [P(x)])
-        {
-            M3<T> u1m = load_m(U1, n2, nb.xm1);
-            M3<T> u2m = load_m(U2, n2, nb.xm1);
-            M3<T> u1mp = load_m(U1, n2, nb.xm1p2);
-            M3<T> P = plaq(u1m, u2x, u1mp, u2m);
-            T pa[8];
-            alg_proj(P, pa);
-            T t[8];
-            transport_dn(u1m, herm_from_alg(pa), t);
-            T px[8];
-            alg_from_herm(Px, px);
-#pragma unroll
-            for (int a = 0; a < 8; a++) fe2[a] = -tau * (t[a] - px[a]);
-        }
-        // scalar couplings: Phi_{+-i}
-        M3<T> lap = m_zero<T>();
-        {
-            T v[8];
-            load_a(in.phi, n2, nb.xp1, v);
-            M3<T> Pf = mul_nd(mul(u1x, herm_from_alg(v)), u1x);
-            T c[8];
-            alg_from_herm(comm_term(ph, Pf, inv_tau), c);
-#pragma unroll
-            for (int a = 0; a < 8; a++) fe1[a] += c[a];
-            lap = add(lap, Pf);
-            load_a(in.phi, n2, nb.xp2, v);
-            Pf = mul_nd(mul(u2x, herm_from_alg(v)), u2x);
-            alg_from_herm(comm_term(ph, Pf, inv_tau), c);
-#pragma unroll
-            for (int a = 0; a < 8; a++) fe2[a] += c[a];
-            lap = add(lap, Pf);
-        }
-        {
-            T v[8];
-            M3<T> u1m = load_m(U1, n2, nb.xm1);
-            load_a(in.phi, n2, nb.xm1, v);
-            lap = add(lap, mul(mul_dn(u1m, herm_from_alg(v)), u1m));
-            M3<T> u2m = load_m(U2, n2, nb.xm2);
-            load_a(in.phi, n2, nb.xm2, v);
-            lap = add(lap, mul(mul_dn(u2m, herm_from_alg(v)), u2m));
-        }
-        T l[8], p0[8];
-        alg_from_herm(lap, l);
-        alg_from_herm(ph, p0);
-#pragma unroll
-        for (int a = 0; a < 8; a++) fpi[a] = inv_tau * (l[a] - T(4) * p0[a]);
-
-        // updates
-        T e[8];
-        const T s = dtau / tau_h;
-        load_a(in.E, n2, nb.x, e);
-#pragma unroll
-        for (int a = 0; a < 8; a++) e[a] += dtau * fe1[a];
-        store_a(out.E, n2, nb.x, e);
-        M3<T> un = mul(expi_alg(e, s), u1x);
-        if (reunit) un = reunitarize(un);
-        store_m(out.U, n2, nb.x, un);
-        load_a(in.E + 8 * n2, n2, nb.x, e);
-#pragma unroll
-        for (int a = 0; a < 8; a++) e[a] += dtau * fe2[a];
-        store_a(out.E + 8 * n2, n2, nb.x, e);
-        un = mul(expi_alg(e, s), u2x);
-        if (reunit) un = reunitarize(un);
-        store_m(out.U + 18 * n2, n2, nb.x, un);
-    }
-    T p[8], f[8];
-    load_a(in.pi, n2, nb.x, p);
-    load_a(in.phi, n2, nb.x, f);
+__device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const T *__restrict__ Uin,
+                                            T *__restrict__ Uout, size_t n2, size_t x, size_t xpi, const T *fe, T dtau,
+                                            T s, int reunit, T *__restrict__ F, int slot, T inv_tau) {
+    T e[8], eb[8];
+    load_a(Ein, n2, x, e);
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        p[a] += dtau * fpi[a];
-        f[a] += dtau * tau_h * p[a];
+        eb[a] = e[a];
+        e[a] += dtau * fe[a];
     }
-    store_a(out.pi, n2, nb.x, p);
-    store_a(out.phi, n2, nb.x, f);
+    store_a(Eout, n2, x, e);
+    const M3<T> u = load_m(Uin, n2, x);
+    M3<T> un = mul(expi_alg(e, s), u);
+    if (reunit) un = reunitarize(un);
+    store_m(Uout, n2, x, un);
+    if (F) {
+        T t[8];
+#pragma unroll
+        for (int a = 0; a < 8; a++) eb[a] = T(0.25) * inv_tau * (eb[a] + e[a]);   // Ebar / (2 tau)
+        store_rec(F, n2, x, slot, eb);
+        transport_dn(u, herm_from_alg(eb), t);
+        store_rec(F, n2, xpi, 48 + slot, t);
+    }
 }
 
+// Phi_{+i}(x) = U_i(x) phi(x+i) U_i^dag(x) and Phi_{-i}(x) = U_i^dag(x-i) phi(x-i) U_i(x-i)
+// as algebra components; adds -(i/tau)[phi(x), Phi_{+i}] to the E_i force
 template <typename T>
-__device__ __forceinline__ void site_fields_site(int N, const FieldPtrs<T> &o, const FieldPtrs<T> &nw,
-                                                 T *__restrict__ F, int ix, int iy, T tau) {
+__device__ __forceinline__ void scalar_links(const T *__restrict__ Ui, const T *__restrict__ phi, size_t n2, size_t x,
+                                             size_t xp, size_t xm, const T *ph, T inv_tau, T *fe, T *pf, T *pb) {
+    T v[8], c[8];
+    const M3<T> u = load_m(Ui, n2, x);
+    load_a(phi, n2, xp, v);
+    M3<T> Pf = mul_nd(mul(u, herm_from_alg(v)), u);
+    alg_from_herm(comm_term(herm_from_alg(ph), Pf, inv_tau), c);
+#pragma unroll
+    for (int a = 0; a < 8; a++) fe[a] += c[a];
+    alg_from_herm(Pf, pf);
+    const M3<T> um = load_m(Ui, n2, xm);
+    load_a(phi, n2, xm, v);
+    alg_from_herm(mul(mul_dn(um, herm_from_alg(v)), um), pb);
+}
+
+// One site of the leapfrog step n -> n+1; (ix, iy) must lie on the lattice.
+// If F is non-null the same pass writes the local-frame site fields at tau_n
+// that the particle push reads (NGP reading of the colored particle-in-cell
+// coupling), reusing the plaquettes and transported scalars of the forces:
+//   E_i = 1/2 [Ebar_i(x) + U_i^dag(x-i) Ebar_i(x-i) U_i(x-i)] / tau,
+//         Ebar = (E^{n-1/2} + E^{n+1/2}) / 2,
+//   E_z = (pi^{n-1/2} + pi^{n+1/2}) / 2,
+//   B_x = -D_2 phi / tau, B_y = D_1 phi / tau, D_i phi = (Phi_{+i} - Phi_{-i}) / 2,
+//   B_z = -(1/4) (sum of the four plaquettes at x, each transported to x).
+// The second half of E_i belongs to the site x+i; this thread owns the link
+// U_i(x) and Ebar_i(x) it needs, so it stores that half at x+i in a plane of
+// its own (slots 48..63) and the push adds the two halves.  Each slot is
+// stored as soon as it is known, which keeps few values live.
+template <typename T>
+__device__ __forceinline__ void field_step_site(int N, const FieldPtrs<T> &in, const FieldPtrs<T> &out,
+                                                T *__restrict__ F, int ix, int iy, T tau, T dtau, T tau_h,
+                                                int reunit) {
     const size_t n2 = plane_pitch(N);
-    Nbr nb = neighbours(ix, iy, N);
-    const T *U1 = o.U, *U2 = o.U + 18 * n2;
+    const Nbr nb = neighbours(ix, iy, N);
+    const T *U1 = in.U, *U2 = in.U + 18 * n2;
     const T inv_tau = T(1) / tau;
-    T out[8];
-    // electric: E_i^s = 1/2 [Ebar_i(x) + U_i^dag(x-i) Ebar_i(x-i) U_i(x-i)]
-#pragma unroll
-    for (int d = 0; d < 2; d++) {
-        size_t xm = d == 0 ? nb.xm1 : nb.xm2;
-        const T *Eo = o.E + 8 * n2 * d, *En = nw.E + 8 * n2 * d;
-        T a[8], b[8], t[8];
-        load_a(Eo, n2, nb.x, a);
-        load_a(En, n2, nb.x, b);
-        T c[8], cm[8];
-#pragma unroll
-        for (int k = 0; k < 8; k++) c[k] = T(0.5) * (a[k] + b[k]);
-        load_a(Eo, n2, xm, a);
-        load_a(En, n2, xm, b);
-#pragma unroll
-        for (int k = 0; k < 8; k++) cm[k] = T(0.5) * (a[k] + b[k]);
-        M3<T> um = load_m(d == 0 ? U1 : U2, n2, xm);
-        transport_dn(um, herm_from_alg(cm), t);
-#pragma unroll
-        for (int k = 0; k < 8; k++) out[k] = T(0.5) * inv_tau * (c[k] + t[k]);
-        store_rec(F, n2, nb.x, 8 * d, out);
-    }
+
+    T fe1[8], fe2[8], cl[8];
     {
-        T a[8], b[8];
-        load_a(o.pi, n2, nb.x, a);
-        load_a(nw.pi, n2, nb.x, b);
+        T px[8];   // [P(x)]_X
+        {
+            const M3<T> P = plaq(load_m(U1, n2, nb.x), load_m(U2, n2, nb.xp1), load_m(U1, n2, nb.xp2),
+                                 load_m(U2, n2, nb.x));
+            alg_proj(P, px);
+        }
+        phase_fence();
+        // E_1 force: -tau([P(x)] - U_2^dag(x-2)[P(x-2)]U_2(x-2))
+        {
+            const M3<T> u2m = load_m(U2, n2, nb.xm2);
+            const M3<T> P = plaq(load_m(U1, n2, nb.xm2), load_m(U2, n2, nb.xp1m2), load_m(U1, n2, nb.x), u2m);
+            T pa[8], t[8];
+            alg_proj(P, pa);
+            transport_dn(u2m, herm_from_alg(pa), t);
 #pragma unroll
-        for (int k = 0; k < 8; k++) out[k] = T(0.5) * (a[k] + b[k]);
-        store_rec(F, n2, nb.x, 16, out);
-    }
-    // magnetic from phi: D_i phi = 1/2 (Phi_{+i} - Phi_{-i})
-    M3<T> u1x = load_m(U1, n2, nb.x), u2x = load_m(U2, n2, nb.x);
+            for (int a = 0; a < 8; a++) {
+                fe1[a] = -tau * (px[a] - t[a]);
+                cl[a] = px[a] + t[a];
+            }
+        }
+        phase_fence();
+        // E_2 force: -tau(U_1^dag(x-1)[P(x-1)]U_1(x-1) - [P(x)])
+        {
+            const M3<T> u1m = load_m(U1, n2, nb.xm1);
+            const M3<T> P = plaq(u1m, load_m(U2, n2, nb.x), load_m(U1, n2, nb.xm1p2), load_m(U2, n2, nb.xm1));
+            T pa[8], t[8];
+            alg_proj(P, pa);
+            transport_dn(u1m, herm_from_alg(pa), t);
 #pragma unroll
-    for (int d = 0; d < 2; d++) {
-        size_t xp = d == 0 ? nb.xp1 : nb.xp2, xm = d == 0 ? nb.xm1 : nb.xm2;
-        T v[8];
-        load_a(o.phi, n2, xp, v);
-        const M3<T> &ux = d == 0 ? u1x : u2x;
-        M3<T> Pf = mul_nd(mul(ux, herm_from_alg(v)), ux);
-        M3<T> um = load_m(d == 0 ? U1 : U2, n2, xm);
-        load_a(o.phi, n2, xm, v);
-        M3<T> Pb = mul(mul_dn(um, herm_from_alg(v)), um);
-        T dphi[8];
-        alg_from_herm(sub(Pf, Pb), dphi);
-        // B_x = -D_2 phi / tau (slot 3), B_y = +D_1 phi / tau (slot 4)
-        T sgn = d == 0 ? T(0.5) : T(-0.5);
-#pragma unroll
-        for (int k = 0; k < 8; k++) out[k] = sgn * inv_tau * dphi[k];
-        store_rec(F, n2, nb.x, 8 * (d == 0 ? 4 : 3), out);
+            for (int a = 0; a < 8; a++) {
+                fe2[a] = -tau * (t[a] - px[a]);
+                cl[a] += t[a];
+            }
+        }
     }
-    // clover
-    T cl[8];
-    {
-        M3<T> P = plaq(u1x, load_m(U2, n2, nb.xp1), load_m(U1, n2, nb.xp2), u2x);
-        alg_proj(P, cl);
-    }
-    {
-        M3<T> u1m = load_m(U1, n2, nb.xm1);
-        M3<T> P = plaq(u1m, u2x, load_m(U1, n2, nb.xm1p2), load_m(U2, n2, nb.xm1));
+    phase_fence();
+    if (F) {
+        // fourth clover plaquette P(x-1-2), moved to x along x-1-2 -> x-2 -> x
+        const M3<T> u1mm = load_m(U1, n2, nb.xm1m2);
+        const M3<T> u2m = load_m(U2, n2, nb.xm2);
+        const M3<T> P = plaq(u1mm, u2m, load_m(U1, n2, nb.xm1), load_m(U2, n2, nb.xm1m2));
         T pa[8], t[8];
         alg_proj(P, pa);
-        transport_dn(u1m, herm_from_alg(pa), t);
+        transport_dn(mul(u1mm, u2m), herm_from_alg(pa), t);
 #pragma unroll
-        for (int k = 0; k < 8; k++) cl[k] += t[k];
+        for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
+        store_rec(F, n2, nb.x, 40, t);   // B_z
     }
-    M3<T> u2m = load_m(U2, n2, nb.xm2);
+    phase_fence();
+    // scalar couplings and the pi force (Laplacian of phi)
+    T ph[8], fpi[8];
+    load_a(in.phi, n2, nb.x, ph);
     {
-        M3<T> P = plaq(load_m(U1, n2, nb.xm2), load_m(U2, n2, nb.xp1m2), u1x, u2m);
-        T pa[8], t[8];
-        alg_proj(P, pa);
-        transport_dn(u2m, herm_from_alg(pa), t);
+        T pf[8], pb[8];
+        scalar_links(U1, in.phi, n2, nb.x, nb.xp1, nb.xm1, ph, inv_tau, fe1, pf, pb);
 #pragma unroll
-        for (int k = 0; k < 8; k++) cl[k] += t[k];
+        for (int a = 0; a < 8; a++) {
+            fpi[a] = pf[a] + pb[a];
+            pf[a] = T(0.5) * inv_tau * (pf[a] - pb[a]);
+        }
+        if (F) store_rec(F, n2, nb.x, 32, pf);   // B_y = D_1 phi / tau
+        phase_fence();
+        scalar_links(U2, in.phi, n2, nb.x, nb.xp2, nb.xm2, ph, inv_tau, fe2, pf, pb);
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            fpi[a] = inv_tau * (fpi[a] + pf[a] + pb[a] - T(4) * ph[a]);
+            pf[a] = T(-0.5) * inv_tau * (pf[a] - pb[a]);
+        }
+        if (F) store_rec(F, n2, nb.x, 24, pf);   // B_x = -D_2 phi / tau
     }
-    {
-        M3<T> u1mm = load_m(U1, n2, nb.xm1m2);
-        M3<T> P = plaq(u1mm, u2m, load_m(U1, n2, nb.xm1), load_m(U2, n2, nb.xm1m2));
-        M3<T> W = mul(u1mm, u2m);   // path x-1-2 -> x-2 -> x
-        T pa[8], t[8];
-        alg_proj(P, pa);
-        transport_dn(W, herm_from_alg(pa), t);
+    phase_fence();
+    const T s = dtau / tau_h;
+    update_link(in.E, out.E, U1, out.U, n2, nb.x, nb.xp1, fe1, dtau, s, reunit, F, 0, inv_tau);
+    phase_fence();
+    update_link(in.E + 8 * n2, out.E + 8 * n2, U2, out.U + 18 * n2, n2, nb.x, nb.xp2, fe2, dtau, s, reunit, F, 8,
+                inv_tau);
+    T p[8], ez[8];
+    load_a(in.pi, n2, nb.x, p);
 #pragma unroll
-        for (int k = 0; k < 8; k++) cl[k] += t[k];
+    for (int a = 0; a < 8; a++) {
+        ez[a] = p[a];
+        p[a] += dtau * fpi[a];
+        ph[a] += dtau * tau_h * p[a];
+        ez[a] = T(0.5) * (ez[a] + p[a]);
     }
-#pragma unroll
-    for (int k = 0; k < 8; k++) out[k] = T(-0.25) * cl[k];
-    store_rec(F, n2, nb.x, 40, out);
-    load_a(o.phi, n2, nb.x, out);
-    store_rec(F, n2, nb.x, 48, out);
+    store_a(out.pi, n2, nb.x, p);
+    store_a(out.phi, n2, nb.x, ph);
+    if (F) store_rec(F, n2, nb.x, 16, ez);   // E_z
 }
 
 }  // namespace gl

@@ -8,13 +8,14 @@ namespace gl {
 
 constexpr int kMaxSpecies = 16;
 constexpr int kPushBlock = 256;   // particles per push workgroup
-constexpr int kSiteRec = 56;      // site-field planes: Ex, Ey, Ez, Bx, By, Bz, phi (8 reals each)
+// site-field planes, 8 reals each: Ex, Ey, Ez, Bx, By, Bz (local frame) and the
+// transported halves of Ex, Ey stored at their site (E_i = slot i + slot 6 + i)
+constexpr int kSiteRec = 64;
 
-#ifndef GL_PLANE_PAD
-#define GL_PLANE_PAD 0
-#endif
 // distance between consecutive planes of a lattice quantity, in elements
-__host__ __device__ __forceinline__ size_t plane_pitch(int N) { return (size_t)N * N + GL_PLANE_PAD; }
+// (packed: a padded pitch against L2 set aliasing of the power-of-two planes
+// measured no faster)
+__host__ __device__ __forceinline__ size_t plane_pitch(int N) { return (size_t)N * N; }
 
 // Workgroup b of a grid of nb runs on XCD b mod 8.  Renumber the grid so
 // that every XCD gets one contiguous run of logical blocks (row bands of a
@@ -67,12 +68,10 @@ struct SpeciesTab {
 };
 
 // ---- launchers (stream-ordered, no synchronisation) --------------------------
+// F: site-field planes at tau_n [kSiteRec][pitch], written when non-null
 template <typename T>
-hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out,
+hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F,
                              double tau, double dtau, int reunit);
-template <typename T>
-hipError_t launch_site_fields(hipStream_t st, int N, FieldPtrs<T> old_, FieldPtrs<T> new_,
-                              T *F, double tau);
 template <typename T>
 hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
                        const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,

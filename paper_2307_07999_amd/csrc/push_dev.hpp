@@ -14,7 +14,7 @@ template <typename T>
 __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const FieldPtrs<T> &f,
                                              const T *__restrict__ F, const SpeciesTab<T> &tab, int n,
                                              T dtau, double *acc) {
-    const size_t n2 = (size_t)N * N;
+    const size_t n2 = plane_pitch(N);
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
     int s = P.species[i];
     if (s >= 0 && n >= tab.nform[s]) {
@@ -32,6 +32,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 se = fma(q[a], F[(size_t)(8 * k + a) * n2 + x], se);
+                if (k < 2) se = fma(q[a], F[(size_t)(48 + 8 * k + a) * n2 + x], se);
                 sb = fma(q[a], F[(size_t)(8 * (3 + k) + a) * n2 + x], sb);
             }
             e[k] = se;
@@ -68,7 +69,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         {
             T ph[8];
 #pragma unroll
-            for (int a = 0; a < 8; a++) ph[a] = F[(size_t)(48 + a) * n2 + x];
+            for (int a = 0; a < 8; a++) ph[a] = f.phi[(size_t)a * n2 + x];
             M3<T> W = expi_alg(ph, -deta);
             Qm = mul_nd(mul(W, Qm), W);
         }
