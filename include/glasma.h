@@ -229,7 +229,7 @@ gl_status gl_batch_required_bytes(gl_event *const *evs, int32_t n_events, size_t
 gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspace, size_t bytes,
                           void *stream, gl_batch **out);
 void gl_batch_destroy(gl_batch *b);
-/* Pick the field-kernel tile shape (0: 32x8, 1: 64x4, 2: 16x16) and the
+/* Pick the field-kernel tile shape in sites (0: 32x4, 1: 64x2, 2: 16x8) and the
  * persistent grid (0: one workgroup per tile, k: k workgroups per compute
  * unit) by timing the field phases on this batch (they are idempotent, so
  * the state does not change), or read the choice from cache_json when it

@@ -24,7 +24,7 @@ struct BatchCtl {
     int64_t n;             // common step index of all events
 };
 
-constexpr int kBatchShapes = 3;   // field-kernel tiles 32x8, 64x4, 16x16
+constexpr int kBatchShapes = 3;   // field-kernel site tiles 32x4, 64x2, 16x8 (two lanes per site)
 
 template <typename T>
 hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs, const int2 *tiles, int64_t total,

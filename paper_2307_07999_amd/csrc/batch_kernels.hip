@@ -29,21 +29,27 @@ __device__ __forceinline__ int64_t xcd_first(int64_t total, int64_t &stride, int
 }
 
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY)
+__global__ void __launch_bounds__(2 * TX *TY)
 k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total, int fpar,
               const BatchCtl *__restrict__ ctl, T dtau) {
+    __shared__ LinkTile<T, TX, TY> tile;
     const int64_t n = ctl->n;
     const T tau = dtau * (T)n, tau_h = dtau * ((T)n + T(0.5));
+    const int lx = threadIdx.x >> 1, ly = threadIdx.y;
     int64_t stride, end;
     for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
         const int2 w = tiles[t];
         const BatchEv<T> &e = evs[w.x];
         const int tx = (e.N + TX - 1) / TX;
-        const int ix = (w.y % tx) * TX + threadIdx.x, iy = (w.y / tx) * TY + threadIdx.y;
+        const int x0 = (w.y % tx) * TX, y0 = (w.y / tx) * TY;
+        __syncthreads();   // the previous tile's reads are done
+        stage_tile(tile, e.N, e.f[fpar], x0, y0, threadIdx.x + 2 * TX * threadIdx.y, 2 * TX * TY);
+        __syncthreads();
+        const int ix = x0 + lx, iy = y0 + ly;
         if (ix < e.N && iy < e.N) {
             int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
-            field_step_site<T>(e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, ix, iy, tau,
-                               dtau, tau_h, reunit);
+            field_step_link(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, ix, iy, lx, ly,
+                            threadIdx.x & 1, tau, dtau, tau_h, reunit);
         }
     }
 }
@@ -104,13 +110,13 @@ hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs,
     unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
 #define GL_SHAPE(TXv, TYv)                                                                                    \
     {                                                                                                         \
-        hipLaunchKernelGGL((k_batch_field<T, TXv, TYv>), dim3(g), dim3(TXv, TYv), 0, st, evs, tiles, total,   \
+        hipLaunchKernelGGL((k_batch_field<T, TXv, TYv>), dim3(g), dim3(2 * TXv, TYv), 0, st, evs, tiles, total,\
                            fpar, ctl, (T)dtau);                                                               \
     }
     switch (shape) {
-        case 0: GL_SHAPE(32, 8) break;
-        case 1: GL_SHAPE(64, 4) break;
-        case 2: GL_SHAPE(16, 16) break;
+        case 0: GL_SHAPE(32, 4) break;
+        case 1: GL_SHAPE(64, 2) break;
+        case 2: GL_SHAPE(16, 8) break;
         default: return hipErrorInvalidValue;
     }
 #undef GL_SHAPE

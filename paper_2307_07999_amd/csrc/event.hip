@@ -55,6 +55,9 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     if (!(d->L_fm > 0) || !(d->dtau_over_a > 0) || d->dtau_over_a > 0.5)
         return fail(GL_EINVAL, "L_fm must be > 0 and 0 < dtau_over_a <= 0.5");
     if (d->precision != 64 && d->precision != 32) return fail(GL_EINVAL, "precision must be 64 or 32");
+    // particle arrays are indexed with 32-bit byte offsets on the device
+    if (d->max_particles > ((int64_t)1 << 28) - ((int64_t)kPushBlock << 5))
+        return fail(GL_EINVAL, "max_particles must be below 2^28 - 8192");
     if (d->max_steps < 0 || d->max_particles < 0 || d->reunit_every < 0)
         return fail(GL_EINVAL, "negative capacity");
     const size_t n2 = (size_t)d->N * d->N, ts = d->precision == 64 ? 8 : 4;
@@ -955,7 +958,7 @@ struct BatchSizes {
     int64_t n_tiles[kBatchShapes], n_pblocks;
 };
 
-const int kShapeTX[kBatchShapes] = {32, 64, 16}, kShapeTY[kBatchShapes] = {8, 4, 16};
+const int kShapeTX[kBatchShapes] = {32, 64, 16}, kShapeTY[kBatchShapes] = {4, 2, 8};
 
 gl_status batch_sizes(gl_event *const *evs, int n, BatchSizes &z) {
     if (!evs || n < 1) return fail(GL_EINVAL, "empty batch");

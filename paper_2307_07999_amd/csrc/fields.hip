@@ -16,26 +16,34 @@
 // This scheme keeps the Gauss law sum_i [E_i(x) - U_i^dag(x-i)E_i(x-i)U_i(x-i)]
 // + i[phi, pi] exactly constant.
 //
-// Kernel design: one thread per site, 2-D workgroups of 32 x 8 sites so that
-// a wave reads 32 consecutive x of two rows from every structure-of-arrays
-// plane (coalesced).  Tiles are numbered so that each XCD owns one band of
+// Kernel design: two lanes per site, one per link direction (the per-site
+// work of one lane needs too many registers for more than one wave per SIMD);
+// workgroups of 32 x 4 sites.  The links and phi of the tile and a one-site
+// halo are staged in LDS with coalesced row reads, and every neighbour of the
+// stencil is read from there: without the tile the step issues ~250 global
+// loads per lane and its waves spend half their time waiting on them.  Tiles are numbered so that each XCD owns one band of
 // rows (xcd_remap): the neighbour reads of the stencil then hit the L2 of the
 // XCD that owns the tile instead of refetching halo lines from memory.
 #include "fields_dev.hpp"
 
 namespace gl {
 
-constexpr int TX = 32, TY = 8;
+constexpr int TX = 32, TY = 8;     // site tiles of the diagnostics
+constexpr int SX = 32, SY = 4;     // site tiles of the step: 2 lanes per site
 
 template <typename T>
-__global__ void __launch_bounds__(TX *TY)
+__global__ void __launch_bounds__(2 * SX * SY)
 k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T *__restrict__ F, T tau, T dtau, T tau_h, int reunit) {
-    const int tx = (N + TX - 1) / TX;
+    __shared__ LinkTile<T, SX, SY> tile;
+    const int tx = (N + SX - 1) / SX;
     const int l = (int)xcd_remap(blockIdx.x, gridDim.x);
-    int ix = (l % tx) * TX + threadIdx.x;
-    int iy = (l / tx) * TY + threadIdx.y;
-    if (ix >= N || iy >= N) return;
-    field_step_site<T>(N, in, out, F, ix, iy, tau, dtau, tau_h, reunit);
+    const int x0 = (l % tx) * SX, y0 = (l / tx) * SY;
+    const int lx = threadIdx.x >> 1, ly = threadIdx.y;
+    stage_tile(tile, N, in, x0, y0, threadIdx.x + 2 * SX * threadIdx.y, 2 * SX * SY);
+    __syncthreads();
+    const int ix = x0 + lx, iy = y0 + ly;
+    if (ix >= N || iy >= N) return;   // both lanes of a pair leave together
+    field_step_link(tile, N, in, out, F, ix, iy, lx, ly, threadIdx.x & 1, tau, dtau, tau_h, reunit);
 }
 
 // Diagnostics per site, reduced per workgroup in FP64:
@@ -153,7 +161,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
 template <typename T>
 hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F, double tau,
                              double dtau, int reunit) {
-    dim3 grid(((N + TX - 1) / TX) * ((N + TY - 1) / TY)), block(TX, TY);
+    dim3 grid(((N + SX - 1) / SX) * ((N + SY - 1) / SY)), block(2 * SX, SY);
     hipLaunchKernelGGL(k_field_step<T>, grid, block, 0, st, N, in, out, F, (T)tau, (T)dtau,
                        (T)(tau + 0.5 * dtau), reunit);
     return hipGetLastError();

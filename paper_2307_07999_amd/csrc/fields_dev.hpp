@@ -65,170 +65,233 @@ __device__ __forceinline__ M3<T> comm_term(const M3<T> &ph, const M3<T> &Ph, T i
 // The second half of E_i belongs to the site x+i; this thread owns the link
 // U_i(x) and Ebar_i(x) it needs, so it stores that half at x+i in a plane of
 // its own (slots 48..63) and the push adds the two halves.
-// Keeps the instruction scheduler from hoisting the next phase's loads above
-// this point: with every load of the step in flight at once the kernel needs
-// more than twice the registers, and the lost occupancy costs more than the
-// overlap gains.
-__device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
-
-// E_i^{n+1/2}(x) and U_i^{n+1}(x) from the force fe; with F, also this
-// site's half of the electric site field and the transported half of x+i
+// Exchange with the partner lane of a site's lane pair (lanes 2s and 2s+1).
 template <typename T>
-__device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const T *__restrict__ Uin,
-                                            T *__restrict__ Uout, size_t n2, size_t x, size_t xpi, const T *fe, T dtau,
-                                            T s, int reunit, T *__restrict__ F, int slot, T inv_tau) {
+__device__ __forceinline__ T pair_swap(T v) {
+    return __shfl_xor(v, 1, 64);
+}
+template <typename T>
+__device__ __forceinline__ M3<T> pair_swap(const M3<T> &m) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            r.re[i][j] = pair_swap(m.re[i][j]);
+            r.im[i][j] = pair_swap(m.im[i][j]);
+        }
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ M3<T> select(bool c, const M3<T> &a, const M3<T> &b) {
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            r.re[i][j] = c ? a.re[i][j] : b.re[i][j];
+            r.im[i][j] = c ? a.im[i][j] : b.im[i][j];
+        }
+    return r;
+}
+
+// Components 4h..4h+3 of an algebra vector v into a record slot (the two
+// lanes of a site store one half each).
+template <typename T>
+__device__ __forceinline__ void store_half(T *__restrict__ F, size_t n2, size_t x, int slot, const T *v, int h) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) pl_st(F, n2, slot + k, x + (size_t)(4 * h) * n2, h ? v[4 + k] : v[k]);
+}
+
+// Link and scalar planes of a block of SX x SY sites and a one-site halo,
+// staged in LDS: planes 0..17 hold U_1, 18..35 U_2, 36..43 phi; region site
+// (rx, ry) is the lattice site (x0 - 1 + rx, y0 - 1 + ry) mod N.  The plane
+// stride RP is padded to 8 mod 16 words, so the two lanes of a site reading
+// U_1 and U_2 (18 planes apart) hit different LDS banks.
+template <typename T, int SX, int SY>
+struct LinkTile {
+    static constexpr int RX = SX + 2, RY = SY + 2, R = RX * RY;
+    static constexpr int RP = R + (24 - R % 16) % 16;
+    T v[44 * RP];
+    __device__ __forceinline__ M3<T> m(int p0, int r) const {
+        M3<T> u;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                u.re[i][j] = v[(p0 + 2 * (3 * i + j)) * RP + r];
+                u.im[i][j] = v[(p0 + 2 * (3 * i + j) + 1) * RP + r];
+            }
+        return u;
+    }
+    __device__ __forceinline__ void phi(int r, T *out) const {
+#pragma unroll
+        for (int a = 0; a < 8; a++) out[a] = v[(36 + a) * RP + r];
+    }
+};
+
+// All threads of the workgroup copy the tile's region from the state; the
+// caller synchronises the workgroup before the tile is read.
+template <typename T, int SX, int SY>
+__device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const FieldPtrs<T> &in, int x0, int y0,
+                                           int tid, int nthreads) {
+    using Tl = LinkTile<T, SX, SY>;
+    const size_t n2 = plane_pitch(N);
+    for (int r = tid; r < Tl::R; r += nthreads) {
+        int gx = (x0 - 1 + r % Tl::RX) % N, gy = (y0 - 1 + r / Tl::RX) % N;
+        gx += gx < 0 ? N : 0;
+        gy += gy < 0 ? N : 0;
+        const size_t site = (size_t)gx + (size_t)N * gy;
+#pragma unroll 6
+        for (int p = 0; p < 36; p++) t.v[p * Tl::RP + r] = pl_ld(in.U, n2, p, site);
+#pragma unroll
+        for (int a = 0; a < 8; a++) t.v[(36 + a) * Tl::RP + r] = pl_ld(in.phi, n2, a, site);
+    }
+}
+
+// E_i^{n+1/2}(x) and U_i^{n+1}(x) from the force fe and U_i(x) = u; with F,
+// also this site's half of the electric site field and the transported half
+// of x+i (offsets: xe = x in the E_i planes, xu = x in the U_i planes, xt =
+// x+i in the E_i slots of the site-field record)
+template <typename T>
+__device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const M3<T> &u,
+                                            T *__restrict__ Uout, size_t n2, size_t xe, size_t xu, size_t xt,
+                                            const T *fe, T dtau, T s, int reunit, T *__restrict__ F, T inv_tau) {
     T e[8], eb[8];
-    load_a(Ein, n2, x, e);
+    load_a(Ein, n2, xe, e);
 #pragma unroll
     for (int a = 0; a < 8; a++) {
         eb[a] = e[a];
         e[a] += dtau * fe[a];
     }
-    store_a(Eout, n2, x, e);
-    const M3<T> u = load_m(Uin, n2, x);
+    store_a(Eout, n2, xe, e);
     M3<T> un = mul(expi_alg(e, s), u);
     if (reunit) un = reunitarize(un);
-    store_m(Uout, n2, x, un);
+    store_m(Uout, n2, xu, un);
     if (F) {
         T t[8];
 #pragma unroll
         for (int a = 0; a < 8; a++) eb[a] = T(0.25) * inv_tau * (eb[a] + e[a]);   // Ebar / (2 tau)
-        store_rec(F, n2, x, slot, eb);
+        store_a(F, n2, xe, eb);
         transport_dn(u, herm_from_alg(eb), t);
-        store_rec(F, n2, xpi, 48 + slot, t);
+        store_a(F + 48 * n2, n2, xt, t);
     }
 }
 
-// Phi_{+i}(x) = U_i(x) phi(x+i) U_i^dag(x) and Phi_{-i}(x) = U_i^dag(x-i) phi(x-i) U_i(x-i)
-// as algebra components; adds -(i/tau)[phi(x), Phi_{+i}] to the E_i force
-template <typename T>
-__device__ __forceinline__ void scalar_links(const T *__restrict__ Ui, const T *__restrict__ phi, size_t n2, size_t x,
-                                             size_t xp, size_t xm, const T *ph, T inv_tau, T *fe, T *pf, T *pb) {
-    T v[8], c[8];
-    const M3<T> u = load_m(Ui, n2, x);
-    load_a(phi, n2, xp, v);
-    M3<T> Pf = mul_nd(mul(u, herm_from_alg(v)), u);
-    alg_from_herm(comm_term(herm_from_alg(ph), Pf, inv_tau), c);
-#pragma unroll
-    for (int a = 0; a < 8; a++) fe[a] += c[a];
-    alg_from_herm(Pf, pf);
-    const M3<T> um = load_m(Ui, n2, xm);
-    load_a(phi, n2, xm, v);
-    alg_from_herm(mul(mul_dn(um, herm_from_alg(v)), um), pb);
-}
-
-// One site of the leapfrog step n -> n+1; (ix, iy) must lie on the lattice.
+// One link direction of one site of the leapfrog step n -> n+1: the two
+// lanes of a pair (d = 0, 1) share the site (ix, iy) = (x0 + lx, y0 + ly) of
+// the staged tile, which must lie on the lattice, and lane d owns direction
+// i = d + 1 (j is the other one).  Lane d forms its staple plaquette at
+// y = x - j, its transported scalars Phi_{+-i}, and updates E_i and U_i; the
+// plaquette at x is assembled from the halves U_i(x) U_j(x+i) of both lanes,
+// and the Laplacian of phi, the clover and the pi, phi update are shared
+// across the pair.  For i = 1, 2:
+//   E_1 += dtau { -tau ([P(x)]_X - U_2^dag(x-2)[P(x-2)]_X U_2(x-2)) - (i/tau)[phi, Phi_{+1}] }
+//   E_2 += dtau { -tau (U_1^dag(x-1)[P(x-1)]_X U_1(x-1) - [P(x)]_X) - (i/tau)[phi, Phi_{+2}] }
+//   pi  += (dtau/tau) sum_i (Phi_{+i} + Phi_{-i} - 2 phi)
+//   U_i <- exp(i dtau E_i / tau_{n+1/2}) U_i,   phi += dtau tau_{n+1/2} pi
 // If F is non-null the same pass writes the local-frame site fields at tau_n
 // that the particle push reads (NGP reading of the colored particle-in-cell
-// coupling), reusing the plaquettes and transported scalars of the forces:
+// coupling):
 //   E_i = 1/2 [Ebar_i(x) + U_i^dag(x-i) Ebar_i(x-i) U_i(x-i)] / tau,
 //         Ebar = (E^{n-1/2} + E^{n+1/2}) / 2,
 //   E_z = (pi^{n-1/2} + pi^{n+1/2}) / 2,
 //   B_x = -D_2 phi / tau, B_y = D_1 phi / tau, D_i phi = (Phi_{+i} - Phi_{-i}) / 2,
 //   B_z = -(1/4) (sum of the four plaquettes at x, each transported to x).
-// The second half of E_i belongs to the site x+i; this thread owns the link
-// U_i(x) and Ebar_i(x) it needs, so it stores that half at x+i in a plane of
-// its own (slots 48..63) and the push adds the two halves.  Each slot is
-// stored as soon as it is known, which keeps few values live.
-template <typename T>
-__device__ __forceinline__ void field_step_site(int N, const FieldPtrs<T> &in, const FieldPtrs<T> &out,
-                                                T *__restrict__ F, int ix, int iy, T tau, T dtau, T tau_h,
-                                                int reunit) {
+// The second half of E_i belongs to the site x+i; lane d owns the link U_i(x)
+// and Ebar_i(x) it needs, so it stores that half at x+i in a plane of its own
+// (slots 48..63) and the push adds the two halves.
+template <typename T, int SX, int SY>
+__device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, int N, const FieldPtrs<T> &in,
+                                                const FieldPtrs<T> &out, T *__restrict__ F, int ix, int iy, int lx,
+                                                int ly, int d, T tau, T dtau, T tau_h, int reunit) {
+    using Tl = LinkTile<T, SX, SY>;
+    constexpr int RX = Tl::RX;
     const size_t n2 = plane_pitch(N);
-    const Nbr nb = neighbours(ix, iy, N);
-    const T *U1 = in.U, *U2 = in.U + 18 * n2;
+    const bool d0 = d == 0;
+    // region indices of the neighbours
+    const int rx = (lx + 1) + RX * (ly + 1);
+    const int di = d0 ? 1 : RX, dj = d0 ? RX : 1;   // steps along i and j
+    const int rpi = rx + di, rmi = rx - di;          // x + i, x - i
+    const int ry = rx - dj;                          // y = x - j
+    const int ry1 = d0 ? ry + 1 : rx, ry2 = d0 ? rx : ry + RX;   // y + 1, y + 2
+    const int rz = rx - 1 - RX, rzi = rz + di;       // z = x - 1 - 2, z + i
+    const int pi_ = 18 * d, pj = 18 - 18 * d;        // first plane of U_i, U_j
+    // lattice indices for the global reads and writes
+    const size_t x = (size_t)ix + (size_t)N * iy;
+    const int ixp = ix + 1 == N ? 0 : ix + 1, iyp = iy + 1 == N ? 0 : iy + 1;
+    const size_t xpi = d0 ? (size_t)ixp + (size_t)N * iy : (size_t)ix + (size_t)N * iyp;
+    const size_t oi = (size_t)(18 * d) * n2, oe = (size_t)(8 * d) * n2;
     const T inv_tau = T(1) / tau;
+    const T sgn = d0 ? T(1) : T(-1);
 
-    T fe1[8], fe2[8], cl[8];
+    const M3<T> ui = tl.m(pi_, rx);   // U_i(x)
+    T fe[8], cl[8];
     {
-        T px[8];   // [P(x)]_X
+        T px[8];   // [P(x)]_X, P(x) = [U_1(x) U_2(x+1)] [U_2(x) U_1(x+2)]^dag
         {
-            const M3<T> P = plaq(load_m(U1, n2, nb.x), load_m(U2, n2, nb.xp1), load_m(U1, n2, nb.xp2),
-                                 load_m(U2, n2, nb.x));
-            alg_proj(P, px);
+            const M3<T> h = mul(ui, tl.m(pj, rpi));
+            const M3<T> o = pair_swap(h);
+            alg_proj(mul_nd(select(d0, h, o), select(d0, o, h)), px);
         }
-        phase_fence();
-        // E_1 force: -tau([P(x)] - U_2^dag(x-2)[P(x-2)]U_2(x-2))
-        {
-            const M3<T> u2m = load_m(U2, n2, nb.xm2);
-            const M3<T> P = plaq(load_m(U1, n2, nb.xm2), load_m(U2, n2, nb.xp1m2), load_m(U1, n2, nb.x), u2m);
-            T pa[8], t[8];
-            alg_proj(P, pa);
-            transport_dn(u2m, herm_from_alg(pa), t);
-#pragma unroll
-            for (int a = 0; a < 8; a++) {
-                fe1[a] = -tau * (px[a] - t[a]);
-                cl[a] = px[a] + t[a];
-            }
-        }
-        phase_fence();
-        // E_2 force: -tau(U_1^dag(x-1)[P(x-1)]U_1(x-1) - [P(x)])
-        {
-            const M3<T> u1m = load_m(U1, n2, nb.xm1);
-            const M3<T> P = plaq(u1m, load_m(U2, n2, nb.x), load_m(U1, n2, nb.xm1p2), load_m(U2, n2, nb.xm1));
-            T pa[8], t[8];
-            alg_proj(P, pa);
-            transport_dn(u1m, herm_from_alg(pa), t);
-#pragma unroll
-            for (int a = 0; a < 8; a++) {
-                fe2[a] = -tau * (t[a] - px[a]);
-                cl[a] += t[a];
-            }
-        }
-    }
-    phase_fence();
-    if (F) {
-        // fourth clover plaquette P(x-1-2), moved to x along x-1-2 -> x-2 -> x
-        const M3<T> u1mm = load_m(U1, n2, nb.xm1m2);
-        const M3<T> u2m = load_m(U2, n2, nb.xm2);
-        const M3<T> P = plaq(u1mm, u2m, load_m(U1, n2, nb.xm1), load_m(U2, n2, nb.xm1m2));
+        // staple: U_j^dag(y) [P(y)]_X U_j(y)
+        const M3<T> uj = tl.m(pj, ry);
+        const M3<T> P = plaq(tl.m(0, ry), tl.m(18, ry1), tl.m(0, ry2), tl.m(18, ry));
         T pa[8], t[8];
         alg_proj(P, pa);
-        transport_dn(mul(u1mm, u2m), herm_from_alg(pa), t);
+        transport_dn(uj, herm_from_alg(pa), t);
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            fe[a] = -tau * sgn * (px[a] - t[a]);
+            cl[a] = px[a] + (t[a] + pair_swap(t[a]));
+        }
+    }
+    if (F) {
+        // fourth clover plaquette P(z) = [U_1(z) U_2(z+1)] [U_2(z) U_1(z+2)]^dag,
+        // moved to x along z -> z+1 -> x, i.e. by C = U_1(z) U_2(z+1)
+        const M3<T> h = mul(tl.m(pi_, rz), tl.m(pj, rzi));
+        const M3<T> o = pair_swap(h);
+        const M3<T> C = select(d0, h, o);
+        T pa[8], t[8];
+        alg_proj(mul_nd(C, select(d0, o, h)), pa);
+        transport_dn(C, herm_from_alg(pa), t);
 #pragma unroll
         for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
-        store_rec(F, n2, nb.x, 40, t);   // B_z
+        store_half(F, n2, x, 40, t, d);   // B_z
     }
-    phase_fence();
-    // scalar couplings and the pi force (Laplacian of phi)
+    // scalar couplings: Phi_{+i} in the E_i force, all four in the pi force
     T ph[8], fpi[8];
-    load_a(in.phi, n2, nb.x, ph);
+    tl.phi(rx, ph);
     {
-        T pf[8], pb[8];
-        scalar_links(U1, in.phi, n2, nb.x, nb.xp1, nb.xm1, ph, inv_tau, fe1, pf, pb);
+        T v[8], c[8], pf[8], pb[8];
+        tl.phi(rpi, v);
+        const M3<T> Pf = mul_nd(mul(ui, herm_from_alg(v)), ui);
+        alg_from_herm(comm_term(herm_from_alg(ph), Pf, inv_tau), c);
+        alg_from_herm(Pf, pf);
+        const M3<T> um = tl.m(pi_, rmi);
+        tl.phi(rmi, v);
+        alg_from_herm(mul(mul_dn(um, herm_from_alg(v)), um), pb);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
-            fpi[a] = pf[a] + pb[a];
-            pf[a] = T(0.5) * inv_tau * (pf[a] - pb[a]);
+            fe[a] += c[a];
+            const T l = pf[a] + pb[a];
+            fpi[a] = inv_tau * ((l + pair_swap(l)) - T(4) * ph[a]);
+            pf[a] = T(0.5) * sgn * inv_tau * (pf[a] - pb[a]);
         }
-        if (F) store_rec(F, n2, nb.x, 32, pf);   // B_y = D_1 phi / tau
-        phase_fence();
-        scalar_links(U2, in.phi, n2, nb.x, nb.xp2, nb.xm2, ph, inv_tau, fe2, pf, pb);
-#pragma unroll
-        for (int a = 0; a < 8; a++) {
-            fpi[a] = inv_tau * (fpi[a] + pf[a] + pb[a] - T(4) * ph[a]);
-            pf[a] = T(-0.5) * inv_tau * (pf[a] - pb[a]);
-        }
-        if (F) store_rec(F, n2, nb.x, 24, pf);   // B_x = -D_2 phi / tau
+        // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
+        if (F) store_rec(F, n2, x + (size_t)(8 - 8 * d) * n2, 24, pf);
     }
-    phase_fence();
-    const T s = dtau / tau_h;
-    update_link(in.E, out.E, U1, out.U, n2, nb.x, nb.xp1, fe1, dtau, s, reunit, F, 0, inv_tau);
-    phase_fence();
-    update_link(in.E + 8 * n2, out.E + 8 * n2, U2, out.U + 18 * n2, n2, nb.x, nb.xp2, fe2, dtau, s, reunit, F, 8,
-                inv_tau);
-    T p[8], ez[8];
-    load_a(in.pi, n2, nb.x, p);
+    update_link(in.E, out.E, ui, out.U, n2, x + oe, x + oi, xpi + oe, fe, dtau, dtau / tau_h, reunit, F, inv_tau);
+    // pi, phi and E_z: lane d takes colour components 4d..4d+3
+    const size_t xo = x + (size_t)(4 * d) * n2;
 #pragma unroll
-    for (int a = 0; a < 8; a++) {
-        ez[a] = p[a];
-        p[a] += dtau * fpi[a];
-        ph[a] += dtau * tau_h * p[a];
-        ez[a] = T(0.5) * (ez[a] + p[a]);
+    for (int k = 0; k < 4; k++) {
+        const T p = pl_ld(in.pi, n2, k, xo);
+        const T pn = p + dtau * (d0 ? fpi[k] : fpi[4 + k]);
+        pl_st(out.pi, n2, k, xo, pn);
+        pl_st(out.phi, n2, k, xo, (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn);
+        if (F) pl_st(F, n2, 16 + k, xo, T(0.5) * (p + pn));
     }
-    store_a(out.pi, n2, nb.x, p);
-    store_a(out.phi, n2, nb.x, ph);
-    if (F) store_rec(F, n2, nb.x, 16, ez);   // E_z
 }
 
 }  // namespace gl

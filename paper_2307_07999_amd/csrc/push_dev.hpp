@@ -16,30 +16,30 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
                                              T dtau, double *acc) {
     const size_t n2 = plane_pitch(N);
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
-    int s = P.species[i];
+    int s = el_ld(P.species, i);
     if (s >= 0 && n >= tab.nform[s]) {
         const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
         const T m = tab.mass[s];
-        int cx = P.cx[i], cy = P.cy[i];
+        int cx = el_ld(P.cx, i), cy = el_ld(P.cy, i);
         size_t x = (size_t)cx + (size_t)N * cy;
         T q[8];
 #pragma unroll
-        for (int a = 0; a < 8; a++) q[a] = P.Q[(size_t)a * P.cap + i];
+        for (int a = 0; a < 8; a++) q[a] = pl_ld(P.Q, P.cap, a, i);
         T e[3], b[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             T se = T(0), sb = T(0);
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                se = fma(q[a], F[(size_t)(8 * k + a) * n2 + x], se);
-                if (k < 2) se = fma(q[a], F[(size_t)(48 + 8 * k + a) * n2 + x], se);
-                sb = fma(q[a], F[(size_t)(8 * (3 + k) + a) * n2 + x], sb);
+                se = fma(q[a], pl_ld(F, n2, 8 * k + a, x), se);
+                if (k < 2) se = fma(q[a], pl_ld(F, n2, 48 + 8 * k + a, x), se);
+                sb = fma(q[a], pl_ld(F, n2, 8 * (3 + k) + a, x), sb);
             }
             e[k] = se;
             b[k] = sb;
         }
         // Boris kick at tau_n
-        T pl[3] = {P.px[i], P.py[i], P.peta[i] / tau};
+        T pl[3] = {el_ld(P.px, i), el_ld(P.py, i), el_ld(P.peta, i) / tau};
         T pm[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) pm[k] = pl[k] + T(0.5) * dtau * e[k];
@@ -59,17 +59,17 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         // drift
         const T pzh = peta / th;
         const T ptau = sqrt(m * m + pl[0] * pl[0] + pl[1] * pl[1] + pzh * pzh);
-        T ox = P.ox[i] + dtau * pl[0] / ptau;
-        T oy = P.oy[i] + dtau * pl[1] / ptau;
+        T ox = el_ld(P.ox, i) + dtau * pl[0] / ptau;
+        T oy = el_ld(P.oy, i) + dtau * pl[1] / ptau;
         const T deta = dtau * peta / (th * th * ptau);
-        const T eta_old = P.eta[i];
+        const T eta_old = el_ld(P.eta, i);
         const T eta_new = eta_old + deta;
         // color rotation along eta with phi^n at the old cell
         M3<T> Qm = herm_from_alg(q);
         {
             T ph[8];
 #pragma unroll
-            for (int a = 0; a < 8; a++) ph[a] = f.phi[(size_t)a * n2 + x];
+            for (int a = 0; a < 8; a++) ph[a] = pl_ld(f.phi, n2, a, x);
             M3<T> W = expi_alg(ph, -deta);
             Qm = mul_nd(mul(W, Qm), W);
         }
@@ -99,20 +99,20 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
             cy = cm;
         }
         alg_from_herm(Qm, q);
-        P.cx[i] = cx;
-        P.cy[i] = cy;
-        P.ox[i] = ox;
-        P.oy[i] = oy;
-        P.eta[i] = eta_new;
-        P.px[i] = pl[0];
-        P.py[i] = pl[1];
-        P.peta[i] = peta;
+        el_st(P.cx, i, cx);
+        el_st(P.cy, i, cy);
+        el_st(P.ox, i, ox);
+        el_st(P.oy, i, oy);
+        el_st(P.eta, i, eta_new);
+        el_st(P.px, i, pl[0]);
+        el_st(P.py, i, pl[1]);
+        el_st(P.peta, i, peta);
 #pragma unroll
-        for (int a = 0; a < 8; a++) P.Q[(size_t)a * P.cap + i] = q[a];
+        for (int a = 0; a < 8; a++) pl_st(P.Q, P.cap, a, i, q[a]);
         // broadening at tau_{n+1/2}, accumulated in FP64
         const double etab = 0.5 * ((double)eta_old + (double)eta_new);
         const double pzlab = (double)ptau * sinh(etab) + (double)pzh * cosh(etab);
-        const double x0 = P.px0[i], y0 = P.py0[i], z0 = P.pz0[i];
+        const double x0 = el_ld(P.px0, i), y0 = el_ld(P.py0, i), z0 = el_ld(P.pz0, i);
         acc[0] = (double)pl[0] * pl[0] - x0 * x0;
         acc[1] = (double)pl[1] * pl[1] - y0 * y0;
         acc[2] = pzlab * pzlab - z0 * z0;

@@ -320,6 +320,57 @@ __device__ __forceinline__ void transport_nd(const M3<T> &U, const M3<T> &X, T *
 }
 
 // ---- structure-of-arrays loads/stores ---------------------------------------
+// Arrays are read and written through buffer resources: the array base lives
+// in scalar registers, the lane's byte offset is one 32-bit vector register
+// and the plane offset a scalar, so the many plane accesses of a site cost no
+// per-lane 64-bit address arithmetic.  Lattice planes hold at most 2^20 sites
+// and particle arrays at most 2^28 entries, so every byte offset fits in 32
+// bits.  Offsets x may include a whole number of planes (a lane-dependent
+// choice of planes).
+constexpr int kBufConfig = 0x00020000;   // raw 32-bit data, gfx9-family layout
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7FFFFFFF, kBufConfig);
+}
+__device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ double bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ int32_t bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, int32_t) {
+    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double v) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, int32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v, r, vo, so, 0);
+}
+
+// element x of plane k of the array at p (planes n2 elements apart)
+template <typename T>
+__device__ __forceinline__ T pl_ld(const T *p, size_t n2, int k, size_t x) {
+    return bld(buf(p), (uint32_t)(x * sizeof(T)), (uint32_t)((size_t)k * n2 * sizeof(T)), T());
+}
+template <typename T>
+__device__ __forceinline__ void pl_st(T *p, size_t n2, int k, size_t x, T v) {
+    bst(buf(p), (uint32_t)(x * sizeof(T)), (uint32_t)((size_t)k * n2 * sizeof(T)), v);
+}
+// element x of a single array
+template <typename T>
+__device__ __forceinline__ T el_ld(const T *p, size_t x) {
+    return bld(buf(p), (uint32_t)(x * sizeof(T)), 0u, T());
+}
+template <typename T>
+__device__ __forceinline__ void el_st(T *p, size_t x, T v) {
+    bst(buf(p), (uint32_t)(x * sizeof(T)), 0u, v);
+}
+
 // A link plane set: 18 planes of n2 values, entry (i,j) real at plane 2(3i+j).
 template <typename T>
 __device__ __forceinline__ M3<T> load_m(const T *__restrict__ base, size_t n2, size_t x) {
@@ -328,8 +379,8 @@ __device__ __forceinline__ M3<T> load_m(const T *__restrict__ base, size_t n2, s
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            r.re[i][j] = base[(size_t)(2 * (3 * i + j)) * n2 + x];
-            r.im[i][j] = base[(size_t)(2 * (3 * i + j) + 1) * n2 + x];
+            r.re[i][j] = pl_ld(base, n2, 2 * (3 * i + j), x);
+            r.im[i][j] = pl_ld(base, n2, 2 * (3 * i + j) + 1, x);
         }
     return r;
 }
@@ -340,21 +391,21 @@ __device__ __forceinline__ void store_m(T *__restrict__ base, size_t n2, size_t 
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            base[(size_t)(2 * (3 * i + j)) * n2 + x] = m.re[i][j];
-            base[(size_t)(2 * (3 * i + j) + 1) * n2 + x] = m.im[i][j];
+            pl_st(base, n2, 2 * (3 * i + j), x, m.re[i][j]);
+            pl_st(base, n2, 2 * (3 * i + j) + 1, x, m.im[i][j]);
         }
 }
 
 template <typename T>
 __device__ __forceinline__ void load_a(const T *__restrict__ base, size_t n2, size_t x, T *v) {
 #pragma unroll
-    for (int a = 0; a < 8; a++) v[a] = base[(size_t)a * n2 + x];
+    for (int a = 0; a < 8; a++) v[a] = pl_ld(base, n2, a, x);
 }
 
 template <typename T>
 __device__ __forceinline__ void store_a(T *__restrict__ base, size_t n2, size_t x, const T *v) {
 #pragma unroll
-    for (int a = 0; a < 8; a++) base[(size_t)a * n2 + x] = v[a];
+    for (int a = 0; a < 8; a++) pl_st(base, n2, a, x, v[a]);
 }
 
 }  // namespace gl
