@@ -68,7 +68,7 @@ __device__ __forceinline__ M3<T> comm_term(const M3<T> &ph, const M3<T> &Ph, T i
 // Exchange with the partner lane of a site's lane pair (lanes 2s and 2s+1).
 template <typename T>
 __device__ __forceinline__ T pair_swap(T v) {
-    return __shfl_xor(v, 1, 64);
+    return dpp<kDppSwap1>(v);
 }
 template <typename T>
 __device__ __forceinline__ M3<T> pair_swap(const M3<T> &m) {

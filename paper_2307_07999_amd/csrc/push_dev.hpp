@@ -123,32 +123,29 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 
 // Per-species workgroup reduction of kPushBlock threads (particles of
 // several species share a workgroup once they are sorted by cell): for each
-// species, wave64 butterflies, then the four waves in order -- a fixed order,
-// so the partial sums are deterministic.  Writes out[sp * 4 + k].
+// species and term, a DPP sum over each 16-lane row, then one lane per row
+// writes its total to LDS and the totals of the kPushBlock / 16 rows are
+// added in row order -- a fixed order, so the partial sums are deterministic.
+// Writes out[sp * 4 + k].
 __device__ __forceinline__ void block_species_reduce(int s, const double *acc, int n_species,
                                                      double *__restrict__ out) {
-    __shared__ double red[kPushBlock / 64][4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int kRows = kPushBlock / 16;
+    __shared__ double red[kMaxSpecies * 4][kRows];
+    const int row = threadIdx.x >> 4;
+    const bool leader = (threadIdx.x & 15) == 0;
     for (int sp = 0; sp < n_species; sp++) {
-        double v[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = s == sp ? acc[k] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; k++) red[wave][k] = v[k];
+        for (int k = 0; k < 4; k++) {
+            const double v = row_sum(s == sp ? acc[k] : 0.0);
+            if (leader) red[sp * 4 + k][row] = v;
         }
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            double t = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < n_species * 4) {
+        double t = 0.0;
 #pragma unroll
-            for (int w = 0; w < kPushBlock / 64; w++) t += red[w][threadIdx.x];
-            out[sp * 4 + threadIdx.x] = t;
-        }
-        __syncthreads();
+        for (int r = 0; r < kRows; r++) t += red[threadIdx.x][r];
+        out[threadIdx.x] = t;
     }
 }
 

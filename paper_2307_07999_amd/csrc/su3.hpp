@@ -319,6 +319,35 @@ __device__ __forceinline__ void transport_nd(const M3<T> &U, const M3<T> &X, T *
     alg_from_herm(mul_nd(mul(U, X), U), out);
 }
 
+// ---- lane exchanges within a wave (DPP, no LDS traffic) -------------------
+// dpp_ctrl codes: quad_perm(1,0,3,2) swaps lanes 2k and 2k+1, quad_perm(2,3,0,1)
+// swaps pairs within a quad, row_half_mirror reverses 8 lanes, row_mirror 16.
+constexpr int kDppSwap1 = 0xB1, kDppSwap2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    i32x2 h = __builtin_bit_cast(i32x2, v);
+    h.x = __builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false);
+    h.y = __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, h);
+}
+
+// Sum over the 16 lanes of each row of the wave; every lane of a row gets
+// the same total (each step adds two partial sums that are equal as a pair).
+template <typename T>
+__device__ __forceinline__ T row_sum(T v) {
+    v += dpp<kDppSwap1>(v);
+    v += dpp<kDppSwap2>(v);
+    v += dpp<kDppHalfMirror>(v);
+    v += dpp<kDppMirror>(v);
+    return v;
+}
+
 // ---- structure-of-arrays loads/stores ---------------------------------------
 // Arrays are read and written through buffer resources: the array base lives
 // in scalar registers, the lane's byte offset is one 32-bit vector register
