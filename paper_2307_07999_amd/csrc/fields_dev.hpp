@@ -38,7 +38,6 @@ __device__ __forceinline__ M3<T> plaq(const M3<T> &u1x, const M3<T> &u2xp1, cons
     return mul_nd(mul_nd(mul(u1x, u2xp1), u1xp2), u2x);
 }
 
-// -(i/tau)[phi, Phi] as a hermitian matrix
 template <typename T>
 __device__ __forceinline__ M3<T> comm_term(const M3<T> &ph, const M3<T> &Ph, T inv_tau) {
     M3<T> c = sub(mul(ph, Ph), mul(Ph, ph));
@@ -265,15 +264,13 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
     {
         T v[8], c[8], pf[8], pb[8];
         tl.phi(rpi, v);
-        const M3<T> Pf = mul_nd(mul(ui, herm_from_alg(v)), ui);
-        alg_from_herm(comm_term(herm_from_alg(ph), Pf, inv_tau), c);
-        alg_from_herm(Pf, pf);
-        const M3<T> um = tl.m(pi_, rmi);
+        transport_nd(ui, herm_from_alg(v), pf);   // Phi_{+i}
+        alg_comm(ph, pf, c);                      // -i[phi, Phi_{+i}]
         tl.phi(rmi, v);
-        alg_from_herm(mul(mul_dn(um, herm_from_alg(v)), um), pb);
+        transport_dn(tl.m(pi_, rmi), herm_from_alg(v), pb);   // Phi_{-i}
 #pragma unroll
         for (int a = 0; a < 8; a++) {
-            fe[a] += c[a];
+            fe[a] = fma(inv_tau, c[a], fe[a]);
             const T l = pf[a] + pb[a];
             fpi[a] = inv_tau * ((l + pair_swap(l)) - T(4) * ph[a]);
             pf[a] = T(0.5) * sgn * inv_tau * (pf[a] - pb[a]);

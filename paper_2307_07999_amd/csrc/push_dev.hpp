@@ -64,41 +64,34 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const T deta = dtau * peta / (th * th * ptau);
         const T eta_old = el_ld(P.eta, i);
         const T eta_new = eta_old + deta;
-        // color rotation along eta with phi^n at the old cell
-        M3<T> Qm = herm_from_alg(q);
+        // colour rotation along eta with phi^n at the old cell: Q <- W Q W^dag
         {
             T ph[8];
 #pragma unroll
             for (int a = 0; a < 8; a++) ph[a] = pl_ld(f.phi, n2, a, x);
-            M3<T> W = expi_alg(ph, -deta);
-            Qm = mul_nd(mul(W, Qm), W);
+            transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
         }
-        // crossings, x first then y
+        // crossings, x first then y: Q <- U^dag Q U forward, U Q U^dag backward
         if (ox >= T(0.5)) {
-            M3<T> u = load_m(f.U, n2, x);
-            Qm = mul(mul_dn(u, Qm), u);
+            transport_dn(load_m(f.U, n2, x), herm_from_alg(q), q);
             ox -= T(1);
             cx = cx + 1 == N ? 0 : cx + 1;
         } else if (ox < T(-0.5)) {
             int cm = cx == 0 ? N - 1 : cx - 1;
-            M3<T> u = load_m(f.U, n2, (size_t)cm + (size_t)N * cy);
-            Qm = mul_nd(mul(u, Qm), u);
+            transport_nd(load_m(f.U, n2, (size_t)cm + (size_t)N * cy), herm_from_alg(q), q);
             ox += T(1);
             cx = cm;
         }
         if (oy >= T(0.5)) {
-            M3<T> u = load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cy);
-            Qm = mul(mul_dn(u, Qm), u);
+            transport_dn(load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cy), herm_from_alg(q), q);
             oy -= T(1);
             cy = cy + 1 == N ? 0 : cy + 1;
         } else if (oy < T(-0.5)) {
             int cm = cy == 0 ? N - 1 : cy - 1;
-            M3<T> u = load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cm);
-            Qm = mul_nd(mul(u, Qm), u);
+            transport_nd(load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cm), herm_from_alg(q), q);
             oy += T(1);
             cy = cm;
         }
-        alg_from_herm(Qm, q);
         el_st(P.cx, i, cx);
         el_st(P.cy, i, cy);
         el_st(P.ox, i, ox);
