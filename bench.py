@@ -114,11 +114,11 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
             "finite": finite}
 
 
-def cpu_baseline(prec_unused, budget_s=20.0):
+def cpu_baseline(budget_s=12.0):
     """The FP64 oracle on a bounded sample of the same workload: coupled steps
-    on the full 512^2 lattice from a seeded state, particle work on a 1e5
-    sample scaled to the 7e5 ensemble.  Single thread."""
-    import numpy as np
+    on the full 512^2 lattice from a seeded state (site fields included), and
+    the particle push on a 1e5 sample scaled to the 7e5 ensemble, repeated
+    until the field work alone has taken budget_s.  Single thread."""
     from oracle import oracle as orc
     from tests import seeded_inputs as si
     a_fm = L_FM / N
@@ -127,19 +127,92 @@ def cpu_baseline(prec_unused, budget_s=20.0):
     s = orc.State(N)
     s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
     P = orc.particles_init(N, SEED, 0, 0, 2.0 * a_gev, N_PER)
-    t0 = time.perf_counter()
-    U0, phi0, n = s.U.copy(), s.phi.copy(), s.n
-    F = orc.field_step(s, DTAU, want_F=True)
-    t_field = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    orc.particle_step(N, n, DTAU, U0, phi0, F, P, [1.27 * a_gev], [1])
-    t_part = (time.perf_counter() - t0) * len(SPECIES)   # scale 1e5 -> 7e5
-    per_step = t_field + t_part
+    t_field = t_part = 0.0
+    steps = 0
+    while steps < 2 or t_field < budget_s:
+        t0 = time.perf_counter()
+        U0, phi0, n = s.U.copy(), s.phi.copy(), s.n
+        F = orc.field_step(s, DTAU, want_F=True)
+        t_field += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        orc.particle_step(N, n, DTAU, U0, phi0, F, P, [1.27 * a_gev], [1])
+        t_part += (time.perf_counter() - t0) * len(SPECIES)   # scale 1e5 -> 7e5
+        steps += 1
+    per_step = (t_field + t_part) / steps
     return {"value": N * N / per_step, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "1 coupled step on the 512^2 lattice (seeded state) with site fields; "
+            "sample": "%d coupled steps on the 512^2 lattice (seeded state) with site fields; "
                       "particle push timed on 1e5 particles and scaled x7 to the 7e5 ensemble; "
-                      "init excluded; field %.1f s + particles %.1f s" % (t_field, t_part),
+                      "init excluded; field %.1f s + particles %.1f s (scaled)" % (steps, t_field, t_part),
             "particle_steps_per_s": N_PER * len(SPECIES) / per_step}
+
+
+# HBM traffic of the dominant kernels, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (bench.py --traffic), valid for the kernel sources whose
+# hash is recorded beside them; stale figures are reported as null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "glasma512_hbm_traffic.md")
+KERNEL_SOURCES = ["su3.hpp", "internal.hpp", "fields_dev.hpp", "fields.hip", "push_dev.hpp", "particles.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2307_07999_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, prec):
+    """Bytes per launch (fetch, write) recorded for this kernel and precision,
+    or None when missing or taken on other kernel sources."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    src = None
+    rows = {}
+    for ln in lines:
+        if ln.startswith("source hash:"):
+            src = ln.split(":", 1)[1].strip().strip("`")
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) >= 4 and cells[0] in ("field_step", "push") and cells[1] in ("32", "64"):
+            rows[(cells[0], int(cells[1]))] = (float(cells[2]), float(cells[3]))
+    if src != kernel_source_hash():
+        return None
+    return rows.get((kernel, prec))
+
+
+def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Rows 'kernel | precision | fetch bytes | write bytes' per launch from
+    two counter runs, each scaled by what the counter reads for the plain
+    1 GiB copy (bench.py --copy-calib 1024)."""
+    import csv
+    import glob
+
+    def means(d, counter):
+        acc = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                a = acc.setdefault(name, [0.0, 0])
+                a[0] += float(r["Counter_Value"])
+                a[1] += 1
+        return {k: v[0] / v[1] for k, v in acc.items()}
+
+    copy_bytes = 1024 * (1 << 20)
+    cf = means(copy_fetch_dir, "FETCH_SIZE")
+    cw = means(copy_write_dir, "WRITE_SIZE")
+    kf = copy_bytes / (1024.0 * max(v for k, v in cf.items() if "copyBuffer" in k))
+    kw = copy_bytes / (1024.0 * max(v for k, v in cw.items() if "copyBuffer" in k))
+    f = means(fetch_dir, "FETCH_SIZE")
+    w = means(write_dir, "WRITE_SIZE")
+    tname = "double" if prec == 64 else "float"
+    print("fetch factor %.4f, write factor %.4f (bytes per KiB counted, from the copy)" % (kf, kw))
+    for kern, short in (("gl::k_field_step<%s>" % tname, "field_step"), ("gl::k_push<%s>" % tname, "push")):
+        print("| %s | %d | %.0f | %.0f |" % (short, prec, f[kern] * 1024 * kf, w[kern] * 1024 * kw))
+    print("source hash: `%s`" % kernel_source_hash())
 
 
 def copy_calibration(mib):
@@ -204,9 +277,14 @@ def main():
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--summarize", nargs=2, metavar=("DIR", "COMMAND"),
                     help="print a markdown summary of a rocprofv3 output directory and exit")
+    ap.add_argument("--traffic", nargs=5, metavar=("PREC", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH", "COPY_WRITE"),
+                    help="print the HBM traffic rows of the dominant kernels from counter runs and exit")
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize)
+        return
+    if args.traffic:
+        traffic_table(int(args.traffic[0]), *args.traffic[1:])
         return
     if args.copy_calib:
         copy_calibration(args.copy_calib)
@@ -266,6 +344,8 @@ def main():
     dom = max(names, key=lambda k: ms[k])
     dname = names[dom]
     achieved = ab[dname] * units[dname] / (avg_us[dname] * 1e-6) / 1e9
+    tr = measured_traffic(dname, args.precision)
+    traffic = None if tr is None else (tr[0] + tr[1]) / (avg_us[dname] * 1e-6) / 1e9
     out = {
         "metric": "particle-steps/s + lattice site-updates/s (SU(3), 512^2, 1 GPU); surrogate vs solver",
         "value": site_updates / wall,
@@ -288,13 +368,14 @@ def main():
         "kernel_avg_us": avg_us,
         "finite": bool(kappa_ok),
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": None if tr is None else tr[0] + tr[1],
                      "alg_bytes_per_unit": ab[dname], "units_per_launch": units[dname]},
     }
     if not args.no_batch:
         out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.precision)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
 
 
