@@ -32,6 +32,9 @@ N_PER = 100000
 SPECIES = ([(1.27, p0, 0) for p0 in (0.0, 2.0, 5.0)] + [(4.18, p0, 0) for p0 in (0.0, 2.0, 5.0)]
            + [(0.0, 10.0, 1)])
 SEED = 2307079992
+# kernel durations are sampled on every PROFILE_PERIOD-th launch of each
+# kernel over the timed region (HIP events on the library's stream)
+PROFILE_PERIOD = 8
 
 
 def coupled_steps(N, L, tau_max=1.0):
@@ -112,6 +115,21 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
             "frac_hbm": step_bytes * steps / t_run / 1e9 / PEAK_HBM_GBS,
             "tile": cfg["tile"], "grid_mult": cfg["grid_mult"], "graph_steps": cfg["graph_steps"],
             "finite": finite}
+
+
+def surrogate_bench(mode):
+    """Surrogate vs solver: the protocol of paper_2307_07999_amd.surrogate
+    (solver-generated training data, BF16 network trained on the GPU, judged
+    against held-out 512^2 solver runs).  'quick' is a reduced protocol that
+    keeps the default run within a few minutes; 'full' is the complete one."""
+    from paper_2307_07999_amd import surrogate
+    if mode == "full":
+        rep = surrogate.protocol(log=lambda *a: None)
+    else:
+        rep = surrogate.protocol(n_train_coarse=400, n_train_fine=128, n_heldout=16, n_noise=4,
+                                 epochs=40, fine_epochs=80, log=lambda *a: None)
+    rep["mode"] = mode
+    return rep
 
 
 def cpu_baseline(budget_s=12.0):
@@ -273,6 +291,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-event batched FP32 workload")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache for the batch")
+    ap.add_argument("--surrogate", default="quick", choices=("quick", "full", "off"),
+                    help="surrogate-vs-solver section: reduced protocol, full protocol or none")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--summarize", nargs=2, metavar=("DIR", "COMMAND"),
@@ -313,7 +333,7 @@ def main():
     # library's stream over the same region
     evs = [run_event(g, torch, args.precision, n_per, steps) for _ in range(args.steps)]
     for e in evs:
-        e.profile(True)
+        e.profile(True, period=PROFILE_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for e in evs:
@@ -374,6 +394,8 @@ def main():
     }
     if not args.no_batch:
         out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache)
+    if args.surrogate != "off":
+        out["surrogate"] = surrogate_bench(args.surrogate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -197,15 +197,17 @@ gl_status gl_get_wilson_line(gl_event *ev, int32_t nucleus, double *V);
 gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t sheet,
                           double sigma, double *rho);
 
-/* Kernel timing with HIP events recorded on the event's stream around every
- * launch of the hot-path kernels while enabled.  gl_profile_read synchronises
+/* Kernel timing with HIP events recorded on the event's stream around the
+ * launches of the hot-path kernels: period 0 switches it off, period p >= 1
+ * times every p-th launch of each kernel class (a sample, so that the event
+ * records barely perturb the run).  gl_profile_read synchronises
  * the stream and returns, per kernel class (0 field step, which also writes
  * the site fields when the event has particles, 1 unused, 2 particle push,
  * 3 series reduction), the summed milliseconds and the
  * launch counts since the last read, then clears them.  Creates HIP events
  * only (no device memory). */
 #define GL_PROF_KERNELS 4
-gl_status gl_profile_enable(gl_event *ev, int32_t on);
+gl_status gl_profile_enable(gl_event *ev, int32_t period);
 gl_status gl_profile_read(gl_event *ev, double *ms, int64_t *launches);
 
 /* Lattice spacing in fm and GeV^-1, and the current step index. */

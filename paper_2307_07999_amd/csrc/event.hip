@@ -84,7 +84,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     L.diag = take(std::max(L.n_diag_blocks * 8, cas_blocks) * sizeof(double));
     L.VA = take(18 * n2 * sizeof(double));
     L.VB = take(18 * n2 * sizeof(double));
-    L.planes = take(4 * n2 * sizeof(double2));
+    L.planes = take((size_t)kSheetChunk * 4 * n2 * sizeof(double2));
     L.U0 = take(36 * n2 * sizeof(double));
     L.pi0 = take(8 * n2 * sizeof(double));
     L.status = take(256);
@@ -120,7 +120,8 @@ struct gl_event {
     int64_t since_sort = 0;
 
     // kernel timing: pairs of events per launch, grouped by kernel class
-    bool prof = false;
+    int32_t prof = 0;                       // time every prof-th launch of each class (0: off)
+    int64_t prof_count[GL_PROF_KERNELS] = {0, 0, 0, 0};
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> prof_marks;   // (class, index of start event)
@@ -184,9 +185,12 @@ gl_status check_ev(gl_event *ev) {
     return GL_OK;
 }
 
-// start/stop marks around one launch of kernel class k (no-ops when disabled)
+// start/stop marks around one launch of kernel class k (no-ops when disabled
+// and for the launches between samples)
+constexpr size_t kNoMark = ~(size_t)0;
 gl_status prof_begin(gl_event *ev, int k, size_t *idx) {
-    if (!ev->prof) return GL_OK;
+    *idx = kNoMark;
+    if (ev->prof <= 0 || (ev->prof_count[k]++ % ev->prof) != 0) return GL_OK;
     while (ev->ev_pool.size() < ev->ev_used + 2) {
         hipEvent_t e;
         HIP_TRY(hipEventCreate(&e));
@@ -200,7 +204,7 @@ gl_status prof_begin(gl_event *ev, int k, size_t *idx) {
 }
 
 gl_status prof_end(gl_event *ev, size_t idx) {
-    if (!ev->prof) return GL_OK;
+    if (idx == kNoMark) return GL_OK;
     HIP_TRY(hipEventRecord(ev->ev_pool[idx + 1], ev->stream));
     return GL_OK;
 }
@@ -554,14 +558,18 @@ static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, double
     double2 *planes = (double2 *)(ev->ws + ev->L.planes);
     for (int nuc = 0; nuc < 2; nuc++) {
         HIP_TRY(launch_wilson_init(ev->stream, N, V[nuc]));
-        for (int sh = 0; sh < n_sheets; sh++) {
-            if (rho_dev)
-                HIP_TRY(launch_charges_to_planes(ev->stream, N, rho_dev + ((size_t)nuc * n_sheets + sh) * 8 * ev->n2,
-                                                 planes));
-            else
-                HIP_TRY(launch_mv_charges(ev->stream, N, sigma, seed, nuc, sh, planes));
-            HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes));
-            HIP_TRY(launch_wilson_accum(ev->stream, N, planes, V[nuc]));
+        for (int sh0 = 0; sh0 < n_sheets; sh0 += kSheetChunk) {
+            const int cnt = std::min(kSheetChunk, n_sheets - sh0);
+            if (rho_dev) {
+                for (int k = 0; k < cnt; k++)
+                    HIP_TRY(launch_charges_to_planes(
+                        ev->stream, N, rho_dev + ((size_t)nuc * n_sheets + sh0 + k) * 8 * ev->n2,
+                        planes + (size_t)k * 4 * ev->n2));
+            } else {
+                HIP_TRY(launch_mv_charges(ev->stream, N, sigma, seed, nuc, sh0, cnt, planes));
+            }
+            HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes, cnt));
+            HIP_TRY(launch_wilson_accum(ev->stream, N, planes, cnt, V[nuc]));
         }
     }
     return ev->fp64() ? finish_init<double>(ev) : finish_init<float>(ev);
@@ -876,16 +884,18 @@ gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t 
     if (check_ev(ev) || !rho || sheet < 0 || nucleus < 0) return fail(GL_EINVAL, "bad argument");
     double2 *planes = (double2 *)(ev->ws + ev->L.planes);
     double *tmp = (double *)(ev->ws + ev->L.U0);
-    HIP_TRY(launch_mv_charges(ev->stream, ev->N, sigma, seed, nucleus, sheet, planes));
+    HIP_TRY(launch_mv_charges(ev->stream, ev->N, sigma, seed, nucleus, sheet, 1, planes));
     HIP_TRY(launch_planes_to_charges(ev->stream, ev->N, planes, tmp));
     HIP_TRY(hipMemcpyAsync(rho, tmp, 8 * ev->n2 * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
     return GL_OK;
 }
 
-gl_status gl_profile_enable(gl_event *ev, int32_t on) {
+gl_status gl_profile_enable(gl_event *ev, int32_t period) {
     if (check_ev(ev)) return GL_EINVAL;
-    ev->prof = on != 0;
+    if (period < 0) return fail(GL_EINVAL, "profiling period must be >= 0");
+    ev->prof = period;
+    for (int k = 0; k < GL_PROF_KERNELS; k++) ev->prof_count[k] = 0;
     return GL_OK;
 }
 

@@ -4,8 +4,10 @@
 //      packed two colors per complex plane (rho^{2j} + i rho^{2j+1}).
 //   2. Poisson solve (-Lap + m^2) Lambda = rho with the 5-point Laplacian,
 //      exact in Fourier space: 2-D FFT by LDS-resident mixed-radix (4, 2, 3)
-//      Stockham line transforms, one workgroup per line.  The kernel is real
-//      and even, so the packed pair separates again after the inverse.
+//      Stockham line transforms, several adjacent lines per workgroup.  The
+//      kernel is real and even, so the packed pair separates again after the
+//      inverse.  Sheets are processed in chunks (charges, transforms and the
+//      Wilson-line products of a chunk in one launch each).
 //   3. Wilson lines V = prod_s exp(-i Lambda_s), sheet 1 leftmost.
 //   4. Matching of the nuclei's pure-gauge links U^n_i(x) = V_n(x) V_n^dag(x+i)
 //      to the forward light cone: [(U^A + U^B)(1 + U^dag)]_X = 0 per link by
@@ -22,17 +24,20 @@
 namespace gl {
 
 // ---- 1. charges ---------------------------------------------------------------
+// sheets sheet0 + blockIdx.y of one nucleus into planes [sheet][4][n2]
 __global__ void __launch_bounds__(256)
-k_mv_charges(int N, double sigma, uint64_t seed, int nucleus, int sheet, double2 *planes) {
+k_mv_charges(int N, double sigma, uint64_t seed, int nucleus, int sheet0, double2 *planes) {
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
+    const int sheet = sheet0 + (int)blockIdx.y;
+    double2 *pl = planes + (size_t)blockIdx.y * 4 * n2;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         U4 w = draw(seed, (uint32_t)x, (uint32_t)(4 * sheet + j), (uint32_t)nucleus);
         double g0, g1;
         box_muller(w, g0, g1);
-        planes[(size_t)j * n2 + x] = make_double2(sigma * g0, sigma * g1);
+        pl[(size_t)j * n2 + x] = make_double2(sigma * g0, sigma * g1);
     }
 }
 
@@ -62,94 +67,142 @@ k_unpack(int N, const double2 *planes, double *rho) {
 // ---- 2. FFT ------------------------------------------------------------------
 constexpr int kFftThreads = 256;
 constexpr int kFftMaxN = 1024;
+constexpr int kFftElems = 2048;   // complex values per workgroup: C lines of N
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// radix sequence of N: 4s, then a 2, then 3s (N = 2^a 3^b)
+// radix sequence of N: n4 radix-4 stages, then n2 (0 or 1) radix-2, then n3
+// radix-3 (N = 2^a 3^b)
 struct Radices {
-    int r[24];
-    int n;
+    int n4, n2, n3;
 };
 
 __host__ __device__ inline bool radices_of(int N, Radices &rs) {
-    rs.n = 0;
+    rs.n4 = rs.n2 = rs.n3 = 0;
     int m = N;
-    while (m % 4 == 0) { rs.r[rs.n++] = 4; m /= 4; }
-    while (m % 2 == 0) { rs.r[rs.n++] = 2; m /= 2; }
-    while (m % 3 == 0) { rs.r[rs.n++] = 3; m /= 3; }
+    while (m % 4 == 0) { rs.n4++; m /= 4; }
+    while (m % 2 == 0) { rs.n2++; m /= 2; }
+    while (m % 3 == 0) { rs.n3++; m /= 3; }
     return m == 1;
 }
 
-// In-place transform of n_lines lines: line l of plane p starts at
-// p * plane_stride + l * line_stride and has N elements elem_stride apart.
-// sign = -1 forward, +1 inverse (unnormalised).
-__global__ void __launch_bounds__(kFftThreads)
-k_fft_lines(double2 *data, int N, size_t elem_stride, size_t line_stride, size_t plane_stride,
-            int lines_per_plane, int sign, Radices rs) {
-    __shared__ double2 buf[2][kFftMaxN];
-    const int line = blockIdx.x % lines_per_plane, plane = blockIdx.x / lines_per_plane;
-    double2 *base = data + (size_t)plane * plane_stride + (size_t)line * line_stride;
-    for (int k = threadIdx.x; k < N; k += kFftThreads) buf[0][k] = base[(size_t)k * elem_stride];
-    __syncthreads();
-    int src = 0, Ns = 1;
-    for (int st = 0; st < rs.n; st++) {
-        const int R = rs.r[st];
-        const int nb = N / R;
-        for (int j = threadIdx.x; j < nb; j += kFftThreads) {
-            const int k = j % Ns;
-            double2 v[4];
-            for (int r = 0; r < R; r++) v[r] = buf[src][j + r * nb];
-            // twiddles exp(sign 2 pi i r k / (Ns R))
-            for (int r = 1; r < R; r++) {
-                double s, c;
-                sincospi(2.0 * sign * (double)(r * k) / (double)(Ns * R), &s, &c);
-                v[r] = cmul(v[r], make_double2(c, s));
-            }
-            double2 o[4];
-            if (R == 2) {
-                o[0] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
-                o[1] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
-            } else if (R == 4) {
-                double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
-                double2 b = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
-                double2 c = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
-                double2 d = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
-                // multiply d by sign*i
-                double2 di = make_double2(-sign * d.y, sign * d.x);
-                o[0] = make_double2(a.x + c.x, a.y + c.y);
-                o[2] = make_double2(a.x - c.x, a.y - c.y);
-                o[1] = make_double2(b.x + di.x, b.y + di.y);
-                o[3] = make_double2(b.x - di.x, b.y - di.y);
-            } else {   // R == 3
-                const double c3 = -0.5, s3 = 0.86602540378443864676 * sign;
-                double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
-                double2 u = make_double2(v[1].x - v[2].x, v[1].y - v[2].y);
-                o[0] = make_double2(v[0].x + t.x, v[0].y + t.y);
-                double2 m = make_double2(v[0].x + c3 * t.x, v[0].y + c3 * t.y);
-                // s3 * i * u
-                double2 iu = make_double2(-s3 * u.y, s3 * u.x);
-                o[1] = make_double2(m.x + iu.x, m.y + iu.y);
-                o[2] = make_double2(m.x - iu.x, m.y - iu.y);
-            }
-            const int idx = (j / Ns) * Ns * R + k;
-            for (int r = 0; r < R; r++) buf[src ^ 1][idx + r * Ns] = o[r];
-        }
-        __syncthreads();
-        src ^= 1;
-        Ns *= R;
-    }
-    for (int k = threadIdx.x; k < N; k += kFftThreads) base[(size_t)k * elem_stride] = buf[src][k];
+// lines per workgroup: the largest power of two that divides N, keeps C N
+// within kFftElems and is at most 64
+static inline int fft_lines_per_group(int N) {
+    int C = 1;
+    while (C < 64 && N % (2 * C) == 0 && 2 * C * N <= kFftElems) C *= 2;
+    return C;
 }
 
-// multiply by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2)) on all 4
-// planes; modes with lattice momentum squared above uv2 > 0 are set to zero
+// radix-R butterfly of v (twiddled inputs), sign = -1 forward, +1 inverse
+template <int R>
+__device__ __forceinline__ void butterfly(const double2 *v, double2 *o, int sign) {
+    if constexpr (R == 2) {
+        o[0] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+        o[1] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+    } else if constexpr (R == 4) {
+        double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+        double2 b = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+        double2 c = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+        double2 d = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+        double2 di = make_double2(-sign * d.y, sign * d.x);   // sign * i * d
+        o[0] = make_double2(a.x + c.x, a.y + c.y);
+        o[2] = make_double2(a.x - c.x, a.y - c.y);
+        o[1] = make_double2(b.x + di.x, b.y + di.y);
+        o[3] = make_double2(b.x - di.x, b.y - di.y);
+    } else {   // R == 3
+        const double c3 = -0.5, s3 = 0.86602540378443864676 * sign;
+        double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
+        double2 u = make_double2(v[1].x - v[2].x, v[1].y - v[2].y);
+        o[0] = make_double2(v[0].x + t.x, v[0].y + t.y);
+        double2 m = make_double2(v[0].x + c3 * t.x, v[0].y + c3 * t.y);
+        double2 iu = make_double2(-s3 * u.y, s3 * u.x);   // s3 * i * u
+        o[1] = make_double2(m.x + iu.x, m.y + iu.y);
+        o[2] = make_double2(m.x - iu.x, m.y - iu.y);
+    }
+}
+
+// One Stockham stage of radix R on the C lines of N values in buf (in place:
+// every thread reads its butterflies into registers, the workgroup
+// synchronises, then the results are written).  Twiddle of (r, k) is
+// tw[r k N / (Ns R)].
+template <int R>
+__device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int N, int C, int Ns, int sign) {
+    constexpr int B = (kFftElems / R + kFftThreads - 1) / kFftThreads;   // butterflies per thread
+    const int nb = N / R, step = N / (Ns * R), total = C * nb;
+    double2 o[B][R];
+    int at[B];
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const int t = threadIdx.x + b * kFftThreads;
+        at[b] = -1;
+        if (t < total) {
+            const int line = t / nb, j = t % nb, k = j % Ns;
+            const double2 *in = buf + line * N;
+            double2 v[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) v[r] = in[j + r * nb];
+#pragma unroll
+            for (int r = 1; r < R; r++) v[r] = cmul(v[r], tw[r * k * step]);
+            butterfly<R>(v, o[b], sign);
+            at[b] = line * N + (j / Ns) * Ns * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; b++)
+        if (at[b] >= 0)
+#pragma unroll
+            for (int r = 0; r < R; r++) buf[at[b] + r * Ns] = o[b][r];
+    __syncthreads();
+}
+
+// In-place transforms of the N x N planes: each workgroup transforms C
+// adjacent lines of one plane (rows if cols == 0, columns otherwise), with
+// the twiddles exp(2 pi i j / N) tabulated once per workgroup in LDS.  Loads
+// and stores walk the C lines together, so a column workgroup reads C
+// consecutive values of each row.  sign = -1 forward, +1 inverse
+// (unnormalised).
+__global__ void __launch_bounds__(kFftThreads)
+k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int groups_per_plane, int sign,
+            Radices rs) {
+    __shared__ double2 buf[kFftElems];
+    __shared__ double2 tw[kFftMaxN];
+    const int g = blockIdx.x % groups_per_plane, plane = blockIdx.x / groups_per_plane;
+    double2 *base = data + (size_t)plane * plane_stride;
+    const int l0 = g * C;
+    for (int j = threadIdx.x; j < N; j += kFftThreads) {
+        double sn, cs;
+        sincospi(2.0 * (double)j / (double)N, &sn, &cs);
+        tw[j] = make_double2(cs, sign < 0 ? -sn : sn);
+    }
+    for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
+        const int line = cols ? i % C : i / N, k = cols ? i / C : i % N;
+        const size_t addr = cols ? (size_t)k * N + (l0 + line) : (size_t)(l0 + line) * N + k;
+        buf[line * N + k] = base[addr];
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int s = 0; s < rs.n4; s++, Ns *= 4) fft_stage<4>(buf, tw, N, C, Ns, sign);
+    for (int s = 0; s < rs.n2; s++, Ns *= 2) fft_stage<2>(buf, tw, N, C, Ns, sign);
+    for (int s = 0; s < rs.n3; s++, Ns *= 3) fft_stage<3>(buf, tw, N, C, Ns, sign);
+    for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
+        const int line = cols ? i % C : i / N, k = cols ? i / C : i % N;
+        const size_t addr = cols ? (size_t)k * N + (l0 + line) : (size_t)(l0 + line) * N + k;
+        base[addr] = buf[line * N + k];
+    }
+}
+
+// multiply by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2)) on the 4
+// planes of sheet blockIdx.y; modes with lattice momentum squared above uv2 > 0 are set to zero
 __global__ void __launch_bounds__(256)
 k_poisson_kernel(int N, double m2, double uv2, double2 *planes) {
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
+    planes += (size_t)blockIdx.y * 4 * n2;
     int kx = (int)(x % N), ky = (int)(x / N);
     double sx = sinpi((double)kx / N), sy = sinpi((double)ky / N);
     double k2 = 4.0 * sx * sx + 4.0 * sy * sy;
@@ -170,20 +223,25 @@ k_wilson_init(int N, double *V) {
     store_m(V, n2, x, m_ident<double>());
 }
 
+// V <- V exp(-i Lambda_s) for the n_sheets sheets of planes [sheet][4][n2], in
+// sheet order (earlier sheets to the left)
 __global__ void __launch_bounds__(256)
-k_wilson_accum(int N, const double2 *planes, double *V) {
+k_wilson_accum(int N, const double2 *planes, int n_sheets, double *V) {
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
-    double lam[8];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        double2 v = planes[(size_t)j * n2 + x];
-        lam[2 * j] = v.x;
-        lam[2 * j + 1] = v.y;
-    }
     M3<double> v = load_m(V, n2, x);
-    store_m(V, n2, x, mul(v, expi_alg(lam, -1.0)));
+    for (int s = 0; s < n_sheets; s++) {
+        double lam[8];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            double2 p = planes[((size_t)s * 4 + j) * n2 + x];
+            lam[2 * j] = p.x;
+            lam[2 * j + 1] = p.y;
+        }
+        v = mul(v, expi_alg(lam, -1.0));
+    }
+    store_m(V, n2, x, v);
 }
 
 // ---- 4. matching ------------------------------------------------------------
@@ -416,9 +474,9 @@ k_first_half_step(int N, const double *U0, const double *pi0, FieldPtrs<T> out, 
 static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed, int nucleus,
-                             int sheet, double2 *planes) {
-    hipLaunchKernelGGL(k_mv_charges, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, sigma,
-                       seed, nucleus, sheet, planes);
+                             int sheet0, int n_sheets, double2 *planes) {
+    hipLaunchKernelGGL(k_mv_charges, dim3(blocks_for((size_t)N * N, 256), n_sheets), dim3(256), 0, st, N,
+                       sigma, seed, nucleus, sheet0, planes);
     return hipGetLastError();
 }
 
@@ -432,29 +490,28 @@ hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes
     return hipGetLastError();
 }
 
-static hipError_t fft2(hipStream_t st, int N, double2 *planes, int sign) {
+static hipError_t fft2(hipStream_t st, int N, double2 *planes, int n_planes, int sign) {
     Radices rs;
     if (N > kFftMaxN || !radices_of(N, rs)) return hipErrorInvalidValue;
-    size_t n2 = (size_t)N * N;
-    // rows: contiguous elements
-    hipLaunchKernelGGL(k_fft_lines, dim3(4 * N), dim3(kFftThreads), 0, st, planes, N, (size_t)1,
-                       (size_t)N, n2, N, sign, rs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // columns: elements N apart
-    hipLaunchKernelGGL(k_fft_lines, dim3(4 * N), dim3(kFftThreads), 0, st, planes, N, (size_t)N,
-                       (size_t)1, n2, N, sign, rs);
-    return hipGetLastError();
+    const size_t n2 = (size_t)N * N;
+    const int C = fft_lines_per_group(N), groups = N / C;
+    for (int cols = 0; cols < 2; cols++) {
+        hipLaunchKernelGGL(k_fft_lines, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, cols, n2,
+                           groups, sign, rs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes) {
-    hipError_t e = fft2(st, N, planes, -1);
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets) {
+    hipError_t e = fft2(st, N, planes, 4 * n_sheets, -1);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_poisson_kernel, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N, m2,
+    hipLaunchKernelGGL(k_poisson_kernel, dim3(blocks_for((size_t)N * N, 256), n_sheets), dim3(256), 0, st, N, m2,
                        uv2, planes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return fft2(st, N, planes, +1);
+    return fft2(st, N, planes, 4 * n_sheets, +1);
 }
 
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V) {
@@ -462,9 +519,9 @@ hipError_t launch_wilson_init(hipStream_t st, int N, double *V) {
     return hipGetLastError();
 }
 
-hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, double *V) {
+hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, int n_sheets, double *V) {
     hipLaunchKernelGGL(k_wilson_accum, dim3(blocks_for((size_t)N * N, 256)), dim3(256), 0, st, N,
-                       planes, V);
+                       planes, n_sheets, V);
     return hipGetLastError();
 }
 

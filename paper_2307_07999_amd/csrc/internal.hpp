@@ -84,15 +84,16 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
                        int *n_blocks_out);
 
 // initial conditions (always FP64 internally)
+constexpr int kSheetChunk = 8;   // MV sheets per initialisation launch
 hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed, int nucleus,
-                             int sheet, double2 *planes /* [4][n2] */);
+                             int sheet0, int n_sheets, double2 *planes /* [n_sheets][4][n2] */);
 hipError_t launch_charges_to_planes(hipStream_t st, int N, const double *rho /* [8][n2] */,
                                  double2 *planes);
 hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes, double *rho);
 hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2,
-                          double2 *planes /* [4][n2] in place */);
+                          double2 *planes /* [n_sheets][4][n2] in place */, int n_sheets);
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V);
-hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, double *V);
+hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, int n_sheets, double *V);
 hipError_t launch_match_pi0(hipStream_t st, int N, const double *VA, const double *VB,
                            double *U0 /* [2][18][n2] FP64 */, double *pi0 /* [8][n2] */,
                            int *status, int max_iter, double tol);

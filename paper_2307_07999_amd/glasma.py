@@ -316,11 +316,13 @@ class Event:
     def set_sort_period(self, every):
         return check(lib().gl_set_sort_period(self._h, every))
 
-    def profile(self, on=True):
-        return check(lib().gl_profile_enable(self._h, 1 if on else 0))
+    def profile(self, on=True, period=1):
+        """Time every period-th launch of each hot-path kernel class (off: on=False)."""
+        return check(lib().gl_profile_enable(self._h, period if on else 0))
 
     def profile_read(self):
-        """(ms[4], launches[4]) per kernel class: field step, site fields, push, reduction."""
+        """(ms[4], launches[4]) of the timed launches per kernel class: field step
+        (with the site fields), unused, push, reduction."""
         ms = np.zeros(4)
         cnt = np.zeros(4, np.int64)
         check(lib().gl_profile_read(self._h, _d(ms), cnt.ctypes.data_as(_I64)))
