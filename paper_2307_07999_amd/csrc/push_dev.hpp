@@ -104,7 +104,10 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         for (int a = 0; a < 8; a++) pl_st(P.Q, P.cap, a, i, q[a]);
         // broadening at tau_{n+1/2}, accumulated in FP64
         const double etab = 0.5 * ((double)eta_old + (double)eta_new);
-        const double pzlab = (double)ptau * sinh(etab) + (double)pzh * cosh(etab);
+        // sinh and cosh from one expm1 (exact-to-rounding for small rapidities)
+        const double em = expm1(etab), ie = 1.0 / (em + 1.0);
+        const double sh = 0.5 * em * (em + 2.0) * ie, ch = 1.0 + 0.5 * em * em * ie;
+        const double pzlab = (double)ptau * sh + (double)pzh * ch;
         const double x0 = el_ld(P.px0, i), y0 = el_ld(P.py0, i), z0 = el_ld(P.pz0, i);
         acc[0] = (double)pl[0] * pl[0] - x0 * x0;
         acc[1] = (double)pl[1] * pl[1] - y0 * y0;
@@ -115,30 +118,36 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 }
 
 // Per-species workgroup reduction of kPushBlock threads (particles of
-// several species share a workgroup once they are sorted by cell): for each
-// species and term, a DPP sum over each 16-lane row, then one lane per row
-// writes its total to LDS and the totals of the kPushBlock / 16 rows are
-// added in row order -- a fixed order, so the partial sums are deterministic.
-// Writes out[sp * 4 + k].
+// several species share a workgroup once they are sorted by cell).  Every
+// thread writes its species and four terms to LDS; then work item (g, c)
+// sums term c % 4 of species c / 4 over the 32 particles of segment g in
+// particle order, and thread c adds the segments in order -- a fixed order,
+// so the partial sums are deterministic.  Writes out[sp * 4 + k].
 __device__ __forceinline__ void block_species_reduce(int s, const double *acc, int n_species,
                                                      double *__restrict__ out) {
-    constexpr int kRows = kPushBlock / 16;
-    __shared__ double red[kMaxSpecies * 4][kRows];
-    const int row = threadIdx.x >> 4;
-    const bool leader = (threadIdx.x & 15) == 0;
-    for (int sp = 0; sp < n_species; sp++) {
+    constexpr int kSeg = 8, kLen = kPushBlock / kSeg;
+    __shared__ double val[4][kPushBlock];
+    __shared__ int spc[kPushBlock];
+    __shared__ double part[kSeg][kMaxSpecies * 4];
+    const int t = threadIdx.x;
+    spc[t] = s;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const double v = row_sum(s == sp ? acc[k] : 0.0);
-            if (leader) red[sp * 4 + k][row] = v;
-        }
+    for (int k = 0; k < 4; k++) val[k][t] = acc[k];
+    __syncthreads();
+    const int ncol = n_species * 4;
+    for (int w = t; w < kSeg * ncol; w += kPushBlock) {
+        const int g = w / ncol, c = w % ncol, sp = c >> 2, k = c & 3;
+        double sum = 0.0;
+#pragma unroll 8
+        for (int i = g * kLen; i < (g + 1) * kLen; i++) sum += spc[i] == sp ? val[k][i] : 0.0;
+        part[g][c] = sum;
     }
     __syncthreads();
-    if (threadIdx.x < n_species * 4) {
-        double t = 0.0;
+    if (t < ncol) {
+        double sum = 0.0;
 #pragma unroll
-        for (int r = 0; r < kRows; r++) t += red[threadIdx.x][r];
-        out[threadIdx.x] = t;
+        for (int g = 0; g < kSeg; g++) sum += part[g][t];
+        out[t] = sum;
     }
 }
 
