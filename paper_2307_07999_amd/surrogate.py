@@ -26,15 +26,32 @@ JET_PT_MIN = 0.5
 TAU_MAX = 1.0
 M_IR = 0.2
 QS_OVER_G2MU = 0.6          # reading of "Q_s = 2 GeV": g^2 mu = Q_s / 0.6
-# network inputs: Q_s, m, p_T0, tau_form and the time since formation
-# tau - tau_form (the same information as tau; it lines up the sharp rise of
-# the coefficients that follows formation)
+# network inputs: Q_s, m, p_T0, tau_form and the square root of the time
+# since the particles start, sqrt(tau - tau_start).  The solver starts them at
+# the first step at or after tau_form, tau_start = ceil(tau_form / dtau) dtau,
+# so curves of different lattice spacings line up at their start; the square
+# root spreads the sharp rise right after formation over the input range.
 IN_LO = np.array([QS_RANGE[0], 0.0, PT_RANGE[0], 0.0, 0.0], np.float32)
-IN_HI = np.array([QS_RANGE[1], MASSES[-1], PT_RANGE[1], 0.2, TAU_MAX], np.float32)
+IN_HI = np.array([QS_RANGE[1], MASSES[-1], PT_RANGE[1], 0.2, math.sqrt(TAU_MAX)], np.float32)
+# the surrogate reproduces the 512^2, L = 10 fm solver (time step a/8)
+REF_N, REF_L_FM = 512, 10.0
+REF_DTAU_FM = 0.125 * REF_L_FM / REF_N
 
 
 def tau_form(m, pt):
     return HBARC / (2.0 * math.sqrt(m * m + pt * pt))
+
+
+def tau_start(m, pt, dtau_fm=REF_DTAU_FM):
+    """First time step at or after the formation time (the solver's rule)."""
+    return max(1, math.ceil(tau_form(m, pt) / dtau_fm - 1e-12)) * dtau_fm
+
+
+def features(qs, m, pt, since_start):
+    since_start = np.maximum(np.asarray(since_start, np.float64), 0.0)
+    one = np.ones_like(since_start)
+    return np.stack([qs * one, m * one, pt * one, tau_form(m, pt) * one, np.sqrt(since_start)],
+                    axis=1).astype(np.float32)
 
 
 def draw_params(n, seed):
@@ -111,13 +128,15 @@ def solver_curves(params, N, L_fm, n_particles, seed, precision=32, sheets=50, b
 
 
 def rows(params, curves):
+    """Network rows of solver curves; each curve is aligned on its own start
+    (its first row is the first step after formation)."""
     X, Y = [], []
     for (qs, m, pt), (tau, kap, dpt) in zip(params, curves):
-        tf = tau_form(m, pt)
-        for t, k, d in zip(tau, kap, dpt):
-            X.append((qs, m, pt, tf, t - tf))
-            Y.append((k, d))
-    return np.asarray(X, np.float32), np.asarray(Y, np.float32)
+        if len(tau) == 0:
+            continue
+        X.append(features(qs, m, pt, tau - tau[0]))
+        Y.append(np.stack([kap, dpt], axis=1))
+    return np.concatenate(X).astype(np.float32), np.concatenate(Y).astype(np.float32)
 
 
 class Surrogate:
@@ -140,12 +159,13 @@ class Surrogate:
         return losses
 
     def predict(self, qs, m, pt, tau):
+        """kappa and <dp_T^2> at tau as the 512^2 solver gives them (zero
+        before its particles start)."""
         tau = np.asarray(tau, np.float64)
-        tf = tau_form(m, pt)
-        X = np.stack([np.full_like(tau, qs), np.full_like(tau, m), np.full_like(tau, pt),
-                      np.full_like(tau, tf), tau - tf], axis=1).astype(np.float32)
-        Y = self.net.infer(X).cpu().numpy()
-        return Y[:, 0], Y[:, 1]
+        since = tau - tau_start(m, pt)
+        Y = self.net.infer(features(qs, m, pt, since)).cpu().numpy()
+        live = since >= -1e-9
+        return np.where(live, Y[:, 0], 0.0), np.where(live, Y[:, 1], 0.0)
 
     def query(self, qs, m, pt, tau, N=512, L_fm=10.0, n_particles=100000, seed=12345):
         """kappa(tau), <dp_T^2>(tau) and whether the solver was used instead
@@ -235,9 +255,7 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_
     torch.cuda.synchronize()
     rep["mlp_s_per_curve"] = (time.perf_counter() - t) / reps
     # a batch of curves in one inference call
-    tf = tau_form(4.18, 2.0)
-    Xq = np.tile(np.stack([np.full(410, 2.0), np.full(410, 4.18), np.full(410, 2.0),
-                           np.full(410, tf), tau - tf], axis=1), (64, 1)).astype(np.float32)
+    Xq = np.tile(features(2.0, 4.18, 2.0, tau - tau_start(4.18, 2.0)), (64, 1))
     Xd = B.net._dev(Xq, 5)
     B.net.infer(Xd)
     torch.cuda.synchronize()
