@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-event batched FP32 workload")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache for the batch")
-    ap.add_argument("--surrogate", default="quick", choices=("quick", "full", "off"),
+    ap.add_argument("--surrogate", default="full", choices=("quick", "full", "off"),
                     help="surrogate-vs-solver section: reduced protocol, full protocol or none")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
