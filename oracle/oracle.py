@@ -328,6 +328,29 @@ def particle_step(N, n, dtau, U, phi, F, P, mass, nform):
     return series
 
 
+def static_series(s, dtau, n_steps, n0=1):
+    """Static-quark momentum broadening from electric-field correlators
+    (Sec. 2, Eq. (4)) on the lattice.  A static quark keeps its colour charge
+    and its site, so delta p_i = sum_n dtau Q^a E_i^a(x, tau_n) with the
+    local-frame site fields the particles read; with <Q^a Q^b> = delta^ab / 2
+    its mean square over the charges is (1/2) sum_a (I_i^a)^2 for
+    I_i^a(x) = sum_n dtau E_i^a(x, tau_n).  Accumulates I over the steps
+    n >= n0 while advancing the State; row k (step n = s.n + k, time
+    tau_{n+1/2}) holds the sums over sites of (1/2) sum_a (I_i^a)^2 for
+    i = x, y, z and the number of sites (0 before n0)."""
+    n2 = s.N * s.N
+    I = np.zeros((n2, 3, 8))
+    rows = np.zeros((n_steps, 4))
+    for k in range(n_steps):
+        n = s.n
+        F = field_step(s, dtau, want_F=True)
+        if n >= n0:
+            I += dtau * F[:, 0:3, :]
+            rows[k, :3] = 0.5 * (I ** 2).sum(axis=(0, 2))
+            rows[k, 3] = n2
+    return rows
+
+
 def run(N, sigma, m2, n_sheets, seed, dtau, n_steps, species):
     """species: list of dicts with kind, mass, p0, nform, n (lattice units)."""
     ns = len(species)

@@ -254,3 +254,34 @@ def test_broadening_gauge_invariant(orc):
     assert np.abs(ra - rb).max() < 1e-12
     assert np.abs(P.p - Pg.p).max() < 1e-12
     assert np.array_equal(P.cell, Pg.cell)
+
+
+def test_static_correlator_is_charge_average_of_static_quarks(orc):
+    """Eq. (4): the correlator sum_a (I_i^a)^2 / 2 at every site equals the
+    mean square momentum of static quarks (m -> infinity) over charges with
+    <Q^a Q^b> = delta^ab / 2.  The eight charges Q = e_b (unit algebra
+    vectors) at every site give sum_b (delta p_i)^2 = sum_b (I_i^b)^2 exactly
+    for the transverse momenta; the lab-frame longitudinal momentum of the
+    push agrees with the E_z integral to O(dtau^2)."""
+    N, steps = 8, 24
+    s, rc, _ = orc.init_glasma(N, 0.6, 0.016, 1, 91, DT)
+    s2 = s.copy()
+    P = orc.Particles(8 * N * N)
+    for x in range(N * N):
+        for b in range(8):
+            i = 8 * x + b
+            P.cell[i] = (x % N, x // N)
+            P.Q[i, b] = 1.0
+    rows, _ = _coupled(orc, s, P, steps, [1e12], [1])
+    stat = orc.static_series(s2, DT, steps, n0=1)
+    assert np.all(stat[:, 3] == N * N)
+    for i in (0, 1):
+        assert np.abs(rows[:, 0, i] - 2.0 * stat[:, i]).max() < 1e-10 * np.abs(stat[:, i]).max()
+    rel_z = np.abs(rows[:, 0, 2] - 2.0 * stat[:, 2]).max() / np.abs(stat[:, 2]).max()
+    print("static limit, longitudinal: max relative difference %.2e" % rel_z)
+    assert rel_z < 0.05, rel_z
+    # the correlator grows from zero and a later start excludes earlier fields
+    s3, _, _ = orc.init_glasma(N, 0.6, 0.016, 1, 91, DT)
+    late = orc.static_series(s3, DT, steps, n0=10)
+    assert np.all(late[:9, 3] == 0) and np.all(late[9:, 3] == N * N)
+    assert np.all(late[:9, :3] == 0) and late[9, 0] < stat[9, 0]
