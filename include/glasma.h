@@ -74,6 +74,7 @@ typedef struct {
     int32_t reunit_every;   /* FP32 only: re-unitarise links when n % reunit_every == reunit_every-1; 0 = never */
     int32_t max_steps;      /* capacity of the broadening series (rows) */
     int64_t max_particles;  /* particle capacity over all species (padding included by the library) */
+    int32_t static_correlator; /* nonzero: reserve the static-quark accumulators (gl_static_start) */
 } gl_lattice_desc;
 
 /* MV-model description (Sec. 1 "Glasma"): per-sheet charge variance
@@ -197,13 +198,31 @@ gl_status gl_get_wilson_line(gl_event *ev, int32_t nucleus, double *V);
 gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t sheet,
                           double sigma, double *rho);
 
+/* Static quarks (Sec. 2, Eq. (4)): a quark of infinite mass keeps its site
+ * and its colour charge, so its momentum change is the time integral of the
+ * colour-electric field; with <Q^a Q^b> = delta^ab / 2 the broadening is
+ * (1/2) sum_a (I_i^a)^2, I_i^a(x) = sum_n dtau E_i^a(x, tau_n), averaged over
+ * the sites (a quark at every site).  E_i are the local-frame site fields
+ * the particles read.  gl_static_start clears the FP64 accumulators and
+ * accumulates from the first step at or after tau_start_fm (not before the
+ * current step); the event must be created with static_correlator != 0.
+ * Every later field step of the event (gl_evolve_fields, gl_run; not the
+ * batched stepping) adds its step.
+ * gl_static_broadening returns rows (tau_{n+1/2} [fm], <dp_x^2>, <dp_y^2>,
+ * <dp_z^2> [GeV^2], sites) for the accumulated steps; out [cap][5] may be
+ * null to query n_rows.  Errors: GL_ESTATE without the accumulators or before
+ * initialisation, GL_EINVAL for a short output. */
+gl_status gl_static_start(gl_event *ev, double tau_start_fm);
+gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows);
+
 /* Kernel timing with HIP events recorded on the event's stream around the
  * launches of the hot-path kernels: period 0 switches it off, period p >= 1
  * times every p-th launch of each kernel class (a sample, so that the event
  * records barely perturb the run).  gl_profile_read synchronises
  * the stream and returns, per kernel class (0 field step, which also writes
- * the site fields when the event has particles, 1 unused, 2 particle push,
- * 3 series reduction), the summed milliseconds and the
+ * the site fields when the event has particles or static quarks, 1 static
+ * quark accumulation, 2 particle push, 3 series reduction), the summed
+ * milliseconds and the
  * launch counts since the last read, then clears them.  Creates HIP events
  * only (no device memory). */
 #define GL_PROF_KERNELS 4

@@ -37,7 +37,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t field[2], F, part[2], id[2], sort_keys[2], sort_vals[2], sort_counts, sort_totals, partials,
-        series, diag, VA, VB, planes, U0, pi0, status, total;
+        series, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, total;
     int64_t slots;         // particle capacity in slots (padding included)
     size_t n_diag_blocks;  // workgroups of the diagnostics kernel
 };
@@ -88,6 +88,11 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     L.U0 = take(36 * n2 * sizeof(double));
     L.pi0 = take(8 * n2 * sizeof(double));
     L.status = take(256);
+    // static-quark accumulators I [24][n2], their per-workgroup partials and series
+    const bool stat = d->static_correlator != 0;
+    L.stat = take(stat ? 24 * n2 * sizeof(double) : 0);
+    L.stat_part = take(stat ? (n2 + 255) / 256 * 4 * sizeof(double) : 0);
+    L.stat_series = take(stat ? std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double) : 0);
     L.total = off;
     return GL_OK;
 }
@@ -118,6 +123,9 @@ struct gl_event {
     int pbuf = 0;               // which particle buffer is current
     int32_t sort_every = 16;    // re-sort particles by cell every this many pushes (0: never)
     int64_t since_sort = 0;
+    bool stat_on = false;       // static-quark accumulation running
+    int64_t stat_n0 = 0;        // first accumulated field step
+    int64_t stat_rows = 0;      // static series rows written
 
     // kernel timing: pairs of events per launch, grouped by kernel class
     int32_t prof = 0;                       // time every prof-th launch of each class (0: off)
@@ -175,6 +183,7 @@ struct gl_event {
         return sc;
     }
     double *series() const { return (double *)(ws + L.series); }
+    double *stat_series() const { return (double *)(ws + L.stat_series); }
     double *partials() const { return (double *)(ws + L.partials); }
 };
 
@@ -229,8 +238,19 @@ gl_status field_step(gl_event *ev, bool site_fields) {
     if (!ev->fp64() && ev->desc.reunit_every > 0 &&
         ev->n % ev->desc.reunit_every == ev->desc.reunit_every - 1)
         reunit = 1;
+    const bool stat = ev->stat_on && ev->n >= ev->stat_n0 && ev->n - 1 < ev->desc.max_steps;
     PROF(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
-                                      site_fields ? (T *)(ev->ws + ev->L.F) : nullptr, tau, ev->dtau, reunit)));
+                                      site_fields || stat ? (T *)(ev->ws + ev->L.F) : nullptr, tau, ev->dtau,
+                                      reunit)));
+    if (stat) {
+        // static quarks: accumulate the site fields at tau_n, series row n - 1 (time tau_{n+1/2})
+        int nb = 0;
+        double *part = (double *)(ev->ws + ev->L.stat_part);
+        PROF(ev, 1, (launch_static_accum<T>(ev->stream, ev->N, (const T *)(ev->ws + ev->L.F),
+                                            (double *)(ev->ws + ev->L.stat), ev->dtau, part, &nb)));
+        HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->stat_series() + (ev->n - 1) * kMaxSpecies * 4));
+        ev->stat_rows = std::max<int64_t>(ev->stat_rows, ev->n);
+    }
     ev->cur = nxt;
     ev->n += 1;
     return GL_OK;
@@ -652,6 +672,48 @@ gl_status gl_run(gl_event *ev, int32_t n_steps) {
             if (s) return s;
         }
     }
+    return GL_OK;
+}
+
+gl_status gl_static_start(gl_event *ev, double tau_start_fm) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (!ev->desc.static_correlator) return fail(GL_ESTATE, "event created without static_correlator");
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    if (!(tau_start_fm >= 0)) return fail(GL_EINVAL, "tau_start_fm must be >= 0");
+    const double r = std::ceil(tau_start_fm / (ev->dtau * ev->a_fm) - 1e-9);
+    int64_t n0 = r < 1.0 ? 1 : (r > 2e9 ? (int64_t)2e9 : (int64_t)r);
+    ev->stat_n0 = std::max<int64_t>(n0, ev->n);
+    HIP_TRY(hipMemsetAsync(ev->ws + ev->L.stat, 0, 24 * ev->n2 * sizeof(double), ev->stream));
+    HIP_TRY(hipMemsetAsync(ev->stat_series(), 0,
+                           std::max(1, ev->desc.max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double), ev->stream));
+    ev->stat_rows = 0;
+    ev->stat_on = true;
+    return GL_OK;
+}
+
+gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows) {
+    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
+    if (!ev->desc.static_correlator) return fail(GL_ESTATE, "event created without static_correlator");
+    std::vector<double> s4((size_t)std::max<int64_t>(ev->stat_rows, 1) * kMaxSpecies * 4, 0.0);
+    if (ev->stat_rows > 0) {
+        HIP_TRY(hipMemcpyAsync(s4.data(), ev->stat_series(), (size_t)ev->stat_rows * kMaxSpecies * 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+    }
+    const double f2 = 1.0 / (ev->a_gev * ev->a_gev), dt_fm = ev->dtau * ev->a_fm;
+    int32_t r = 0;
+    for (int64_t k = 0; k < ev->stat_rows; k++) {
+        const double *row = s4.data() + (size_t)k * kMaxSpecies * 4;
+        if (!(row[3] > 0)) continue;
+        if (out) {
+            if (r >= cap) return fail(GL_EINVAL, "output too small");
+            out[r * 5 + 0] = (k + 1.5) * dt_fm;
+            for (int c = 0; c < 3; c++) out[r * 5 + 1 + c] = row[c] / row[3] * f2;
+            out[r * 5 + 4] = row[3];
+        }
+        r++;
+    }
+    *n_rows = r;
     return GL_OK;
 }
 

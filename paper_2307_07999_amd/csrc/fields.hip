@@ -48,6 +48,45 @@ k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T *__restrict__ F, T tau,
     field_step_link(tile, N, in, out, F, ix, iy, lx, ly, threadIdx.x & 1, tau, dtau, tau_h, reunit);
 }
 
+// Static quarks (Sec. 2, Eq. (4)): I_i^a(x) += dtau E_i^a(x, tau_n) from the
+// site fields at tau_n (E_x and E_y as their two stored halves), FP64, and
+// per workgroup the sums over its sites of (1/2) sum_a (I_i^a)^2 for
+// i = x, y, z with the site count, added in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_static_accum(int N, const T *__restrict__ F, double *__restrict__ I, double dtau, double *__restrict__ partials) {
+    __shared__ double red[4][256];
+    const size_t n2 = plane_pitch(N);
+    const size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (x < (size_t)N * N) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                double e = (double)pl_ld(F, n2, 8 * i + a, x);
+                if (i < 2) e += (double)pl_ld(F, n2, 48 + 8 * i + a, x);
+                const double t = pl_ld(I, n2, 8 * i + a, x) + dtau * e;
+                pl_st(I, n2, 8 * i + a, x, t);
+                s += t * t;
+            }
+            v[i] = 0.5 * s;
+        }
+        v[3] = 1.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // Diagnostics per site, reduced per workgroup in FP64:
 // [0] max |G^a|, [1] max |E^a|, [2] max |U U^dag - 1|, [3..6] energy terms,
 // [7] non-finite count.
@@ -170,6 +209,15 @@ hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T
 }
 
 template <typename T>
+hipError_t launch_static_accum(hipStream_t st, int N, const T *F, double *I, double dtau, double *partials,
+                               int *n_blocks_out) {
+    const int nb = (int)(((size_t)N * N + 255) / 256);
+    *n_blocks_out = nb;
+    hipLaunchKernelGGL(k_static_accum<T>, dim3(nb), dim3(256), 0, st, N, F, I, dtau, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
                        int *n_blocks_out) {
     dim3 grid((N + TX - 1) / TX, (N + TY - 1) / TY), block(TX, TY);
@@ -181,7 +229,8 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
 #define GL_INST(T)                                                                           \
     template hipError_t launch_field_step<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, T *,    \
                                              double, double, int);                           \
-    template hipError_t launch_diag<T>(hipStream_t, int, FieldPtrs<T>, double, double *, int *);
+    template hipError_t launch_diag<T>(hipStream_t, int, FieldPtrs<T>, double, double *, int *);     \
+    template hipError_t launch_static_accum<T>(hipStream_t, int, const T *, double *, double, double *, int *);
 GL_INST(double)
 GL_INST(float)
 #undef GL_INST

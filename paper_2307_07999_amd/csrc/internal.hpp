@@ -79,6 +79,10 @@ hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, Fi
 hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, int32_t base);
 hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
                                 double *row);
+// static-quark accumulators I [24][n2] FP64; partials [blocks][4]
+template <typename T>
+hipError_t launch_static_accum(hipStream_t st, int N, const T *F, double *I, double dtau, double *partials,
+                               int *n_blocks_out);
 template <typename T>
 hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
                        int *n_blocks_out);

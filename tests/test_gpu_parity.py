@@ -30,9 +30,9 @@ def gl():
     return g
 
 
-def _event(gl, N, L=4.0, prec=64, max_particles=0, max_steps=128, reunit=16):
+def _event(gl, N, L=4.0, prec=64, max_particles=0, max_steps=128, reunit=16, static_correlator=False):
     return gl.Event(N, L, 0.125, precision=prec, reunit_every=reunit, max_steps=max_steps,
-                    max_particles=max_particles)
+                    max_particles=max_particles, static_correlator=static_correlator)
 
 
 def test_charges_match_oracle(gl, orc):
@@ -289,3 +289,41 @@ def test_particle_sort_is_transparent_and_deterministic(gl, orc):
     # identical configuration -> bitwise identical series and particles
     assert np.array_equal(results[3][1], results[0][1])
     assert np.array_equal(results[3][0]["p"], results[0][0]["p"])
+
+
+def test_static_correlator_matches_oracle(gl, orc):
+    """Static quarks (Eq. (4)) on the 32^2 configuration: FP64 accumulators
+    of the site fields from tau_start on, against the oracle's correlator, in
+    FP64 and in FP32 (the FP32 fields against the FP64 oracle at the 1e-3
+    observable target).  Fields only: the accumulation needs no particles."""
+    cfg = H.C1
+    N = cfg["N"]
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    steps = H.n_steps(cfg)
+    tau0 = 0.05                          # fm: start after a few steps
+    n0 = int(np.ceil(tau0 / (0.125 * a_fm) - 1e-9))
+    s, rc, _ = orc.init_glasma(N, sigma, m2, 1, cfg["seed"], 0.125)
+    assert rc == 0
+    rows = orc.static_series(s, 0.125, steps, n0=n0)
+    f2, _ = orc.to_physical(a_fm)
+    act = rows[:, 3] > 0
+    want = rows[act, :3] / rows[act, 3:4] * f2
+    for prec, tol in ((64, 1e-9), (32, 1e-3)):
+        ev = _event(gl, N, cfg["L"], prec=prec, max_steps=steps, static_correlator=True)
+        ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
+        ev.static_start(tau0)
+        ev.evolve_fields(steps)
+        got = ev.static_broadening()
+        assert len(got) == int(act.sum()) == steps - n0 + 1
+        assert np.allclose(got[:, 0], (np.nonzero(act)[0] + 1.5) * 0.125 * a_fm)
+        assert np.all(got[:, 4] == N * N)
+        for c in range(3):
+            err = H.rel_err(got[:, 1 + c], want[:, c])
+            print("static correlator FP%d component %d: rel err %.2e" % (prec, c, err))
+            assert err < tol
+        ev.close()
+    # without the accumulators the calls refuse
+    ev = _event(gl, N, cfg["L"], max_steps=steps)
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
+    with pytest.raises(gl.GlasmaError):
+        ev.static_start(0.0)
