@@ -351,6 +351,48 @@ def static_series(s, dtau, n_steps, n0=1):
     return rows
 
 
+def lightlike_series(s, dtau, n_steps, n0=1):
+    """Lightlike-jet momentum broadening from parallel-transported field
+    correlators (Sec. 2, Eq. (5)) on the lattice.  A jet starting at the
+    centre of site x0 at step n0 moves along +x at the speed of light: at step
+    n = n0 + k it sits in the cell x0 + floor(k dtau + 1/2) (the NGP rule of
+    the particle push), feels F_x = E_x, F_y = E_y - B_z, F_z = E_z + B_y of the
+    local-frame site fields there, and its colour frame is carried by W, the
+    product of the x links it crossed, each taken at its crossing step (W is
+    multiplied by U_x(cell) at the tau_n of a step whose drift ends in the
+    next cell).  I_i^a(x0) = sum_n dtau [W F_i W^dag]^a and, with
+    <Q^a Q^b> = delta^ab / 2, row k (step n = s.n + k, time tau_{n+1/2}) holds
+    the sums over start sites of (1/2) sum_a (I_i^a)^2, i = x, y, z, and the
+    number of sites (0 before n0).  Advances the State."""
+    N = s.N
+    n2 = N * N
+    x0 = np.arange(n2) % N
+    y0 = np.arange(n2) // N
+    T = np.array([generator(a) for a in range(8)])
+    W = np.broadcast_to(np.eye(3, dtype=np.complex128), (n2, 3, 3)).copy()
+    I = np.zeros((n2, 3, 8))
+    rows = np.zeros((n_steps, 4))
+    for k in range(n_steps):
+        n = s.n
+        U1 = d2m(s.U[0]).copy()          # x links at tau_n
+        F = field_step(s, dtau, want_F=True)
+        if n < n0:
+            continue
+        j = n - n0
+        shift = int(np.floor(j * dtau + 0.5))
+        c = (x0 + shift) % N + N * y0
+        f = F[c]
+        for i, Fi in enumerate((f[:, 0], f[:, 1] - f[:, 5], f[:, 2] + f[:, 4])):
+            M = np.einsum("na,aij->nij", Fi, T)
+            Mt = W @ M @ np.conj(np.swapaxes(W, 1, 2))
+            I[:, i] += dtau * 2.0 * np.real(np.einsum("aij,nji->na", T, Mt))
+        rows[k, :3] = 0.5 * (I ** 2).sum(axis=(0, 2))
+        rows[k, 3] = n2
+        if int(np.floor((j + 1) * dtau + 0.5)) > shift:
+            W = W @ U1[c]
+    return rows
+
+
 def run(N, sigma, m2, n_sheets, seed, dtau, n_steps, species):
     """species: list of dicts with kind, mass, p0, nform, n (lattice units)."""
     ns = len(species)

@@ -285,3 +285,31 @@ def test_static_correlator_is_charge_average_of_static_quarks(orc):
     late = orc.static_series(s3, DT, steps, n0=10)
     assert np.all(late[:9, 3] == 0) and np.all(late[9:, 3] == N * N)
     assert np.all(late[:9, :3] == 0) and late[9, 0] < stat[9, 0]
+
+
+def test_lightlike_correlator_is_charge_average_of_lightlike_jets(orc):
+    """Eq. (5): the transported-field correlator equals the mean square
+    momentum of massless jets with p_x -> infinity (p_x = 1e12, velocity 1 to
+    double precision) started at every site centre, over the eight basis
+    charges Q = e_b, so sum_b (delta p_y)^2 = sum_b (I_y^b)^2 exactly; the
+    lab-frame longitudinal momentum agrees to O(dtau^2).  The jets cross
+    cells every eight steps, so the colour transport is exercised."""
+    N, steps = 8, 40
+    s, rc, _ = orc.init_glasma(N, 0.6, 0.016, 1, 93, DT)
+    s2 = s.copy()
+    P = orc.Particles(8 * N * N)
+    for x in range(N * N):
+        for b in range(8):
+            i = 8 * x + b
+            P.cell[i] = (x % N, x // N)
+            P.Q[i, b] = 1.0
+            P.p[i, 0] = P.p0[i, 0] = 1e12
+    rows, _ = _coupled(orc, s, P, steps, [0.0], [1])
+    ll = orc.lightlike_series(s2, DT, steps, n0=1)
+    assert np.all(ll[:, 3] == N * N)
+    assert np.abs(rows[:, 0, 1] - 2.0 * ll[:, 1]).max() < 1e-10 * np.abs(ll[:, 1]).max()
+    rel_z = np.abs(rows[:, 0, 2] - 2.0 * ll[:, 2]).max() / np.abs(ll[:, 2]).max()
+    print("lightlike limit, longitudinal: max relative difference %.2e" % rel_z)
+    assert rel_z < 0.05, rel_z
+    # the jets moved 5 cells, so the colour transport took part
+    assert np.all(P.cell[:, 0] == (np.repeat(np.arange(N * N) % N, 8) + 5) % N)
