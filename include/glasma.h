@@ -75,6 +75,7 @@ typedef struct {
     int32_t max_steps;      /* capacity of the broadening series (rows) */
     int64_t max_particles;  /* particle capacity over all species (padding included by the library) */
     int32_t static_correlator; /* nonzero: reserve the static-quark accumulators (gl_static_start) */
+    int32_t lightlike_correlator; /* nonzero: reserve the lightlike-jet accumulators (gl_lightlike_start) */
 } gl_lattice_desc;
 
 /* MV-model description (Sec. 1 "Glasma"): per-sheet charge variance
@@ -215,13 +216,31 @@ gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t 
 gl_status gl_static_start(gl_event *ev, double tau_start_fm);
 gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows);
 
+/* Lightlike jets (Sec. 2, Eq. (5)): a jet with p_x -> infinity started at
+ * the centre of every site x0 moves along +x at the speed of light (at step
+ * n0 + k it sits in the cell x0 + floor(k dtau + 1/2), the NGP rule of the
+ * particle push) and feels the colour force F_x = E_x, F_y = E_y - B_z,
+ * F_z = E_z + B_y of the local-frame site fields, parallel transported to
+ * its start with the product W of the x links it crossed (each at its
+ * crossing step): I_i^a(x0) = sum_n dtau [W F_i W^dag]^a, FP64, and the
+ * broadening is (1/2) sum_a (I_i^a)^2 averaged over the start sites.
+ * gl_lightlike_start resets W to the identity and I to zero and starts at
+ * the first step at or after tau_start_fm (not before the current step);
+ * the event must be created with lightlike_correlator != 0.  Later field
+ * steps of the event add theirs.  gl_lightlike_broadening returns rows
+ * (tau_{n+1/2} [fm], <dp_x^2>, <dp_y^2>, <dp_z^2> [GeV^2], sites) like
+ * gl_static_broadening; the same errors. */
+gl_status gl_lightlike_start(gl_event *ev, double tau_start_fm);
+gl_status gl_lightlike_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows);
+
 /* Kernel timing with HIP events recorded on the event's stream around the
  * launches of the hot-path kernels: period 0 switches it off, period p >= 1
  * times every p-th launch of each kernel class (a sample, so that the event
  * records barely perturb the run).  gl_profile_read synchronises
  * the stream and returns, per kernel class (0 field step, which also writes
- * the site fields when the event has particles or static quarks, 1 static
- * quark accumulation, 2 particle push, 3 series reduction), the summed
+ * the site fields when the event has particles or correlators, 1 static
+ * quark and lightlike jet accumulation, 2 particle push, 3 series
+ * reduction), the summed
  * milliseconds and the
  * launch counts since the last read, then clears them.  Creates HIP events
  * only (no device memory). */

@@ -37,7 +37,8 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t field[2], F, part[2], id[2], sort_keys[2], sort_vals[2], sort_counts, sort_totals, partials,
-        series, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, total;
+        series, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, ll, ll_part,
+        ll_series, total;
     int64_t slots;         // particle capacity in slots (padding included)
     size_t n_diag_blocks;  // workgroups of the diagnostics kernel
 };
@@ -93,6 +94,11 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     L.stat = take(stat ? 24 * n2 * sizeof(double) : 0);
     L.stat_part = take(stat ? (n2 + 255) / 256 * 4 * sizeof(double) : 0);
     L.stat_series = take(stat ? std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double) : 0);
+    // lightlike-jet transports W [18][n2] and accumulators I [24][n2], partials and series
+    const bool ll = d->lightlike_correlator != 0;
+    L.ll = take(ll ? 42 * n2 * sizeof(double) : 0);
+    L.ll_part = take(ll ? (n2 + 255) / 256 * 4 * sizeof(double) : 0);
+    L.ll_series = take(ll ? std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double) : 0);
     L.total = off;
     return GL_OK;
 }
@@ -126,6 +132,9 @@ struct gl_event {
     bool stat_on = false;       // static-quark accumulation running
     int64_t stat_n0 = 0;        // first accumulated field step
     int64_t stat_rows = 0;      // static series rows written
+    bool ll_on = false;         // lightlike-jet accumulation running
+    int64_t ll_n0 = 0;          // first accumulated field step
+    int64_t ll_rows = 0;
 
     // kernel timing: pairs of events per launch, grouped by kernel class
     int32_t prof = 0;                       // time every prof-th launch of each class (0: off)
@@ -184,6 +193,7 @@ struct gl_event {
     }
     double *series() const { return (double *)(ws + L.series); }
     double *stat_series() const { return (double *)(ws + L.stat_series); }
+    double *ll_series() const { return (double *)(ws + L.ll_series); }
     double *partials() const { return (double *)(ws + L.partials); }
 };
 
@@ -239,9 +249,10 @@ gl_status field_step(gl_event *ev, bool site_fields) {
         ev->n % ev->desc.reunit_every == ev->desc.reunit_every - 1)
         reunit = 1;
     const bool stat = ev->stat_on && ev->n >= ev->stat_n0 && ev->n - 1 < ev->desc.max_steps;
+    const bool ll = ev->ll_on && ev->n >= ev->ll_n0 && ev->n - 1 < ev->desc.max_steps;
     PROF(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
-                                      site_fields || stat ? (T *)(ev->ws + ev->L.F) : nullptr, tau, ev->dtau,
-                                      reunit)));
+                                      site_fields || stat || ll ? (T *)(ev->ws + ev->L.F) : nullptr, tau,
+                                      ev->dtau, reunit)));
     if (stat) {
         // static quarks: accumulate the site fields at tau_n, series row n - 1 (time tau_{n+1/2})
         int nb = 0;
@@ -250,6 +261,17 @@ gl_status field_step(gl_event *ev, bool site_fields) {
                                             (double *)(ev->ws + ev->L.stat), ev->dtau, part, &nb)));
         HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->stat_series() + (ev->n - 1) * kMaxSpecies * 4));
         ev->stat_rows = std::max<int64_t>(ev->stat_rows, ev->n);
+    }
+    if (ll) {
+        // lightlike jets: transported forces at tau_n with the x links of tau_n (state cur)
+        int nb = 0;
+        double *part = (double *)(ev->ws + ev->L.ll_part);
+        double *W = (double *)(ev->ws + ev->L.ll), *I = W + 18 * ev->n2;
+        PROF(ev, 1, (launch_lightlike_accum<T>(ev->stream, ev->N, (const T *)(ev->ws + ev->L.F),
+                                               ev->fields<T>(ev->cur).U, W, I, ev->n - ev->ll_n0, ev->dtau, part,
+                                               &nb)));
+        HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->ll_series() + (ev->n - 1) * kMaxSpecies * 4));
+        ev->ll_rows = std::max<int64_t>(ev->ll_rows, ev->n);
     }
     ev->cur = nxt;
     ev->n += 1;
@@ -691,18 +713,17 @@ gl_status gl_static_start(gl_event *ev, double tau_start_fm) {
     return GL_OK;
 }
 
-gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows) {
-    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
-    if (!ev->desc.static_correlator) return fail(GL_ESTATE, "event created without static_correlator");
-    std::vector<double> s4((size_t)std::max<int64_t>(ev->stat_rows, 1) * kMaxSpecies * 4, 0.0);
-    if (ev->stat_rows > 0) {
-        HIP_TRY(hipMemcpyAsync(s4.data(), ev->stat_series(), (size_t)ev->stat_rows * kMaxSpecies * 4 * sizeof(double),
+static gl_status correlator_rows(gl_event *ev, const double *series, int64_t rows, double *out, int32_t cap,
+                                 int32_t *n_rows) {
+    std::vector<double> s4((size_t)std::max<int64_t>(rows, 1) * kMaxSpecies * 4, 0.0);
+    if (rows > 0) {
+        HIP_TRY(hipMemcpyAsync(s4.data(), series, (size_t)rows * kMaxSpecies * 4 * sizeof(double),
                                hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipStreamSynchronize(ev->stream));
     }
     const double f2 = 1.0 / (ev->a_gev * ev->a_gev), dt_fm = ev->dtau * ev->a_fm;
     int32_t r = 0;
-    for (int64_t k = 0; k < ev->stat_rows; k++) {
+    for (int64_t k = 0; k < rows; k++) {
         const double *row = s4.data() + (size_t)k * kMaxSpecies * 4;
         if (!(row[3] > 0)) continue;
         if (out) {
@@ -715,6 +736,36 @@ gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *
     }
     *n_rows = r;
     return GL_OK;
+}
+
+gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows) {
+    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
+    if (!ev->desc.static_correlator) return fail(GL_ESTATE, "event created without static_correlator");
+    return correlator_rows(ev, ev->stat_series(), ev->stat_rows, out, cap, n_rows);
+}
+
+gl_status gl_lightlike_start(gl_event *ev, double tau_start_fm) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (!ev->desc.lightlike_correlator) return fail(GL_ESTATE, "event created without lightlike_correlator");
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    if (!(tau_start_fm >= 0)) return fail(GL_EINVAL, "tau_start_fm must be >= 0");
+    const double r = std::ceil(tau_start_fm / (ev->dtau * ev->a_fm) - 1e-9);
+    int64_t n0 = r < 1.0 ? 1 : (r > 2e9 ? (int64_t)2e9 : (int64_t)r);
+    ev->ll_n0 = std::max<int64_t>(n0, ev->n);
+    double *W = (double *)(ev->ws + ev->L.ll);
+    HIP_TRY(launch_wilson_init(ev->stream, ev->N, W));   // W = 1 at every start site
+    HIP_TRY(hipMemsetAsync(W + 18 * ev->n2, 0, 24 * ev->n2 * sizeof(double), ev->stream));
+    HIP_TRY(hipMemsetAsync(ev->ll_series(), 0,
+                           std::max(1, ev->desc.max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double), ev->stream));
+    ev->ll_rows = 0;
+    ev->ll_on = true;
+    return GL_OK;
+}
+
+gl_status gl_lightlike_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows) {
+    if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
+    if (!ev->desc.lightlike_correlator) return fail(GL_ESTATE, "event created without lightlike_correlator");
+    return correlator_rows(ev, ev->ll_series(), ev->ll_rows, out, cap, n_rows);
 }
 
 gl_status gl_series(gl_event *ev, double *out, int32_t cap_rows, int32_t *n_rows) {

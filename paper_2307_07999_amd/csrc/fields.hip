@@ -87,6 +87,72 @@ k_static_accum(int N, const T *__restrict__ F, double *__restrict__ I, double dt
     if (threadIdx.x < 4) partials[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Lightlike jets (Sec. 2, Eq. (5)): one jet per start site x0, step j since
+// its start; it sits in the cell x0 + floor(j dtau + 1/2) along x and feels
+// F_x = E_x, F_y = E_y - B_z, F_z = E_z + B_y there (site fields at tau_n),
+// transported to its start with W (FP64): I_i += dtau [W F_i W^dag]; when
+// this step's drift ends in the next cell, W <- W U_x(cell) with the links of
+// tau_n.  Per workgroup: sums of (1/2) sum_a (I_i^a)^2 and the site count.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_lightlike_accum(int N, const T *__restrict__ F, const T *__restrict__ U, double *__restrict__ W,
+                  double *__restrict__ I, int64_t j, double dtau, double *__restrict__ partials) {
+    __shared__ double red[4][256];
+    const size_t n2 = plane_pitch(N);
+    const size_t x0 = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (x0 < (size_t)N * N) {
+        const int64_t shift = (int64_t)floor((double)j * dtau + 0.5);
+        const int ix = (int)(((int64_t)(x0 % N) + shift) % N), iy = (int)(x0 / N);
+        const size_t c = (size_t)ix + (size_t)N * iy;
+        M3<double> w = load_m(W, n2, x0);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            double f[8], t[8];
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                if (i == 0) f[a] = (double)pl_ld(F, n2, a, c) + (double)pl_ld(F, n2, 48 + a, c);
+                else if (i == 1)
+                    f[a] = ((double)pl_ld(F, n2, 8 + a, c) + (double)pl_ld(F, n2, 56 + a, c)) -
+                           (double)pl_ld(F, n2, 40 + a, c);
+                else f[a] = (double)pl_ld(F, n2, 16 + a, c) + (double)pl_ld(F, n2, 32 + a, c);
+            }
+            transport_nd(w, herm_from_alg(f), t);
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                const double q = pl_ld(I, n2, 8 * i + a, x0) + dtau * t[a];
+                pl_st(I, n2, 8 * i + a, x0, q);
+                s += q * q;
+            }
+            v[i] = 0.5 * s;
+        }
+        v[3] = 1.0;
+        if ((int64_t)floor((double)(j + 1) * dtau + 0.5) > shift) {
+            const M3<T> u = load_m(U, n2, c);
+            M3<double> ud;
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    ud.re[r][q] = (double)u.re[r][q];
+                    ud.im[r][q] = (double)u.im[r][q];
+                }
+            store_m(W, n2, x0, mul(w, ud));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w2 = 128; w2 > 0; w2 >>= 1) {
+        if (threadIdx.x < w2)
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w2];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // Diagnostics per site, reduced per workgroup in FP64:
 // [0] max |G^a|, [1] max |E^a|, [2] max |U U^dag - 1|, [3..6] energy terms,
 // [7] non-finite count.
@@ -218,6 +284,15 @@ hipError_t launch_static_accum(hipStream_t st, int N, const T *F, double *I, dou
 }
 
 template <typename T>
+hipError_t launch_lightlike_accum(hipStream_t st, int N, const T *F, const T *U, double *W, double *I, int64_t j,
+                                  double dtau, double *partials, int *n_blocks_out) {
+    const int nb = (int)(((size_t)N * N + 255) / 256);
+    *n_blocks_out = nb;
+    hipLaunchKernelGGL(k_lightlike_accum<T>, dim3(nb), dim3(256), 0, st, N, F, U, W, I, j, dtau, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
                        int *n_blocks_out) {
     dim3 grid((N + TX - 1) / TX, (N + TY - 1) / TY), block(TX, TY);
@@ -230,7 +305,9 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
     template hipError_t launch_field_step<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, T *,    \
                                              double, double, int);                           \
     template hipError_t launch_diag<T>(hipStream_t, int, FieldPtrs<T>, double, double *, int *);     \
-    template hipError_t launch_static_accum<T>(hipStream_t, int, const T *, double *, double, double *, int *);
+    template hipError_t launch_static_accum<T>(hipStream_t, int, const T *, double *, double, double *, int *); \
+    template hipError_t launch_lightlike_accum<T>(hipStream_t, int, const T *, const T *, double *, double *, \
+                                                  int64_t, double, double *, int *);
 GL_INST(double)
 GL_INST(float)
 #undef GL_INST

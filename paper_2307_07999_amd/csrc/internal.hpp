@@ -83,6 +83,10 @@ hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_bl
 template <typename T>
 hipError_t launch_static_accum(hipStream_t st, int N, const T *F, double *I, double dtau, double *partials,
                                int *n_blocks_out);
+// lightlike-jet transports W [18][n2] and accumulators I [24][n2] FP64; U the x links at tau_n
+template <typename T>
+hipError_t launch_lightlike_accum(hipStream_t st, int N, const T *F, const T *U, double *W, double *I, int64_t j,
+                                  double dtau, double *partials, int *n_blocks_out);
 template <typename T>
 hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
                        int *n_blocks_out);

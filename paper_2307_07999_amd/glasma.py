@@ -29,7 +29,7 @@ class LatticeDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("L_fm", ctypes.c_double), ("dtau_over_a", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("reunit_every", ctypes.c_int32),
                 ("max_steps", ctypes.c_int32), ("max_particles", ctypes.c_int64),
-                ("static_correlator", ctypes.c_int32)]
+                ("static_correlator", ctypes.c_int32), ("lightlike_correlator", ctypes.c_int32)]
 
 
 class MVDesc(ctypes.Structure):
@@ -68,6 +68,8 @@ _SIGS = {
     "gl_series": [_VP, _D, ctypes.c_int32, _I32],
     "gl_static_start": [_VP, ctypes.c_double],
     "gl_static_broadening": [_VP, _D, ctypes.c_int32, _I32],
+    "gl_lightlike_start": [_VP, ctypes.c_double],
+    "gl_lightlike_broadening": [_VP, _D, ctypes.c_int32, _I32],
     "gl_rates_from_series": [_D, ctypes.c_int32, ctypes.c_double, _D],
     "gl_diagnostics": [_VP, ctypes.POINTER(Diag)],
     "gl_set_state": [_VP, _D, _D, _D, _D, ctypes.c_int64],
@@ -159,12 +161,13 @@ class Event:
     """One Glasma event with its particles, on a torch-allocated workspace."""
 
     def __init__(self, N, L_fm, dtau_over_a=0.125, precision=64, reunit_every=16, max_steps=512,
-                 max_particles=0, device="cuda", stream=None, static_correlator=False):
+                 max_particles=0, device="cuda", stream=None, static_correlator=False,
+                 lightlike_correlator=False):
         import torch
         self.torch = torch
         self.N, self.L_fm, self.precision = N, L_fm, precision
         self.desc = LatticeDesc(N, L_fm, dtau_over_a, precision, reunit_every, max_steps, max_particles,
-                                1 if static_correlator else 0)
+                                1 if static_correlator else 0, 1 if lightlike_correlator else 0)
         nbytes = ctypes.c_size_t(0)
         check(lib().gl_required_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
         self.nbytes = nbytes.value
@@ -239,13 +242,24 @@ class Event:
         """Start the static-quark correlator of Eq. (4) at tau_start_fm."""
         return check(lib().gl_static_start(self._h, tau_start_fm))
 
+    def _corr_rows(self, fn):
+        n = ctypes.c_int32(0)
+        check(fn(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), 5))
+        check(fn(self._h, _d(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
+
     def static_broadening(self):
         """Rows (tau_{n+1/2} [fm], <dp_x^2>, <dp_y^2>, <dp_z^2> [GeV^2], sites)."""
-        n = ctypes.c_int32(0)
-        check(lib().gl_static_broadening(self._h, None, 0, ctypes.byref(n)))
-        out = np.zeros((max(n.value, 1), 5))
-        check(lib().gl_static_broadening(self._h, _d(out), n.value, ctypes.byref(n)))
-        return out[:n.value]
+        return self._corr_rows(lib().gl_static_broadening)
+
+    def lightlike_start(self, tau_start_fm=0.0):
+        """Start the lightlike-jet correlator of Eq. (5) at tau_start_fm."""
+        return check(lib().gl_lightlike_start(self._h, tau_start_fm))
+
+    def lightlike_broadening(self):
+        """Rows (tau_{n+1/2} [fm], <dp_x^2>, <dp_y^2>, <dp_z^2> [GeV^2], sites)."""
+        return self._corr_rows(lib().gl_lightlike_broadening)
 
     def kappa(self, species):
         return self._rows(lib().gl_kappa, species, 4)

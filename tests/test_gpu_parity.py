@@ -30,9 +30,11 @@ def gl():
     return g
 
 
-def _event(gl, N, L=4.0, prec=64, max_particles=0, max_steps=128, reunit=16, static_correlator=False):
+def _event(gl, N, L=4.0, prec=64, max_particles=0, max_steps=128, reunit=16, static_correlator=False,
+           lightlike_correlator=False):
     return gl.Event(N, L, 0.125, precision=prec, reunit_every=reunit, max_steps=max_steps,
-                    max_particles=max_particles, static_correlator=static_correlator)
+                    max_particles=max_particles, static_correlator=static_correlator,
+                    lightlike_correlator=lightlike_correlator)
 
 
 def test_charges_match_oracle(gl, orc):
@@ -327,3 +329,42 @@ def test_static_correlator_matches_oracle(gl, orc):
     ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
     with pytest.raises(gl.GlasmaError):
         ev.static_start(0.0)
+
+
+def test_lightlike_correlator_matches_oracle(gl, orc):
+    """Lightlike jets (Eq. (5)) on the 32^2 configuration, run together with
+    the static correlator and with particles (the site fields are shared):
+    transported forces accumulated from tau_start on, against the oracle's
+    correlator, in FP64 and FP32."""
+    cfg = H.C1
+    N = cfg["N"]
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    steps = H.n_steps(cfg)
+    tau0 = 0.03
+    n0 = int(np.ceil(tau0 / (0.125 * a_fm) - 1e-9))
+    s, rc, _ = orc.init_glasma(N, sigma, m2, 1, cfg["seed"], 0.125)
+    s2 = s.copy()
+    rows = orc.lightlike_series(s, 0.125, steps, n0=n0)
+    srows = orc.static_series(s2, 0.125, steps, n0=1)
+    f2, _ = orc.to_physical(a_fm)
+    act = rows[:, 3] > 0
+    want = rows[act, :3] / rows[act, 3:4] * f2
+    swant = srows[:, :3] / srows[:, 3:4] * f2
+    for prec, tol in ((64, 1e-9), (32, 1e-3)):
+        ev = _event(gl, N, cfg["L"], prec=prec, max_steps=steps, max_particles=256, static_correlator=True,
+                    lightlike_correlator=True)
+        ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
+        ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 256, 7)
+        ev.lightlike_start(tau0)
+        ev.static_start(0.0)
+        ev.run(steps)
+        got = ev.lightlike_broadening()
+        assert len(got) == int(act.sum()) == steps - n0 + 1
+        assert np.all(got[:, 4] == N * N)
+        sgot = ev.static_broadening()
+        for c in range(3):
+            err = H.rel_err(got[:, 1 + c], want[:, c])
+            serr = H.rel_err(sgot[:, 1 + c], swant[:, c])
+            print("FP%d component %d: lightlike rel err %.2e, static rel err %.2e" % (prec, c, err, serr))
+            assert err < tol and serr < tol
+        ev.close()
