@@ -188,6 +188,22 @@ def poisson_uv(N, m2, uv2, src):
     return out
 
 
+def dipole(N, V, rmax):
+    """Dipole correlator of a Wilson line, D(r) = (1/3) < Re Tr V(x) V^dag(x+r) >,
+    averaged over the sites x and the two lattice directions of the
+    separation, for r = 0..rmax (lattice units).  V [N*N][18]."""
+    M = d2m(np.asarray(V)).reshape(N, N, 3, 3)          # [y][x]
+    Md = np.conj(np.swapaxes(M, -1, -2))
+    D = np.zeros(rmax + 1)
+    for r in range(rmax + 1):
+        sx = np.roll(Md, -r, axis=1)                     # V^dag(x + r e_x)
+        sy = np.roll(Md, -r, axis=0)                     # V^dag(x + r e_y)
+        tx = np.real(np.einsum("yxij,yxji->yx", M, sx)).mean()
+        ty = np.real(np.einsum("yxij,yxji->yx", M, sy)).mean()
+        D[r] = (tx + ty) / 6.0
+    return D
+
+
 def nucleus_links(N, V):
     out = np.zeros((2, N * N, 18))
     lib().orc_nucleus_links(N, _d(np.ascontiguousarray(V)), _d(out))

@@ -247,6 +247,12 @@ def test_fp32_observables_within_target(gl, orc):
     print("FP32 vs FP64 oracle errors:", errs)
     for k, v in errs.items():
         assert v < 1e-3, (k, v)
+    # particles whose cell sequence left the FP64 one (a crossing decided the
+    # other way near a cell boundary): compared through the final cells
+    d = ev.get_particles()
+    frac = float(np.mean(np.any(d["cell"].T != P.cell, axis=1)))
+    print("FP32: fraction of particles whose final cell differs from FP64: %.4f" % frac)
+    assert frac < 0.02
 
 
 def test_call_order_errors(gl):

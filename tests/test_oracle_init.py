@@ -189,3 +189,21 @@ def test_poisson_uv_cut_keeps_low_and_removes_high_modes(orc):
     assert np.abs(out - low / (k2(2, 1) + m2)).max() < 1e-13
     # no cut reproduces the plain solve
     assert np.abs(orc.poisson_uv(N, m2, 0.0, low + high) - orc.poisson(N, m2, low + high)).max() < 1e-15
+
+
+def test_dipole_of_abelian_plane_wave(orc):
+    """V(x) = diag(e^{i alpha ix}, e^{-i alpha ix}, 1): along x,
+    Tr V(x) V^dag(x+r) = 2 cos(alpha r) + 1, along y it is 3, so
+    D(r) = [(2 cos(alpha r) + 1) / 3 + 1] / 2; D(0) = 1 for any V."""
+    N = 12
+    alpha = 2 * np.pi * 2 / N
+    V = np.zeros((N * N, 3, 3), complex)
+    for y in range(N):
+        for x in range(N):
+            V[x + N * y] = np.diag([np.exp(1j * alpha * x), np.exp(-1j * alpha * x), 1.0])
+    D = orc.dipole(N, orc.m2d(V), N // 2)
+    r = np.arange(N // 2 + 1)
+    assert np.abs(D - ((2 * np.cos(alpha * r) + 1) / 3 + 1) / 2).max() < 1e-14
+    W = orc.wilson_line(N, 0.6, 0.01, 2, 3, 0)
+    D = orc.dipole(N, W, N // 2)
+    assert abs(D[0] - 1.0) < 1e-13 and np.all(D[1:] < 1.0)
