@@ -26,15 +26,20 @@ PEAK_HBM_GBS = 8000.0
 
 # paper-scale workload
 N, L_FM, SHEETS, M_IR, QS = 512, 10.0, 50, 0.2, 2.0
-G2MU = QS / 0.6            # MV ratio Q_s ~ 0.6 g^2 mu (reading of the paper's "Q_s = 2 GeV")
+# g^2 mu whose MV Wilson lines have Q_s = 2 GeV (D(sqrt(2)/Q_s) = exp(-1/2)):
+# gl_calibrate_g2mu at 512^2, L = 10 fm, 50 sheets, m_IR = 0.2 GeV, 4 seeds
+# (Q_s / g^2 mu = 0.722); reproduced by the GPU tests
+G2MU = 2.767
 DTAU = 0.125
 N_PER = 100000
 SPECIES = ([(1.27, p0, 0) for p0 in (0.0, 2.0, 5.0)] + [(4.18, p0, 0) for p0 in (0.0, 2.0, 5.0)]
            + [(0.0, 10.0, 1)])
 SEED = 2307079992
 # kernel durations are sampled on every PROFILE_PERIOD-th launch of each
-# kernel over the timed region (HIP events on the library's stream)
-PROFILE_PERIOD = 8
+# kernel over the timed region (HIP events on the library's stream); the
+# period is coprime with the 16-step particle sort cycle so that the samples
+# cover every phase of it (the push is fastest right after a sort)
+PROFILE_PERIOD = 7
 
 
 def coupled_steps(N, L, tau_max=1.0):

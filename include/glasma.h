@@ -194,6 +194,23 @@ gl_status gl_species_info(gl_event *ev, int32_t species, int32_t *nform, double 
 
 /* Wilson line V of one nucleus after gl_init_glasma: [18][N*N], FP64. */
 gl_status gl_get_wilson_line(gl_event *ev, int32_t nucleus, double *V);
+/* Saturation scale of the MV Wilson lines (reading of "Q_s = 2 GeV", which
+ * the paper states without a conversion to g^2 mu): the dipole correlator
+ * D(r) = (1/3) <Re Tr V(x) V^dag(x+r)>, averaged over the sites and the two
+ * lattice directions, and Q_s defined by D(sqrt(2)/Q_s) = exp(-1/2).
+ * gl_dipole writes D[0..rmax] (1 <= rmax <= N/2) of the stored Wilson line
+ * of one nucleus (after gl_init_glasma).  gl_saturation_scale averages Q_s
+ * over both nuclei, r interpolated linearly between lattice separations;
+ * GL_ENUMERIC if D stays above exp(-1/2) up to N/2.  gl_calibrate_g2mu
+ * searches g^2 mu (starting from mv->g2mu_GeV, or Q_s/0.6 if it is 0) so
+ * that Q_s averaged over n_seeds MV draws (seeds seed .. seed+n_seeds-1)
+ * equals qs_target_GeV within 0.1 %, with mv's sheets and regulators; it
+ * overwrites the stored Wilson lines and leaves the field state alone. */
+gl_status gl_dipole(gl_event *ev, int32_t nucleus, int32_t rmax, double *D);
+gl_status gl_saturation_scale(gl_event *ev, double *qs_GeV);
+gl_status gl_calibrate_g2mu(gl_event *ev, const gl_mv_desc *mv, double qs_target_GeV, uint64_t seed,
+                            int32_t n_seeds, double *g2mu_out, double *qs_out);
+
 /* MV charges of one (nucleus, sheet) drawn exactly as gl_init_glasma draws
  * them: [8][N*N] FP64, lattice units, for standard deviation sigma. */
 gl_status gl_draw_charges(gl_event *ev, uint64_t seed, int32_t nucleus, int32_t sheet,

@@ -589,8 +589,9 @@ void gl_event_destroy(gl_event *ev) {
     delete ev;
 }
 
-static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, double uv_GeV, const double *rho_dev,
-                             double sigma, uint64_t seed) {
+// the Wilson lines of both nuclei into VA, VB (steps 1-3 of the MV initialisation)
+static gl_status wilson_lines(gl_event *ev, int n_sheets, double m_ir_GeV, double uv_GeV, const double *rho_dev,
+                              double sigma, uint64_t seed) {
     const int N = ev->N;
     double m2 = (m_ir_GeV * ev->a_gev) * (m_ir_GeV * ev->a_gev);
     double uv2 = uv_GeV > 0 ? (uv_GeV * ev->a_gev) * (uv_GeV * ev->a_gev) : 0.0;
@@ -614,7 +615,40 @@ static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, double
             HIP_TRY(launch_wilson_accum(ev->stream, N, planes, cnt, V[nuc]));
         }
     }
+    return GL_OK;
+}
+
+static gl_status init_common(gl_event *ev, int n_sheets, double m_ir_GeV, double uv_GeV, const double *rho_dev,
+                             double sigma, uint64_t seed) {
+    gl_status s = wilson_lines(ev, n_sheets, m_ir_GeV, uv_GeV, rho_dev, sigma, seed);
+    if (s) return s;
     return ev->fp64() ? finish_init<double>(ev) : finish_init<float>(ev);
+}
+
+// D(r), r = 0..rmax, of the stored Wilson line of one nucleus (device
+// kernels; partials in the initialisation scratch planes)
+static gl_status dipole_curve(gl_event *ev, int nucleus, int rmax, std::vector<double> &D) {
+    const double *V = (const double *)(ev->ws + (nucleus == 0 ? ev->L.VA : ev->L.VB));
+    double *part = (double *)(ev->ws + ev->L.planes);
+    const int nb = (int)((ev->n2 + 255) / 256);
+    double *Dd = part + (size_t)(rmax + 1) * nb;
+    HIP_TRY(launch_dipole(ev->stream, ev->N, V, rmax, part, Dd));
+    D.assign(rmax + 1, 0.0);
+    HIP_TRY(hipMemcpyAsync(D.data(), Dd, (rmax + 1) * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+// Q_s [GeV] from D(sqrt(2)/Q_s) = exp(-1/2), r linearly interpolated between
+// the lattice separations around the crossing; 0 if D stays above it
+static double qs_from_dipole(const std::vector<double> &D, double a_gev) {
+    const double target = std::exp(-0.5);
+    for (size_t r = 1; r < D.size(); r++)
+        if (D[r] <= target) {
+            const double rs = (double)(r - 1) + (D[r - 1] - target) / (D[r - 1] - D[r]);
+            return std::sqrt(2.0) / (rs * a_gev);
+        }
+    return 0.0;
 }
 
 gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed) {
@@ -990,6 +1024,55 @@ gl_status gl_get_wilson_line(gl_event *ev, int32_t nucleus, double *V) {
     HIP_TRY(hipMemcpyAsync(V, ev->ws + (nucleus == 0 ? ev->L.VA : ev->L.VB), 18 * ev->n2 * sizeof(double),
                            hipMemcpyDeviceToHost, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+gl_status gl_dipole(gl_event *ev, int32_t nucleus, int32_t rmax, double *D) {
+    if (check_ev(ev) || !D || (nucleus != 0 && nucleus != 1)) return fail(GL_EINVAL, "bad argument");
+    if (rmax < 1 || rmax > ev->N / 2) return fail(GL_EINVAL, "rmax must be in [1, N/2]");
+    std::vector<double> d;
+    gl_status s = dipole_curve(ev, nucleus, rmax, d);
+    if (s) return s;
+    std::copy(d.begin(), d.end(), D);
+    return GL_OK;
+}
+
+gl_status gl_saturation_scale(gl_event *ev, double *qs_GeV) {
+    if (check_ev(ev) || !qs_GeV) return fail(GL_EINVAL, "null argument");
+    double sum = 0.0;
+    for (int nuc = 0; nuc < 2; nuc++) {
+        std::vector<double> d;
+        gl_status s = dipole_curve(ev, nuc, ev->N / 2, d);
+        if (s) return s;
+        const double q = qs_from_dipole(d, ev->a_gev);
+        if (!(q > 0)) return fail(GL_ENUMERIC, "dipole does not fall to exp(-1/2) within N/2 sites");
+        sum += q;
+    }
+    *qs_GeV = 0.5 * sum;
+    return GL_OK;
+}
+
+gl_status gl_calibrate_g2mu(gl_event *ev, const gl_mv_desc *mv, double qs_target_GeV, uint64_t seed,
+                            int32_t n_seeds, double *g2mu_out, double *qs_out) {
+    if (check_ev(ev) || !mv || !g2mu_out) return fail(GL_EINVAL, "null argument");
+    if (!(qs_target_GeV > 0) || n_seeds < 1 || mv->n_sheets < 1) return fail(GL_EINVAL, "bad argument");
+    double g = mv->g2mu_GeV > 0 ? mv->g2mu_GeV : qs_target_GeV / 0.6, q = 0.0;
+    for (int it = 0; it < 12; it++) {
+        q = 0.0;
+        for (int k = 0; k < n_seeds; k++) {
+            const double sigma = g * ev->a_gev / std::sqrt((double)mv->n_sheets);
+            gl_status s = wilson_lines(ev, mv->n_sheets, mv->m_ir_GeV, mv->uv_cut_GeV, nullptr, sigma, seed + k);
+            if (s) return s;
+            double qk = 0.0;
+            s = gl_saturation_scale(ev, &qk);
+            if (s) return s;
+            q += qk / n_seeds;
+        }
+        if (std::fabs(q - qs_target_GeV) <= 1e-3 * qs_target_GeV) break;
+        g *= qs_target_GeV / q;   // Q_s grows about linearly with g^2 mu
+    }
+    *g2mu_out = g;
+    if (qs_out) *qs_out = q;
     return GL_OK;
 }
 

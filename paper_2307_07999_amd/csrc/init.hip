@@ -244,6 +244,54 @@ k_wilson_accum(int N, const double2 *planes, int n_sheets, double *V) {
     store_m(V, n2, x, v);
 }
 
+// ---- dipole correlator (calibration of Q_s) -----------------------------------
+// Workgroup (b, r): sum over its 256 sites of
+// Re Tr V(x) V^dag(x + r e_x) + Re Tr V(x) V^dag(x + r e_y); partials [r][b]
+__global__ void __launch_bounds__(256)
+k_dipole(int N, const double *__restrict__ V, double *__restrict__ partials) {
+    __shared__ double red[256];
+    const size_t n2 = (size_t)N * N;
+    const size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    double v = 0.0;
+    if (x < n2) {
+        const int ix = (int)(x % N), iy = (int)(x / N);
+        const M3<double> a = load_m(V, n2, x);
+        const size_t nb[2] = {(size_t)((ix + r) % N) + (size_t)N * iy, (size_t)ix + (size_t)N * ((iy + r) % N)};
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const M3<double> b = load_m(V, n2, nb[d]);
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) v += a.re[i][j] * b.re[i][j] + a.im[i][j] * b.im[i][j];
+        }
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[(size_t)r * gridDim.x + blockIdx.x] = red[0];
+}
+
+// D[r] = (sum of the partials of r in a fixed order) / (6 N^2)
+__global__ void __launch_bounds__(256)
+k_dipole_reduce(int N, const double *__restrict__ partials, int nb, double *__restrict__ D) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += partials[(size_t)r * nb + b];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) D[r] = red[0] / (6.0 * (double)N * (double)N);
+}
+
 // ---- 4. matching ------------------------------------------------------------
 __device__ inline void cdiv(double ar, double ai, double br, double bi, double &cr, double &ci) {
     double d = br * br + bi * bi;
@@ -512,6 +560,15 @@ hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return fft2(st, N, planes, 4 * n_sheets, +1);
+}
+
+hipError_t launch_dipole(hipStream_t st, int N, const double *V, int rmax, double *partials, double *D) {
+    const int nb = (int)blocks_for((size_t)N * N, 256);
+    hipLaunchKernelGGL(k_dipole, dim3(nb, rmax + 1), dim3(256), 0, st, N, V, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dipole_reduce, dim3(rmax + 1), dim3(256), 0, st, N, (const double *)partials, nb, D);
+    return hipGetLastError();
 }
 
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V) {

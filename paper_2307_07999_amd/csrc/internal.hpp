@@ -101,6 +101,8 @@ hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes
 hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2,
                           double2 *planes /* [n_sheets][4][n2] in place */, int n_sheets);
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V);
+// dipole correlator D[0..rmax] of a Wilson line; partials [(rmax+1)][ceil(N^2/256)]
+hipError_t launch_dipole(hipStream_t st, int N, const double *V, int rmax, double *partials, double *D);
 hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, int n_sheets, double *V);
 hipError_t launch_match_pi0(hipStream_t st, int N, const double *VA, const double *VB,
                            double *U0 /* [2][18][n2] FP64 */, double *pi0 /* [8][n2] */,

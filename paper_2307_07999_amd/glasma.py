@@ -67,6 +67,9 @@ _SIGS = {
     "gl_qhat": [_VP, ctypes.c_int32, _D, ctypes.c_int32, _I32],
     "gl_series": [_VP, _D, ctypes.c_int32, _I32],
     "gl_static_start": [_VP, ctypes.c_double],
+    "gl_dipole": [_VP, ctypes.c_int32, ctypes.c_int32, _D],
+    "gl_saturation_scale": [_VP, _D],
+    "gl_calibrate_g2mu": [_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, _D, _D],
     "gl_static_broadening": [_VP, _D, ctypes.c_int32, _I32],
     "gl_lightlike_start": [_VP, ctypes.c_double],
     "gl_lightlike_broadening": [_VP, _D, ctypes.c_int32, _I32],
@@ -237,6 +240,26 @@ class Event:
 
     def broadening(self, species):
         return self._rows(lib().gl_broadening, species, 5)
+
+    def dipole(self, nucleus, rmax):
+        """D(r), r = 0..rmax, of the stored Wilson line of one nucleus."""
+        D = np.zeros(rmax + 1)
+        check(lib().gl_dipole(self._h, nucleus, rmax, _d(D)))
+        return D
+
+    def saturation_scale(self):
+        """Q_s [GeV] of the stored Wilson lines, D(sqrt(2)/Q_s) = exp(-1/2)."""
+        q = ctypes.c_double(0)
+        check(lib().gl_saturation_scale(self._h, ctypes.byref(q)))
+        return q.value
+
+    def calibrate_g2mu(self, qs_GeV, m_ir_GeV, n_sheets, seed, n_seeds=2, g2mu_start=0.0, uv_cut_GeV=0.0):
+        """g^2 mu [GeV] whose MV Wilson lines have Q_s = qs_GeV; returns (g2mu, Q_s reached)."""
+        mv = MVDesc(g2mu_start, m_ir_GeV, n_sheets, uv_cut_GeV)
+        g, q = ctypes.c_double(0), ctypes.c_double(0)
+        check(lib().gl_calibrate_g2mu(self._h, ctypes.byref(mv), qs_GeV, seed, n_seeds, ctypes.byref(g),
+                                      ctypes.byref(q)))
+        return g.value, q.value
 
     def static_start(self, tau_start_fm=0.0):
         """Start the static-quark correlator of Eq. (4) at tau_start_fm."""

@@ -25,7 +25,10 @@ PT_RANGE = (0.0, 10.0)
 JET_PT_MIN = 0.5
 TAU_MAX = 1.0
 M_IR = 0.2
-QS_OVER_G2MU = 0.6          # reading of "Q_s = 2 GeV": g^2 mu = Q_s / 0.6
+# Q_s / g^2 mu of the MV Wilson lines (dipole definition D(sqrt(2)/Q_s) =
+# exp(-1/2)), measured with gl_calibrate_g2mu at L = 10 fm, 50 sheets,
+# m_IR = 0.2 GeV: 0.722 at 512^2, 0.7245 at 256^2
+QS_OVER_G2MU = 0.722
 # network inputs: Q_s, m, p_T0, tau_form and the square root of the time
 # since the particles start, sqrt(tau - tau_start).  The solver starts them at
 # the first step at or after tau_form, tau_start = ceil(tau_form / dtau) dtau,

@@ -374,3 +374,42 @@ def test_lightlike_correlator_matches_oracle(gl, orc):
             print("FP%d component %d: lightlike rel err %.2e, static rel err %.2e" % (prec, c, err, serr))
             assert err < tol and serr < tol
         ev.close()
+
+
+def test_dipole_and_saturation_scale_match_oracle(gl, orc):
+    """Dipole correlator of the device Wilson lines against the oracle's, and
+    Q_s from the exp(-1/2) crossing computed from the oracle curve."""
+    N, L = 48, 4.0
+    a_fm = L / N
+    a_gev = a_fm / H.HBARC
+    g2mu, m_ir, sheets, seed = 2.0, 0.2, 3, 17
+    sigma = g2mu * a_gev / math.sqrt(sheets)
+    ev = _event(gl, N, L)
+    ev.init_glasma(g2mu, m_ir, sheets, seed)
+    qs = []
+    for nuc in (0, 1):
+        D = ev.dipole(nuc, N // 2)
+        W = orc.wilson_line(N, sigma, (m_ir * a_gev) ** 2, sheets, seed, nuc)
+        Do = orc.dipole(N, W, N // 2)
+        assert np.abs(D - Do).max() < 1e-12
+        r = int(np.argmax(Do <= np.exp(-0.5)))
+        rs = (r - 1) + (Do[r - 1] - np.exp(-0.5)) / (Do[r - 1] - Do[r])
+        qs.append(math.sqrt(2.0) / (rs * a_gev))
+    assert abs(ev.saturation_scale() - 0.5 * (qs[0] + qs[1])) < 1e-10
+    # the calibration reaches its target and leaves the fields alone
+    U0 = ev.get_state()[0]
+    g, q = ev.calibrate_g2mu(1.0, m_ir, sheets, seed, n_seeds=1)
+    assert abs(q - 1.0) < 1e-3 and g > 0
+    assert np.array_equal(ev.get_state()[0], U0)
+
+
+def test_paper_scale_g2mu_gives_qs_2_gev(gl):
+    """The 512^2 workload's g^2 mu (2.767 GeV) is the calibrated one: the MV
+    Wilson lines of 4 seeds at L = 10 fm, 50 sheets, m_IR = 0.2 GeV have
+    Q_s = 2 GeV by the dipole definition."""
+    import bench
+    ev = gl.Event(512, 10.0, 0.125, precision=64, max_steps=1)
+    g, q = ev.calibrate_g2mu(2.0, bench.M_IR, bench.SHEETS, bench.SEED, n_seeds=4)
+    ev.close()
+    print("calibrated g2mu %.4f GeV (Q_s %.4f GeV)" % (g, q))
+    assert abs(g - bench.G2MU) < 5e-3
