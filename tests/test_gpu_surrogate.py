@@ -19,8 +19,8 @@ N, L_FM = 64, 10.0 * 64 / 512
 def trained():
     import torch
     from paper_2307_07999_amd import surrogate as S
-    train = S.draw_params(1024, 11)
-    curves, _ = S.solver_curves(train, N, L_FM, 20000, 12)
+    train = S.draw_params(2048, 11)
+    curves, _ = S.solver_curves(train, N, L_FM, 40000, 12)
     X, Y = S.rows(train, curves)
     held = S.draw_params(16, 13)
     t0 = time.perf_counter()
