@@ -186,6 +186,7 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, prec):
+    import re
     """Bytes per launch (fetch, write) recorded for this kernel and precision,
     or None when missing or taken on other kernel sources."""
     try:
@@ -196,7 +197,8 @@ def measured_traffic(kernel, prec):
     rows = {}
     for ln in lines:
         if ln.startswith("source hash:"):
-            src = ln.split(":", 1)[1].strip().strip("`")
+            m = re.search(r"`([0-9a-f]+)`", ln)
+            src = m.group(1) if m else None
         cells = [c.strip() for c in ln.strip().strip("|").split("|")]
         if len(cells) >= 4 and cells[0] in ("field_step", "push") and cells[1] in ("32", "64"):
             rows[(cells[0], int(cells[1]))] = (float(cells[2]), float(cells[3]))

@@ -1,6 +1,7 @@
 // fields_dev.hpp -- per-site device functions of the leapfrog step and of the
 // local-frame site fields, shared by the single-event and the batched kernels.
-// The scheme and the site-field reading are described in fields.hip.
+// The scheme is described in fields.hip, the site-field reading at
+// field_step_link.
 #pragma once
 #include "internal.hpp"
 #include "su3.hpp"
@@ -38,32 +39,6 @@ __device__ __forceinline__ M3<T> plaq(const M3<T> &u1x, const M3<T> &u2xp1, cons
     return mul_nd(mul_nd(mul(u1x, u2xp1), u1xp2), u2x);
 }
 
-template <typename T>
-__device__ __forceinline__ M3<T> comm_term(const M3<T> &ph, const M3<T> &Ph, T inv_tau) {
-    M3<T> c = sub(mul(ph, Ph), mul(Ph, ph));
-    M3<T> r;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {   // -(i/tau) * (cr + i ci) = (ci - i cr)/tau
-            r.re[i][j] = c.im[i][j] * inv_tau;
-            r.im[i][j] = -c.re[i][j] * inv_tau;
-        }
-    return r;
-}
-
-// One site of the leapfrog step n -> n+1; (ix, iy) must lie on the lattice.
-// If F is non-null the same pass writes the local-frame site fields at tau_n
-// that the particle push reads (NGP reading of the colored particle-in-cell
-// coupling), reusing the plaquettes and transported scalars of the forces:
-//   E_i = 1/2 [Ebar_i(x) + U_i^dag(x-i) Ebar_i(x-i) U_i(x-i)] / tau,
-//         Ebar = (E^{n-1/2} + E^{n+1/2}) / 2,
-//   E_z = (pi^{n-1/2} + pi^{n+1/2}) / 2,
-//   B_x = -D_2 phi / tau, B_y = D_1 phi / tau, D_i phi = (Phi_{+i} - Phi_{-i}) / 2,
-//   B_z = -(1/4) (sum of the four plaquettes at x, each transported to x).
-// The second half of E_i belongs to the site x+i; this thread owns the link
-// U_i(x) and Ebar_i(x) it needs, so it stores that half at x+i in a plane of
-// its own (slots 48..63) and the push adds the two halves.
 // Exchange with the partner lane of a site's lane pair (lanes 2s and 2s+1).
 template <typename T>
 __device__ __forceinline__ T pair_swap(T v) {
