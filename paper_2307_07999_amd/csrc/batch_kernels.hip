@@ -28,6 +28,23 @@ __device__ __forceinline__ int64_t xcd_first(int64_t total, int64_t &stride, int
     return lo + j;
 }
 
+// one tile of an event: stage its links and phi, then the step of its sites
+template <typename T, int TX, int TY>
+__device__ __forceinline__ void batch_field_tile(LinkTile<T, TX, TY> &tile, const BatchEv<T> &e, int2 w, int fpar,
+                                                 int64_t n, T tau, T dtau, T tau_h) {
+    const int lx = threadIdx.x >> 1, ly = threadIdx.y;
+    const int tx = (e.N + TX - 1) / TX;
+    const int x0 = (w.y % tx) * TX, y0 = (w.y / tx) * TY;
+    stage_tile(tile, e.N, e.f[fpar], x0, y0, threadIdx.x + 2 * TX * threadIdx.y, 2 * TX * TY);
+    __syncthreads();
+    const int ix = x0 + lx, iy = y0 + ly;
+    if (ix < e.N && iy < e.N) {
+        int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
+        field_step_link(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, ix, iy, lx, ly,
+                        threadIdx.x & 1, tau, dtau, tau_h, reunit);
+    }
+}
+
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__(2 * TX *TY)
 k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total, int fpar,
@@ -35,23 +52,35 @@ k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles
     __shared__ LinkTile<T, TX, TY> tile;
     const int64_t n = ctl->n;
     const T tau = dtau * (T)n, tau_h = dtau * ((T)n + T(0.5));
-    const int lx = threadIdx.x >> 1, ly = threadIdx.y;
     int64_t stride, end;
     for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
         const int2 w = tiles[t];
-        const BatchEv<T> &e = evs[w.x];
-        const int tx = (e.N + TX - 1) / TX;
-        const int x0 = (w.y % tx) * TX, y0 = (w.y / tx) * TY;
         __syncthreads();   // the previous tile's reads are done
-        stage_tile(tile, e.N, e.f[fpar], x0, y0, threadIdx.x + 2 * TX * threadIdx.y, 2 * TX * TY);
-        __syncthreads();
-        const int ix = x0 + lx, iy = y0 + ly;
-        if (ix < e.N && iy < e.N) {
-            int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
-            field_step_link(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, ix, iy, lx, ly,
-                            threadIdx.x & 1, tau, dtau, tau_h, reunit);
-        }
+        batch_field_tile(tile, evs[w.x], w, fpar, n, tau, dtau, tau_h);
     }
+}
+
+// One workgroup per table entry (grid = entries), numbered so that each XCD
+// takes one contiguous run of the table: the walk of the persistent kernel
+// without its loop, which holds registers the step can use.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(2 * TX *TY)
+k_batch_field_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total, int fpar,
+                   const BatchCtl *__restrict__ ctl, T dtau) {
+    __shared__ LinkTile<T, TX, TY> tile;
+    const int64_t n = ctl->n;
+    const T tau = dtau * (T)n, tau_h = dtau * ((T)n + T(0.5));
+    const int2 w = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    batch_field_tile(tile, evs[w.x], w, fpar, n, tau, dtau, tau_h);
+}
+
+template <typename T>
+__device__ __forceinline__ void batch_push_block(const BatchEv<T> &e, int2 w, int fpar, int ppar, int n, T dtau) {
+    const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int s = -1;
+    if (i < e.n_slots) s = push_particle<T>(e.N, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+    block_species_reduce(s, acc, e.n_species, e.partials + (size_t)w.y * e.n_species * 4);
 }
 
 template <typename T>
@@ -62,13 +91,16 @@ k_batch_push(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks
     int64_t stride, end;
     for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
         const int2 w = blocks[t];
-        const BatchEv<T> &e = evs[w.x];
-        const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int s = -1;
-        if (i < e.n_slots) s = push_particle<T>(e.N, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
-        block_species_reduce(s, acc, e.n_species, e.partials + (size_t)w.y * e.n_species * 4);
+        batch_push_block(evs[w.x], w, fpar, ppar, n, dtau);
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPushBlock)
+k_batch_push_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks, int64_t total, int fpar,
+                  int ppar, const BatchCtl *__restrict__ ctl, T dtau) {
+    const int2 w = blocks[xcd_remap(blockIdx.x, gridDim.x)];
+    batch_push_block(evs[w.x], w, fpar, ppar, (int)ctl->n, dtau);
 }
 
 // one workgroup per (event, species): fixed-order sum of the event's partial
@@ -110,8 +142,12 @@ hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs,
     unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
 #define GL_SHAPE(TXv, TYv)                                                                                    \
     {                                                                                                         \
-        hipLaunchKernelGGL((k_batch_field<T, TXv, TYv>), dim3(g), dim3(2 * TXv, TYv), 0, st, evs, tiles, total,\
-                           fpar, ctl, (T)dtau);                                                               \
+        if (g == total)                                                                                       \
+            hipLaunchKernelGGL((k_batch_field_flat<T, TXv, TYv>), dim3(g), dim3(2 * TXv, TYv), 0, st, evs,    \
+                               tiles, total, fpar, ctl, (T)dtau);                                             \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_batch_field<T, TXv, TYv>), dim3(g), dim3(2 * TXv, TYv), 0, st, evs, tiles,  \
+                               total, fpar, ctl, (T)dtau);                                                    \
     }
     switch (shape) {
         case 0: GL_SHAPE(32, 4) break;
@@ -128,8 +164,12 @@ hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *
                              int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events) {
     if (total > 0) {
         unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
-        hipLaunchKernelGGL(k_batch_push<T>, dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, fpar, ppar, ctl,
-                           (T)dtau);
+        if (g == total)
+            hipLaunchKernelGGL(k_batch_push_flat<T>, dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, fpar,
+                               ppar, ctl, (T)dtau);
+        else
+            hipLaunchKernelGGL(k_batch_push<T>, dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, fpar, ppar,
+                               ctl, (T)dtau);
         hipLaunchKernelGGL(k_batch_reduce<T>, dim3(n_events, kMaxSpecies), dim3(256), 0, st, evs, ctl);
     }
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, st, (BatchCtl *)ctl);
