@@ -4,10 +4,12 @@
 //      packed two colors per complex plane (rho^{2j} + i rho^{2j+1}).
 //   2. Poisson solve (-Lap + m^2) Lambda = rho with the 5-point Laplacian,
 //      exact in Fourier space: 2-D FFT by LDS-resident mixed-radix (4, 2, 3)
-//      Stockham line transforms, several adjacent lines per workgroup.  The
-//      kernel is real and even, so the packed pair separates again after the
-//      inverse.  Sheets are processed in chunks (charges, transforms and the
-//      Wilson-line products of a chunk in one launch each).
+//      Stockham line transforms, several adjacent lines per workgroup; the
+//      kernel multiplication sits between the forward and inverse column
+//      transforms of one pass.  The kernel is real and even, so the packed
+//      pair separates again after the inverse.  Sheets are processed in
+//      chunks (charges, transforms and the Wilson-line products of a chunk
+//      in one launch each).
 //   3. Wilson lines V = prod_s exp(-i Lambda_s), sheet 1 leftmost.
 //   4. Matching of the nuclei's pure-gauge links U^n_i(x) = V_n(x) V_n^dag(x+i)
 //      to the forward light cone: [(U^A + U^B)(1 + U^dag)]_X = 0 per link by
@@ -130,6 +132,7 @@ __device__ __forceinline__ void butterfly(const double2 *v, double2 *o, int sign
 // tw[r k N / (Ns R)].
 template <int R>
 __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int N, int C, int Ns, int sign) {
+    // tw holds exp(-2 pi i j / N); the inverse uses its conjugate
     constexpr int B = (kFftElems / R + kFftThreads - 1) / kFftThreads;   // butterflies per thread
     const int nb = N / R, step = N / (Ns * R), total = C * nb;
     double2 o[B][R];
@@ -145,7 +148,11 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int N
 #pragma unroll
             for (int r = 0; r < R; r++) v[r] = in[j + r * nb];
 #pragma unroll
-            for (int r = 1; r < R; r++) v[r] = cmul(v[r], tw[r * k * step]);
+            for (int r = 1; r < R; r++) {
+                double2 w = tw[r * k * step];
+                if (sign > 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
             butterfly<R>(v, o[b], sign);
             at[b] = line * N + (j / Ns) * Ns * R + k;
         }
@@ -159,24 +166,40 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int N
     __syncthreads();
 }
 
+__device__ __forceinline__ void fft_stages(double2 *buf, const double2 *tw, int N, int C, int sign, Radices rs) {
+    int Ns = 1;
+    for (int s = 0; s < rs.n4; s++, Ns *= 4) fft_stage<4>(buf, tw, N, C, Ns, sign);
+    for (int s = 0; s < rs.n2; s++, Ns *= 2) fft_stage<2>(buf, tw, N, C, Ns, sign);
+    for (int s = 0; s < rs.n3; s++, Ns *= 3) fft_stage<3>(buf, tw, N, C, Ns, sign);
+}
+
 // In-place transforms of the N x N planes: each workgroup transforms C
 // adjacent lines of one plane (rows if cols == 0, columns otherwise), with
-// the twiddles exp(2 pi i j / N) tabulated once per workgroup in LDS.  Loads
+// the twiddles exp(-2 pi i j / N) tabulated once per workgroup in LDS.  Loads
 // and stores walk the C lines together, so a column workgroup reads C
 // consecutive values of each row.  sign = -1 forward, +1 inverse
-// (unnormalised).
+// (unnormalised).  POISSON (columns only, after the forward row pass): the
+// forward column transform, the multiplication of mode (kx, ky) by
+// 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m2)) (zero above uv2 > 0)
+// and the inverse column transform, in one pass.
+template <bool POISSON>
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int groups_per_plane, int sign,
-            Radices rs) {
+            Radices rs, double m2, double uv2) {
     __shared__ double2 buf[kFftElems];
     __shared__ double2 tw[kFftMaxN];
+    __shared__ double s2[POISSON ? kFftMaxN : 1];
     const int g = blockIdx.x % groups_per_plane, plane = blockIdx.x / groups_per_plane;
     double2 *base = data + (size_t)plane * plane_stride;
     const int l0 = g * C;
     for (int j = threadIdx.x; j < N; j += kFftThreads) {
         double sn, cs;
         sincospi(2.0 * (double)j / (double)N, &sn, &cs);
-        tw[j] = make_double2(cs, sign < 0 ? -sn : sn);
+        tw[j] = make_double2(cs, -sn);
+        if (POISSON) {
+            const double h = sinpi((double)j / (double)N);
+            s2[j] = 4.0 * h * h;
+        }
     }
     for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
         const int line = cols ? i % C : i / N, k = cols ? i / C : i % N;
@@ -184,33 +207,24 @@ k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int grou
         buf[line * N + k] = base[addr];
     }
     __syncthreads();
-    int Ns = 1;
-    for (int s = 0; s < rs.n4; s++, Ns *= 4) fft_stage<4>(buf, tw, N, C, Ns, sign);
-    for (int s = 0; s < rs.n2; s++, Ns *= 2) fft_stage<2>(buf, tw, N, C, Ns, sign);
-    for (int s = 0; s < rs.n3; s++, Ns *= 3) fft_stage<3>(buf, tw, N, C, Ns, sign);
+    if (POISSON) {
+        fft_stages(buf, tw, N, C, -1, rs);
+        const double nn = (double)N * (double)N;
+        for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
+            const int line = i / N, k = i % N;   // kx = l0 + line, ky = k
+            const double k2 = s2[l0 + line] + s2[k];
+            const double gk = (uv2 > 0.0 && k2 > uv2) ? 0.0 : 1.0 / (nn * (k2 + m2));
+            buf[i] = make_double2(buf[i].x * gk, buf[i].y * gk);
+        }
+        __syncthreads();
+        fft_stages(buf, tw, N, C, +1, rs);
+    } else {
+        fft_stages(buf, tw, N, C, sign, rs);
+    }
     for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
         const int line = cols ? i % C : i / N, k = cols ? i / C : i % N;
         const size_t addr = cols ? (size_t)k * N + (l0 + line) : (size_t)(l0 + line) * N + k;
         base[addr] = buf[line * N + k];
-    }
-}
-
-// multiply by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m^2)) on the 4
-// planes of sheet blockIdx.y; modes with lattice momentum squared above uv2 > 0 are set to zero
-__global__ void __launch_bounds__(256)
-k_poisson_kernel(int N, double m2, double uv2, double2 *planes) {
-    size_t n2 = (size_t)N * N;
-    size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (x >= n2) return;
-    planes += (size_t)blockIdx.y * 4 * n2;
-    int kx = (int)(x % N), ky = (int)(x / N);
-    double sx = sinpi((double)kx / N), sy = sinpi((double)ky / N);
-    double k2 = 4.0 * sx * sx + 4.0 * sy * sy;
-    double g = (uv2 > 0.0 && k2 > uv2) ? 0.0 : 1.0 / (((double)N * N) * (k2 + m2));
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        double2 v = planes[(size_t)j * n2 + x];
-        planes[(size_t)j * n2 + x] = make_double2(v.x * g, v.y * g);
     }
 }
 
@@ -538,28 +552,24 @@ hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes
     return hipGetLastError();
 }
 
-static hipError_t fft2(hipStream_t st, int N, double2 *planes, int n_planes, int sign) {
+// Poisson solve of n_sheets x 4 planes: forward row transforms, the fused
+// column pass (forward, kernel, inverse) and inverse row transforms
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets) {
     Radices rs;
     if (N > kFftMaxN || !radices_of(N, rs)) return hipErrorInvalidValue;
     const size_t n2 = (size_t)N * N;
-    const int C = fft_lines_per_group(N), groups = N / C;
-    for (int cols = 0; cols < 2; cols++) {
-        hipLaunchKernelGGL(k_fft_lines, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, cols, n2,
-                           groups, sign, rs);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets) {
-    hipError_t e = fft2(st, N, planes, 4 * n_sheets, -1);
+    const int C = fft_lines_per_group(N), groups = N / C, n_planes = 4 * n_sheets;
+    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, 0, n2,
+                       groups, -1, rs, m2, uv2);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_poisson_kernel, dim3(blocks_for((size_t)N * N, 256), n_sheets), dim3(256), 0, st, N, m2,
-                       uv2, planes);
+    hipLaunchKernelGGL(k_fft_lines<true>, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, 1, n2,
+                       groups, -1, rs, m2, uv2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return fft2(st, N, planes, 4 * n_sheets, +1);
+    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, 0, n2,
+                       groups, +1, rs, m2, uv2);
+    return hipGetLastError();
 }
 
 hipError_t launch_dipole(hipStream_t st, int N, const double *V, int rmax, double *partials, double *D) {
