@@ -189,7 +189,10 @@ k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int grou
     __shared__ double2 buf[kFftElems];
     __shared__ double2 tw[kFftMaxN];
     __shared__ double s2[POISSON ? kFftMaxN : 1];
-    const int g = blockIdx.x % groups_per_plane, plane = blockIdx.x / groups_per_plane;
+    // contiguous runs of groups per XCD: the C-wide column segments of
+    // neighbouring groups share cache lines, which then meet in one L2
+    const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int g = bid % groups_per_plane, plane = bid / groups_per_plane;
     double2 *base = data + (size_t)plane * plane_stride;
     const int l0 = g * C;
     for (int j = threadIdx.x; j < N; j += kFftThreads) {
