@@ -9,23 +9,31 @@
 namespace gl {
 
 // one particle step of slot i (i < number of slots); returns the species of
-// an active particle (-1 otherwise) and its broadening terms in acc
+// an active particle (-1 otherwise) and its broadening terms in acc.  Loads
+// are grouped so that a wave makes three dependent trips to memory: the
+// particle state (all of it, before the activity test), the site fields and
+// phi of its cell, and the links of both crossings together.
 template <typename T>
 __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const FieldPtrs<T> &f,
                                              const T *__restrict__ F, const SpeciesTab<T> &tab, int n,
                                              T dtau, double *acc) {
     const size_t n2 = plane_pitch(N);
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
-    int s = el_ld(P.species, i);
-    if (s >= 0 && n >= tab.nform[s]) {
+    const int s = el_ld(P.species, i);
+    int cx = el_ld(P.cx, i), cy = el_ld(P.cy, i);
+    T q[8];
+#pragma unroll
+    for (int a = 0; a < 8; a++) q[a] = pl_ld(P.Q, P.cap, a, i);
+    T pl[3] = {el_ld(P.px, i), el_ld(P.py, i), el_ld(P.peta, i)};
+    T ox = el_ld(P.ox, i), oy = el_ld(P.oy, i);
+    const T eta_old = el_ld(P.eta, i);
+    const double x0 = el_ld(P.px0, i), y0 = el_ld(P.py0, i), z0 = el_ld(P.pz0, i);
+    const bool active = s >= 0 && n >= tab.nform[s];
+    if (active) {
         const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
         const T m = tab.mass[s];
-        int cx = el_ld(P.cx, i), cy = el_ld(P.cy, i);
-        size_t x = (size_t)cx + (size_t)N * cy;
-        T q[8];
-#pragma unroll
-        for (int a = 0; a < 8; a++) q[a] = pl_ld(P.Q, P.cap, a, i);
-        T e[3], b[3];
+        const size_t x = (size_t)cx + (size_t)N * cy;
+        T e[3], b[3], ph[8];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             T se = T(0), sb = T(0);
@@ -38,8 +46,10 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
             e[k] = se;
             b[k] = sb;
         }
+#pragma unroll
+        for (int a = 0; a < 8; a++) ph[a] = pl_ld(f.phi, n2, a, x);
         // Boris kick at tau_n
-        T pl[3] = {el_ld(P.px, i), el_ld(P.py, i), el_ld(P.peta, i) / tau};
+        pl[2] /= tau;
         T pm[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) pm[k] = pl[k] + T(0.5) * dtau * e[k];
@@ -59,41 +69,31 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         // drift
         const T pzh = peta / th;
         const T ptau = sqrt(m * m + pl[0] * pl[0] + pl[1] * pl[1] + pzh * pzh);
-        T ox = el_ld(P.ox, i) + dtau * pl[0] / ptau;
-        T oy = el_ld(P.oy, i) + dtau * pl[1] / ptau;
+        ox += dtau * pl[0] / ptau;
+        oy += dtau * pl[1] / ptau;
         const T deta = dtau * peta / (th * th * ptau);
-        const T eta_old = el_ld(P.eta, i);
         const T eta_new = eta_old + deta;
+        // cells crossed, x first then y; the links of both crossings are
+        // loaded before either transport
+        const int sx = ox >= T(0.5) ? 1 : (ox < T(-0.5) ? -1 : 0);
+        const int sy = oy >= T(0.5) ? 1 : (oy < T(-0.5) ? -1 : 0);
+        const int cxm = cx == 0 ? N - 1 : cx - 1, cym = cy == 0 ? N - 1 : cy - 1;
+        const int cx1 = sx > 0 ? (cx + 1 == N ? 0 : cx + 1) : (sx < 0 ? cxm : cx);
+        const int cy1 = sy > 0 ? (cy + 1 == N ? 0 : cy + 1) : (sy < 0 ? cym : cy);
+        M3<T> ux, uy;
+        if (sx != 0) ux = load_m(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy);
+        if (sy != 0) uy = load_m(f.U + 18 * n2, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym));
         // colour rotation along eta with phi^n at the old cell: Q <- W Q W^dag
-        {
-            T ph[8];
-#pragma unroll
-            for (int a = 0; a < 8; a++) ph[a] = pl_ld(f.phi, n2, a, x);
-            transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
-        }
-        // crossings, x first then y: Q <- U^dag Q U forward, U Q U^dag backward
-        if (ox >= T(0.5)) {
-            transport_dn(load_m(f.U, n2, x), herm_from_alg(q), q);
-            ox -= T(1);
-            cx = cx + 1 == N ? 0 : cx + 1;
-        } else if (ox < T(-0.5)) {
-            int cm = cx == 0 ? N - 1 : cx - 1;
-            transport_nd(load_m(f.U, n2, (size_t)cm + (size_t)N * cy), herm_from_alg(q), q);
-            ox += T(1);
-            cx = cm;
-        }
-        if (oy >= T(0.5)) {
-            transport_dn(load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cy), herm_from_alg(q), q);
-            oy -= T(1);
-            cy = cy + 1 == N ? 0 : cy + 1;
-        } else if (oy < T(-0.5)) {
-            int cm = cy == 0 ? N - 1 : cy - 1;
-            transport_nd(load_m(f.U + 18 * n2, n2, (size_t)cx + (size_t)N * cm), herm_from_alg(q), q);
-            oy += T(1);
-            cy = cm;
-        }
-        el_st(P.cx, i, cx);
-        el_st(P.cy, i, cy);
+        transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
+        // crossings: Q <- U^dag Q U forward, U Q U^dag backward
+        if (sx > 0) transport_dn(ux, herm_from_alg(q), q);
+        else if (sx < 0) transport_nd(ux, herm_from_alg(q), q);
+        if (sy > 0) transport_dn(uy, herm_from_alg(q), q);
+        else if (sy < 0) transport_nd(uy, herm_from_alg(q), q);
+        ox -= (T)sx;
+        oy -= (T)sy;
+        el_st(P.cx, i, cx1);
+        el_st(P.cy, i, cy1);
         el_st(P.ox, i, ox);
         el_st(P.oy, i, oy);
         el_st(P.eta, i, eta_new);
@@ -108,13 +108,12 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const double em = expm1(etab), ie = 1.0 / (em + 1.0);
         const double sh = 0.5 * em * (em + 2.0) * ie, ch = 1.0 + 0.5 * em * em * ie;
         const double pzlab = (double)ptau * sh + (double)pzh * ch;
-        const double x0 = el_ld(P.px0, i), y0 = el_ld(P.py0, i), z0 = el_ld(P.pz0, i);
         acc[0] = (double)pl[0] * pl[0] - x0 * x0;
         acc[1] = (double)pl[1] * pl[1] - y0 * y0;
         acc[2] = pzlab * pzlab - z0 * z0;
         acc[3] = 1.0;
     }
-    return s >= 0 && n >= tab.nform[s] ? s : -1;
+    return active ? s : -1;
 }
 
 // Per-species workgroup reduction of kPushBlock threads (particles of
