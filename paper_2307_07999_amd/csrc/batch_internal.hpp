@@ -16,6 +16,7 @@ struct BatchEv {
     PartPtrs<T> P[2];      // particle buffers; the current one alternates at each sort
     T *F;                  // site-field planes, written by the field phase when n_species > 0
     double *partials;      // [n_slots / kPushBlock][n_species][4]
+    const double *p0sum;   // [kMaxSpecies][4]: sums of the squared momenta at formation
     double *series;        // [max_steps][kMaxSpecies][4]
     SpeciesTab<T> tab;
 };

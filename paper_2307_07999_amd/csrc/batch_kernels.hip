@@ -128,7 +128,11 @@ k_batch_reduce(const BatchEv<T> *__restrict__ evs, const BatchCtl *__restrict__ 
             for (int k = 0; k < 4; k++) red[threadIdx.x][k] += red[threadIdx.x + w][k];
         __syncthreads();
     }
-    if (threadIdx.x < 4) e.series[((size_t)row * kMaxSpecies + s) * 4 + threadIdx.x] = red[0][threadIdx.x];
+    if (threadIdx.x < 4) {
+        double v = red[0][threadIdx.x];
+        if (threadIdx.x < 3 && red[0][3] > 0.0) v -= e.p0sum[s * 4 + threadIdx.x];
+        e.series[((size_t)row * kMaxSpecies + s) * 4 + threadIdx.x] = v;
+    }
 }
 
 __global__ void k_batch_advance(BatchCtl *ctl) {

@@ -37,7 +37,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t field[2], F, part[2], id[2], sort_keys[2], sort_vals[2], sort_counts, sort_totals, partials,
-        series, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, ll, ll_part,
+        series, p0sum, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, ll, ll_part,
         ll_series, total;
     int64_t slots;         // particle capacity in slots (padding included)
     size_t n_diag_blocks;  // workgroups of the diagnostics kernel
@@ -80,6 +80,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     L.sort_totals = take(256 * sizeof(uint32_t));
     L.partials = take(std::max<int64_t>(1, L.slots / kPushBlock) * kMaxSpecies * 4 * sizeof(double));
     L.series = take(std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double));
+    L.p0sum = take((size_t)kMaxSpecies * 4 * sizeof(double));
     L.n_diag_blocks = (size_t)((d->N + 31) / 32) * ((d->N + 7) / 8);
     size_t cas_blocks = (size_t)std::max<int64_t>(1, (L.slots + 255) / 256);
     L.diag = take(std::max(L.n_diag_blocks * 8, cas_blocks) * sizeof(double));
@@ -195,6 +196,7 @@ struct gl_event {
     double *stat_series() const { return (double *)(ws + L.stat_series); }
     double *ll_series() const { return (double *)(ws + L.ll_series); }
     double *partials() const { return (double *)(ws + L.partials); }
+    double *p0sum() const { return (double *)(ws + L.p0sum); }
 };
 
 namespace {
@@ -259,7 +261,8 @@ gl_status field_step(gl_event *ev, bool site_fields) {
         double *part = (double *)(ev->ws + ev->L.stat_part);
         PROF(ev, 1, (launch_static_accum<T>(ev->stream, ev->N, (const T *)(ev->ws + ev->L.F),
                                             (double *)(ev->ws + ev->L.stat), ev->dtau, part, &nb)));
-        HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->stat_series() + (ev->n - 1) * kMaxSpecies * 4));
+        HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->stat_series() + (ev->n - 1) * kMaxSpecies * 4,
+                                     nullptr));
         ev->stat_rows = std::max<int64_t>(ev->stat_rows, ev->n);
     }
     if (ll) {
@@ -270,7 +273,8 @@ gl_status field_step(gl_event *ev, bool site_fields) {
         PROF(ev, 1, (launch_lightlike_accum<T>(ev->stream, ev->N, (const T *)(ev->ws + ev->L.F),
                                                ev->fields<T>(ev->cur).U, W, I, ev->n - ev->ll_n0, ev->dtau, part,
                                                &nb)));
-        HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->ll_series() + (ev->n - 1) * kMaxSpecies * 4));
+        HIP_TRY(launch_series_reduce(ev->stream, part, nb, 1, ev->ll_series() + (ev->n - 1) * kMaxSpecies * 4,
+                                     nullptr));
         ev->ll_rows = std::max<int64_t>(ev->ll_rows, ev->n);
     }
     ev->cur = nxt;
@@ -288,7 +292,7 @@ gl_status push(gl_event *ev) {
                                 (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev, ev->dtau,
                                 ev->partials())));
     PROF(ev, 3, (launch_series_reduce(ev->stream, ev->partials(), (int)(ev->slots_used / kPushBlock), ns,
-                                      ev->series() + row * kMaxSpecies * 4)));
+                                      ev->series() + row * kMaxSpecies * 4, ev->p0sum())));
     ev->rows = std::max<int64_t>(ev->rows, row + 1);
     ev->push_due = false;
     ev->since_sort++;
@@ -308,6 +312,21 @@ gl_status sort_t(gl_event *ev) {
 gl_status sort_particles(gl_event *ev) {
     if (ev->slots_used == 0) return GL_OK;
     return ev->fp64() ? sort_t<double>(ev) : sort_t<float>(ev);
+}
+
+// the per-species sums of the squared momenta at formation, which the
+// momentum series subtract (Sec. 2: broadening relative to formation); taken
+// once whenever the particle set changes
+gl_status p0_sums(gl_event *ev) {
+    const int ns = (int)ev->species.size();
+    if (ev->slots_used == 0 || ns == 0) return GL_OK;
+    if (ev->fp64())
+        HIP_TRY(launch_p0_sums<double>(ev->stream, ev->parts<double>(), ev->slots_used, ns, ev->partials(),
+                                       ev->p0sum()));
+    else
+        HIP_TRY(launch_p0_sums<float>(ev->stream, ev->parts<float>(), ev->slots_used, ns, ev->partials(),
+                                      ev->p0sum()));
+    return GL_OK;
 }
 
 gl_status do_field_step(gl_event *ev, bool sf) {
@@ -686,6 +705,8 @@ gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uin
     if (s) return s;
     s = sort_particles(ev);
     if (s) return s;
+    s = p0_sums(ev);
+    if (s) return s;
     if (species_id) *species_id = sid;
     return GL_OK;
 }
@@ -990,7 +1011,9 @@ gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_des
     gl_status s = ev->fp64() ? set_particles_t<double>(ev, n, cell, off, eta, p, Q, p0, species)
                              : set_particles_t<float>(ev, n, cell, off, eta, p, Q, p0, species);
     if (s) return s;
-    return sort_particles(ev);
+    s = sort_particles(ev);
+    if (s) return s;
+    return p0_sums(ev);
 }
 
 gl_status gl_set_sort_period(gl_event *ev, int32_t every) {
@@ -1207,6 +1230,7 @@ BatchEv<T> batch_desc(const gl_batch *b, int e) {
     d.P[1] = ev->parts<T>(1 - b->pbuf0[e]);
     d.F = (T *)(ev->ws + ev->L.F);
     d.partials = ev->partials();
+    d.p0sum = ev->p0sum();
     d.series = ev->series();
     d.tab = ev->tab<T>();
     return d;

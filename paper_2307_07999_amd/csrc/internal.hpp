@@ -77,8 +77,16 @@ hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, Fi
                        const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
                        double *partials);
 hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, int32_t base);
+// fixed-order sum of per-workgroup partial rows into a series row; a
+// non-null sub [kMaxSpecies][4] is subtracted from the first three terms of
+// every species with a non-zero count
 hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
-                                double *row);
+                                double *row, const double *sub);
+// per-species sums (p_x0^2, p_y0^2, p_z0^2, count) of the momenta at
+// formation into out [kMaxSpecies][4], through the partial rows
+template <typename T>
+hipError_t launch_p0_sums(hipStream_t st, PartPtrs<T> p, int64_t n_slots, int n_species, double *partials,
+                          double *out);
 // static-quark accumulators I [24][n2] FP64; partials [blocks][4]
 template <typename T>
 hipError_t launch_static_accum(hipStream_t st, int N, const T *F, double *I, double dtau, double *partials,

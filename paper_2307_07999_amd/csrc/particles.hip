@@ -36,9 +36,10 @@ k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restric
 }
 
 // series row [kMaxSpecies][4]: species s sums the partial rows of all push
-// workgroups in a fixed order.
+// workgroups in a fixed order; with sub, a species with active particles
+// then has sub[s][k] (k < 3) subtracted from its three momentum sums.
 __global__ void __launch_bounds__(256)
-k_series_reduce(const double *__restrict__ partials, int n_blocks, int n_species,
+k_series_reduce(const double *__restrict__ partials, int n_blocks, int n_species, const double *__restrict__ sub,
                 double *__restrict__ row) {
     const int s = blockIdx.x;
     __shared__ double red[256][4];
@@ -57,7 +58,11 @@ k_series_reduce(const double *__restrict__ partials, int n_blocks, int n_species
             for (int k = 0; k < 4; k++) red[threadIdx.x][k] += red[threadIdx.x + w][k];
         __syncthreads();
     }
-    if (threadIdx.x < 4) row[s * 4 + threadIdx.x] = red[0][threadIdx.x];
+    if (threadIdx.x < 4) {
+        double v = red[0][threadIdx.x];
+        if (sub && threadIdx.x < 3 && red[0][3] > 0.0) v -= sub[s * 4 + threadIdx.x];
+        row[s * 4 + threadIdx.x] = v;
+    }
 }
 
 // Particle initialisation (Sec. 2 toy model, Sec. 1 color charges): counter
@@ -157,6 +162,38 @@ k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, 
     for (int a = 0; a < 8; a++) P.Q[(size_t)a * P.cap + j] = (T)q[a];
 }
 
+// Per-species partial sums of the squared momenta at formation (p_x0^2,
+// p_y0^2, p_z0^2, count) over the particles of each kPushBlock workgroup,
+// with the push's fixed-order block reduction; the series reduction of
+// these rows gives the sums the momentum series subtract.
+template <typename T>
+__global__ void __launch_bounds__(kPushBlock)
+k_p0_sums(PartPtrs<T> P, int64_t n_slots, int n_species, double *__restrict__ partials) {
+    const int64_t i = (int64_t)blockIdx.x * kPushBlock + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int s = -1;
+    if (i < n_slots && P.species[i] >= 0) {
+        s = P.species[i];
+        const double x0 = P.px0[i], y0 = P.py0[i], z0 = P.pz0[i];
+        acc[0] = x0 * x0;
+        acc[1] = y0 * y0;
+        acc[2] = z0 * z0;
+        acc[3] = 1.0;
+    }
+    block_species_reduce(s, acc, n_species, partials + (size_t)blockIdx.x * n_species * 4);
+}
+
+template <typename T>
+hipError_t launch_p0_sums(hipStream_t st, PartPtrs<T> p, int64_t n_slots, int n_species, double *partials,
+                          double *out) {
+    if (n_slots <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
+    hipLaunchKernelGGL(k_p0_sums<T>, dim3(blocks), dim3(kPushBlock), 0, st, p, n_slots, n_species, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_series_reduce(st, partials, (int)blocks, n_species, out, nullptr);
+}
+
 // max |Q^a Q^a - 4| per workgroup over particles (padding excluded)
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -214,9 +251,9 @@ hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, Fi
 }
 
 hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
-                                double *row) {
+                                double *row, const double *sub) {
     hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies), dim3(256), 0, st, partials, n_blocks,
-                       n_species, row);
+                       n_species, sub, row);
     return hipGetLastError();
 }
 
@@ -235,7 +272,8 @@ hipError_t launch_particles_init(hipStream_t st, int N, PartPtrs<T> p, int64_t s
                                        const T *, SpeciesTab<T>, int, int, double, double *);    \
     template hipError_t launch_particles_init<T>(hipStream_t, int, PartPtrs<T>, int64_t, int64_t, \
                                                  uint64_t, int, int, double);                    \
-    template hipError_t launch_casimir<T>(hipStream_t, PartPtrs<T>, int64_t, double *, int *);
+    template hipError_t launch_casimir<T>(hipStream_t, PartPtrs<T>, int64_t, double *, int *);             \
+    template hipError_t launch_p0_sums<T>(hipStream_t, PartPtrs<T>, int64_t, int, double *, double *);
 GL_INST(double)
 GL_INST(float)
 #undef GL_INST

@@ -9,7 +9,9 @@
 namespace gl {
 
 // one particle step of slot i (i < number of slots); returns the species of
-// an active particle (-1 otherwise) and its broadening terms in acc.  Loads
+// an active particle (-1 otherwise) and in acc its squared momenta p_x^2,
+// p_y^2, p_z^2 (lab frame) at tau_{n+1/2} and a count of 1; the series
+// reduction subtracts the species' sums of the squared momenta at formation.  Loads
 // are grouped so that a wave makes three dependent trips to memory: the
 // particle state (all of it, before the activity test), the site fields and
 // phi of its cell, and the links of both crossings together.
@@ -27,7 +29,6 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
     T pl[3] = {el_ld(P.px, i), el_ld(P.py, i), el_ld(P.peta, i)};
     T ox = el_ld(P.ox, i), oy = el_ld(P.oy, i);
     const T eta_old = el_ld(P.eta, i);
-    const double x0 = el_ld(P.px0, i), y0 = el_ld(P.py0, i), z0 = el_ld(P.pz0, i);
     const bool active = s >= 0 && n >= tab.nform[s];
     if (active) {
         const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
@@ -108,9 +109,9 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const double em = expm1(etab), ie = 1.0 / (em + 1.0);
         const double sh = 0.5 * em * (em + 2.0) * ie, ch = 1.0 + 0.5 * em * em * ie;
         const double pzlab = (double)ptau * sh + (double)pzh * ch;
-        acc[0] = (double)pl[0] * pl[0] - x0 * x0;
-        acc[1] = (double)pl[1] * pl[1] - y0 * y0;
-        acc[2] = pzlab * pzlab - z0 * z0;
+        acc[0] = (double)pl[0] * pl[0];
+        acc[1] = (double)pl[1] * pl[1];
+        acc[2] = pzlab * pzlab;
         acc[3] = 1.0;
     }
     return active ? s : -1;
