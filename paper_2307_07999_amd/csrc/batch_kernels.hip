@@ -64,7 +64,7 @@ k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles
 // takes one contiguous run of the table: the walk of the persistent kernel
 // without its loop, which holds registers the step can use.
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(2 * TX *TY)
+__global__ void __launch_bounds__(2 * TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4, 8)))
 k_batch_field_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles, int64_t total, int fpar,
                    const BatchCtl *__restrict__ ctl, T dtau) {
     __shared__ LinkTile<T, TX, TY> tile;

@@ -34,7 +34,7 @@ constexpr int SX = 32, SY = 4;     // site tiles of the step: 2 lanes per site
 // FP64: two waves per SIMD at the cost of a few spilled registers is faster
 // than one wave with everything in registers.
 template <typename T>
-__global__ void __launch_bounds__(2 * SX * SY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 1, 8)))
+__global__ void __launch_bounds__(2 * SX * SY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4, 8)))
 k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T *__restrict__ F, T tau, T dtau, T tau_h, int reunit) {
     __shared__ LinkTile<T, SX, SY> tile;
     const int tx = (N + SX - 1) / SX;

@@ -202,11 +202,15 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
     const M3<T> ui = tl.m(pi_, rx);   // U_i(x)
     T fe[8], cl[8];
     {
-        T px[8];   // [P(x)]_X, P(x) = [U_1(x) U_2(x+1)] [U_2(x) U_1(x+2)]^dag
+        // [P(x)]_X, P(x) = h0 h1^dag with the half products h0 = U_1(x) U_2(x+1)
+        // (lane 0) and h1 = U_2(x) U_1(x+2) (lane 1); lane 1 forms h1 h0^dag =
+        // P(x)^dag, whose projection is -[P(x)]_X
+        T px[8];
         {
             const M3<T> h = mul(ui, tl.m(pj, rpi));
-            const M3<T> o = pair_swap(h);
-            alg_proj(mul_nd(select(d0, h, o), select(d0, o, h)), px);
+            alg_proj(mul_nd(h, pair_swap(h)), px);
+#pragma unroll
+            for (int a = 0; a < 8; a++) px[a] *= sgn;
         }
         // staple: U_j^dag(y) [P(y)]_X U_j(y)
         const M3<T> uj = tl.m(pj, ry);
@@ -222,13 +226,15 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
     }
     if (F) {
         // fourth clover plaquette P(z) = [U_1(z) U_2(z+1)] [U_2(z) U_1(z+2)]^dag,
-        // moved to x along z -> z+1 -> x, i.e. by C = U_1(z) U_2(z+1)
+        // moved to x along z -> z+1 -> x, i.e. by C = U_1(z) U_2(z+1) (the
+        // half product of lane 0; lane 1 projects P(z)^dag as above)
         const M3<T> h = mul(tl.m(pi_, rz), tl.m(pj, rzi));
         const M3<T> o = pair_swap(h);
-        const M3<T> C = select(d0, h, o);
         T pa[8], t[8];
-        alg_proj(mul_nd(C, select(d0, o, h)), pa);
-        transport_dn(C, herm_from_alg(pa), t);
+        alg_proj(mul_nd(h, o), pa);
+#pragma unroll
+        for (int a = 0; a < 8; a++) pa[a] *= sgn;
+        transport_dn(select(d0, h, o), herm_from_alg(pa), t);
 #pragma unroll
         for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
         store_half(F, n2, x, 40, t, d);   // B_z
