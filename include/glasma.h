@@ -257,7 +257,8 @@ gl_status gl_lightlike_broadening(gl_event *ev, double *out, int32_t cap, int32_
  * the stream and returns, per kernel class (0 field step, which also writes
  * the site fields when the event has particles or correlators, 1 static
  * quark and lightlike jet accumulation, 2 particle push, 3 series
- * reduction), the summed
+ * reduction: one launch reduces the partial rows of up to 16 pushes), the
+ * summed
  * milliseconds and the
  * launch counts since the last read, then clears them.  Creates HIP events
  * only (no device memory). */

@@ -35,6 +35,14 @@ gl_status fail(gl_status s, const std::string &msg) {
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// The push writes per-workgroup partial rows; their fixed-order reduction
+// into the series is deferred and done for up to kReduceSlots steps in one
+// launch (the series is only read between runs).
+constexpr int kReduceSlots = 16;
+inline size_t partial_slot_stride(int64_t slots) {
+    return (size_t)std::max<int64_t>(1, slots / kPushBlock) * kMaxSpecies * 4;
+}
+
 struct Layout {
     size_t field[2], F, part[2], id[2], sort_keys[2], sort_vals[2], sort_counts, sort_totals, partials,
         series, p0sum, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, ll, ll_part,
@@ -78,7 +86,8 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     for (int b = 0; b < 2; b++) L.sort_vals[b] = take((size_t)L.slots * sizeof(int32_t));
     L.sort_counts = take((size_t)256 * std::max<int64_t>(1, sort_tiles(L.slots)) * sizeof(uint32_t));
     L.sort_totals = take(256 * sizeof(uint32_t));
-    L.partials = take(std::max<int64_t>(1, L.slots / kPushBlock) * kMaxSpecies * 4 * sizeof(double));
+    // partial rows of up to kReduceSlots pushes, reduced into the series in one launch
+    L.partials = take(kReduceSlots * partial_slot_stride(L.slots) * sizeof(double));
     L.series = take(std::max(1, d->max_steps) * (size_t)kMaxSpecies * 4 * sizeof(double));
     L.p0sum = take((size_t)kMaxSpecies * 4 * sizeof(double));
     L.n_diag_blocks = (size_t)((d->N + 31) / 32) * ((d->N + 7) / 8);
@@ -125,6 +134,8 @@ struct gl_event {
     int64_t n = 0;
     bool ready = false, push_due = false;
     int64_t rows = 0;           // series rows written
+    int64_t pend_row0 = 0;      // first series row of the pending partial rows
+    int pend = 0;               // pushes whose partial rows are not reduced yet
     int64_t slots_used = 0;
     std::vector<SpeciesInfo> species;
     int pbuf = 0;               // which particle buffer is current
@@ -195,7 +206,9 @@ struct gl_event {
     double *series() const { return (double *)(ws + L.series); }
     double *stat_series() const { return (double *)(ws + L.stat_series); }
     double *ll_series() const { return (double *)(ws + L.ll_series); }
-    double *partials() const { return (double *)(ws + L.partials); }
+    double *partials(int slot = 0) const {
+        return (double *)(ws + L.partials) + (size_t)slot * partial_slot_stride(L.slots);
+    }
     double *p0sum() const { return (double *)(ws + L.p0sum); }
 };
 
@@ -282,17 +295,32 @@ gl_status field_step(gl_event *ev, bool site_fields) {
     return GL_OK;
 }
 
+// reduce the pending partial rows into their series rows (one launch)
+gl_status flush_series(gl_event *ev) {
+    if (ev->pend == 0) return GL_OK;
+    const int ns = (int)ev->species.size();
+    PROF(ev, 3, (launch_series_reduce_steps(ev->stream, ev->partials(), partial_slot_stride(ev->L.slots), ev->pend,
+                                            (int)(ev->slots_used / kPushBlock), ns,
+                                            ev->series() + ev->pend_row0 * kMaxSpecies * 4, ev->p0sum())));
+    ev->pend = 0;
+    return GL_OK;
+}
+
 template <typename T>
 gl_status push(gl_event *ev) {
     const int64_t n_prev = ev->n - 1;   // particles advance n_prev -> n
     const int64_t row = n_prev - 1;
     if (row >= ev->desc.max_steps) return fail(GL_EINVAL, "series capacity (max_steps) exhausted");
     const int ns = (int)ev->species.size();
+    if (ev->pend == 0) ev->pend_row0 = row;
     PROF(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used, ev->fields<T>(1 - ev->cur),
                                 (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev, ev->dtau,
-                                ev->partials())));
-    PROF(ev, 3, (launch_series_reduce(ev->stream, ev->partials(), (int)(ev->slots_used / kPushBlock), ns,
-                                      ev->series() + row * kMaxSpecies * 4, ev->p0sum())));
+                                ev->partials(ev->pend))));
+    ev->pend++;
+    if (ev->pend == kReduceSlots) {
+        gl_status s = flush_series(ev);
+        if (s) return s;
+    }
     ev->rows = std::max<int64_t>(ev->rows, row + 1);
     ev->push_due = false;
     ev->since_sort++;
@@ -729,7 +757,9 @@ gl_status gl_evolve_fields(gl_event *ev, int32_t n_steps) {
 gl_status gl_push_particles(gl_event *ev) {
     if (check_ev(ev)) return GL_EINVAL;
     if (!ev->push_due) return fail(GL_ESTATE, "no particle step is due: call gl_evolve_fields(ev, 1) first");
-    return do_push(ev);
+    gl_status s = do_push(ev);
+    if (s) return s;
+    return flush_series(ev);
 }
 
 gl_status gl_run(gl_event *ev, int32_t n_steps) {
@@ -749,7 +779,7 @@ gl_status gl_run(gl_event *ev, int32_t n_steps) {
             if (s) return s;
         }
     }
-    return GL_OK;
+    return flush_series(ev);
 }
 
 gl_status gl_static_start(gl_event *ev, double tau_start_fm) {

@@ -82,6 +82,10 @@ hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, 
 // every species with a non-zero count
 hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
                                 double *row, const double *sub);
+// the same for n_rows consecutive steps at once: step r reads the partial
+// rows at partials + r * slot_stride and writes row + r * kMaxSpecies * 4
+hipError_t launch_series_reduce_steps(hipStream_t st, const double *partials, size_t slot_stride, int n_rows,
+                                      int n_blocks, int n_species, double *row, const double *sub);
 // per-species sums (p_x0^2, p_y0^2, p_z0^2, count) of the momenta at
 // formation into out [kMaxSpecies][4], through the partial rows
 template <typename T>

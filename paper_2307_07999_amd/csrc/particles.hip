@@ -40,8 +40,11 @@ k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restric
 // then has sub[s][k] (k < 3) subtracted from its three momentum sums.
 __global__ void __launch_bounds__(256)
 k_series_reduce(const double *__restrict__ partials, int n_blocks, int n_species, const double *__restrict__ sub,
-                double *__restrict__ row) {
+                double *__restrict__ row, size_t slot_stride) {
+    // blockIdx.y: one of several steps reduced in one launch
     const int s = blockIdx.x;
+    partials += (size_t)blockIdx.y * slot_stride;
+    row += (size_t)blockIdx.y * kMaxSpecies * 4;
     __shared__ double red[256][4];
     double acc[4] = {0, 0, 0, 0};
     if (s < n_species) {
@@ -253,7 +256,15 @@ hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, Fi
 hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
                                 double *row, const double *sub) {
     hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies), dim3(256), 0, st, partials, n_blocks,
-                       n_species, sub, row);
+                       n_species, sub, row, (size_t)0);
+    return hipGetLastError();
+}
+
+hipError_t launch_series_reduce_steps(hipStream_t st, const double *partials, size_t slot_stride, int n_rows,
+                                      int n_blocks, int n_species, double *row, const double *sub) {
+    if (n_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies, n_rows), dim3(256), 0, st, partials, n_blocks,
+                       n_species, sub, row, slot_stride);
     return hipGetLastError();
 }
 

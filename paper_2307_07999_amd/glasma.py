@@ -375,7 +375,8 @@ class Event:
 
     def profile_read(self):
         """(ms[4], launches[4]) of the timed launches per kernel class: field step
-        (with the site fields), unused, push, reduction."""
+        (with the site fields), correlators, push, series reduction (one launch per
+        up to 16 pushes)."""
         ms = np.zeros(4)
         cnt = np.zeros(4, np.int64)
         check(lib().gl_profile_read(self._h, _d(ms), cnt.ctypes.data_as(_I64)))
