@@ -465,8 +465,13 @@ gl_status get_site_fields_t(gl_event *ev, double *F) {
     std::vector<T> tmp((size_t)kSiteRec * n2);
     HIP_TRY(hipMemcpyAsync(tmp.data(), ev->ws + ev->L.F, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
-    for (size_t i = 0; i < 48 * n2; i++) F[i] = (double)tmp[i];
-    for (size_t i = 0; i < 16 * n2; i++) F[i] += (double)tmp[48 * n2 + i];
+    // device records in chunked planes: value k of site x at ((k / NV) n2 + x) NV + k mod NV
+    const size_t NV = 16 / sizeof(T);
+    auto at = [&](int k, size_t x) { return (double)tmp[((size_t)k / NV * n2 + x) * NV + (size_t)k % NV]; };
+    for (int k = 0; k < 48; k++)
+        for (size_t x = 0; x < n2; x++) F[(size_t)k * n2 + x] = at(k, x);
+    for (int k = 0; k < 16; k++)
+        for (size_t x = 0; x < n2; x++) F[(size_t)k * n2 + x] += at(48 + k, x);
     return GL_OK;
 }
 

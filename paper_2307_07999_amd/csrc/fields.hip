@@ -65,8 +65,8 @@ k_static_accum(int N, const T *__restrict__ F, double *__restrict__ I, double dt
             double s = 0.0;
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                double e = (double)pl_ld(F, n2, 8 * i + a, x);
-                if (i < 2) e += (double)pl_ld(F, n2, 48 + 8 * i + a, x);
+                double e = (double)chunk_ld(F, n2, x, 8 * i + a);
+                if (i < 2) e += (double)chunk_ld(F, n2, x, 48 + 8 * i + a);
                 const double t = pl_ld(I, n2, 8 * i + a, x) + dtau * e;
                 pl_st(I, n2, 8 * i + a, x, t);
                 s += t * t;
@@ -111,11 +111,11 @@ k_lightlike_accum(int N, const T *__restrict__ F, const T *__restrict__ U, doubl
             double f[8], t[8];
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                if (i == 0) f[a] = (double)pl_ld(F, n2, a, c) + (double)pl_ld(F, n2, 48 + a, c);
+                if (i == 0) f[a] = (double)chunk_ld(F, n2, c, a) + (double)chunk_ld(F, n2, c, 48 + a);
                 else if (i == 1)
-                    f[a] = ((double)pl_ld(F, n2, 8 + a, c) + (double)pl_ld(F, n2, 56 + a, c)) -
-                           (double)pl_ld(F, n2, 40 + a, c);
-                else f[a] = (double)pl_ld(F, n2, 16 + a, c) + (double)pl_ld(F, n2, 32 + a, c);
+                    f[a] = ((double)chunk_ld(F, n2, c, 8 + a) + (double)chunk_ld(F, n2, c, 56 + a)) -
+                           (double)chunk_ld(F, n2, c, 40 + a);
+                else f[a] = (double)chunk_ld(F, n2, c, 16 + a) + (double)chunk_ld(F, n2, c, 32 + a);
             }
             transport_nd(w, herm_from_alg(f), t);
             double s = 0.0;

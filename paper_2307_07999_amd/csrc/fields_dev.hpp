@@ -8,9 +8,12 @@
 
 namespace gl {
 
+// values slot..slot+7 of the site-field record of site x
 template <typename T>
 __device__ __forceinline__ void store_rec(T *__restrict__ F, size_t n2, size_t x, int slot, const T *v) {
-    store_a(F + (size_t)slot * n2, n2, x, v);
+    constexpr int NV = 16 / sizeof(T);
+#pragma unroll
+    for (int a = 0; a < 8; a += NV) chunk_st16(F, n2, x, slot + a, v + a);
 }
 
 struct Nbr {
@@ -73,8 +76,12 @@ __device__ __forceinline__ M3<T> select(bool c, const M3<T> &a, const M3<T> &b) 
 // lanes of a site store one half each).
 template <typename T>
 __device__ __forceinline__ void store_half(T *__restrict__ F, size_t n2, size_t x, int slot, const T *v, int h) {
+    constexpr int NV = 16 / sizeof(T);
+    T w[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) pl_st(F, n2, slot + k, x + (size_t)(4 * h) * n2, h ? v[4 + k] : v[k]);
+    for (int k = 0; k < 4; k++) w[k] = h ? v[4 + k] : v[k];
+#pragma unroll
+    for (int k = 0; k < 4; k += NV) chunk_st16(F, n2, x, slot + 4 * h + k, w + k);
 }
 
 // Link and scalar planes of a block of SX x SY sites and a one-site halo,
@@ -124,13 +131,14 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
 }
 
 // E_i^{n+1/2}(x) and U_i^{n+1}(x) from the force fe and U_i(x) = u; with F,
-// also this site's half of the electric site field and the transported half
-// of x+i (offsets: xe = x in the E_i planes, xu = x in the U_i planes, xt =
-// x+i in the E_i slots of the site-field record)
+// also this site's half of the electric site field (record of site x, slot
+// fs) and the transported half of x+i (record of site xt, slot 48 + fs)
+// (offsets: xe = x in the E_i planes, xu = x in the U_i planes)
 template <typename T>
 __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const M3<T> &u,
-                                            T *__restrict__ Uout, size_t n2, size_t xe, size_t xu, size_t xt,
-                                            const T *fe, T dtau, T s, int reunit, T *__restrict__ F, T inv_tau) {
+                                            T *__restrict__ Uout, size_t n2, size_t xe, size_t xu, size_t x,
+                                            size_t xt, int fs, const T *fe, T dtau, T s, int reunit,
+                                            T *__restrict__ F, T inv_tau) {
     T e[8], eb[8];
     load_a(Ein, n2, xe, e);
 #pragma unroll
@@ -146,9 +154,9 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
         T t[8];
 #pragma unroll
         for (int a = 0; a < 8; a++) eb[a] = T(0.25) * inv_tau * (eb[a] + e[a]);   // Ebar / (2 tau)
-        store_a(F, n2, xe, eb);
+        store_rec(F, n2, x, fs, eb);
         transport_dn(u, herm_from_alg(eb), t);
-        store_a(F + 48 * n2, n2, xt, t);
+        store_rec(F, n2, xt, 48 + fs, t);
     }
 }
 
@@ -257,18 +265,25 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
             pf[a] = T(0.5) * sgn * inv_tau * (pf[a] - pb[a]);
         }
         // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
-        if (F) store_rec(F, n2, x + (size_t)(8 - 8 * d) * n2, 24, pf);
+        if (F) store_rec(F, n2, x, 32 - 8 * d, pf);
     }
-    update_link(in.E, out.E, ui, out.U, n2, x + oe, x + oi, xpi + oe, fe, dtau, dtau / tau_h, reunit, F, inv_tau);
+    update_link(in.E, out.E, ui, out.U, n2, x + oe, x + oi, x, xpi, 8 * d, fe, dtau, dtau / tau_h, reunit, F,
+                inv_tau);
     // pi, phi and E_z: lane d takes colour components 4d..4d+3
     const size_t xo = x + (size_t)(4 * d) * n2;
+    T ez[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const T p = pl_ld(in.pi, n2, k, xo);
         const T pn = p + dtau * (d0 ? fpi[k] : fpi[4 + k]);
         pl_st(out.pi, n2, k, xo, pn);
         pl_st(out.phi, n2, k, xo, (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn);
-        if (F) pl_st(F, n2, 16 + k, xo, T(0.5) * (p + pn));
+        ez[k] = T(0.5) * (p + pn);
+    }
+    if (F) {
+        constexpr int NV = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < 4; k += NV) chunk_st16(F, n2, x, 16 + 4 * d + k, ez + k);
     }
 }
 

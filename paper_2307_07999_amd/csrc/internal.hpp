@@ -8,8 +8,12 @@ namespace gl {
 
 constexpr int kMaxSpecies = 16;
 constexpr int kPushBlock = 256;   // particles per push workgroup
-// site-field planes, 8 reals each: Ex, Ey, Ez, Bx, By, Bz (local frame) and the
-// transported halves of Ex, Ey stored at their site (E_i = slot i + slot 6 + i)
+// site-field record of kSiteRec reals per site in chunked planes (16-byte
+// chunks of consecutive values, one chunk plane per chunk index over all
+// sites): slots of 8 reals Ex, Ey, Ez, Bx, By, Bz (local frame) and the
+// transported halves of Ex, Ey stored at their site (E_i = slot i + slot
+// 6 + i).  A particle reads its cell's record in 16-byte loads, and the
+// field step's lanes store neighbouring chunks.
 constexpr int kSiteRec = 64;
 
 // distance between consecutive planes of a lattice quantity, in elements
@@ -68,7 +72,7 @@ struct SpeciesTab {
 };
 
 // ---- launchers (stream-ordered, no synchronisation) --------------------------
-// F: site-field planes at tau_n [kSiteRec][pitch], written when non-null
+// F: site-field records at tau_n in chunked planes, written when non-null
 template <typename T>
 hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F,
                              double tau, double dtau, int reunit);

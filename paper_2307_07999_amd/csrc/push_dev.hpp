@@ -34,15 +34,19 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
         const T m = tab.mass[s];
         const size_t x = (size_t)cx + (size_t)N * cy;
+        // the cell's whole site-field record, in 16-byte loads
+        T rec[kSiteRec];
+#pragma unroll
+        for (int j = 0; j < kSiteRec; j += 16 / (int)sizeof(T)) chunk_ld16(F, n2, x, j, rec + j);
         T e[3], b[3], ph[8];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             T se = T(0), sb = T(0);
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                se = fma(q[a], pl_ld(F, n2, 8 * k + a, x), se);
-                if (k < 2) se = fma(q[a], pl_ld(F, n2, 48 + 8 * k + a, x), se);
-                sb = fma(q[a], pl_ld(F, n2, 8 * (3 + k) + a, x), sb);
+                se = fma(q[a], rec[8 * k + a], se);
+                if (k < 2) se = fma(q[a], rec[48 + 8 * k + a], se);
+                sb = fma(q[a], rec[8 * (3 + k) + a], sb);
             }
             e[k] = se;
             b[k] = sb;

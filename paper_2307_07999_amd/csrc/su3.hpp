@@ -532,6 +532,39 @@ __device__ __forceinline__ void el_st(T *p, size_t x, T v) {
     bst(buf(p), (uint32_t)(x * sizeof(T)), 0u, v);
 }
 
+// Chunked planes: values are grouped in 16-byte chunks of NV = 16 /
+// sizeof(T) consecutive values k; chunk plane k / NV holds the chunks of
+// all n2 sites in site order, so value k of site x sits at element
+// ((k / NV) n2 + x) NV + k mod NV.  One lane reads or writes a chunk in one
+// 16-byte access, and lanes of neighbouring sites touch neighbouring chunks.
+template <typename T>
+__device__ __forceinline__ T chunk_ld(const T *p, size_t n2, size_t x, int k) {
+    constexpr int NV = 16 / (int)sizeof(T);
+    return bld(buf(p), (uint32_t)(x * 16 + (k % NV) * sizeof(T)), (uint32_t)((size_t)(k / NV) * n2 * 16), T());
+}
+template <typename T>
+__device__ __forceinline__ void chunk_ld16(const T *p, size_t n2, size_t x, int k, T *out) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    struct V { T v[16 / sizeof(T)]; };
+    constexpr int NV = 16 / (int)sizeof(T);
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(buf(p), (uint32_t)(x * 16),
+                                                          (uint32_t)((size_t)(k / NV) * n2 * 16), 0);
+    const V r = __builtin_bit_cast(V, w);
+#pragma unroll
+    for (int i = 0; i < NV; i++) out[i] = r.v[i];
+}
+template <typename T>
+__device__ __forceinline__ void chunk_st16(T *p, size_t n2, size_t x, int k, const T *in) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    struct V { T v[16 / sizeof(T)]; };
+    constexpr int NV = 16 / (int)sizeof(T);
+    V r;
+#pragma unroll
+    for (int i = 0; i < NV; i++) r.v[i] = in[i];
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p), (uint32_t)(x * 16),
+                                           (uint32_t)((size_t)(k / NV) * n2 * 16), 0);
+}
+
 // A link plane set: 18 planes of n2 values, entry (i,j) real at plane 2(3i+j).
 template <typename T>
 __device__ __forceinline__ M3<T> load_m(const T *__restrict__ base, size_t n2, size_t x) {
