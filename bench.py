@@ -187,9 +187,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, prec):
-    import re
     """Bytes per launch (fetch, write) recorded for this kernel and precision,
     or None when missing or taken on other kernel sources."""
+    import re
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
