@@ -14,7 +14,7 @@ struct BatchEv {
     int64_t n_slots;
     FieldPtrs<T> f[2];     // f[p] and f[p ^ 1]: state at step n and at n + 1 for parity p
     PartPtrs<T> P[2];      // particle buffers; the current one alternates at each sort
-    T *F;                  // site-field planes, written by the field phase when n_species > 0
+    T *F;                  // site-field records (chunked planes), written by the field phase when n_species > 0
     double *partials;      // [n_slots / kPushBlock][n_species][4]
     const double *p0sum;   // [kMaxSpecies][4]: sums of the squared momenta at formation
     double *series;        // [max_steps][kMaxSpecies][4]

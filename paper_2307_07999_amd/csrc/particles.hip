@@ -1,10 +1,10 @@
 // particles.hip -- colored particles in the Glasma: initialisation, the push
 // of Wong's equations (Eq. (2)) and the FP64 momentum-broadening sums.
 //
-// Push (one thread per particle, reading the site-field planes F^n at its
-// cell -- the six local-frame fields, E_x and E_y as two stored halves -- and
-// phi^n from the field state; the particles are kept sorted by cell so that a
-// wave's gathers hit neighbouring addresses):
+// Push (one thread per particle, reading the site-field record F^n of its
+// cell -- the six local-frame fields, E_x and E_y as two stored halves, in
+// 16-byte chunks -- and phi^n from the field state; the particles are kept
+// sorted by cell so that a wave's gathers hit neighbouring addresses):
 //   e_k = Q^a E_k^a, b_k = Q^a B_k^a in the local frame at tau_n
 //   Boris kick of dp/dtau = e + v x b on (p_x, p_y, P_eta/tau_n), P_eta = tau^2 p^eta
 //   drift with velocities at tau_{n+1/2}; rapidity step d_eta
@@ -13,10 +13,12 @@
 //   U Q U^dag (backward) with the crossed link: the link-built particle
 //   Wilson line of the colored-particle-in-cell method, which conserves the
 //   Casimirs of Q.
-//   broadening at tau_{n+1/2}: dp_x^2, dp_y^2 and the lab-frame dp_z^2.
-// Each workgroup writes one FP64 partial row per species; a second kernel
-// sums the rows of each species in a fixed order, so the series is
-// deterministic for a given particle order.
+//   broadening at tau_{n+1/2}: p_x^2, p_y^2 and the lab-frame p_z^2, less the
+//   species' sums of the squares at formation (taken once, see k_p0_sums).
+// Each workgroup writes one FP64 partial row per species into the step's
+// slot; a second kernel sums the rows of each species in a fixed order for
+// up to 16 steps at once, so the series is deterministic for a given
+// particle order.
 #include "philox.hpp"
 #include "push_dev.hpp"
 
