@@ -45,7 +45,7 @@ inline size_t partial_slot_stride(int64_t slots) {
 
 struct Layout {
     size_t field[2], F, part[2], id[2], sort_keys[2], sort_vals[2], sort_counts, sort_totals, partials,
-        series, p0sum, diag, VA, VB, planes, U0, pi0, status, stat, stat_part, stat_series, ll, ll_part,
+        series, p0sum, diag, VA, VB, planes, fft_tab, U0, pi0, status, stat, stat_part, stat_series, ll, ll_part,
         ll_series, total;
     int64_t slots;         // particle capacity in slots (padding included)
     size_t n_diag_blocks;  // workgroups of the diagnostics kernel
@@ -96,6 +96,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     L.VA = take(18 * n2 * sizeof(double));
     L.VB = take(18 * n2 * sizeof(double));
     L.planes = take((size_t)kSheetChunk * 4 * n2 * sizeof(double2));
+    L.fft_tab = take(kFftTableBytes);
     L.U0 = take(36 * n2 * sizeof(double));
     L.pi0 = take(8 * n2 * sizeof(double));
     L.status = take(256);
@@ -651,6 +652,8 @@ static gl_status wilson_lines(gl_event *ev, int n_sheets, double m_ir_GeV, doubl
     if (!valid_N_for_fft(N)) return fail(GL_EINVAL, "MV initialisation needs N = 2^a 3^b");
     double *V[2] = {(double *)(ev->ws + ev->L.VA), (double *)(ev->ws + ev->L.VB)};
     double2 *planes = (double2 *)(ev->ws + ev->L.planes);
+    double2 *tab = (double2 *)(ev->ws + ev->L.fft_tab);
+    HIP_TRY(launch_fft_tables(ev->stream, N, tab));
     for (int nuc = 0; nuc < 2; nuc++) {
         HIP_TRY(launch_wilson_init(ev->stream, N, V[nuc]));
         for (int sh0 = 0; sh0 < n_sheets; sh0 += kSheetChunk) {
@@ -663,7 +666,7 @@ static gl_status wilson_lines(gl_event *ev, int n_sheets, double m_ir_GeV, doubl
             } else {
                 HIP_TRY(launch_mv_charges(ev->stream, N, sigma, seed, nuc, sh0, cnt, planes));
             }
-            HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes, cnt));
+            HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes, cnt, tab));
             HIP_TRY(launch_wilson_accum(ev->stream, N, planes, cnt, V[nuc]));
         }
     }

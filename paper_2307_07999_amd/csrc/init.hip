@@ -3,7 +3,7 @@
 //   1. Gaussian color charges rho^a per (nucleus, sheet, site) from Philox,
 //      packed two colors per complex plane (rho^{2j} + i rho^{2j+1}).
 //   2. Poisson solve (-Lap + m^2) Lambda = rho with the 5-point Laplacian,
-//      exact in Fourier space: 2-D FFT by LDS-resident mixed-radix (4, 2, 3)
+//      exact in Fourier space: 2-D FFT by LDS-resident mixed-radix (8, 4, 2, 3)
 //      Stockham line transforms, several adjacent lines per workgroup; the
 //      kernel multiplication sits between the forward and inverse column
 //      transforms of one pass.  The kernel is real and even, so the packed
@@ -75,15 +75,16 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// radix sequence of N: n4 radix-4 stages, then n2 (0 or 1) radix-2, then n3
-// radix-3 (N = 2^a 3^b)
+// radix sequence of N: n8 radix-8 stages, then n4 (0 or 1) radix-4, n2 (0
+// or 1) radix-2, then n3 radix-3 (N = 2^a 3^b)
 struct Radices {
-    int n4, n2, n3;
+    int n8, n4, n2, n3;
 };
 
 __host__ __device__ inline bool radices_of(int N, Radices &rs) {
-    rs.n4 = rs.n2 = rs.n3 = 0;
+    rs.n8 = rs.n4 = rs.n2 = rs.n3 = 0;
     int m = N;
+    while (m % 8 == 0) { rs.n8++; m /= 8; }
     while (m % 4 == 0) { rs.n4++; m /= 4; }
     while (m % 2 == 0) { rs.n2++; m /= 2; }
     while (m % 3 == 0) { rs.n3++; m /= 3; }
@@ -114,6 +115,25 @@ __device__ __forceinline__ void butterfly(const double2 *v, double2 *o, int sign
         o[2] = make_double2(a.x - c.x, a.y - c.y);
         o[1] = make_double2(b.x + di.x, b.y + di.y);
         o[3] = make_double2(b.x - di.x, b.y - di.y);
+    } else if constexpr (R == 8) {
+        // even and odd halves as radix-4 transforms, joined by
+        // t_k = exp(sign i pi k / 4): o[k] = E[k] + t_k O[k], o[k+4] = E[k] - t_k O[k]
+        const double h = 0.70710678118654752440;
+        const double2 ve[4] = {v[0], v[2], v[4], v[6]}, vo[4] = {v[1], v[3], v[5], v[7]};
+        double2 E[4], O[4];
+        butterfly<4>(ve, E, sign);
+        butterfly<4>(vo, O, sign);
+        const double2 t1 = make_double2(h * (O[1].x - sign * O[1].y), h * (O[1].y + sign * O[1].x));
+        const double2 t2 = make_double2(-sign * O[2].y, sign * O[2].x);
+        const double2 t3 = make_double2(-h * (O[3].x + sign * O[3].y), h * (sign * O[3].x - O[3].y));
+        o[0] = make_double2(E[0].x + O[0].x, E[0].y + O[0].y);
+        o[4] = make_double2(E[0].x - O[0].x, E[0].y - O[0].y);
+        o[1] = make_double2(E[1].x + t1.x, E[1].y + t1.y);
+        o[5] = make_double2(E[1].x - t1.x, E[1].y - t1.y);
+        o[2] = make_double2(E[2].x + t2.x, E[2].y + t2.y);
+        o[6] = make_double2(E[2].x - t2.x, E[2].y - t2.y);
+        o[3] = make_double2(E[3].x + t3.x, E[3].y + t3.y);
+        o[7] = make_double2(E[3].x - t3.x, E[3].y - t3.y);
     } else {   // R == 3
         const double c3 = -0.5, s3 = 0.86602540378443864676 * sign;
         double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
@@ -168,14 +188,28 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int N
 
 __device__ __forceinline__ void fft_stages(double2 *buf, const double2 *tw, int N, int C, int sign, Radices rs) {
     int Ns = 1;
+    for (int s = 0; s < rs.n8; s++, Ns *= 8) fft_stage<8>(buf, tw, N, C, Ns, sign);
     for (int s = 0; s < rs.n4; s++, Ns *= 4) fft_stage<4>(buf, tw, N, C, Ns, sign);
     for (int s = 0; s < rs.n2; s++, Ns *= 2) fft_stage<2>(buf, tw, N, C, Ns, sign);
     for (int s = 0; s < rs.n3; s++, Ns *= 3) fft_stage<3>(buf, tw, N, C, Ns, sign);
 }
 
+// Tables of one solve, filled once: tw[j] = exp(-2 pi i j / N) and
+// s2[j] = 4 sin^2(pi j / N), j < N.
+__global__ void __launch_bounds__(256)
+k_fft_tables(int N, double2 *__restrict__ tw, double *__restrict__ s2) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    double sn, cs;
+    sincospi(2.0 * (double)j / (double)N, &sn, &cs);
+    tw[j] = make_double2(cs, -sn);
+    const double h = sinpi((double)j / (double)N);
+    s2[j] = 4.0 * h * h;
+}
+
 // In-place transforms of the N x N planes: each workgroup transforms C
 // adjacent lines of one plane (rows if cols == 0, columns otherwise), with
-// the twiddles exp(-2 pi i j / N) tabulated once per workgroup in LDS.  Loads
+// the twiddles exp(-2 pi i j / N) copied from the solve's table into LDS.  Loads
 // and stores walk the C lines together, so a column workgroup reads C
 // consecutive values of each row.  sign = -1 forward, +1 inverse
 // (unnormalised).  POISSON (columns only, after the forward row pass): the
@@ -185,10 +219,11 @@ __device__ __forceinline__ void fft_stages(double2 *buf, const double2 *tw, int 
 template <bool POISSON>
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int groups_per_plane, int sign,
-            Radices rs, double m2, double uv2) {
-    __shared__ double2 buf[kFftElems];
-    __shared__ double2 tw[kFftMaxN];
-    __shared__ double s2[POISSON ? kFftMaxN : 1];
+            Radices rs, double m2, double uv2, const double2 *__restrict__ tw_tab, const double *__restrict__ s2_tab) {
+    // dynamic LDS sized for this N: the lines, then tw[N], then (POISSON) s2[N]
+    extern __shared__ double2 lds[];
+    double2 *buf = lds, *tw = lds + kFftElems;
+    double *s2 = (double *)(tw + N);
     // contiguous runs of groups per XCD: the C-wide column segments of
     // neighbouring groups share cache lines, which then meet in one L2
     const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -196,13 +231,8 @@ k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int grou
     double2 *base = data + (size_t)plane * plane_stride;
     const int l0 = g * C;
     for (int j = threadIdx.x; j < N; j += kFftThreads) {
-        double sn, cs;
-        sincospi(2.0 * (double)j / (double)N, &sn, &cs);
-        tw[j] = make_double2(cs, -sn);
-        if (POISSON) {
-            const double h = sinpi((double)j / (double)N);
-            s2[j] = 4.0 * h * h;
-        }
+        tw[j] = tw_tab[j];
+        if (POISSON) s2[j] = s2_tab[j];
     }
     for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
         const int line = cols ? i % C : i / N, k = cols ? i / C : i % N;
@@ -555,23 +585,33 @@ hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes
     return hipGetLastError();
 }
 
+hipError_t launch_fft_tables(hipStream_t st, int N, double2 *tab) {
+    if (N > kFftMaxN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fft_tables, dim3((N + 255) / 256), dim3(256), 0, st, N, tab, (double *)(tab + kFftMaxN));
+    return hipGetLastError();
+}
+
 // Poisson solve of n_sheets x 4 planes: forward row transforms, the fused
-// column pass (forward, kernel, inverse) and inverse row transforms
-hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets) {
+// column pass (forward, kernel, inverse) and inverse row transforms; tab
+// holds the tables of launch_fft_tables for this N
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets,
+                          const double2 *tab) {
     Radices rs;
     if (N > kFftMaxN || !radices_of(N, rs)) return hipErrorInvalidValue;
     const size_t n2 = (size_t)N * N;
     const int C = fft_lines_per_group(N), groups = N / C, n_planes = 4 * n_sheets;
-    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, 0, n2,
-                       groups, -1, rs, m2, uv2);
+    const double *s2 = (const double *)(tab + kFftMaxN);
+    const size_t lds_lines = (kFftElems + (size_t)N) * sizeof(double2), lds_poisson = lds_lines + N * sizeof(double);
+    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes, N, C,
+                       0, n2, groups, -1, rs, m2, uv2, tab, s2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fft_lines<true>, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, 1, n2,
-                       groups, -1, rs, m2, uv2);
+    hipLaunchKernelGGL(k_fft_lines<true>, dim3(n_planes * groups), dim3(kFftThreads), lds_poisson, st, planes, N,
+                       C, 1, n2, groups, -1, rs, m2, uv2, tab, s2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), 0, st, planes, N, C, 0, n2,
-                       groups, +1, rs, m2, uv2);
+    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes, N, C,
+                       0, n2, groups, +1, rs, m2, uv2, tab, s2);
     return hipGetLastError();
 }
 

@@ -114,8 +114,11 @@ hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed,
 hipError_t launch_charges_to_planes(hipStream_t st, int N, const double *rho /* [8][n2] */,
                                  double2 *planes);
 hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes, double *rho);
-hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2,
-                          double2 *planes /* [n_sheets][4][n2] in place */, int n_sheets);
+// the twiddle and sin^2 tables of one solve size into tab (kFftTableBytes)
+constexpr size_t kFftTableBytes = 1024 * (sizeof(double2) + sizeof(double));
+hipError_t launch_fft_tables(hipStream_t st, int N, double2 *tab);
+hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets,
+                          const double2 *tab);
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V);
 // dipole correlator D[0..rmax] of a Wilson line; partials [(rmax+1)][ceil(N^2/256)]
 hipError_t launch_dipole(hipStream_t st, int N, const double *V, int rmax, double *partials, double *D);
