@@ -430,32 +430,33 @@ gl_status finish_init(gl_event *ev) {
     return GL_OK;
 }
 
+// element of value k of site x in chunked planes: ((k / NV) n2 + x) NV + k mod NV
 template <typename T>
-void to_T(const double *src, std::vector<T> &dst, size_t n) {
-    dst.resize(n);
-    for (size_t i = 0; i < n; i++) dst[i] = (T)src[i];
+inline size_t chunk_index(size_t n2, int k, size_t x) {
+    const size_t NV = 16 / sizeof(T);
+    return ((size_t)k / NV * n2 + x) * NV + (size_t)k % NV;
 }
 
+// K host planes [K][n2] (FP64) into a device array in chunked planes
 template <typename T>
-gl_status copy_in(gl_event *ev, void *dev, const double *host, size_t n) {
-    if (sizeof(T) == 8) {
-        HIP_TRY(hipMemcpyAsync(dev, host, n * 8, hipMemcpyHostToDevice, ev->stream));
-        HIP_TRY(hipStreamSynchronize(ev->stream));
-    } else {
-        std::vector<T> tmp;
-        to_T(host, tmp, n);
-        HIP_TRY(hipMemcpyAsync(dev, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, ev->stream));
-        HIP_TRY(hipStreamSynchronize(ev->stream));
-    }
+gl_status copy_in(gl_event *ev, void *dev, const double *host, int K) {
+    const size_t n2 = ev->n2;
+    std::vector<T> tmp((size_t)K * n2);
+    for (int k = 0; k < K; k++)
+        for (size_t x = 0; x < n2; x++) tmp[chunk_index<T>(n2, k, x)] = (T)host[(size_t)k * n2 + x];
+    HIP_TRY(hipMemcpyAsync(dev, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
     return GL_OK;
 }
 
 template <typename T>
-gl_status copy_out(gl_event *ev, double *host, const void *dev, size_t n) {
-    std::vector<T> tmp(n);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), dev, n * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
+gl_status copy_out(gl_event *ev, double *host, const void *dev, int K) {
+    const size_t n2 = ev->n2;
+    std::vector<T> tmp((size_t)K * n2);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), dev, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
-    for (size_t i = 0; i < n; i++) host[i] = (double)tmp[i];
+    for (int k = 0; k < K; k++)
+        for (size_t x = 0; x < n2; x++) host[(size_t)k * n2 + x] = (double)tmp[chunk_index<T>(n2, k, x)];
     return GL_OK;
 }
 
@@ -466,9 +467,8 @@ gl_status get_site_fields_t(gl_event *ev, double *F) {
     std::vector<T> tmp((size_t)kSiteRec * n2);
     HIP_TRY(hipMemcpyAsync(tmp.data(), ev->ws + ev->L.F, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
-    // device records in chunked planes: value k of site x at ((k / NV) n2 + x) NV + k mod NV
-    const size_t NV = 16 / sizeof(T);
-    auto at = [&](int k, size_t x) { return (double)tmp[((size_t)k / NV * n2 + x) * NV + (size_t)k % NV]; };
+    // device records in chunked planes
+    auto at = [&](int k, size_t x) { return (double)tmp[chunk_index<T>(n2, k, x)]; };
     for (int k = 0; k < 48; k++)
         for (size_t x = 0; x < n2; x++) F[(size_t)k * n2 + x] = at(k, x);
     for (int k = 0; k < 16; k++)
@@ -480,20 +480,20 @@ template <typename T>
 gl_status set_state_t(gl_event *ev, const double *U, const double *E, const double *phi, const double *pi) {
     FieldPtrs<T> f = ev->fields<T>(ev->cur);
     gl_status s;
-    if ((s = copy_in<T>(ev, f.U, U, 36 * ev->n2))) return s;
-    if ((s = copy_in<T>(ev, f.E, E, 16 * ev->n2))) return s;
-    if ((s = copy_in<T>(ev, f.phi, phi, 8 * ev->n2))) return s;
-    return copy_in<T>(ev, f.pi, pi, 8 * ev->n2);
+    if ((s = copy_in<T>(ev, f.U, U, 36))) return s;
+    if ((s = copy_in<T>(ev, f.E, E, 16))) return s;
+    if ((s = copy_in<T>(ev, f.phi, phi, 8))) return s;
+    return copy_in<T>(ev, f.pi, pi, 8);
 }
 
 template <typename T>
 gl_status get_state_t(gl_event *ev, double *U, double *E, double *phi, double *pi) {
     FieldPtrs<T> f = ev->fields<T>(ev->cur);
     gl_status s;
-    if (U && (s = copy_out<T>(ev, U, f.U, 36 * ev->n2))) return s;
-    if (E && (s = copy_out<T>(ev, E, f.E, 16 * ev->n2))) return s;
-    if (phi && (s = copy_out<T>(ev, phi, f.phi, 8 * ev->n2))) return s;
-    if (pi && (s = copy_out<T>(ev, pi, f.pi, 8 * ev->n2))) return s;
+    if (U && (s = copy_out<T>(ev, U, f.U, 36))) return s;
+    if (E && (s = copy_out<T>(ev, E, f.E, 16))) return s;
+    if (phi && (s = copy_out<T>(ev, phi, f.phi, 8))) return s;
+    if (pi && (s = copy_out<T>(ev, pi, f.pi, 8))) return s;
     return GL_OK;
 }
 

@@ -129,7 +129,7 @@ k_lightlike_accum(int N, const T *__restrict__ F, const T *__restrict__ U, doubl
         }
         v[3] = 1.0;
         if ((int64_t)floor((double)(j + 1) * dtau + 0.5) > shift) {
-            const M3<T> u = load_m(U, n2, c);
+            const M3<T> u = chunk_load_m(U, n2, c, 0);
             M3<double> ud;
 #pragma unroll
             for (int r = 0; r < 3; r++)
@@ -169,16 +169,15 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
     if (ix < N && iy < N) {
         const size_t n2 = (size_t)N * N;
         Nbr nb = neighbours(ix, iy, N);
-        const T *U1 = f.U, *U2 = f.U + 18 * n2;
-        M3<T> u1x = load_m(U1, n2, nb.x), u2x = load_m(U2, n2, nb.x);
+        M3<T> u1x = chunk_load_m(f.U, n2, nb.x, 0), u2x = chunk_load_m(f.U, n2, nb.x, 18);
         T e1[8], e2[8], e1m[8], e2m[8], ph[8], p[8];
-        load_a(f.E, n2, nb.x, e1);
-        load_a(f.E + 8 * n2, n2, nb.x, e2);
-        load_a(f.E, n2, nb.xm1, e1m);
-        load_a(f.E + 8 * n2, n2, nb.xm2, e2m);
-        load_a(f.phi, n2, nb.x, ph);
-        load_a(f.pi, n2, nb.x, p);
-        M3<T> u1m = load_m(U1, n2, nb.xm1), u2m = load_m(U2, n2, nb.xm2);
+        chunk_load_a(f.E, n2, nb.x, 0, e1);
+        chunk_load_a(f.E, n2, nb.x, 8, e2);
+        chunk_load_a(f.E, n2, nb.xm1, 0, e1m);
+        chunk_load_a(f.E, n2, nb.xm2, 8, e2m);
+        chunk_load_a(f.phi, n2, nb.x, 0, ph);
+        chunk_load_a(f.pi, n2, nb.x, 0, p);
+        M3<T> u1m = chunk_load_m(f.U, n2, nb.xm1, 0), u2m = chunk_load_m(f.U, n2, nb.xm2, 18);
         T t1[8], t2[8];
         transport_dn(u1m, herm_from_alg(e1m), t1);
         transport_dn(u2m, herm_from_alg(e2m), t2);
@@ -224,7 +223,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
 #pragma unroll
         for (int d = 0; d < 2; d++) {
             T v2[8];
-            load_a(f.phi, n2, xps[d], v2);
+            chunk_load_a(f.phi, n2, xps[d], 0, v2);
             M3<T> Pf = mul_nd(mul(ups[d], herm_from_alg(v2)), ups[d]);
             T df[8];
             alg_from_herm(Pf, df);
@@ -234,7 +233,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
                 bt += 0.5 * dd * dd;
             }
         }
-        M3<T> P = plaq(u1x, load_m(U2, n2, nb.xp1), load_m(U1, n2, nb.xp2), u2x);
+        M3<T> P = plaq(u1x, chunk_load_m(f.U, n2, nb.xp1, 18), chunk_load_m(f.U, n2, nb.xp2, 0), u2x);
         double bl = 3.0 - ((double)P.re[0][0] + (double)P.re[1][1] + (double)P.re[2][2]);
         v[0] = gmax;
         v[1] = emax;

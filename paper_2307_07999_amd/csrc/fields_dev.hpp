@@ -11,9 +11,7 @@ namespace gl {
 // values slot..slot+7 of the site-field record of site x
 template <typename T>
 __device__ __forceinline__ void store_rec(T *__restrict__ F, size_t n2, size_t x, int slot, const T *v) {
-    constexpr int NV = 16 / sizeof(T);
-#pragma unroll
-    for (int a = 0; a < 8; a += NV) chunk_st16(F, n2, x, slot + a, v + a);
+    chunk_store_n_l<8>(F, n2, x, slot, v);
 }
 
 struct Nbr {
@@ -81,7 +79,7 @@ __device__ __forceinline__ void store_half(T *__restrict__ F, size_t n2, size_t 
 #pragma unroll
     for (int k = 0; k < 4; k++) w[k] = h ? v[4 + k] : v[k];
 #pragma unroll
-    for (int k = 0; k < 4; k += NV) chunk_st16(F, n2, x, slot + 4 * h + k, w + k);
+    for (int k = 0; k < 4; k += NV) chunk_st16_l(F, n2, x, slot + 4 * h + k, w + k);
 }
 
 // Link and scalar planes of a block of SX x SY sites and a one-site halo,
@@ -123,33 +121,52 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
         gx += gx < 0 ? N : 0;
         gy += gy < 0 ? N : 0;
         const size_t site = (size_t)gx + (size_t)N * gy;
-#pragma unroll 6
-        for (int p = 0; p < 36; p++) t.v[p * Tl::RP + r] = pl_ld(in.U, n2, p, site);
+        constexpr int NV = 16 / (int)sizeof(T);
+#pragma unroll 3
+        for (int c = 0; c < 36; c += NV) {
+            T v[NV];
+            chunk_ld16(in.U, n2, site, c, v);
 #pragma unroll
-        for (int a = 0; a < 8; a++) t.v[(36 + a) * Tl::RP + r] = pl_ld(in.phi, n2, a, site);
+            for (int k = 0; k < NV; k++) t.v[(c + k) * Tl::RP + r] = v[k];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; c += NV) {
+            T v[NV];
+            chunk_ld16(in.phi, n2, site, c, v);
+#pragma unroll
+            for (int k = 0; k < NV; k++) t.v[(36 + c + k) * Tl::RP + r] = v[k];
+        }
     }
 }
 
-// E_i^{n+1/2}(x) and U_i^{n+1}(x) from the force fe and U_i(x) = u; with F,
-// also this site's half of the electric site field (record of site x, slot
-// fs) and the transported half of x+i (record of site xt, slot 48 + fs)
-// (offsets: xe = x in the E_i planes, xu = x in the U_i planes)
+// E_i^{n+1/2}(x) and U_i^{n+1}(x), i = d + 1, from the force fe and U_i(x) =
+// u; with F, also this site's half of the electric site field (record of
+// site x, slot 8d) and the transported half of x+i (record of site xt, slot
+// 48 + 8d)
 template <typename T>
 __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const M3<T> &u,
-                                            T *__restrict__ Uout, size_t n2, size_t xe, size_t xu, size_t x,
-                                            size_t xt, int fs, const T *fe, T dtau, T s, int reunit,
-                                            T *__restrict__ F, T inv_tau) {
+                                            T *__restrict__ Uout, size_t n2, size_t x, size_t xt, int d,
+                                            const T *fe, T dtau, T s, int reunit, T *__restrict__ F, T inv_tau) {
+    const int fs = 8 * d;
     T e[8], eb[8];
-    load_a(Ein, n2, xe, e);
+    chunk_load_n_l<8>(Ein, n2, x, 8 * d, e);
 #pragma unroll
     for (int a = 0; a < 8; a++) {
         eb[a] = e[a];
         e[a] += dtau * fe[a];
     }
-    store_a(Eout, n2, xe, e);
+    chunk_store_n_l<8>(Eout, n2, x, 8 * d, e);
     M3<T> un = mul(expi_alg(e, s), u);
     if (reunit) un = reunitarize(un);
-    store_m(Uout, n2, xu, un);
+    T uv[18];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            uv[2 * (3 * i + j)] = un.re[i][j];
+            uv[2 * (3 * i + j) + 1] = un.im[i][j];
+        }
+    chunk_store_link_l(Uout, n2, x, d, uv);
     if (F) {
         T t[8];
 #pragma unroll
@@ -203,7 +220,6 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
     const size_t x = (size_t)ix + (size_t)N * iy;
     const int ixp = ix + 1 == N ? 0 : ix + 1, iyp = iy + 1 == N ? 0 : iy + 1;
     const size_t xpi = d0 ? (size_t)ixp + (size_t)N * iy : (size_t)ix + (size_t)N * iyp;
-    const size_t oi = (size_t)(18 * d) * n2, oe = (size_t)(8 * d) * n2;
     const T inv_tau = T(1) / tau;
     const T sgn = d0 ? T(1) : T(-1);
 
@@ -267,24 +283,19 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
         // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
         if (F) store_rec(F, n2, x, 32 - 8 * d, pf);
     }
-    update_link(in.E, out.E, ui, out.U, n2, x + oe, x + oi, x, xpi, 8 * d, fe, dtau, dtau / tau_h, reunit, F,
-                inv_tau);
+    update_link(in.E, out.E, ui, out.U, n2, x, xpi, d, fe, dtau, dtau / tau_h, reunit, F, inv_tau);
     // pi, phi and E_z: lane d takes colour components 4d..4d+3
-    const size_t xo = x + (size_t)(4 * d) * n2;
-    T ez[4];
+    T pv[4], pn[4], phn[4], ez[4];
+    chunk_load_n_l<4>(in.pi, n2, x, 4 * d, pv);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const T p = pl_ld(in.pi, n2, k, xo);
-        const T pn = p + dtau * (d0 ? fpi[k] : fpi[4 + k]);
-        pl_st(out.pi, n2, k, xo, pn);
-        pl_st(out.phi, n2, k, xo, (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn);
-        ez[k] = T(0.5) * (p + pn);
+        pn[k] = pv[k] + dtau * (d0 ? fpi[k] : fpi[4 + k]);
+        phn[k] = (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn[k];
+        ez[k] = T(0.5) * (pv[k] + pn[k]);
     }
-    if (F) {
-        constexpr int NV = 16 / sizeof(T);
-#pragma unroll
-        for (int k = 0; k < 4; k += NV) chunk_st16(F, n2, x, 16 + 4 * d + k, ez + k);
-    }
+    chunk_store_n_l<4>(out.pi, n2, x, 4 * d, pn);
+    chunk_store_n_l<4>(out.phi, n2, x, 4 * d, phn);
+    if (F) chunk_store_n_l<4>(F, n2, x, 16 + 4 * d, ez);
 }
 
 }  // namespace gl

@@ -555,13 +555,14 @@ k_first_half_step(int N, const double *U0, const double *pi0, FieldPtrs<T> out, 
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
-    for (int c = 0; c < 36; c++) out.U[(size_t)c * n2 + x] = (T)U0[(size_t)c * n2 + x];
-    for (int c = 0; c < 16; c++) out.E[(size_t)c * n2 + x] = T(0);
+    // the field state is stored in chunked planes
+    for (int c = 0; c < 36; c++) chunk_st(out.U, n2, x, c, (T)U0[(size_t)c * n2 + x]);
+    for (int c = 0; c < 16; c++) chunk_st(out.E, n2, x, c, T(0));
     const double th = 0.5 * dtau;
     for (int a = 0; a < 8; a++) {
         double p = pi0[(size_t)a * n2 + x];
-        out.pi[(size_t)a * n2 + x] = (T)p;
-        out.phi[(size_t)a * n2 + x] = (T)(dtau * th * p);
+        chunk_st(out.pi, n2, x, a, (T)p);
+        chunk_st(out.phi, n2, x, a, (T)(dtau * th * p));
     }
 }
 

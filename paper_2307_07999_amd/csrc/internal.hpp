@@ -30,8 +30,11 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
     return x * q + (x < r ? x : r) + j;
 }
 
-// One field state in structure-of-arrays planes of n2 = N*N values:
-//   U   [2][18][n2], E [2][8][n2], phi [8][n2], pi [8][n2]
+// One field state, each array in chunked planes over the n2 = N*N sites
+// (16-byte chunks of consecutive values; value k of site x at element
+// ((k / NV) n2 + x) NV + k mod NV, NV = 16 / sizeof(T)):
+//   U: 36 values per site, link U_i at 18 (i - 1) (entry (a,b) real at
+//   + 2(3a+b), imaginary next to it); E: 16, E_i at 8 (i - 1); phi: 8; pi: 8
 template <typename T>
 struct FieldPtrs {
     T *U;

@@ -51,8 +51,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
             e[k] = se;
             b[k] = sb;
         }
-#pragma unroll
-        for (int a = 0; a < 8; a++) ph[a] = pl_ld(f.phi, n2, a, x);
+        chunk_load_a(f.phi, n2, x, 0, ph);
         // Boris kick at tau_n
         pl[2] /= tau;
         T pm[3];
@@ -86,8 +85,8 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const int cx1 = sx > 0 ? (cx + 1 == N ? 0 : cx + 1) : (sx < 0 ? cxm : cx);
         const int cy1 = sy > 0 ? (cy + 1 == N ? 0 : cy + 1) : (sy < 0 ? cym : cy);
         M3<T> ux, uy;
-        if (sx != 0) ux = load_m(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy);
-        if (sy != 0) uy = load_m(f.U + 18 * n2, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym));
+        if (sx != 0) ux = chunk_load_m(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy, 0);
+        if (sy != 0) uy = chunk_load_m(f.U, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym), 18);
         // colour rotation along eta with phi^n at the old cell: Q <- W Q W^dag
         transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
         // crossings: Q <- U^dag Q U forward, U Q U^dag backward
