@@ -82,30 +82,57 @@ __device__ __forceinline__ void store_half(T *__restrict__ F, size_t n2, size_t 
     for (int k = 0; k < 4; k += NV) chunk_st16_l(F, n2, x, slot + 4 * h + k, w + k);
 }
 
-// Link and scalar planes of a block of SX x SY sites and a one-site halo,
-// staged in LDS: planes 0..17 hold U_1, 18..35 U_2, 36..43 phi; region site
-// (rx, ry) is the lattice site (x0 - 1 + rx, y0 - 1 + ry) mod N.  The plane
-// stride RP is padded to 8 mod 16 words, so the two lanes of a site reading
-// U_1 and U_2 (18 planes apart) hit different LDS banks.
+// Links and phi of a block of SX x SY sites and a one-site halo, staged in
+// LDS; region site (rx, ry) is the lattice site (x0 - 1 + rx, y0 - 1 + ry)
+// mod N.  Chunk-major like the field state: the values of a site are held
+// in 16-byte chunks (NV = 16 / sizeof(T) values), chunk c of all region
+// sites contiguous, so a lane reads a link with 16-byte LDS accesses.  Per
+// site: U_1 in chunks [0, LC), U_2 in [LC, 2 LC), phi in the next 8 / NV
+// chunks; a link is its 18 values (entry (i,j) real at 2(3i+j), imaginary
+// next to it), padded in FP32 to 5 whole chunks.
 template <typename T, int SX, int SY>
 struct LinkTile {
+    static constexpr int NV = 16 / (int)sizeof(T);
+    static constexpr int LC = (18 + NV - 1) / NV;      // chunks per link
+    static constexpr int NC = 2 * LC + 8 / NV;         // chunks per site
     static constexpr int RX = SX + 2, RY = SY + 2, R = RX * RY;
-    static constexpr int RP = R + (24 - R % 16) % 16;
-    T v[44 * RP];
-    __device__ __forceinline__ M3<T> m(int p0, int r) const {
+    struct alignas(16) Chunk {
+        T v[NV];
+    };
+    Chunk c[NC * R];
+    // link d (0: U_1, 1: U_2) of region site r
+    __device__ __forceinline__ M3<T> m(int d, int r) const {
+        T v[LC * NV];
+        const Chunk *p = c + (size_t)(LC * d) * R + r;
+#pragma unroll
+        for (int j = 0; j < 18 / NV; j++) {
+            const Chunk w = p[j * R];
+#pragma unroll
+            for (int k = 0; k < NV; k++) v[j * NV + k] = w.v[k];
+        }
+        if constexpr (18 % NV != 0) {   // FP32: values 16 and 17 in the first half of the fifth chunk
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            const T2 h = *reinterpret_cast<const T2 *>(&p[(18 / NV) * R]);
+            v[16] = h.x;
+            v[17] = h.y;
+        }
         M3<T> u;
 #pragma unroll
         for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int j = 0; j < 3; j++) {
-                u.re[i][j] = v[(p0 + 2 * (3 * i + j)) * RP + r];
-                u.im[i][j] = v[(p0 + 2 * (3 * i + j) + 1) * RP + r];
+                u.re[i][j] = v[2 * (3 * i + j)];
+                u.im[i][j] = v[2 * (3 * i + j) + 1];
             }
         return u;
     }
     __device__ __forceinline__ void phi(int r, T *out) const {
 #pragma unroll
-        for (int a = 0; a < 8; a++) out[a] = v[(36 + a) * RP + r];
+        for (int j = 0; j < 8 / NV; j++) {
+            const Chunk w = c[(size_t)(2 * LC + j) * R + r];
+#pragma unroll
+            for (int k = 0; k < NV; k++) out[j * NV + k] = w.v[k];
+        }
     }
 };
 
@@ -115,26 +142,38 @@ template <typename T, int SX, int SY>
 __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const FieldPtrs<T> &in, int x0, int y0,
                                            int tid, int nthreads) {
     using Tl = LinkTile<T, SX, SY>;
+    using Chunk = typename Tl::Chunk;
+    constexpr int NV = Tl::NV, LC = Tl::LC, R = Tl::R;
     const size_t n2 = plane_pitch(N);
-    for (int r = tid; r < Tl::R; r += nthreads) {
+    for (int r = tid; r < R; r += nthreads) {
         int gx = (x0 - 1 + r % Tl::RX) % N, gy = (y0 - 1 + r / Tl::RX) % N;
         gx += gx < 0 ? N : 0;
         gy += gy < 0 ? N : 0;
         const size_t site = (size_t)gx + (size_t)N * gy;
-        constexpr int NV = 16 / (int)sizeof(T);
-#pragma unroll 3
-        for (int c = 0; c < 36; c += NV) {
-            T v[NV];
-            chunk_ld16(in.U, n2, site, c, v);
+        // the 36 link values and 8 phi values of the site, in 16-byte loads
+        T u[36], ph[8];
 #pragma unroll
-            for (int k = 0; k < NV; k++) t.v[(c + k) * Tl::RP + r] = v[k];
-        }
+        for (int k = 0; k < 36; k += NV) chunk_ld16(in.U, n2, site, k, u + k);
 #pragma unroll
-        for (int c = 0; c < 8; c += NV) {
-            T v[NV];
-            chunk_ld16(in.phi, n2, site, c, v);
+        for (int k = 0; k < 8; k += NV) chunk_ld16(in.phi, n2, site, k, ph + k);
 #pragma unroll
-            for (int k = 0; k < NV; k++) t.v[(36 + c + k) * Tl::RP + r] = v[k];
+        for (int d = 0; d < 2; d++)
+#pragma unroll
+            for (int j = 0; j < LC; j++) {
+                Chunk w;
+#pragma unroll
+                for (int k = 0; k < NV; k++) {
+                    const int i = j * NV + k;   // value of the link; FP32 pads 18, 19
+                    w.v[k] = i < 18 ? u[18 * d + i] : T(0);
+                }
+                t.c[(size_t)(LC * d + j) * R + r] = w;
+            }
+#pragma unroll
+        for (int j = 0; j < 8 / NV; j++) {
+            Chunk w;
+#pragma unroll
+            for (int k = 0; k < NV; k++) w.v[k] = ph[j * NV + k];
+            t.c[(size_t)(2 * LC + j) * R + r] = w;
         }
     }
 }
@@ -215,7 +254,7 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
     const int ry = rx - dj;                          // y = x - j
     const int ry1 = d0 ? ry + 1 : rx, ry2 = d0 ? rx : ry + RX;   // y + 1, y + 2
     const int rz = rx - 1 - RX, rzi = rz + di;       // z = x - 1 - 2, z + i
-    const int pi_ = 18 * d, pj = 18 - 18 * d;        // first plane of U_i, U_j
+    const int li = d, lj = 1 - d;                    // tile links of U_i, U_j
     // lattice indices for the global reads and writes
     const size_t x = (size_t)ix + (size_t)N * iy;
     const int ixp = ix + 1 == N ? 0 : ix + 1, iyp = iy + 1 == N ? 0 : iy + 1;
@@ -223,7 +262,7 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
     const T inv_tau = T(1) / tau;
     const T sgn = d0 ? T(1) : T(-1);
 
-    const M3<T> ui = tl.m(pi_, rx);   // U_i(x)
+    const M3<T> ui = tl.m(li, rx);   // U_i(x)
     T fe[8], cl[8];
     {
         // [P(x)]_X, P(x) = h0 h1^dag with the half products h0 = U_1(x) U_2(x+1)
@@ -231,14 +270,14 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
         // P(x)^dag, whose projection is -[P(x)]_X
         T px[8];
         {
-            const M3<T> h = mul(ui, tl.m(pj, rpi));
+            const M3<T> h = mul(ui, tl.m(lj, rpi));
             alg_proj(mul_nd(h, pair_swap(h)), px);
 #pragma unroll
             for (int a = 0; a < 8; a++) px[a] *= sgn;
         }
         // staple: U_j^dag(y) [P(y)]_X U_j(y)
-        const M3<T> uj = tl.m(pj, ry);
-        const M3<T> P = plaq(tl.m(0, ry), tl.m(18, ry1), tl.m(0, ry2), tl.m(18, ry));
+        const M3<T> uj = tl.m(lj, ry);
+        const M3<T> P = plaq(tl.m(0, ry), tl.m(1, ry1), tl.m(0, ry2), tl.m(1, ry));
         T pa[8], t[8];
         alg_proj(P, pa);
         transport_dn(uj, herm_from_alg(pa), t);
@@ -252,7 +291,7 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
         // fourth clover plaquette P(z) = [U_1(z) U_2(z+1)] [U_2(z) U_1(z+2)]^dag,
         // moved to x along z -> z+1 -> x, i.e. by C = U_1(z) U_2(z+1) (the
         // half product of lane 0; lane 1 projects P(z)^dag as above)
-        const M3<T> h = mul(tl.m(pi_, rz), tl.m(pj, rzi));
+        const M3<T> h = mul(tl.m(li, rz), tl.m(lj, rzi));
         const M3<T> o = pair_swap(h);
         T pa[8], t[8];
         alg_proj(mul_nd(h, o), pa);
@@ -272,7 +311,7 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
         transport_nd(ui, herm_from_alg(v), pf);   // Phi_{+i}
         alg_comm(ph, pf, c);                      // -i[phi, Phi_{+i}]
         tl.phi(rmi, v);
-        transport_dn(tl.m(pi_, rmi), herm_from_alg(v), pb);   // Phi_{-i}
+        transport_dn(tl.m(li, rmi), herm_from_alg(v), pb);   // Phi_{-i}
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             fe[a] = fma(inv_tau, c[a], fe[a]);
