@@ -80,7 +80,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     };
     for (int b = 0; b < 2; b++) L.field[b] = take(68 * n2 * ts);
     L.F = take((size_t)kSiteRec * n2 * ts);
-    for (int b = 0; b < 2; b++) L.part[b] = take((size_t)L.slots * (17 * ts + 12));
+    for (int b = 0; b < 2; b++) L.part[b] = take((size_t)L.slots * ((kPartRec + 3) * ts + 12));
     for (int b = 0; b < 2; b++) L.id[b] = take((size_t)L.slots * sizeof(int32_t));
     for (int b = 0; b < 2; b++) L.sort_keys[b] = take((size_t)L.slots * sizeof(uint32_t));
     for (int b = 0; b < 2; b++) L.sort_vals[b] = take((size_t)L.slots * sizeof(int32_t));
@@ -170,17 +170,11 @@ struct gl_event {
         p.cx = (int32_t *)b;
         p.cy = p.cx + c;
         p.species = p.cy + c;
-        T *t = (T *)(b + 12 * c);
-        p.ox = t;
-        p.oy = t + c;
-        p.eta = t + 2 * c;
-        p.px = t + 3 * c;
-        p.py = t + 4 * c;
-        p.peta = t + 5 * c;
-        p.px0 = t + 6 * c;
-        p.py0 = t + 7 * c;
-        p.pz0 = t + 8 * c;
-        p.Q = t + 9 * c;
+        T *t = (T *)(b + 12 * c);   // 16-byte aligned: c is a multiple of kPushBlock
+        p.st = t;
+        p.px0 = t + kPartRec * c;
+        p.py0 = p.px0 + c;
+        p.pz0 = p.py0 + c;
         p.cap = c;
         return p;
     }
@@ -502,29 +496,32 @@ gl_status set_particles_t(gl_event *ev, int64_t n, const int32_t *cell, const do
                           const double *p, const double *Q, const double *p0, const int32_t *species) {
     const int64_t c = ev->L.slots;
     std::vector<int32_t> cx(c, 0), cy(c, 0), sp(c, -1), id(c, -1);
-    std::vector<T> f(17 * (size_t)c, T(0));
+    // the record planes followed by px0, py0, pz0 (contiguous on the device)
+    std::vector<T> f((kPartRec + 3) * (size_t)c, T(0));
+    auto rec = [&](int k, int64_t i) -> T & { return f[chunk_index<T>((size_t)c, k, (size_t)i)]; };
+    T *f0 = f.data() + kPartRec * (size_t)c;
     for (int64_t i = 0; i < n; i++) {
         id[i] = (int32_t)i;
         cx[i] = cell[i];
         cy[i] = cell[n + i];
         sp[i] = species[i];
-        f[0 * c + i] = (T)off[i];
-        f[1 * c + i] = (T)off[n + i];
-        f[2 * c + i] = (T)eta[i];
-        f[3 * c + i] = (T)p[i];
-        f[4 * c + i] = (T)p[n + i];
-        f[5 * c + i] = (T)p[2 * n + i];
-        f[6 * c + i] = (T)p0[i];
-        f[7 * c + i] = (T)p0[n + i];
-        f[8 * c + i] = (T)p0[2 * n + i];
-        for (int a = 0; a < 8; a++) f[(9 + a) * c + i] = (T)Q[a * n + i];
+        rec(kOx, i) = (T)off[i];
+        rec(kOy, i) = (T)off[n + i];
+        rec(kEta, i) = (T)eta[i];
+        rec(kPx, i) = (T)p[i];
+        rec(kPy, i) = (T)p[n + i];
+        rec(kPeta, i) = (T)p[2 * n + i];
+        for (int a = 0; a < 8; a++) rec(kQ + a, i) = (T)Q[a * n + i];
+        f0[0 * c + i] = (T)p0[i];
+        f0[1 * c + i] = (T)p0[n + i];
+        f0[2 * c + i] = (T)p0[2 * n + i];
     }
     PartPtrs<T> P = ev->parts<T>();
     HIP_TRY(hipMemcpyAsync(ev->ids(), id.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipMemcpyAsync(P.cx, cx.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipMemcpyAsync(P.cy, cy.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipMemcpyAsync(P.species, sp.data(), c * 4, hipMemcpyHostToDevice, ev->stream));
-    HIP_TRY(hipMemcpyAsync(P.ox, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice, ev->stream));
+    HIP_TRY(hipMemcpyAsync(P.st, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice, ev->stream));
     HIP_TRY(hipStreamSynchronize(ev->stream));
     return GL_OK;
 }
@@ -534,14 +531,16 @@ gl_status get_particles_t(gl_event *ev, int64_t n, int32_t *cell, double *off, d
                           double *Q, double *p0, int32_t *species) {
     const int64_t c = ev->L.slots;
     std::vector<int32_t> cx(c), cy(c), sp(c), id(c);
-    std::vector<T> f(17 * (size_t)c);
+    std::vector<T> f((kPartRec + 3) * (size_t)c);
+    auto rec = [&](int k, int64_t j) { return (double)f[chunk_index<T>((size_t)c, k, (size_t)j)]; };
+    const T *f0 = f.data() + kPartRec * (size_t)c;
     PartPtrs<T> P = ev->parts<T>();
     if (c > 0) {
         HIP_TRY(hipMemcpyAsync(id.data(), ev->ids(), c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(cx.data(), P.cx, c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(cy.data(), P.cy, c * 4, hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipMemcpyAsync(sp.data(), P.species, c * 4, hipMemcpyDeviceToHost, ev->stream));
-        HIP_TRY(hipMemcpyAsync(f.data(), P.ox, f.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
+        HIP_TRY(hipMemcpyAsync(f.data(), P.st, f.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipStreamSynchronize(ev->stream));
     }
     for (int64_t j = 0; j < ev->slots_used; j++) {
@@ -551,12 +550,12 @@ gl_status get_particles_t(gl_event *ev, int64_t n, int32_t *cell, double *off, d
             if (i >= n) return fail(GL_EDEVICE, "corrupt particle id");
             if (cell) { cell[i] = cx[j]; cell[n + i] = cy[j]; }
             if (species) species[i] = sp[j];
-            if (off) { off[i] = f[0 * c + j]; off[n + i] = f[1 * c + j]; }
-            if (eta) eta[i] = f[2 * c + j];
-            if (p) { p[i] = f[3 * c + j]; p[n + i] = f[4 * c + j]; p[2 * n + i] = f[5 * c + j]; }
-            if (p0) { p0[i] = f[6 * c + j]; p0[n + i] = f[7 * c + j]; p0[2 * n + i] = f[8 * c + j]; }
+            if (off) { off[i] = rec(kOx, j); off[n + i] = rec(kOy, j); }
+            if (eta) eta[i] = rec(kEta, j);
+            if (p) { p[i] = rec(kPx, j); p[n + i] = rec(kPy, j); p[2 * n + i] = rec(kPeta, j); }
+            if (p0) { p0[i] = f0[0 * c + j]; p0[n + i] = f0[1 * c + j]; p0[2 * n + i] = f0[2 * c + j]; }
             if (Q)
-                for (int a = 0; a < 8; a++) Q[a * n + i] = f[(9 + a) * c + j];
+                for (int a = 0; a < 8; a++) Q[a * n + i] = rec(kQ + a, j);
         }
     }
     return GL_OK;

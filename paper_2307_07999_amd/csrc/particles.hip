@@ -89,9 +89,11 @@ k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, 
     int cx = (int)fx, cy = (int)fy;
     P.cx[j] = cx >= N ? cx - N : cx;
     P.cy[j] = cy >= N ? cy - N : cy;
-    P.ox[j] = (T)(X - fx);
-    P.oy[j] = (T)(Y - fy);
-    P.eta[j] = T(0);
+    T r[kPartRec];
+#pragma unroll
+    for (int k = 0; k < kPartRec; k++) r[k] = T(0);
+    r[kOx] = (T)(X - fx);
+    r[kOy] = (T)(Y - fy);
     w = draw(seed, (uint32_t)i, 1u, stream);
     double az = 6.283185307179586476925286766559 * uniform53(w.v[0], w.v[1]);
     double px, py;
@@ -104,7 +106,8 @@ k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, 
         px = p0;
         py = 0.0;
     }
-    P.px[j] = (T)px; P.py[j] = (T)py; P.peta[j] = T(0);
+    r[kPx] = (T)px;
+    r[kPy] = (T)py;
     P.px0[j] = (T)px; P.py0[j] = (T)py; P.pz0[j] = T(0);
     P.species[j] = species;
     // Gaussian complex matrix, columns orthonormalised in order
@@ -164,7 +167,9 @@ k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, 
     double q[8];
     alg_from_herm(Qm, q);
 #pragma unroll
-    for (int a = 0; a < 8; a++) P.Q[(size_t)a * P.cap + j] = (T)q[a];
+    for (int a = 0; a < 8; a++) r[kQ + a] = (T)q[a];
+#pragma unroll
+    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(P.st, (size_t)P.cap, (size_t)j, k, r + k);
 }
 
 // Per-species partial sums of the squared momenta at formation (p_x0^2,
@@ -209,7 +214,7 @@ k_casimir(PartPtrs<T> P, int64_t n_slots, double *partials) {
         double q2 = 0.0;
 #pragma unroll
         for (int a = 0; a < 8; a++) {
-            double q = P.Q[(size_t)a * P.cap + i];
+            double q = chunk_ld(P.st, (size_t)P.cap, (size_t)i, kQ + a);
             q2 += q * q;
         }
         v = fabs(q2 - 4.0);

@@ -23,12 +23,16 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
     const int s = el_ld(P.species, i);
     int cx = el_ld(P.cx, i), cy = el_ld(P.cy, i);
+    // the state record in 16-byte loads
+    T r[kPartRec];
+#pragma unroll
+    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_ld16(P.st, (size_t)P.cap, (size_t)i, k, r + k);
     T q[8];
 #pragma unroll
-    for (int a = 0; a < 8; a++) q[a] = pl_ld(P.Q, P.cap, a, i);
-    T pl[3] = {el_ld(P.px, i), el_ld(P.py, i), el_ld(P.peta, i)};
-    T ox = el_ld(P.ox, i), oy = el_ld(P.oy, i);
-    const T eta_old = el_ld(P.eta, i);
+    for (int a = 0; a < 8; a++) q[a] = r[kQ + a];
+    T pl[3] = {r[kPx], r[kPy], r[kPeta]};
+    T ox = r[kOx], oy = r[kOy];
+    const T eta_old = r[kEta];
     const bool active = s >= 0 && n >= tab.nform[s];
     if (active) {
         const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
@@ -98,14 +102,16 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         oy -= (T)sy;
         el_st(P.cx, i, cx1);
         el_st(P.cy, i, cy1);
-        el_st(P.ox, i, ox);
-        el_st(P.oy, i, oy);
-        el_st(P.eta, i, eta_new);
-        el_st(P.px, i, pl[0]);
-        el_st(P.py, i, pl[1]);
-        el_st(P.peta, i, peta);
+        r[kOx] = ox;
+        r[kOy] = oy;
+        r[kEta] = eta_new;
+        r[kPx] = pl[0];
+        r[kPy] = pl[1];
+        r[kPeta] = peta;
 #pragma unroll
-        for (int a = 0; a < 8; a++) pl_st(P.Q, P.cap, a, i, q[a]);
+        for (int a = 0; a < 8; a++) r[kQ + a] = q[a];
+#pragma unroll
+        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(P.st, (size_t)P.cap, (size_t)i, k, r + k);
         // broadening at tau_{n+1/2}, accumulated in FP64
         const double etab = 0.5 * ((double)eta_old + (double)eta_new);
         // sinh and cosh from one expm1 (exact-to-rounding for small rapidities)

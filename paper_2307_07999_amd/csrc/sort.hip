@@ -6,6 +6,7 @@
 // workgroups, and a stable scatter whose in-workgroup ranks come from wave64
 // ballots.
 #include "internal.hpp"
+#include "su3.hpp"
 
 namespace gl {
 
@@ -136,17 +137,15 @@ k_permute(PartPtrs<T> src, PartPtrs<T> dst, const int32_t *__restrict__ perm, in
     dst.cx[j] = src.cx[i];
     dst.cy[j] = src.cy[i];
     dst.species[j] = src.species[i];
-    dst.ox[j] = src.ox[i];
-    dst.oy[j] = src.oy[i];
-    dst.eta[j] = src.eta[i];
-    dst.px[j] = src.px[i];
-    dst.py[j] = src.py[i];
-    dst.peta[j] = src.peta[i];
+#pragma unroll
+    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) {
+        T v[16 / sizeof(T)];
+        chunk_ld16(src.st, (size_t)src.cap, (size_t)i, k, v);
+        chunk_st16(dst.st, (size_t)dst.cap, (size_t)j, k, v);
+    }
     dst.px0[j] = src.px0[i];
     dst.py0[j] = src.py0[i];
     dst.pz0[j] = src.pz0[i];
-#pragma unroll
-    for (int a = 0; a < 8; a++) dst.Q[(size_t)a * dst.cap + j] = src.Q[(size_t)a * src.cap + i];
     id_dst[j] = id_src[i];
 }
 
