@@ -1,6 +1,6 @@
 // event.hip -- runtime behind the C-ABI of include/glasma.h: one event holds
 // a caller-owned workspace carved into ping-pong field buffers, the site-field
-// planes, the padded particle arrays, the FP64 broadening series and the
+// records, the padded particle arrays, the FP64 broadening series and the
 // initial-condition scratch, and orders every launch on the caller's stream.
 #include <hip/hip_runtime.h>
 

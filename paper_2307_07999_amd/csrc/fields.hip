@@ -19,11 +19,13 @@
 // Kernel design: two lanes per site, one per link direction (the per-site
 // work of one lane needs too many registers for more than one wave per SIMD);
 // workgroups of 32 x 4 sites.  The links and phi of the tile and a one-site
-// halo are staged in LDS with coalesced row reads, and every neighbour of the
-// stencil is read from there: without the tile the step issues ~250 global
-// loads per lane and its waves spend half their time waiting on them.  Tiles are numbered so that each XCD owns one band of
-// rows (xcd_remap): the neighbour reads of the stencil then hit the L2 of the
-// XCD that owns the tile instead of refetching halo lines from memory.
+// halo are staged in LDS with coalesced 16-byte reads of the chunked field
+// state, and every neighbour of the stencil is read from there: without the
+// tile the step issues ~250 global loads per lane and its waves spend half
+// their time waiting on them.  Tiles are numbered so that each XCD owns one
+// band of rows (xcd_remap): the neighbour reads of the stencil then hit the
+// L2 of the XCD that owns the tile instead of refetching halo lines from
+// memory.
 #include "fields_dev.hpp"
 
 namespace gl {

@@ -237,8 +237,8 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
 //   B_x = -D_2 phi / tau, B_y = D_1 phi / tau, D_i phi = (Phi_{+i} - Phi_{-i}) / 2,
 //   B_z = -(1/4) (sum of the four plaquettes at x, each transported to x).
 // The second half of E_i belongs to the site x+i; lane d owns the link U_i(x)
-// and Ebar_i(x) it needs, so it stores that half at x+i in a plane of its own
-// (slots 48..63) and the push adds the two halves.
+// and Ebar_i(x) it needs, so it stores that half at x+i in slots of its own
+// (48..63) and the push adds the two halves.
 template <typename T, int SX, int SY>
 __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, int N, const FieldPtrs<T> &in,
                                                 const FieldPtrs<T> &out, T *__restrict__ F, int ix, int iy, int lx,
