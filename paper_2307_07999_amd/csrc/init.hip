@@ -441,24 +441,38 @@ __device__ inline double match_residual(const M3<double> &W, const M3<double> &U
     return m;
 }
 
+// Gaussian elimination with partial pivoting, unrolled so that J and b stay
+// in registers: each column's largest remaining entry is moved to the pivot
+// row by conditional swaps with the rows below it.
 __device__ inline bool solve8(double J[8][8], double *b) {
+#pragma unroll
     for (int c = 0; c < 8; c++) {
-        int piv = c;
-        for (int r = c + 1; r < 8; r++)
-            if (fabs(J[r][c]) > fabs(J[piv][c])) piv = r;
-        if (J[piv][c] == 0.0) return false;
-        if (piv != c) {
-            for (int k = 0; k < 8; k++) { double t = J[c][k]; J[c][k] = J[piv][k]; J[piv][k] = t; }
-            double t = b[c]; b[c] = b[piv]; b[piv] = t;
-        }
+#pragma unroll
         for (int r = c + 1; r < 8; r++) {
-            double f = J[r][c] / J[c][c];
+            const bool sw = fabs(J[r][c]) > fabs(J[c][c]);
+#pragma unroll
+            for (int k = c; k < 8; k++) {
+                const double t = J[c][k];
+                J[c][k] = sw ? J[r][k] : t;
+                J[r][k] = sw ? t : J[r][k];
+            }
+            const double t = b[c];
+            b[c] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
+        }
+        if (J[c][c] == 0.0) return false;
+#pragma unroll
+        for (int r = c + 1; r < 8; r++) {
+            const double f = J[r][c] / J[c][c];
+#pragma unroll
             for (int k = c; k < 8; k++) J[r][k] -= f * J[c][k];
             b[r] -= f * b[c];
         }
     }
+#pragma unroll
     for (int i = 7; i >= 0; i--) {
         double s = b[i];
+#pragma unroll
         for (int k = i + 1; k < 8; k++) s -= J[i][k] * b[k];
         b[i] = s / J[i][i];
     }
@@ -489,6 +503,9 @@ k_match(int N, const double *VA, const double *VB, double *U0, int *status, int 
     while (rn >= tol && it < max_iter) {
         M3<double> M = mul_nd(W, U);
         double J[8][8];
+        // unrolled: e is a constant unit vector, so M T^b folds to the few
+        // non-zero entries of the generator
+#pragma unroll
         for (int b = 0; b < 8; b++) {
             double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             e[b] = 1.0;
