@@ -35,14 +35,14 @@ __device__ __forceinline__ void batch_field_tile(LinkTile<T, TX, TY> &tile, cons
     const int lx = threadIdx.x >> 1, ly = threadIdx.y;
     const int tx = (e.N + TX - 1) / TX;
     const int x0 = (w.y % tx) * TX, y0 = (w.y / tx) * TY;
-    stage_tile(tile, e.N, e.f[fpar], x0, y0, threadIdx.x + 2 * TX * threadIdx.y, 2 * TX * TY);
+    const int tid = threadIdx.x + 2 * TX * threadIdx.y;
+    stage_tile(tile, e.N, e.f[fpar], x0, y0, tid, 2 * TX * TY);
     __syncthreads();
-    const int ix = x0 + lx, iy = y0 + ly;
-    if (ix < e.N && iy < e.N) {
-        int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
-        field_step_link(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, ix, iy, lx, ly,
-                        threadIdx.x & 1, tau, dtau, tau_h, reunit);
-    }
+    // every thread takes part (the step synchronises the workgroup)
+    const bool active = x0 + lx < e.N && y0 + ly < e.N;
+    const int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
+    field_step_link(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, x0, y0, lx, ly,
+                    threadIdx.x & 1, tid, active, tau, dtau, tau_h, reunit);
 }
 
 template <typename T, int TX, int TY>

@@ -43,11 +43,13 @@ k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T *__restrict__ F, T tau,
     const int l = (int)xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (l % tx) * SX, y0 = (l / tx) * SY;
     const int lx = threadIdx.x >> 1, ly = threadIdx.y;
-    stage_tile(tile, N, in, x0, y0, threadIdx.x + 2 * SX * threadIdx.y, 2 * SX * SY);
+    const int tid = threadIdx.x + 2 * SX * threadIdx.y;
+    stage_tile(tile, N, in, x0, y0, tid, 2 * SX * SY);
     __syncthreads();
-    const int ix = x0 + lx, iy = y0 + ly;
-    if (ix >= N || iy >= N) return;   // both lanes of a pair leave together
-    field_step_link(tile, N, in, out, F, ix, iy, lx, ly, threadIdx.x & 1, tau, dtau, tau_h, reunit);
+    // every thread takes part (the step synchronises the workgroup); both
+    // lanes of a pair are on or off the lattice together
+    const bool active = x0 + lx < N && y0 + ly < N;
+    field_step_link(tile, N, in, out, F, x0, y0, lx, ly, threadIdx.x & 1, tid, active, tau, dtau, tau_h, reunit);
 }
 
 // Static quarks (Sec. 2, Eq. (4)): I_i^a(x) += dtau E_i^a(x, tau_n) from the

@@ -82,24 +82,29 @@ __device__ __forceinline__ void store_half(T *__restrict__ F, size_t n2, size_t 
     for (int k = 0; k < 4; k += NV) chunk_st16_l(F, n2, x, slot + 4 * h + k, w + k);
 }
 
-// Links and phi of a block of SX x SY sites and a one-site halo, staged in
-// LDS; region site (rx, ry) is the lattice site (x0 - 1 + rx, y0 - 1 + ry)
-// mod N.  Chunk-major like the field state: the values of a site are held
-// in 16-byte chunks (NV = 16 / sizeof(T) values), chunk c of all region
-// sites contiguous, so a lane reads a link with 16-byte LDS accesses.  Per
-// site: U_1 in chunks [0, LC), U_2 in [LC, 2 LC), phi in the next 8 / NV
-// chunks; a link is its 18 values (entry (i,j) real at 2(3i+j), imaginary
-// next to it), padded in FP32 to 5 whole chunks.
+// Links of a block of SX x SY sites and a one-site halo, staged in LDS;
+// region site (rx, ry) is the lattice site (x0 - 1 + rx, y0 - 1 + ry) mod N.
+// Chunk-major like the field state: the values of a site are held in
+// 16-byte chunks (NV = 16 / sizeof(T) values), chunk c of all region sites
+// contiguous, so a lane reads a link with 16-byte LDS accesses.  Per site:
+// U_1 in chunks [0, LC), U_2 in [LC, 2 LC); a link is its 18 values (entry
+// (i,j) real at 2(3i+j), imaginary next to it), padded in FP32 to 5 whole
+// chunks.  The tile also holds the plaquette algebra [P(x)]_X of the region
+// sites (rx, ry), rx <= SX, ry <= SY (the block and its lower and left halo),
+// computed once per step and read by the staples and the clover of the
+// neighbouring sites.
 template <typename T, int SX, int SY>
 struct LinkTile {
     static constexpr int NV = 16 / (int)sizeof(T);
     static constexpr int LC = (18 + NV - 1) / NV;      // chunks per link
-    static constexpr int NC = 2 * LC + 8 / NV;         // chunks per site
+    static constexpr int NC = 2 * LC;                  // chunks per site
     static constexpr int RX = SX + 2, RY = SY + 2, R = RX * RY;
+    static constexpr int PX = SX + 1, PN = PX * (SY + 1);   // plaquette-algebra region
     struct alignas(16) Chunk {
         T v[NV];
     };
     Chunk c[NC * R];
+    Chunk pa[(8 / NV) * PN];
     // link d (0: U_1, 1: U_2) of region site r
     __device__ __forceinline__ M3<T> m(int d, int r) const {
         T v[LC * NV];
@@ -126,17 +131,28 @@ struct LinkTile {
             }
         return u;
     }
-    __device__ __forceinline__ void phi(int r, T *out) const {
+    // index of region site (rx, ry) in the plaquette-algebra region
+    static __device__ __forceinline__ int pidx(int rx, int ry) { return rx + PX * ry; }
+    __device__ __forceinline__ void plaq(int p, T *out) const {
 #pragma unroll
         for (int j = 0; j < 8 / NV; j++) {
-            const Chunk w = c[(size_t)(2 * LC + j) * R + r];
+            const Chunk w = pa[j * PN + p];
 #pragma unroll
             for (int k = 0; k < NV; k++) out[j * NV + k] = w.v[k];
         }
     }
+    __device__ __forceinline__ void put_plaq(int p, const T *v) {
+#pragma unroll
+        for (int j = 0; j < 8 / NV; j++) {
+            Chunk w;
+#pragma unroll
+            for (int k = 0; k < NV; k++) w.v[k] = v[j * NV + k];
+            pa[j * PN + p] = w;
+        }
+    }
 };
 
-// All threads of the workgroup copy the tile's region from the state; the
+// All threads of the workgroup copy the tile's links from the state; the
 // caller synchronises the workgroup before the tile is read.
 template <typename T, int SX, int SY>
 __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const FieldPtrs<T> &in, int x0, int y0,
@@ -150,12 +166,10 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
         gx += gx < 0 ? N : 0;
         gy += gy < 0 ? N : 0;
         const size_t site = (size_t)gx + (size_t)N * gy;
-        // the 36 link values and 8 phi values of the site, in 16-byte loads
-        T u[36], ph[8];
+        // the 36 link values of the site, in 16-byte loads
+        T u[36];
 #pragma unroll
         for (int k = 0; k < 36; k += NV) chunk_ld16(in.U, n2, site, k, u + k);
-#pragma unroll
-        for (int k = 0; k < 8; k += NV) chunk_ld16(in.phi, n2, site, k, ph + k);
 #pragma unroll
         for (int d = 0; d < 2; d++)
 #pragma unroll
@@ -168,13 +182,6 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
                 }
                 t.c[(size_t)(LC * d + j) * R + r] = w;
             }
-#pragma unroll
-        for (int j = 0; j < 8 / NV; j++) {
-            Chunk w;
-#pragma unroll
-            for (int k = 0; k < NV; k++) w.v[k] = ph[j * NV + k];
-            t.c[(size_t)(2 * LC + j) * R + r] = w;
-        }
     }
 }
 
@@ -218,12 +225,16 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
 
 // One link direction of one site of the leapfrog step n -> n+1: the two
 // lanes of a pair (d = 0, 1) share the site (ix, iy) = (x0 + lx, y0 + ly) of
-// the staged tile, which must lie on the lattice, and lane d owns direction
-// i = d + 1 (j is the other one).  Lane d forms its staple plaquette at
-// y = x - j, its transported scalars Phi_{+-i}, and updates E_i and U_i; the
-// plaquette at x is assembled from the halves U_i(x) U_j(x+i) of both lanes,
-// and the Laplacian of phi, the clover and the pi, phi update are shared
-// across the pair.  For i = 1, 2:
+// the staged tile, and lane d owns direction i = d + 1 (j is the other one).
+// Every thread of the workgroup calls this (active: the site lies on the
+// lattice), since it synchronises the workgroup once.  First the plaquette
+// at x is assembled from the halves U_i(x) U_j(x+i) of both lanes and its
+// algebra stored in the tile, with those of the tile's lower and left halo
+// sites (computed by the first threads); then lane d reads the staple
+// plaquette at y = x - j and the clover's corner plaquette from the tile,
+// forms its transported scalars Phi_{+-i} (phi read from the state), and
+// updates E_i and U_i; the Laplacian of phi, the clover and the pi, phi
+// update are shared across the pair.  For i = 1, 2:
 //   E_1 += dtau { -tau ([P(x)]_X - U_2^dag(x-2)[P(x-2)]_X U_2(x-2)) - (i/tau)[phi, Phi_{+1}] }
 //   E_2 += dtau { -tau (U_1^dag(x-1)[P(x-1)]_X U_1(x-1) - [P(x)]_X) - (i/tau)[phi, Phi_{+2}] }
 //   pi  += (dtau/tau) sum_i (Phi_{+i} + Phi_{-i} - 2 phi)
@@ -240,47 +251,71 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
 // and Ebar_i(x) it needs, so it stores that half at x+i in slots of its own
 // (48..63) and the push adds the two halves.
 template <typename T, int SX, int SY>
-__device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, int N, const FieldPtrs<T> &in,
-                                                const FieldPtrs<T> &out, T *__restrict__ F, int ix, int iy, int lx,
-                                                int ly, int d, T tau, T dtau, T tau_h, int reunit) {
+__device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, const FieldPtrs<T> &in,
+                                                const FieldPtrs<T> &out, T *__restrict__ F, int x0, int y0, int lx,
+                                                int ly, int d, int tid, bool active, T tau, T dtau, T tau_h,
+                                                int reunit) {
     using Tl = LinkTile<T, SX, SY>;
     constexpr int RX = Tl::RX;
     const size_t n2 = plane_pitch(N);
     const bool d0 = d == 0;
+    const int ix = x0 + lx, iy = y0 + ly;
     // region indices of the neighbours
     const int rx = (lx + 1) + RX * (ly + 1);
-    const int di = d0 ? 1 : RX, dj = d0 ? RX : 1;   // steps along i and j
+    const int di = d0 ? 1 : RX;                      // step along i
     const int rpi = rx + di, rmi = rx - di;          // x + i, x - i
-    const int ry = rx - dj;                          // y = x - j
-    const int ry1 = d0 ? ry + 1 : rx, ry2 = d0 ? rx : ry + RX;   // y + 1, y + 2
-    const int rz = rx - 1 - RX, rzi = rz + di;       // z = x - 1 - 2, z + i
+    const int ry = rx - (d0 ? RX : 1);               // y = x - j
+    const int rz = rx - 1 - RX;                      // z = x - 1 - 2
     const int li = d, lj = 1 - d;                    // tile links of U_i, U_j
     // lattice indices for the global reads and writes
-    const size_t x = (size_t)ix + (size_t)N * iy;
     const int ixp = ix + 1 == N ? 0 : ix + 1, iyp = iy + 1 == N ? 0 : iy + 1;
+    const int ixm = ix == 0 ? N - 1 : ix - 1, iym = iy == 0 ? N - 1 : iy - 1;
+    const size_t x = (size_t)ix + (size_t)N * iy;
     const size_t xpi = d0 ? (size_t)ixp + (size_t)N * iy : (size_t)ix + (size_t)N * iyp;
+    const size_t xmi = d0 ? (size_t)ixm + (size_t)N * iy : (size_t)ix + (size_t)N * iym;
     const T inv_tau = T(1) / tau;
     const T sgn = d0 ? T(1) : T(-1);
+
+    // phi at x and x +- i, in flight during the plaquettes
+    T ph[8], php[8], phm[8];
+    if (active) {
+        chunk_load_a(in.phi, n2, x, 0, ph);
+        chunk_load_a(in.phi, n2, xpi, 0, php);
+        chunk_load_a(in.phi, n2, xmi, 0, phm);
+    }
+    // [P(x)]_X, P(x) = h0 h1^dag with the half products h0 = U_1(x) U_2(x+1)
+    // (lane 0) and h1 = U_2(x) U_1(x+2) (lane 1); lane 1 forms h1 h0^dag =
+    // P(x)^dag, whose projection is -[P(x)]_X.  Lane 0 stores the algebra,
+    // computed exactly as for the halo sites, so the stored values do not
+    // depend on the tiling.
+    T px[8];
+    if (active) {
+        const M3<T> h = mul(tl.m(li, rx), tl.m(lj, rpi));
+        alg_proj(mul_nd(h, pair_swap(h)), px);
+#pragma unroll
+        for (int a = 0; a < 8; a++) px[a] *= sgn;
+        if (d0) tl.put_plaq(Tl::pidx(lx + 1, ly + 1), px);
+    }
+    // the halo plaquettes: region row 0 (rx = 0..SX) and column 0 (ry = 1..SY),
+    // whole, one per thread, as h0 h1^dag like the block's
+    for (int hh = tid; hh < SX + SY + 1; hh += 2 * SX * SY) {
+        const int hx = hh <= SX ? hh : 0, hy = hh <= SX ? 0 : hh - SX;
+        const int r = hx + RX * hy;
+        const M3<T> h0 = mul(tl.m(0, r), tl.m(1, r + 1)), h1 = mul(tl.m(1, r), tl.m(0, r + RX));
+        T v[8];
+        alg_proj(mul_nd(h0, h1), v);
+        tl.put_plaq(Tl::pidx(hx, hy), v);
+    }
+    __syncthreads();
+    if (!active) return;
 
     const M3<T> ui = tl.m(li, rx);   // U_i(x)
     T fe[8], cl[8];
     {
-        // [P(x)]_X, P(x) = h0 h1^dag with the half products h0 = U_1(x) U_2(x+1)
-        // (lane 0) and h1 = U_2(x) U_1(x+2) (lane 1); lane 1 forms h1 h0^dag =
-        // P(x)^dag, whose projection is -[P(x)]_X
-        T px[8];
-        {
-            const M3<T> h = mul(ui, tl.m(lj, rpi));
-            alg_proj(mul_nd(h, pair_swap(h)), px);
-#pragma unroll
-            for (int a = 0; a < 8; a++) px[a] *= sgn;
-        }
         // staple: U_j^dag(y) [P(y)]_X U_j(y)
-        const M3<T> uj = tl.m(lj, ry);
-        const M3<T> P = plaq(tl.m(0, ry), tl.m(1, ry1), tl.m(0, ry2), tl.m(1, ry));
         T pa[8], t[8];
-        alg_proj(P, pa);
-        transport_dn(uj, herm_from_alg(pa), t);
+        tl.plaq(Tl::pidx(lx + 1 - d, ly + d), pa);
+        transport_dn(tl.m(lj, ry), herm_from_alg(pa), t);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             fe[a] = -tau * sgn * (px[a] - t[a]);
@@ -288,30 +323,22 @@ __device__ __forceinline__ void field_step_link(const LinkTile<T, SX, SY> &tl, i
         }
     }
     if (F) {
-        // fourth clover plaquette P(z) = [U_1(z) U_2(z+1)] [U_2(z) U_1(z+2)]^dag,
-        // moved to x along z -> z+1 -> x, i.e. by C = U_1(z) U_2(z+1) (the
-        // half product of lane 0; lane 1 projects P(z)^dag as above)
-        const M3<T> h = mul(tl.m(li, rz), tl.m(lj, rzi));
-        const M3<T> o = pair_swap(h);
+        // fourth clover plaquette P(z), moved to x along z -> z+1 -> x, i.e.
+        // by C = U_1(z) U_2(z+1)
         T pa[8], t[8];
-        alg_proj(mul_nd(h, o), pa);
-#pragma unroll
-        for (int a = 0; a < 8; a++) pa[a] *= sgn;
-        transport_dn(select(d0, h, o), herm_from_alg(pa), t);
+        tl.plaq(Tl::pidx(lx, ly), pa);
+        transport_dn(mul(tl.m(0, rz), tl.m(1, rz + 1)), herm_from_alg(pa), t);
 #pragma unroll
         for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
         store_half(F, n2, x, 40, t, d);   // B_z
     }
     // scalar couplings: Phi_{+i} in the E_i force, all four in the pi force
-    T ph[8], fpi[8];
-    tl.phi(rx, ph);
+    T fpi[8];
     {
-        T v[8], c[8], pf[8], pb[8];
-        tl.phi(rpi, v);
-        transport_nd(ui, herm_from_alg(v), pf);   // Phi_{+i}
-        alg_comm(ph, pf, c);                      // -i[phi, Phi_{+i}]
-        tl.phi(rmi, v);
-        transport_dn(tl.m(li, rmi), herm_from_alg(v), pb);   // Phi_{-i}
+        T c[8], pf[8], pb[8];
+        transport_nd(ui, herm_from_alg(php), pf);   // Phi_{+i}
+        alg_comm(ph, pf, c);                        // -i[phi, Phi_{+i}]
+        transport_dn(tl.m(li, rmi), herm_from_alg(phm), pb);   // Phi_{-i}
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             fe[a] = fma(inv_tau, c[a], fe[a]);
