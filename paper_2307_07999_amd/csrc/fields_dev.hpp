@@ -57,18 +57,6 @@ __device__ __forceinline__ M3<T> pair_swap(const M3<T> &m) {
         }
     return r;
 }
-template <typename T>
-__device__ __forceinline__ M3<T> select(bool c, const M3<T> &a, const M3<T> &b) {
-    M3<T> r;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            r.re[i][j] = c ? a.re[i][j] : b.re[i][j];
-            r.im[i][j] = c ? a.im[i][j] : b.im[i][j];
-        }
-    return r;
-}
 
 // Components 4h..4h+3 of an algebra vector v into a record slot (the two
 // lanes of a site store one half each).

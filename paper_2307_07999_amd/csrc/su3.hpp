@@ -676,18 +676,6 @@ __device__ __forceinline__ void store_m(T *__restrict__ base, size_t n2, size_t 
         }
 }
 
-template <typename T>
-__device__ __forceinline__ void load_a(const T *__restrict__ base, size_t n2, size_t x, T *v) {
-#pragma unroll
-    for (int a = 0; a < 8; a++) v[a] = pl_ld(base, n2, a, x);
-}
-
-template <typename T>
-__device__ __forceinline__ void store_a(T *__restrict__ base, size_t n2, size_t x, const T *v) {
-#pragma unroll
-    for (int a = 0; a < 8; a++) pl_st(base, n2, a, x, v[a]);
-}
-
 // The field state in chunked planes: a link is the 18 values k0..k0+17
 // (entry (i,j) real at k0 + 2(3i+j), imaginary next to it; k0 = 0 or 18,
 // the same for all lanes), an algebra vector the 8 values k0..k0+7 (k0 a
