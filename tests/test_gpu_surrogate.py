@@ -22,7 +22,7 @@ def trained():
     train = S.draw_params(2048, 11)
     curves, _ = S.solver_curves(train, N, L_FM, 40000, 12)
     X, Y = S.rows(train, curves)
-    held = S.draw_params(16, 13)
+    held = S.draw_params(32, 13)
     t0 = time.perf_counter()
     ref, _ = S.solver_curves(held, N, L_FM, 50000, 14, batch=16)
     torch.cuda.synchronize()
