@@ -125,8 +125,8 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
 
 def surrogate_bench(mode):
     """Surrogate vs solver: the protocol of paper_2307_07999_amd.surrogate
-    (solver-generated training data, BF16 network trained on the GPU, judged
-    against held-out 512^2 solver runs).  'quick' is a reduced protocol that
+    (solver-generated training data, BF16 network trained on the GPU,
+    evaluated against held-out 512^2 solver runs).  'quick' is a reduced protocol that
     keeps the default run within a few minutes; 'full' is the complete one."""
     from paper_2307_07999_amd import surrogate
     if mode == "full":

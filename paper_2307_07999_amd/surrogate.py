@@ -219,7 +219,7 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_
     noise = [curve_error(a[1], np.interp(a[0], b[0], b[1])) for a, b in zip(hc[:n_noise], hc2)]
     rep["noise_floor_kappa"] = {"median": float(np.median(noise)), "max": float(np.max(noise))}
 
-    def judge(sur):
+    def evaluate(sur):
         ek, ed = [], []
         for (qs, m, pt), (tau, k, d) in zip(hp, hc):
             kp, dp = sur.predict(qs, m, pt, tau)
@@ -246,8 +246,8 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_
     torch.cuda.synchronize()
     rep["train_s"] = time.perf_counter() - t
     rep["loss_final"] = [float(la[-1]), float(lb[-1])]
-    rep["coarse_only"] = judge(A)
-    rep["fine_tuned"] = judge(B)
+    rep["coarse_only"] = evaluate(A)
+    rep["fine_tuned"] = evaluate(B)
     tau = np.linspace(0.0025, 1.0, 410)
     B.predict(2.0, 4.18, 2.0, tau)
     torch.cuda.synchronize()

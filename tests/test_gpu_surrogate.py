@@ -1,6 +1,6 @@
 """The learned surrogate end to end on the GPU, at a small lattice: solver
 runs generate the training rows, the network trains with the library's BF16
-kernels, and it is judged against held-out solver runs.  The test states what
+kernels, and it is evaluated against held-out solver runs.  The test states what
 the network gains over the plain solver (time per kappa(tau) curve at the
 measured accuracy) and that queries outside the training domain go to the
 solver.  The lattice spacing equals that of 512^2 at L = 10 fm, so the time
