@@ -318,7 +318,7 @@ def main():
         copy_calibration(args.copy_calib)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+        print("bench.py measures one GPU only; --gpus %d is not supported "
               "(events shard across GPUs without exchange; see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

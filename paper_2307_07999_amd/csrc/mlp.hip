@@ -3,7 +3,7 @@
 // FP32 accumulation on the matrix cores, FP32 master weights and Adam.  It
 // maps (Q_s, quark mass, initial p_T, formation time, tau) to the broadening
 // observables the solver produces; the solver generates its training data and
-// measures its error (see the Python driver).
+// measures its error (paper_2307_07999_amd/surrogate.py).
 //
 // Dense products use v_mfma_f32_16x16x16_bf16: a 64 x 64 output tile per
 // 256-thread workgroup, each wave a 32 x 32 quarter as 2 x 2 MFMA blocks,
