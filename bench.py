@@ -319,7 +319,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "
-              "(events shard across GPUs without exchange; see the design notes)" % args.gpus,
+              "(independent events would shard across GPUs without exchange)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
