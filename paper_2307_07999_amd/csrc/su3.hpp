@@ -553,6 +553,12 @@ __device__ __forceinline__ void chunk_ld16(const T *p, size_t n2, size_t x, int 
 #pragma unroll
     for (int i = 0; i < NV; i++) out[i] = r.v[i];
 }
+// A store of more than 8 bytes needs one wait state before a vector
+// instruction may overwrite its data registers.  The compiler inserts it only
+// for buffer stores without a scalar offset register, and on gfx950 the
+// hazard is also there with one: the data of a 16-byte store was overwritten
+// by the next instruction in a few lanes.  Every 16-byte store therefore puts
+// its whole offset in the vector offset and passes a constant zero soffset.
 template <typename T>
 __device__ __forceinline__ void chunk_st16(T *p, size_t n2, size_t x, int k, const T *in) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -561,8 +567,8 @@ __device__ __forceinline__ void chunk_st16(T *p, size_t n2, size_t x, int k, con
     V r;
 #pragma unroll
     for (int i = 0; i < NV; i++) r.v[i] = in[i];
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p), (uint32_t)(x * 16),
-                                           (uint32_t)((size_t)(k / NV) * n2 * 16), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p),
+                                           (uint32_t)((x + (size_t)(k / NV) * n2) * 16), 0u, 0);
 }
 
 template <typename T>
