@@ -79,7 +79,7 @@ __device__ __forceinline__ void batch_push_block(const BatchEv<T> &e, int2 w, in
     const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int s = -1;
-    if (i < e.n_slots) s = push_particle<T>(e.N, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+    if (i < e.n_slots) s = push_particle<T>(e.N, e.P[ppar], i, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
     block_species_reduce(s, acc, e.n_species, e.partials + (size_t)w.y * e.n_species * 4);
 }
 

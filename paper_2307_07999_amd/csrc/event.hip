@@ -140,6 +140,10 @@ struct gl_event {
     int64_t slots_used = 0;
     std::vector<SpeciesInfo> species;
     int pbuf = 0;               // which particle buffer is current
+    // a sort whose permutation (in the sort scratch) the next push applies:
+    // within a run the particles move to their sorted slots while being
+    // pushed; every call returns with none pending
+    bool perm_pending = false;
     int32_t sort_every = 16;    // re-sort particles by cell every this many pushes (0: never)
     int64_t since_sort = 0;
     bool stat_on = false;       // static-quark accumulation running
@@ -308,9 +312,20 @@ gl_status push(gl_event *ev) {
     if (row >= ev->desc.max_steps) return fail(GL_EINVAL, "series capacity (max_steps) exhausted");
     const int ns = (int)ev->species.size();
     if (ev->pend == 0) ev->pend_row0 = row;
-    PROF(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used, ev->fields<T>(1 - ev->cur),
-                                (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev, ev->dtau,
-                                ev->partials(ev->pend))));
+    if (ev->perm_pending) {
+        const int nb = 1 - ev->pbuf;
+        PROF(ev, 2, (launch_push_permuted<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->parts<T>(nb),
+                                             sort_perm(ev->scratch()), ev->ids(ev->pbuf), ev->ids(nb),
+                                             ev->slots_used, ev->fields<T>(1 - ev->cur),
+                                             (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev,
+                                             ev->dtau, ev->partials(ev->pend))));
+        ev->pbuf = nb;
+        ev->perm_pending = false;
+    } else {
+        PROF(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used, ev->fields<T>(1 - ev->cur),
+                                    (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev, ev->dtau,
+                                    ev->partials(ev->pend))));
+    }
     ev->pend++;
     if (ev->pend == kReduceSlots) {
         gl_status s = flush_series(ev);
@@ -329,12 +344,38 @@ gl_status sort_t(gl_event *ev) {
                                      ev->scratch(), ev->ids(ev->pbuf), ev->ids(nb)));
     ev->pbuf = nb;
     ev->since_sort = 0;
+    ev->perm_pending = false;   // a full sort supersedes a pending order
     return GL_OK;
 }
 
 gl_status sort_particles(gl_event *ev) {
     if (ev->slots_used == 0) return GL_OK;
     return ev->fp64() ? sort_t<double>(ev) : sort_t<float>(ev);
+}
+
+// the sorted order only; the next push moves the particles by it
+template <typename T>
+gl_status sort_order_t(gl_event *ev) {
+    HIP_TRY(launch_sort_order<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->slots_used, ev->scratch()));
+    ev->perm_pending = true;
+    ev->since_sort = 0;
+    return GL_OK;
+}
+
+// apply a pending sort permutation without a push
+template <typename T>
+gl_status apply_pending_t(gl_event *ev) {
+    const int nb = 1 - ev->pbuf;
+    HIP_TRY(launch_permute<T>(ev->stream, ev->parts<T>(ev->pbuf), ev->parts<T>(nb), sort_perm(ev->scratch()),
+                              ev->slots_used, ev->ids(ev->pbuf), ev->ids(nb)));
+    ev->pbuf = nb;
+    ev->perm_pending = false;
+    return GL_OK;
+}
+
+gl_status apply_pending_sort(gl_event *ev) {
+    if (!ev->perm_pending) return GL_OK;
+    return ev->fp64() ? apply_pending_t<double>(ev) : apply_pending_t<float>(ev);
 }
 
 // the per-species sums of the squared momenta at formation, which the
@@ -357,10 +398,15 @@ gl_status do_field_step(gl_event *ev, bool sf) {
 }
 gl_status sort_particles(gl_event *ev);
 
-gl_status do_push(gl_event *ev) {
+// the push, then a sort when one is due: with defer, only the sorted order,
+// which the next push applies
+gl_status do_push(gl_event *ev, bool defer = false) {
     gl_status s = ev->fp64() ? push<double>(ev) : push<float>(ev);
     if (s) return s;
-    if (ev->sort_every > 0 && ev->since_sort >= ev->sort_every) return sort_particles(ev);
+    if (ev->sort_every > 0 && ev->since_sort >= ev->sort_every && ev->slots_used > 0) {
+        if (defer) return ev->fp64() ? sort_order_t<double>(ev) : sort_order_t<float>(ev);
+        return sort_particles(ev);
+    }
     return GL_OK;
 }
 
@@ -777,15 +823,17 @@ gl_status gl_run(gl_event *ev, int32_t n_steps) {
     bool has_particles = ev->slots_used > 0;
     if (has_particles && ev->n - 1 + n_steps > ev->desc.max_steps)
         return fail(GL_EINVAL, "series capacity (max_steps) too small for this run");
-    for (int32_t k = 0; k < n_steps; k++) {
-        gl_status s = do_field_step(ev, has_particles);
-        if (s) return s;
-        if (has_particles) {
-            ev->push_due = true;
-            s = do_push(ev);
-            if (s) return s;
-        }
+    gl_status s = GL_OK;
+    for (int32_t k = 0; k < n_steps && !s; k++) {
+        s = do_field_step(ev, has_particles);
+        if (s || !has_particles) continue;
+        ev->push_due = true;
+        s = do_push(ev, true);
     }
+    // no sort is left pending, also after an error
+    const gl_status sp = apply_pending_sort(ev);
+    if (s) return s;
+    if (sp) return sp;
     return flush_series(ev);
 }
 

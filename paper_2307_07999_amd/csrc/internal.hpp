@@ -71,6 +71,14 @@ int64_t sort_tiles(int64_t n);
 template <typename T>
 hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtrs<T> dst, int64_t n,
                                  SortScratch s, int32_t *id_src, int32_t *id_dst);
+// the two halves of launch_sort_particles: the sorted order (its
+// permutation then at sort_perm), and moving every particle array by it
+template <typename T>
+hipError_t launch_sort_order(hipStream_t st, int N, PartPtrs<T> src, int64_t n, SortScratch s);
+const int32_t *sort_perm(SortScratch s);
+template <typename T>
+hipError_t launch_permute(hipStream_t st, PartPtrs<T> src, PartPtrs<T> dst, const int32_t *perm, int64_t n,
+                          int32_t *id_src, int32_t *id_dst);
 
 template <typename T>
 struct SpeciesTab {
@@ -87,6 +95,14 @@ template <typename T>
 hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
                        const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
                        double *partials);
+// the push of particles still to be moved by a sort permutation: position j
+// is pushed from slot perm[j] of p and written, with the particle's other
+// arrays and id, to slot j of dst
+template <typename T>
+hipError_t launch_push_permuted(hipStream_t st, int N, PartPtrs<T> p, PartPtrs<T> dst, const int32_t *perm,
+                                const int32_t *id_src, int32_t *id_dst, int64_t n_slots, FieldPtrs<T> f,
+                                const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
+                                double *partials);
 hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, int32_t base);
 // fixed-order sum of per-workgroup partial rows into a series row; a
 // non-null sub [kMaxSpecies][4] is subtracted from the first three terms of

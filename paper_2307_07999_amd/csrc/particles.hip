@@ -33,7 +33,33 @@ k_push(int N, PartPtrs<T> P, int64_t n_slots, FieldPtrs<T> f, const T *__restric
     const int64_t i = blk * kPushBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int s = -1;
-    if (i < n_slots) s = push_particle<T>(N, P, i, f, F, tab, n, dtau, acc);
+    if (i < n_slots) s = push_particle<T>(N, P, i, P, i, f, F, tab, n, dtau, acc);
+    block_species_reduce(s, acc, n_species, partials + (size_t)blk * n_species * 4);
+}
+
+// The push that also applies a pending sort: position j takes the particle
+// in slot perm[j] of P, pushes it and writes it, with its species, momenta at
+// formation and id, to slot j of W.  The blocks (and so the partial rows) are
+// those of a push after the permutation.
+template <typename T>
+__global__ void __launch_bounds__(kPushBlock)
+k_push_permuted(int N, PartPtrs<T> P, PartPtrs<T> W, const int32_t *__restrict__ perm,
+                const int32_t *__restrict__ id_src, int32_t *__restrict__ id_dst, int64_t n_slots, FieldPtrs<T> f,
+                const T *__restrict__ F, SpeciesTab<T> tab, int n_species, int n, T dtau,
+                double *__restrict__ partials) {
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t j = blk * kPushBlock + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int s = -1;
+    if (j < n_slots) {
+        const int64_t i = perm[j];
+        s = push_particle<T, true>(N, P, i, W, j, f, F, tab, n, dtau, acc);
+        W.species[j] = P.species[i];
+        W.px0[j] = P.px0[i];
+        W.py0[j] = P.py0[i];
+        W.pz0[j] = P.pz0[i];
+        id_dst[j] = id_src[i];
+    }
     block_species_reduce(s, acc, n_species, partials + (size_t)blk * n_species * 4);
 }
 
@@ -260,6 +286,18 @@ hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, Fi
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_push_permuted(hipStream_t st, int N, PartPtrs<T> p, PartPtrs<T> dst, const int32_t *perm,
+                                const int32_t *id_src, int32_t *id_dst, int64_t n_slots, FieldPtrs<T> f,
+                                const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
+                                double *partials) {
+    if (n_slots <= 0) return hipSuccess;
+    unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
+    hipLaunchKernelGGL(k_push_permuted<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, dst, perm, id_src, id_dst,
+                       n_slots, f, F, tab, n_species, n, (T)dtau, partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_series_reduce(hipStream_t st, const double *partials, int n_blocks, int n_species,
                                 double *row, const double *sub) {
     hipLaunchKernelGGL(k_series_reduce, dim3(kMaxSpecies), dim3(256), 0, st, partials, n_blocks,
@@ -288,6 +326,10 @@ hipError_t launch_particles_init(hipStream_t st, int N, PartPtrs<T> p, int64_t s
 #define GL_INST(T)                                                                               \
     template hipError_t launch_push<T>(hipStream_t, int, PartPtrs<T>, int64_t, FieldPtrs<T>,      \
                                        const T *, SpeciesTab<T>, int, int, double, double *);    \
+    template hipError_t launch_push_permuted<T>(hipStream_t, int, PartPtrs<T>, PartPtrs<T>,       \
+                                                const int32_t *, const int32_t *, int32_t *,     \
+                                                int64_t, FieldPtrs<T>, const T *, SpeciesTab<T>, \
+                                                int, int, double, double *);                     \
     template hipError_t launch_particles_init<T>(hipStream_t, int, PartPtrs<T>, int64_t, int64_t, \
                                                  uint64_t, int, int, double);                    \
     template hipError_t launch_casimir<T>(hipStream_t, PartPtrs<T>, int64_t, double *, int *);             \

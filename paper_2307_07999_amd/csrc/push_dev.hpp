@@ -8,17 +8,19 @@
 
 namespace gl {
 
-// one particle step of slot i (i < number of slots); returns the species of
-// an active particle (-1 otherwise) and in acc its squared momenta p_x^2,
-// p_y^2, p_z^2 (lab frame) at tau_{n+1/2} and a count of 1; the series
-// reduction subtracts the species' sums of the squared momenta at formation.  Loads
-// are grouped so that a wave makes three dependent trips to memory: the
-// particle state (all of it, before the activity test), the site fields and
-// phi of its cell, and the links of both crossings together.
-template <typename T>
-__device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const FieldPtrs<T> &f,
-                                             const T *__restrict__ F, const SpeciesTab<T> &tab, int n,
-                                             T dtau, double *acc) {
+// One particle step: the particle in slot i of P is written to slot j of W
+// (the same slot of the same arrays, or its sorted position in the other
+// buffer; with MOVE, also a particle that is not pushed).  Returns the
+// species of an active particle (-1 otherwise) and in acc its squared
+// momenta p_x^2, p_y^2, p_z^2 (lab frame) at tau_{n+1/2} and a count of 1;
+// the series reduction subtracts the species' sums of the squared momenta at
+// formation.  Loads are grouped so that a wave makes three dependent trips
+// to memory: the particle state (all of it, before the activity test), the
+// site fields and phi of its cell, and the links of both crossings together.
+template <typename T, bool MOVE = false>
+__device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const PartPtrs<T> &W, int64_t j,
+                                             const FieldPtrs<T> &f, const T *__restrict__ F,
+                                             const SpeciesTab<T> &tab, int n, T dtau, double *acc) {
     const size_t n2 = plane_pitch(N);
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
     const int s = el_ld(P.species, i);
@@ -100,8 +102,8 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         else if (sy < 0) transport_nd(uy, herm_from_alg(q), q);
         ox -= (T)sx;
         oy -= (T)sy;
-        el_st(P.cx, i, cx1);
-        el_st(P.cy, i, cy1);
+        el_st(W.cx, j, cx1);
+        el_st(W.cy, j, cy1);
         r[kOx] = ox;
         r[kOy] = oy;
         r[kEta] = eta_new;
@@ -111,7 +113,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 #pragma unroll
         for (int a = 0; a < 8; a++) r[kQ + a] = q[a];
 #pragma unroll
-        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(P.st, (size_t)P.cap, (size_t)i, k, r + k);
+        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(W.st, (size_t)W.cap, (size_t)j, k, r + k);
         // broadening at tau_{n+1/2}, accumulated in FP64
         const double etab = 0.5 * ((double)eta_old + (double)eta_new);
         // sinh and cosh from one expm1 (exact-to-rounding for small rapidities)
@@ -122,6 +124,11 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         acc[1] = (double)pl[1] * pl[1];
         acc[2] = pzlab * pzlab;
         acc[3] = 1.0;
+    } else if (MOVE) {
+        el_st(W.cx, j, cx);
+        el_st(W.cy, j, cy);
+#pragma unroll
+        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(W.st, (size_t)W.cap, (size_t)j, k, r + k);
     }
     return active ? s : -1;
 }

@@ -149,9 +149,10 @@ k_permute(PartPtrs<T> src, PartPtrs<T> dst, const int32_t *__restrict__ perm, in
     id_dst[j] = id_src[i];
 }
 
+// The sorted order of the n slots of src by cell: perm[j] is the slot that
+// goes to position j (in the sort scratch, see sort_perm).
 template <typename T>
-hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtrs<T> dst, int64_t n,
-                                 SortScratch s, int32_t *id_src, int32_t *id_dst) {
+hipError_t launch_sort_order(hipStream_t st, int N, PartPtrs<T> src, int64_t n, SortScratch s) {
     if (n <= 0) return hipSuccess;
     const int64_t tiles = sort_tiles(n);
     unsigned b256 = (unsigned)((n + 255) / 256);
@@ -171,13 +172,37 @@ hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtr
         if (e != hipSuccess) return e;
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_permute<T>, dim3(b256), dim3(256), 0, st, src, dst, s.vals[cur], n, id_src, id_dst);
+    return hipSuccess;
+}
+
+// three digit passes leave the permutation in the second value buffer
+const int32_t *sort_perm(SortScratch s) { return s.vals[1]; }
+
+template <typename T>
+hipError_t launch_permute(hipStream_t st, PartPtrs<T> src, PartPtrs<T> dst, const int32_t *perm, int64_t n,
+                          int32_t *id_src, int32_t *id_dst) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, perm, n, id_src,
+                       id_dst);
     return hipGetLastError();
 }
 
-template hipError_t launch_sort_particles<double>(hipStream_t, int, PartPtrs<double>, PartPtrs<double>,
-                                                  int64_t, SortScratch, int32_t *, int32_t *);
-template hipError_t launch_sort_particles<float>(hipStream_t, int, PartPtrs<float>, PartPtrs<float>,
-                                                 int64_t, SortScratch, int32_t *, int32_t *);
+template <typename T>
+hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtrs<T> dst, int64_t n,
+                                 SortScratch s, int32_t *id_src, int32_t *id_dst) {
+    hipError_t e = launch_sort_order<T>(st, N, src, n, s);
+    if (e != hipSuccess) return e;
+    return launch_permute<T>(st, src, dst, sort_perm(s), n, id_src, id_dst);
+}
+
+#define GL_INST(T)                                                                                            \
+    template hipError_t launch_sort_particles<T>(hipStream_t, int, PartPtrs<T>, PartPtrs<T>, int64_t, SortScratch, \
+                                                 int32_t *, int32_t *);                                          \
+    template hipError_t launch_sort_order<T>(hipStream_t, int, PartPtrs<T>, int64_t, SortScratch);                \
+    template hipError_t launch_permute<T>(hipStream_t, PartPtrs<T>, PartPtrs<T>, const int32_t *, int64_t,        \
+                                          int32_t *, int32_t *);
+GL_INST(double)
+GL_INST(float)
+#undef GL_INST
 
 }  // namespace gl

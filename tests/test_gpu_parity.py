@@ -299,6 +299,40 @@ def test_particle_sort_is_transparent_and_deterministic(gl, orc):
     assert np.array_equal(results[3][0]["p"], results[0][0]["p"])
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_sort_applied_by_the_next_push_is_bitwise_transparent(gl, prec):
+    """Within a run a due sort only computes the sorted order, and the next
+    push moves each particle to its sorted slot while pushing it.  That must
+    give bitwise the same particles and series as sorting at once (stepwise
+    field steps and pushes), also when the run ends right after a sort is due
+    and when it is split into two runs."""
+    N = 48
+    out = []
+    for mode in ("run", "stepwise", "split"):
+        ev = _event(gl, N, 6.0, prec=prec, max_particles=5000, max_steps=30)
+        ev.set_sort_period(3)
+        ev.init_glasma(1.0, 0.2, 2, 11)
+        ev.add_species(1.27, 5.0, gl.KIND_HEAVY_QUARK, 2000, 3)
+        ev.add_species(0.0, 10.0, gl.KIND_JET, 2500, 4)
+        if mode == "run":
+            ev.run(24)
+        elif mode == "split":
+            ev.run(9)
+            ev.run(15)
+        else:
+            for _ in range(24):
+                ev.evolve_fields(1)
+                ev.push_particles()
+        out.append((ev.get_particles(), ev.series()))
+        ev.close()
+    ref_p, ref_s = out[1]
+    for parts, ser in (out[0], out[2]):
+        assert np.array_equal(ser, ref_s)
+        for k in ("cell", "off", "p", "Q", "eta"):
+            assert np.array_equal(parts[k], ref_p[k]), k
+        assert np.isfinite(parts["Q"]).all()
+
+
 def test_static_correlator_matches_oracle(gl, orc):
     """Static quarks (Eq. (4)) on the 32^2 configuration: FP64 accumulators
     of the site fields from tau_start on, against the oracle's correlator, in
