@@ -257,12 +257,12 @@ gl_status gl_lightlike_broadening(gl_event *ev, double *out, int32_t cap, int32_
  * the stream and returns, per kernel class (0 field step, which also writes
  * the site fields when the event has particles or correlators, 1 static
  * quark and lightlike jet accumulation, 2 particle push, 3 series
- * reduction: one launch reduces the partial rows of up to 16 pushes), the
- * summed
- * milliseconds and the
- * launch counts since the last read, then clears them.  Creates HIP events
- * only (no device memory). */
-#define GL_PROF_KERNELS 4
+ * reduction: one launch reduces the partial rows of up to 16 pushes, 4 the
+ * particle push that also moves the particles to a newly sorted order, once
+ * per sort period within gl_run), the summed milliseconds and the launch
+ * counts since the last read, then clears them; ms and launches hold
+ * GL_PROF_KERNELS entries.  Creates HIP events only (no device memory). */
+#define GL_PROF_KERNELS 5
 gl_status gl_profile_enable(gl_event *ev, int32_t period);
 gl_status gl_profile_read(gl_event *ev, double *ms, int64_t *launches);
 

@@ -155,7 +155,7 @@ struct gl_event {
 
     // kernel timing: pairs of events per launch, grouped by kernel class
     int32_t prof = 0;                       // time every prof-th launch of each class (0: off)
-    int64_t prof_count[GL_PROF_KERNELS] = {0, 0, 0, 0};
+    int64_t prof_count[GL_PROF_KERNELS] = {};
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> prof_marks;   // (class, index of start event)
@@ -314,7 +314,7 @@ gl_status push(gl_event *ev) {
     if (ev->pend == 0) ev->pend_row0 = row;
     if (ev->perm_pending) {
         const int nb = 1 - ev->pbuf;
-        PROF(ev, 2, (launch_push_permuted<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->parts<T>(nb),
+        PROF(ev, 4, (launch_push_permuted<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->parts<T>(nb),
                                              sort_perm(ev->scratch()), ev->ids(ev->pbuf), ev->ids(nb),
                                              ev->slots_used, ev->fields<T>(1 - ev->cur),
                                              (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev,

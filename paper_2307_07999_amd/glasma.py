@@ -374,11 +374,11 @@ class Event:
         return check(lib().gl_profile_enable(self._h, period if on else 0))
 
     def profile_read(self):
-        """(ms[4], launches[4]) of the timed launches per kernel class: field step
+        """(ms[5], launches[5]) of the timed launches per kernel class: field step
         (with the site fields), correlators, push, series reduction (one launch per
-        up to 16 pushes)."""
-        ms = np.zeros(4)
-        cnt = np.zeros(4, np.int64)
+        up to 16 pushes), push that also applies a sort (once per sort period)."""
+        ms = np.zeros(5)
+        cnt = np.zeros(5, np.int64)
         check(lib().gl_profile_read(self._h, _d(ms), cnt.ctypes.data_as(_I64)))
         return ms, cnt
 
