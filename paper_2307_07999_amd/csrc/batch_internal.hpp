@@ -19,6 +19,9 @@ struct BatchEv {
     const double *p0sum;   // [kMaxSpecies][4]: sums of the squared momenta at formation
     double *series;        // [max_steps][kMaxSpecies][4]
     SpeciesTab<T> tab;
+    SortScratch sort;      // the event's radix-sort scratch
+    int64_t sort_tiles;    // sort tiles over n_slots
+    int32_t *ids[2];       // particle ids, alternating with P
 };
 
 struct BatchCtl {
@@ -30,6 +33,12 @@ constexpr int kBatchShapes = 3;   // field-kernel site tiles 32x4, 64x2, 16x8 (t
 template <typename T>
 hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs, const int2 *tiles, int64_t total,
                                int fpar, const BatchCtl *ctl, double dtau, int grid);
+// the particle sort of every event (buffer parity ppar to ppar ^ 1), one
+// launch per phase; pblocks (event, particle block) and stiles (event, sort
+// tile) cover each event's used slots
+template <typename T>
+hipError_t launch_batch_sort(hipStream_t st, const BatchEv<T> *evs, int n_events, const int2 *pblocks,
+                             int64_t n_pblocks, const int2 *stiles, int64_t n_stiles, int ppar);
 template <typename T>
 hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *blocks, int64_t total, int fpar,
                              int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events);

@@ -1253,8 +1253,8 @@ struct gl_batch {
     double dtau = 0.125;
     hipStream_t stream = nullptr;
     char *ws = nullptr;
-    size_t desc = 0, tiles[kBatchShapes] = {0, 0, 0}, pblocks = 0, ctl = 0;
-    int64_t total_tiles[kBatchShapes] = {0, 0, 0}, total_pblocks = 0;
+    size_t desc = 0, tiles[kBatchShapes] = {0, 0, 0}, pblocks = 0, stiles = 0, ctl = 0;
+    int64_t total_tiles[kBatchShapes] = {0, 0, 0}, total_pblocks = 0, total_stiles = 0;
     int shape = 0, grid_mult = 4, cus = 256;
     int fpar = 0, ppar = 0;
     int64_t since_sort = 0;
@@ -1268,8 +1268,8 @@ struct gl_batch {
 namespace {
 
 struct BatchSizes {
-    size_t desc, tiles[kBatchShapes], pblocks, ctl, total;
-    int64_t n_tiles[kBatchShapes], n_pblocks;
+    size_t desc, tiles[kBatchShapes], pblocks, stiles, ctl, total;
+    int64_t n_tiles[kBatchShapes], n_pblocks, n_stiles;
 };
 
 const int kShapeTX[kBatchShapes] = {32, 64, 16}, kShapeTY[kBatchShapes] = {4, 2, 8};
@@ -1295,6 +1295,9 @@ gl_status batch_sizes(gl_event *const *evs, int n, BatchSizes &z) {
     z.n_pblocks = 0;
     for (int e = 0; e < n; e++) z.n_pblocks += evs[e]->L.slots / kPushBlock;
     z.pblocks = take((size_t)std::max<int64_t>(1, z.n_pblocks) * sizeof(int2));
+    z.n_stiles = 0;
+    for (int e = 0; e < n; e++) z.n_stiles += evs[e]->slots_used > 0 ? sort_tiles(evs[e]->slots_used) : 0;
+    z.stiles = take((size_t)std::max<int64_t>(1, z.n_stiles) * sizeof(int2));
     z.ctl = take(sizeof(BatchCtl));
     z.total = off;
     return GL_OK;
@@ -1318,6 +1321,10 @@ BatchEv<T> batch_desc(const gl_batch *b, int e) {
     d.p0sum = ev->p0sum();
     d.series = ev->series();
     d.tab = ev->tab<T>();
+    d.sort = ev->scratch();
+    d.sort_tiles = ev->slots_used > 0 ? sort_tiles(ev->slots_used) : 0;
+    d.ids[0] = ev->ids(b->pbuf0[e]);
+    d.ids[1] = ev->ids(1 - b->pbuf0[e]);
     return d;
 }
 
@@ -1333,13 +1340,8 @@ gl_status batch_step(gl_batch *b) {
     b->fpar ^= 1;
     b->since_sort++;
     if (b->any_particles && b->sort_every > 0 && b->since_sort >= b->sort_every) {
-        for (size_t e = 0; e < b->evs.size(); e++) {
-            gl_event *ev = b->evs[e];
-            if (ev->slots_used == 0) continue;
-            int src = b->pbuf0[e] ^ b->ppar;
-            HIP_TRY(launch_sort_particles<T>(b->stream, ev->N, ev->parts<T>(src), ev->parts<T>(1 - src),
-                                             ev->slots_used, ev->scratch(), ev->ids(src), ev->ids(1 - src)));
-        }
+        HIP_TRY(launch_batch_sort<T>(b->stream, d, (int)b->evs.size(), (const int2 *)(b->ws + b->pblocks),
+                                     b->total_pblocks, (const int2 *)(b->ws + b->stiles), b->total_stiles, b->ppar));
         b->ppar ^= 1;
         b->since_sort = 0;
     }
@@ -1530,6 +1532,7 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
         b->total_tiles[k] = z.n_tiles[k];
     }
     b->pblocks = z.pblocks;
+    b->stiles = z.stiles;
     b->ctl = z.ctl;
     for (auto *ev : b->evs) {
         b->cur0.push_back(ev->cur);
@@ -1567,6 +1570,14 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
     for (int e = 0; e < n_events; e++)
         for (int64_t j = 0; j < evs[e]->slots_used / kPushBlock; j++) pb.push_back(make_int2(e, (int)j));
     b->total_pblocks = (int64_t)pb.size();
+    std::vector<int2> stl;
+    for (int e = 0; e < n_events; e++)
+        if (evs[e]->slots_used > 0)
+            for (int64_t j = 0; j < sort_tiles(evs[e]->slots_used); j++) stl.push_back(make_int2(e, (int)j));
+    b->total_stiles = (int64_t)stl.size();
+    if (!stl.empty() && hipMemcpyAsync(b->ws + b->stiles, stl.data(), stl.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                       b->stream) != hipSuccess)
+        return cleanup(fail(GL_EDEVICE, "sort table upload failed"));
     BatchCtl c;
     c.n = e0->n;
     if ((!pb.empty() && hipMemcpyAsync(b->ws + b->pblocks, pb.data(), pb.size() * sizeof(int2), hipMemcpyHostToDevice,

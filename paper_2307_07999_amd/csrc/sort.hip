@@ -5,7 +5,7 @@
 // passes, deterministic: counts per (digit, workgroup), a per-digit scan over
 // workgroups, and a stable scatter whose in-workgroup ranks come from wave64
 // ballots.
-#include "internal.hpp"
+#include "batch_internal.hpp"
 #include "su3.hpp"
 
 namespace gl {
@@ -17,38 +17,38 @@ constexpr int kDigits = 256;
 
 int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
+// ---- the phases, for one tile (workgroup) of one sort ---------------------
+
+// key and initial value of slot i < n
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_sort_keys(PartPtrs<T> P, int64_t n, int N, uint32_t *__restrict__ keys, int32_t *__restrict__ vals) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void sort_key_one(const PartPtrs<T> &P, int64_t i, int N, uint32_t *__restrict__ keys,
+                                             int32_t *__restrict__ vals) {
     keys[i] = P.species[i] >= 0 ? (uint32_t)(P.cx[i] + N * P.cy[i]) : 0xFFFFFu;
     vals[i] = (int32_t)i;
 }
 
-__global__ void __launch_bounds__(kSortThreads)
-k_radix_count(const uint32_t *__restrict__ keys, int64_t n, int shift, int64_t tiles,
-              uint32_t *__restrict__ counts) {
+// per-digit counts of tile `tile` (kSortTile keys), stored digit-major:
+// counts[d * tiles + tile]
+__device__ __forceinline__ void radix_count_tile(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                                                 int64_t tiles, int64_t tile, uint32_t *__restrict__ counts) {
     __shared__ uint32_t h[kDigits];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    int64_t base = tile * kSortTile + (int64_t)threadIdx.x * kSortItems;
 #pragma unroll
     for (int k = 0; k < kSortItems; k++) {
         int64_t i = base + k;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFF], 1u);
     }
     __syncthreads();
-    counts[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+    counts[(size_t)threadIdx.x * tiles + tile] = h[threadIdx.x];
 }
 
-// per digit d (one workgroup each): exclusive scan of counts[d][0..tiles) in
-// place, and the digit's total
-__global__ void __launch_bounds__(256)
-k_scan_rows(uint32_t *__restrict__ counts, int64_t tiles, uint32_t *__restrict__ totals) {
+// exclusive scan of one digit's row of per-tile counts in place (256
+// threads), and the digit's total
+__device__ __forceinline__ void scan_row(uint32_t *__restrict__ row, int64_t tiles, uint32_t *__restrict__ total) {
     __shared__ uint32_t part[256];
     const int t = threadIdx.x;
-    uint32_t *row = counts + (size_t)blockIdx.x * tiles;
     int64_t chunk = (tiles + 255) / 256;
     int64_t lo = t * chunk, hi = lo + chunk < tiles ? lo + chunk : tiles;
     uint32_t s = 0;
@@ -67,14 +67,15 @@ k_scan_rows(uint32_t *__restrict__ counts, int64_t tiles, uint32_t *__restrict__
         row[i] = run;
         run += v;
     }
-    if (t == 255) totals[blockIdx.x] = part[255];
+    if (t == 255) *total = part[255];
 }
 
-__global__ void __launch_bounds__(kSortThreads)
-k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n,
-                int shift, int64_t tiles, const uint32_t *__restrict__ offs,
-                const uint32_t *__restrict__ totals, uint32_t *__restrict__ kout,
-                int32_t *__restrict__ vout) {
+// stable scatter of tile `tile` by the digit at `shift`
+__device__ __forceinline__ void radix_scatter_tile(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
+                                                   int64_t n, int shift, int64_t tiles, int64_t tile,
+                                                   const uint32_t *__restrict__ offs,
+                                                   const uint32_t *__restrict__ totals, uint32_t *__restrict__ kout,
+                                                   int32_t *__restrict__ vout) {
     __shared__ uint32_t wcount[kSortThreads / 64][kDigits];
     __shared__ uint32_t running[kDigits];
     __shared__ uint32_t gstart[kDigits];
@@ -88,7 +89,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vi
         gstart[t] += v;
         __syncthreads();
     }
-    uint32_t base = (t > 0 ? gstart[t - 1] : 0u) + offs[(size_t)t * tiles + blockIdx.x];
+    uint32_t base = (t > 0 ? gstart[t - 1] : 0u) + offs[(size_t)t * tiles + tile];
     __syncthreads();
     gstart[t] = base;
     running[t] = 0;
@@ -97,7 +98,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vi
 #pragma unroll
         for (int w = 0; w < kSortThreads / 64; w++) wcount[w][t] = 0;
         __syncthreads();
-        int64_t i = (int64_t)blockIdx.x * kSortTile + (int64_t)r * kSortThreads + t;
+        int64_t i = tile * kSortTile + (int64_t)r * kSortThreads + t;
         bool valid = i < n;
         uint32_t key = valid ? kin[i] : 0u;
         uint32_t d = (key >> shift) & 0xFF;
@@ -127,12 +128,11 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vi
     }
 }
 
+// position j of dst takes every array of slot perm[j] of src
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_permute(PartPtrs<T> src, PartPtrs<T> dst, const int32_t *__restrict__ perm, int64_t n,
-          int32_t *__restrict__ id_src, int32_t *__restrict__ id_dst) {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
+__device__ __forceinline__ void permute_one(const PartPtrs<T> &src, const PartPtrs<T> &dst,
+                                            const int32_t *__restrict__ perm, int64_t j,
+                                            const int32_t *__restrict__ id_src, int32_t *__restrict__ id_dst) {
     int64_t i = perm[j];
     dst.cx[j] = src.cx[i];
     dst.cy[j] = src.cy[i];
@@ -147,6 +147,93 @@ k_permute(PartPtrs<T> src, PartPtrs<T> dst, const int32_t *__restrict__ perm, in
     dst.py0[j] = src.py0[i];
     dst.pz0[j] = src.pz0[i];
     id_dst[j] = id_src[i];
+}
+
+// ---- single-sort kernels ----------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_keys(PartPtrs<T> P, int64_t n, int N, uint32_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) sort_key_one(P, i, N, keys, vals);
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_count(const uint32_t *__restrict__ keys, int64_t n, int shift, int64_t tiles,
+              uint32_t *__restrict__ counts) {
+    radix_count_tile(keys, n, shift, tiles, blockIdx.x, counts);
+}
+
+// per digit d (one workgroup each): exclusive scan of counts[d][0..tiles) in
+// place, and the digit's total
+__global__ void __launch_bounds__(256)
+k_scan_rows(uint32_t *__restrict__ counts, int64_t tiles, uint32_t *__restrict__ totals) {
+    scan_row(counts + (size_t)blockIdx.x * tiles, tiles, totals + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n,
+                int shift, int64_t tiles, const uint32_t *__restrict__ offs,
+                const uint32_t *__restrict__ totals, uint32_t *__restrict__ kout,
+                int32_t *__restrict__ vout) {
+    radix_scatter_tile(kin, vin, n, shift, tiles, blockIdx.x, offs, totals, kout, vout);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_permute(PartPtrs<T> src, PartPtrs<T> dst, const int32_t *__restrict__ perm, int64_t n,
+          int32_t *__restrict__ id_src, int32_t *__restrict__ id_dst) {
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < n) permute_one(src, dst, perm, j, id_src, id_dst);
+}
+
+// ---- batched kernels: one launch per phase for all events of a batch -------
+// Work tables: pblocks (event, block of kPushBlock slots) over each event's
+// used slots, stiles (event, sort tile); an event's particles move from
+// buffer parity ppar to ppar ^ 1.
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_batch_sort_keys(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ pblocks, int ppar) {
+    const int2 w = pblocks[blockIdx.x];
+    const BatchEv<T> &e = evs[w.x];
+    const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
+    if (i < e.n_slots) sort_key_one(e.P[ppar], i, e.N, e.sort.keys[0], e.sort.vals[0]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSortThreads)
+k_batch_radix_count(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ stiles, int shift, int cur) {
+    const int2 w = stiles[blockIdx.x];
+    const BatchEv<T> &e = evs[w.x];
+    radix_count_tile(e.sort.keys[cur], e.n_slots, shift, e.sort_tiles, w.y, e.sort.counts);
+}
+
+// workgroup e * 256 + d scans digit d of event e
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_scan_rows(const BatchEv<T> *__restrict__ evs) {
+    const BatchEv<T> &e = evs[blockIdx.x >> 8];
+    const int d = blockIdx.x & 255;
+    if (e.n_slots <= 0) return;
+    scan_row(e.sort.counts + (size_t)d * e.sort_tiles, e.sort_tiles, e.sort.totals + d);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSortThreads)
+k_batch_radix_scatter(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ stiles, int shift, int cur) {
+    const int2 w = stiles[blockIdx.x];
+    const BatchEv<T> &e = evs[w.x];
+    radix_scatter_tile(e.sort.keys[cur], e.sort.vals[cur], e.n_slots, shift, e.sort_tiles, w.y, e.sort.counts,
+                       e.sort.totals, e.sort.keys[cur ^ 1], e.sort.vals[cur ^ 1]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_batch_permute(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ pblocks, int ppar) {
+    const int2 w = pblocks[blockIdx.x];
+    const BatchEv<T> &e = evs[w.x];
+    const int64_t j = (int64_t)w.y * kPushBlock + threadIdx.x;
+    if (j < e.n_slots) permute_one(e.P[ppar], e.P[ppar ^ 1], e.sort.vals[1], j, e.ids[ppar], e.ids[ppar ^ 1]);
 }
 
 // The sorted order of the n slots of src by cell: perm[j] is the slot that
@@ -195,12 +282,36 @@ hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtr
     return launch_permute<T>(st, src, dst, sort_perm(s), n, id_src, id_dst);
 }
 
+// the sort of every event of a batch by cell, from buffer parity ppar to
+// ppar ^ 1: keys, three digit passes (count, scan, scatter) and the
+// permutation, one launch each for all events
+template <typename T>
+hipError_t launch_batch_sort(hipStream_t st, const BatchEv<T> *evs, int n_events, const int2 *pblocks,
+                             int64_t n_pblocks, const int2 *stiles, int64_t n_stiles, int ppar) {
+    if (n_pblocks <= 0 || n_stiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_sort_keys<T>, dim3((unsigned)n_pblocks), dim3(256), 0, st, evs, pblocks, ppar);
+    int cur = 0;
+    for (int pass = 0; pass < 3; pass++) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_batch_radix_count<T>, dim3((unsigned)n_stiles), dim3(kSortThreads), 0, st, evs, stiles,
+                           shift, cur);
+        hipLaunchKernelGGL(k_batch_scan_rows<T>, dim3((unsigned)n_events * kDigits), dim3(256), 0, st, evs);
+        hipLaunchKernelGGL(k_batch_radix_scatter<T>, dim3((unsigned)n_stiles), dim3(kSortThreads), 0, st, evs,
+                           stiles, shift, cur);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_batch_permute<T>, dim3((unsigned)n_pblocks), dim3(256), 0, st, evs, pblocks, ppar);
+    return hipGetLastError();
+}
+
 #define GL_INST(T)                                                                                            \
     template hipError_t launch_sort_particles<T>(hipStream_t, int, PartPtrs<T>, PartPtrs<T>, int64_t, SortScratch, \
                                                  int32_t *, int32_t *);                                          \
     template hipError_t launch_sort_order<T>(hipStream_t, int, PartPtrs<T>, int64_t, SortScratch);                \
     template hipError_t launch_permute<T>(hipStream_t, PartPtrs<T>, PartPtrs<T>, const int32_t *, int64_t,        \
-                                          int32_t *, int32_t *);
+                                          int32_t *, int32_t *);                                                  \
+    template hipError_t launch_batch_sort<T>(hipStream_t, const BatchEv<T> *, int, const int2 *, int64_t,         \
+                                             const int2 *, int64_t, int);
 GL_INST(double)
 GL_INST(float)
 #undef GL_INST
