@@ -189,7 +189,7 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
         eb[a] = e[a];
         e[a] += dtau * fe[a];
     }
-    chunk_store_n_l<8>(Eout, n2, x, 8 * d, e);
+    chunk_store_n_l<8, kStream<T>>(Eout, n2, x, 8 * d, e);   // the new state is streamed
     M3<T> un = mul(expi_alg(e, s), u);
     if (reunit) un = reunitarize(un);
     T uv[18];
@@ -200,7 +200,7 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
             uv[2 * (3 * i + j)] = un.re[i][j];
             uv[2 * (3 * i + j) + 1] = un.im[i][j];
         }
-    chunk_store_link_l(Uout, n2, x, d, uv);
+    chunk_store_link_l<kStream<T>>(Uout, n2, x, d, uv);
     if (F) {
         T t[8];
 #pragma unroll
@@ -347,8 +347,8 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
         phn[k] = (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn[k];
         ez[k] = T(0.5) * (pv[k] + pn[k]);
     }
-    chunk_store_n_l<4>(out.pi, n2, x, 4 * d, pn);
-    chunk_store_n_l<4>(out.phi, n2, x, 4 * d, phn);
+    chunk_store_n_l<4, kStream<T>>(out.pi, n2, x, 4 * d, pn);
+    chunk_store_n_l<4, kStream<T>>(out.phi, n2, x, 4 * d, phn);
     if (F) chunk_store_n_l<4>(F, n2, x, 16 + 4 * d, ez);
 }
 

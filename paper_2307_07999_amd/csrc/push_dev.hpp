@@ -23,12 +23,13 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
                                              const SpeciesTab<T> &tab, int n, T dtau, double *acc) {
     const size_t n2 = plane_pitch(N);
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
-    const int s = el_ld(P.species, i);
-    int cx = el_ld(P.cx, i), cy = el_ld(P.cy, i);
+    constexpr int CP = kStream<T>;   // the particle arrays are streamed
+    const int s = el_ld_i32<CP>(P.species, i);
+    int cx = el_ld_i32<CP>(P.cx, i), cy = el_ld_i32<CP>(P.cy, i);
     // the state record in 16-byte loads
     T r[kPartRec];
 #pragma unroll
-    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_ld16(P.st, (size_t)P.cap, (size_t)i, k, r + k);
+    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_ld16<CP>(P.st, (size_t)P.cap, (size_t)i, k, r + k);
     T q[8];
 #pragma unroll
     for (int a = 0; a < 8; a++) q[a] = r[kQ + a];
@@ -102,8 +103,8 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         else if (sy < 0) transport_nd(uy, herm_from_alg(q), q);
         ox -= (T)sx;
         oy -= (T)sy;
-        el_st(W.cx, j, cx1);
-        el_st(W.cy, j, cy1);
+        el_st_i32<CP>(W.cx, j, cx1);
+        el_st_i32<CP>(W.cy, j, cy1);
         r[kOx] = ox;
         r[kOy] = oy;
         r[kEta] = eta_new;
@@ -113,7 +114,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 #pragma unroll
         for (int a = 0; a < 8; a++) r[kQ + a] = q[a];
 #pragma unroll
-        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(W.st, (size_t)W.cap, (size_t)j, k, r + k);
+        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16<CP>(W.st, (size_t)W.cap, (size_t)j, k, r + k);
         // broadening at tau_{n+1/2}, accumulated in FP64
         const double etab = 0.5 * ((double)eta_old + (double)eta_new);
         // sinh and cosh from one expm1 (exact-to-rounding for small rapidities)
@@ -125,10 +126,10 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         acc[2] = pzlab * pzlab;
         acc[3] = 1.0;
     } else if (MOVE) {
-        el_st(W.cx, j, cx);
-        el_st(W.cy, j, cy);
+        el_st_i32<CP>(W.cx, j, cx);
+        el_st_i32<CP>(W.cy, j, cy);
 #pragma unroll
-        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(W.st, (size_t)W.cap, (size_t)j, k, r + k);
+        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16<CP>(W.st, (size_t)W.cap, (size_t)j, k, r + k);
     }
     return active ? s : -1;
 }

@@ -489,6 +489,18 @@ __device__ __forceinline__ T row_sum(T v) {
 // bits.  Offsets x may include a whole number of planes (a lane-dependent
 // choice of planes).
 constexpr int kBufConfig = 0x00020000;   // raw 32-bit data, gfx9-family layout
+// cache-policy operand of a buffer access: the non-temporal hint, for data
+// read or written once per kernel and not again until much other traffic
+// has passed (it then leaves the caches to data that is reused).
+// kStream<T> is the policy of such streamed arrays in precision T: in FP64
+// the working set of a step (field state, site fields, particles: over
+// 400 MB at 512^2) overflows the 256 MB last-level cache, and streaming the
+// particle records and the new field state keeps the gathered site fields
+// cached (push 113 -> 94 us); in FP32 it all fits, and the hint only sends
+// the next kernel's inputs to HBM (step 89 -> 100 us), so FP32 uses none.
+constexpr int kNonTemporal = 2;
+template <typename T>
+constexpr int kStream = sizeof(T) == 8 ? kNonTemporal : 0;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7FFFFFFF, kBufConfig);
@@ -531,6 +543,15 @@ template <typename T>
 __device__ __forceinline__ void el_st(T *p, size_t x, T v) {
     bst(buf(p), (uint32_t)(x * sizeof(T)), 0u, v);
 }
+// element x of a 32-bit integer array with the cache policy CP
+template <int CP>
+__device__ __forceinline__ int32_t el_ld_i32(const int32_t *p, size_t x) {
+    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(buf(p), (uint32_t)(x * 4), 0u, CP);
+}
+template <int CP>
+__device__ __forceinline__ void el_st_i32(int32_t *p, size_t x, int32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v, buf(p), (uint32_t)(x * 4), 0u, CP);
+}
 
 // Chunked planes: values are grouped in 16-byte chunks of NV = 16 /
 // sizeof(T) consecutive values k; chunk plane k / NV holds the chunks of
@@ -542,13 +563,13 @@ __device__ __forceinline__ T chunk_ld(const T *p, size_t n2, size_t x, int k) {
     constexpr int NV = 16 / (int)sizeof(T);
     return bld(buf(p), (uint32_t)(x * 16 + (k % NV) * sizeof(T)), (uint32_t)((size_t)(k / NV) * n2 * 16), T());
 }
-template <typename T>
+template <int CP = 0, typename T>
 __device__ __forceinline__ void chunk_ld16(const T *p, size_t n2, size_t x, int k, T *out) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     struct V { T v[16 / sizeof(T)]; };
     constexpr int NV = 16 / (int)sizeof(T);
     const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(buf(p), (uint32_t)(x * 16),
-                                                          (uint32_t)((size_t)(k / NV) * n2 * 16), 0);
+                                                          (uint32_t)((size_t)(k / NV) * n2 * 16), CP);
     const V r = __builtin_bit_cast(V, w);
 #pragma unroll
     for (int i = 0; i < NV; i++) out[i] = r.v[i];
@@ -559,7 +580,7 @@ __device__ __forceinline__ void chunk_ld16(const T *p, size_t n2, size_t x, int 
 // hazard is also there with one: the data of a 16-byte store was overwritten
 // by the next instruction in a few lanes.  Every 16-byte store therefore puts
 // its whole offset in the vector offset and passes a constant zero soffset.
-template <typename T>
+template <int CP = 0, typename T>
 __device__ __forceinline__ void chunk_st16(T *p, size_t n2, size_t x, int k, const T *in) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     struct V { T v[16 / sizeof(T)]; };
@@ -568,7 +589,7 @@ __device__ __forceinline__ void chunk_st16(T *p, size_t n2, size_t x, int k, con
 #pragma unroll
     for (int i = 0; i < NV; i++) r.v[i] = in[i];
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p),
-                                           (uint32_t)((x + (size_t)(k / NV) * n2) * 16), 0u, 0);
+                                           (uint32_t)((x + (size_t)(k / NV) * n2) * 16), 0u, CP);
 }
 
 template <typename T>
@@ -613,21 +634,22 @@ __device__ __forceinline__ void chunk_ld16_l(const T *p, size_t n2, size_t x, in
 #pragma unroll
     for (int i = 0; i < (int)(16 / sizeof(T)); i++) out[i] = r.v[i];
 }
-template <typename T>
+template <int CP = 0, typename T>
 __device__ __forceinline__ void chunk_st16_l(T *p, size_t n2, size_t x, int k, const T *in) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     struct V { T v[16 / sizeof(T)]; };
     V r;
 #pragma unroll
     for (int i = 0; i < (int)(16 / sizeof(T)); i++) r.v[i] = in[i];
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p), chunk_off<T>(n2, x, k), 0u, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p), chunk_off<T>(n2, x, k), 0u, CP);
 }
 // values k, k + 1 of an FP32 array (k even) in one 8-byte access
+template <int CP = 0>
 __device__ __forceinline__ void chunk_st8_l(float *p, size_t n2, size_t x, int k, float a, float b) {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     struct V { float v[2]; };
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, V{{a, b}}), buf(p), chunk_off<float>(n2, x, k),
-                                          0u, 0);
+                                          0u, CP);
 }
 // n values k0.. (k0 and n multiples of 16 / sizeof(T)), lane-dependent k0
 template <int n, typename T>
@@ -635,16 +657,16 @@ __device__ __forceinline__ void chunk_load_n_l(const T *p, size_t n2, size_t x, 
 #pragma unroll
     for (int k = 0; k < n; k += 16 / (int)sizeof(T)) chunk_ld16_l(p, n2, x, k0 + k, v + k);
 }
-template <int n, typename T>
+template <int n, int CP = 0, typename T>
 __device__ __forceinline__ void chunk_store_n_l(T *p, size_t n2, size_t x, int k0, const T *v) {
 #pragma unroll
-    for (int k = 0; k < n; k += 16 / (int)sizeof(T)) chunk_st16_l(p, n2, x, k0 + k, v + k);
+    for (int k = 0; k < n; k += 16 / (int)sizeof(T)) chunk_st16_l<CP>(p, n2, x, k0 + k, v + k);
 }
 // the link of direction d + 1 (values 18d .. 18d + 17) of site x, d lane-dependent
-template <typename T>
+template <int CP = 0, typename T>
 __device__ __forceinline__ void chunk_store_link_l(T *p, size_t n2, size_t x, int d, const T *v) {
     if constexpr (sizeof(T) == 8) {
-        chunk_store_n_l<18>(p, n2, x, 18 * d, v);
+        chunk_store_n_l<18, CP>(p, n2, x, 18 * d, v);
     } else {
         // d = 0: four chunks (values 0..15) then the pair 16, 17; d = 1: the
         // pair 18, 19 then four chunks (20..35)
@@ -652,8 +674,8 @@ __device__ __forceinline__ void chunk_store_link_l(T *p, size_t n2, size_t x, in
         T w[16];
 #pragma unroll
         for (int i = 0; i < 16; i++) w[i] = lo ? v[i] : v[i + 2];
-        chunk_store_n_l<16>(p, n2, x, 18 * d + (lo ? 0 : 2), w);
-        chunk_st8_l(p, n2, x, 18 * d + (lo ? 16 : 0), lo ? v[16] : v[0], lo ? v[17] : v[1]);
+        chunk_store_n_l<16, CP>(p, n2, x, 18 * d + (lo ? 0 : 2), w);
+        chunk_st8_l<CP>(p, n2, x, 18 * d + (lo ? 16 : 0), lo ? v[16] : v[0], lo ? v[17] : v[1]);
     }
 }
 
