@@ -183,7 +183,7 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
                                             const T *fe, T dtau, T s, int reunit, T *__restrict__ F, T inv_tau) {
     const int fs = 8 * d;
     T e[8], eb[8];
-    chunk_load_n_l<8>(Ein, n2, x, 8 * d, e);
+    chunk_load_n_l<8, kStream<T>>(Ein, n2, x, 8 * d, e);   // E and pi are read once per step
 #pragma unroll
     for (int a = 0; a < 8; a++) {
         eb[a] = e[a];
@@ -340,7 +340,7 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
     update_link(in.E, out.E, ui, out.U, n2, x, xpi, d, fe, dtau, dtau / tau_h, reunit, F, inv_tau);
     // pi, phi and E_z: lane d takes colour components 4d..4d+3
     T pv[4], pn[4], phn[4], ez[4];
-    chunk_load_n_l<4>(in.pi, n2, x, 4 * d, pv);
+    chunk_load_n_l<4, kStream<T>>(in.pi, n2, x, 4 * d, pv);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         pn[k] = pv[k] + dtau * (d0 ? fpi[k] : fpi[4 + k]);

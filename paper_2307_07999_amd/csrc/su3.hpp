@@ -626,11 +626,11 @@ __device__ __forceinline__ uint32_t chunk_off(size_t n2, size_t x, int k) {
     constexpr int NV = 16 / (int)sizeof(T);
     return (uint32_t)((x + (size_t)(k / NV) * n2) * 16 + (size_t)(k % NV) * sizeof(T));
 }
-template <typename T>
+template <int CP = 0, typename T>
 __device__ __forceinline__ void chunk_ld16_l(const T *p, size_t n2, size_t x, int k, T *out) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     struct V { T v[16 / sizeof(T)]; };
-    const V r = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(buf(p), chunk_off<T>(n2, x, k), 0u, 0));
+    const V r = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(buf(p), chunk_off<T>(n2, x, k), 0u, CP));
 #pragma unroll
     for (int i = 0; i < (int)(16 / sizeof(T)); i++) out[i] = r.v[i];
 }
@@ -652,10 +652,10 @@ __device__ __forceinline__ void chunk_st8_l(float *p, size_t n2, size_t x, int k
                                           0u, CP);
 }
 // n values k0.. (k0 and n multiples of 16 / sizeof(T)), lane-dependent k0
-template <int n, typename T>
+template <int n, int CP = 0, typename T>
 __device__ __forceinline__ void chunk_load_n_l(const T *p, size_t n2, size_t x, int k0, T *v) {
 #pragma unroll
-    for (int k = 0; k < n; k += 16 / (int)sizeof(T)) chunk_ld16_l(p, n2, x, k0 + k, v + k);
+    for (int k = 0; k < n; k += 16 / (int)sizeof(T)) chunk_ld16_l<CP>(p, n2, x, k0 + k, v + k);
 }
 template <int n, int CP = 0, typename T>
 __device__ __forceinline__ void chunk_store_n_l(T *p, size_t n2, size_t x, int k0, const T *v) {
