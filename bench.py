@@ -50,9 +50,10 @@ def coupled_steps(N, L, tau_max=1.0):
 def alg_bytes(prec):
     ts = 8 if prec == 64 else 4
     return {
-        # one pass: U (36) E (16) phi (8) pi (8) read once and written once per
-        # site, and the six local-frame site fields (48) written
-        "field_step": (2 * 68 + 48) * ts,
+        # one pass: U (24: the first two rows of each link) E (16) phi (8)
+        # pi (8) read once and written once per site, and the six
+        # local-frame site fields (48) written
+        "field_step": (2 * 56 + 48) * ts,
         # state read (cell 8 B, species 4 B, 14 reals), site fields 48 + phi 8
         # reals gathered, state written (cell 8 B, 14 reals); the momenta at
         # formation enter only through per-species sums taken once

@@ -13,6 +13,7 @@
 
 #include "../../include/glasma.h"
 #include "internal.hpp"
+#include "su3.hpp"
 
 using namespace gl;
 
@@ -78,7 +79,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
         off = align256(off + bytes);
         return o;
     };
-    for (int b = 0; b < 2; b++) L.field[b] = take(68 * n2 * ts);
+    for (int b = 0; b < 2; b++) L.field[b] = take(kStateVals * n2 * ts);
     L.F = take((size_t)kSiteRec * n2 * ts);
     for (int b = 0; b < 2; b++) L.part[b] = take((size_t)L.slots * ((kPartRec + 3) * ts + 12));
     for (int b = 0; b < 2; b++) L.id[b] = take((size_t)L.slots * sizeof(int32_t));
@@ -164,7 +165,8 @@ struct gl_event {
     template <typename T>
     FieldPtrs<T> fields(int b) const {
         T *base = (T *)(ws + L.field[b]);
-        return FieldPtrs<T>{base, base + 36 * n2, base + 52 * n2, base + 60 * n2};
+        return FieldPtrs<T>{base, base + 2 * kLinkVals * n2, base + (2 * kLinkVals + 16) * n2,
+                            base + (2 * kLinkVals + 24) * n2};
     }
     template <typename T>
     PartPtrs<T> parts(int buf = -1) const {
@@ -516,11 +518,48 @@ gl_status get_site_fields_t(gl_event *ev, double *F) {
     return GL_OK;
 }
 
+// links: the host holds all 18 values of each link ([36][n2], U_1 then U_2),
+// the state its first two rows; the third row comes back as the conjugate
+// cross product of the two
+template <typename T>
+gl_status copy_in_links(gl_event *ev, void *dev, const double *host) {
+    const size_t n2 = ev->n2;
+    std::vector<double> rows((size_t)2 * kLinkVals * n2);
+    for (int d = 0; d < 2; d++)
+        for (int c = 0; c < kLinkVals; c++)
+            std::copy(host + (size_t)(18 * d + c) * n2, host + (size_t)(18 * d + c + 1) * n2,
+                      rows.begin() + (size_t)(kLinkVals * d + c) * n2);
+    return copy_in<T>(ev, dev, rows.data(), 2 * kLinkVals);
+}
+template <typename T>
+gl_status copy_out_links(gl_event *ev, double *host, const void *dev) {
+    const size_t n2 = ev->n2;
+    std::vector<double> rows((size_t)2 * kLinkVals * n2);
+    gl_status s = copy_out<T>(ev, rows.data(), dev, 2 * kLinkVals);
+    if (s) return s;
+    for (int d = 0; d < 2; d++)
+        for (size_t x = 0; x < n2; x++) {
+            auto v = [&](int c) { return rows[(size_t)(kLinkVals * d + c) * n2 + x]; };
+            for (int c = 0; c < kLinkVals; c++) host[(size_t)(18 * d + c) * n2 + x] = v(c);
+            // row 2 = conj(r0 x r1); entry (i, j) at 2(3i + j)
+            for (int k = 0; k < 3; k++) {
+                const int a = (k + 1) % 3, b = (k + 2) % 3;
+                const double r0a = v(2 * a), i0a = v(2 * a + 1), r0b = v(2 * b), i0b = v(2 * b + 1);
+                const double r1a = v(2 * (3 + a)), i1a = v(2 * (3 + a) + 1), r1b = v(2 * (3 + b)), i1b = v(2 * (3 + b) + 1);
+                const double cr = r0a * r1b - i0a * i1b - (r0b * r1a - i0b * i1a);
+                const double ci = r0a * i1b + i0a * r1b - (r0b * i1a + i0b * r1a);
+                host[(size_t)(18 * d + 2 * (6 + k)) * n2 + x] = cr;
+                host[(size_t)(18 * d + 2 * (6 + k) + 1) * n2 + x] = -ci;
+            }
+        }
+    return GL_OK;
+}
+
 template <typename T>
 gl_status set_state_t(gl_event *ev, const double *U, const double *E, const double *phi, const double *pi) {
     FieldPtrs<T> f = ev->fields<T>(ev->cur);
     gl_status s;
-    if ((s = copy_in<T>(ev, f.U, U, 36))) return s;
+    if ((s = copy_in_links<T>(ev, f.U, U))) return s;
     if ((s = copy_in<T>(ev, f.E, E, 16))) return s;
     if ((s = copy_in<T>(ev, f.phi, phi, 8))) return s;
     return copy_in<T>(ev, f.pi, pi, 8);
@@ -530,7 +569,7 @@ template <typename T>
 gl_status get_state_t(gl_event *ev, double *U, double *E, double *phi, double *pi) {
     FieldPtrs<T> f = ev->fields<T>(ev->cur);
     gl_status s;
-    if (U && (s = copy_out<T>(ev, U, f.U, 36))) return s;
+    if (U && (s = copy_out_links<T>(ev, U, f.U))) return s;
     if (E && (s = copy_out<T>(ev, E, f.E, 16))) return s;
     if (phi && (s = copy_out<T>(ev, phi, f.phi, 8))) return s;
     if (pi && (s = copy_out<T>(ev, pi, f.pi, 8))) return s;

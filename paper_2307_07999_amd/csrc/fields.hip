@@ -133,7 +133,7 @@ k_lightlike_accum(int N, const T *__restrict__ F, const T *__restrict__ U, doubl
         }
         v[3] = 1.0;
         if ((int64_t)floor((double)(j + 1) * dtau + 0.5) > shift) {
-            const M3<T> u = chunk_load_m(U, n2, c, 0);
+            const M3<T> u = chunk_load_link(U, n2, c, 0);
             M3<double> ud;
 #pragma unroll
             for (int r = 0; r < 3; r++)
@@ -173,7 +173,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
     if (ix < N && iy < N) {
         const size_t n2 = (size_t)N * N;
         Nbr nb = neighbours(ix, iy, N);
-        M3<T> u1x = chunk_load_m(f.U, n2, nb.x, 0), u2x = chunk_load_m(f.U, n2, nb.x, 18);
+        M3<T> u1x = chunk_load_link(f.U, n2, nb.x, 0), u2x = chunk_load_link(f.U, n2, nb.x, 1);
         T e1[8], e2[8], e1m[8], e2m[8], ph[8], p[8];
         chunk_load_a(f.E, n2, nb.x, 0, e1);
         chunk_load_a(f.E, n2, nb.x, 8, e2);
@@ -181,7 +181,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
         chunk_load_a(f.E, n2, nb.xm2, 8, e2m);
         chunk_load_a(f.phi, n2, nb.x, 0, ph);
         chunk_load_a(f.pi, n2, nb.x, 0, p);
-        M3<T> u1m = chunk_load_m(f.U, n2, nb.xm1, 0), u2m = chunk_load_m(f.U, n2, nb.xm2, 18);
+        M3<T> u1m = chunk_load_link(f.U, n2, nb.xm1, 0), u2m = chunk_load_link(f.U, n2, nb.xm2, 1);
         T t1[8], t2[8];
         transport_dn(u1m, herm_from_alg(e1m), t1);
         transport_dn(u2m, herm_from_alg(e2m), t2);
@@ -237,7 +237,7 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
                 bt += 0.5 * dd * dd;
             }
         }
-        M3<T> P = plaq(u1x, chunk_load_m(f.U, n2, nb.xp1, 18), chunk_load_m(f.U, n2, nb.xp2, 0), u2x);
+        M3<T> P = plaq(u1x, chunk_load_link(f.U, n2, nb.xp1, 1), chunk_load_link(f.U, n2, nb.xp2, 0), u2x);
         double bl = 3.0 - ((double)P.re[0][0] + (double)P.re[1][1] + (double)P.re[2][2]);
         v[0] = gmax;
         v[1] = emax;

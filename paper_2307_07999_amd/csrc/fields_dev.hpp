@@ -154,10 +154,22 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
         gx += gx < 0 ? N : 0;
         gy += gy < 0 ? N : 0;
         const size_t site = (size_t)gx + (size_t)N * gy;
-        // the 36 link values of the site, in 16-byte loads
-        T u[36];
+        // the stored rows of the site's two links, in 16-byte loads; each
+        // link is completed with its third row once here
+        T s[2 * kLinkVals], u[36];
 #pragma unroll
-        for (int k = 0; k < 36; k += NV) chunk_ld16(in.U, n2, site, k, u + k);
+        for (int k = 0; k < 2 * kLinkVals; k += NV) chunk_ld16(in.U, n2, site, k, s + k);
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const M3<T> m = link_from_rows(s + kLinkVals * d);
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    u[18 * d + 2 * (3 * i + j)] = m.re[i][j];
+                    u[18 * d + 2 * (3 * i + j) + 1] = m.im[i][j];
+                }
+        }
 #pragma unroll
         for (int d = 0; d < 2; d++)
 #pragma unroll

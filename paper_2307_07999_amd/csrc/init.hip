@@ -572,14 +572,26 @@ k_first_half_step(int N, const double *U0, const double *pi0, FieldPtrs<T> out, 
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
-    // the field state is stored in chunked planes
-    for (int c = 0; c < 36; c++) chunk_st(out.U, n2, x, c, (T)U0[(size_t)c * n2 + x]);
-    for (int c = 0; c < 16; c++) chunk_st(out.E, n2, x, c, T(0));
+    // the field state is stored in chunked planes, written here in whole
+    // chunks; it keeps the first two rows of each link
+    constexpr int NV = 16 / (int)sizeof(T);
+    for (int d = 0; d < 2; d++) {
+        T v[kLinkVals];
+        for (int c = 0; c < kLinkVals; c++) v[c] = (T)U0[(size_t)(18 * d + c) * n2 + x];
+        for (int c = 0; c < kLinkVals; c += NV) chunk_st16(out.U, n2, x, kLinkVals * d + c, v + c);
+    }
+    const T zero[NV] = {};
+    for (int c = 0; c < 16; c += NV) chunk_st16(out.E, n2, x, c, zero);
     const double th = 0.5 * dtau;
+    T pv[8], fv[8];
     for (int a = 0; a < 8; a++) {
         double p = pi0[(size_t)a * n2 + x];
-        chunk_st(out.pi, n2, x, a, (T)p);
-        chunk_st(out.phi, n2, x, a, (T)(dtau * th * p));
+        pv[a] = (T)p;
+        fv[a] = (T)(dtau * th * p);
+    }
+    for (int a = 0; a < 8; a += NV) {
+        chunk_st16(out.pi, n2, x, a, pv + a);
+        chunk_st16(out.phi, n2, x, a, fv + a);
     }
 }
 

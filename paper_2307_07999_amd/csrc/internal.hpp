@@ -33,8 +33,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 // One field state, each array in chunked planes over the n2 = N*N sites
 // (16-byte chunks of consecutive values; value k of site x at element
 // ((k / NV) n2 + x) NV + k mod NV, NV = 16 / sizeof(T)):
-//   U: 36 values per site, link U_i at 18 (i - 1) (entry (a,b) real at
-//   + 2(3a+b), imaginary next to it); E: 16, E_i at 8 (i - 1); phi: 8; pi: 8
+//   U: 24 values per site, the first two rows of link U_i at 12 (i - 1)
+//   (entry (a,b) real at + 2(3a+b), imaginary next to it, a = 0, 1; the
+//   third row is rebuilt where a link is read); E: 16, E_i at 8 (i - 1);
+//   phi: 8; pi: 8.  kStateVals reals per site in all.
+constexpr int kStateVals = 2 * 12 + 16 + 8 + 8;
+
 template <typename T>
 struct FieldPtrs {
     T *U;

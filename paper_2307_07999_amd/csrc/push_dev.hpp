@@ -92,8 +92,8 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const int cx1 = sx > 0 ? (cx + 1 == N ? 0 : cx + 1) : (sx < 0 ? cxm : cx);
         const int cy1 = sy > 0 ? (cy + 1 == N ? 0 : cy + 1) : (sy < 0 ? cym : cy);
         M3<T> ux, uy;
-        if (sx != 0) ux = chunk_load_m(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy, 0);
-        if (sy != 0) uy = chunk_load_m(f.U, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym), 18);
+        if (sx != 0) ux = chunk_load_link(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy, 0);
+        if (sy != 0) uy = chunk_load_link(f.U, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym), 1);
         // colour rotation along eta with phi^n at the old cell: Q <- W Q W^dag
         transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
         // crossings: Q <- U^dag Q U forward, U Q U^dag backward

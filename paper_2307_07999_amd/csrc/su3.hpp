@@ -489,6 +489,7 @@ __device__ __forceinline__ T row_sum(T v) {
 // bits.  Offsets x may include a whole number of planes (a lane-dependent
 // choice of planes).
 constexpr int kBufConfig = 0x00020000;   // raw 32-bit data, gfx9-family layout
+constexpr int kLinkVals = 12;            // stored values of a link (its first two rows)
 // cache-policy operand of a buffer access: the non-temporal hint, for data
 // read or written once per kernel and not again until much other traffic
 // has passed (it then leaves the caches to data that is reused).
@@ -592,29 +593,11 @@ __device__ __forceinline__ void chunk_st16(T *p, size_t n2, size_t x, int k, con
                                            (uint32_t)((x + (size_t)(k / NV) * n2) * 16), 0u, CP);
 }
 
+
 template <typename T>
 __device__ __forceinline__ void chunk_st(T *p, size_t n2, size_t x, int k, T v) {
     constexpr int NV = 16 / (int)sizeof(T);
     bst(buf(p), (uint32_t)(x * 16 + (k % NV) * sizeof(T)), (uint32_t)((size_t)(k / NV) * n2 * 16), v);
-}
-// values k and k + 1 (k even) in one 8-byte (FP32) or 16-byte (FP64) access
-template <typename T>
-__device__ __forceinline__ void chunk_ld2(const T *p, size_t n2, size_t x, int k, T &a, T &b) {
-    constexpr int NV = 16 / (int)sizeof(T);
-    const uint32_t vo = (uint32_t)(x * 16 + (k % NV) * sizeof(T)), so = (uint32_t)((size_t)(k / NV) * n2 * 16);
-    if constexpr (sizeof(T) == 8) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        struct V { double v[2]; };
-        const V r = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(buf(p), vo, so, 0));
-        a = r.v[0];
-        b = r.v[1];
-    } else {
-        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-        struct V { float v[2]; };
-        const V r = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(buf(p), vo, so, 0));
-        a = r.v[0];
-        b = r.v[1];
-    }
 }
 
 // Accesses whose value index differs between the lanes of a wave (the two
@@ -643,14 +626,6 @@ __device__ __forceinline__ void chunk_st16_l(T *p, size_t n2, size_t x, int k, c
     for (int i = 0; i < (int)(16 / sizeof(T)); i++) r.v[i] = in[i];
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), buf(p), chunk_off<T>(n2, x, k), 0u, CP);
 }
-// values k, k + 1 of an FP32 array (k even) in one 8-byte access
-template <int CP = 0>
-__device__ __forceinline__ void chunk_st8_l(float *p, size_t n2, size_t x, int k, float a, float b) {
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    struct V { float v[2]; };
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, V{{a, b}}), buf(p), chunk_off<float>(n2, x, k),
-                                          0u, CP);
-}
 // n values k0.. (k0 and n multiples of 16 / sizeof(T)), lane-dependent k0
 template <int n, int CP = 0, typename T>
 __device__ __forceinline__ void chunk_load_n_l(const T *p, size_t n2, size_t x, int k0, T *v) {
@@ -662,21 +637,11 @@ __device__ __forceinline__ void chunk_store_n_l(T *p, size_t n2, size_t x, int k
 #pragma unroll
     for (int k = 0; k < n; k += 16 / (int)sizeof(T)) chunk_st16_l<CP>(p, n2, x, k0 + k, v + k);
 }
-// the link of direction d + 1 (values 18d .. 18d + 17) of site x, d lane-dependent
+// the stored rows of link d + 1 of site x (values 12d .. 12d + 11) from the
+// first 12 of the link's 18 values v, d lane-dependent
 template <int CP = 0, typename T>
 __device__ __forceinline__ void chunk_store_link_l(T *p, size_t n2, size_t x, int d, const T *v) {
-    if constexpr (sizeof(T) == 8) {
-        chunk_store_n_l<18, CP>(p, n2, x, 18 * d, v);
-    } else {
-        // d = 0: four chunks (values 0..15) then the pair 16, 17; d = 1: the
-        // pair 18, 19 then four chunks (20..35)
-        const bool lo = d == 0;
-        T w[16];
-#pragma unroll
-        for (int i = 0; i < 16; i++) w[i] = lo ? v[i] : v[i + 2];
-        chunk_store_n_l<16, CP>(p, n2, x, 18 * d + (lo ? 0 : 2), w);
-        chunk_st8_l<CP>(p, n2, x, 18 * d + (lo ? 16 : 0), lo ? v[16] : v[0], lo ? v[17] : v[1]);
-    }
+    chunk_store_n_l<kLinkVals, CP>(p, n2, x, kLinkVals * d, v);
 }
 
 // A link plane set: 18 planes of n2 values, entry (i,j) real at plane 2(3i+j).
@@ -704,35 +669,54 @@ __device__ __forceinline__ void store_m(T *__restrict__ base, size_t n2, size_t 
         }
 }
 
-// The field state in chunked planes: a link is the 18 values k0..k0+17
-// (entry (i,j) real at k0 + 2(3i+j), imaginary next to it; k0 = 0 or 18,
-// the same for all lanes), an algebra vector the 8 values k0..k0+7 (k0 a
-// multiple of 4).  Links are read in whole chunks and, in FP32, one pair.
+// Links in the field state hold their first two rows, kLinkVals = 12 values
+// (entry (i,j) real at 2(3i+j), imaginary next to it, i = 0, 1): for SU(3)
+// the third row is the complex conjugate of the cross product of the first
+// two (its cofactors), rebuilt where a link is read.  Link d + 1 of a site
+// is the values 12d .. 12d + 11 of its record (three chunks in FP32, six in
+// FP64).
+
+// row 2 of m from rows 0 and 1: conj(r0 x r1)
 template <typename T>
-__device__ __forceinline__ M3<T> chunk_load_m(const T *__restrict__ p, size_t n2, size_t x, int k0) {
-    T v[18];
-    if constexpr (sizeof(T) == 8) {
+__device__ __forceinline__ void third_row(M3<T> &m) {
 #pragma unroll
-        for (int k = 0; k < 18; k += 2) chunk_ld16(p, n2, x, k0 + k, v + k);
-    } else if (k0 % 4 == 0) {
-#pragma unroll
-        for (int k = 0; k < 16; k += 4) chunk_ld16(p, n2, x, k0 + k, v + k);
-        chunk_ld2(p, n2, x, k0 + 16, v[16], v[17]);
-    } else {
-        chunk_ld2(p, n2, x, k0, v[0], v[1]);
-#pragma unroll
-        for (int k = 2; k < 18; k += 4) chunk_ld16(p, n2, x, k0 + k, v + k);
+    for (int k = 0; k < 3; k++) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        const T cr = m.re[0][a] * m.re[1][b] - m.im[0][a] * m.im[1][b] -
+                     (m.re[0][b] * m.re[1][a] - m.im[0][b] * m.im[1][a]);
+        const T ci = m.re[0][a] * m.im[1][b] + m.im[0][a] * m.re[1][b] -
+                     (m.re[0][b] * m.im[1][a] + m.im[0][b] * m.re[1][a]);
+        m.re[2][k] = cr;
+        m.im[2][k] = -ci;
     }
+}
+
+// the link from its two stored rows v[0..11]
+template <typename T>
+__device__ __forceinline__ M3<T> link_from_rows(const T *v) {
     M3<T> r;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             r.re[i][j] = v[2 * (3 * i + j)];
             r.im[i][j] = v[2 * (3 * i + j) + 1];
         }
+    third_row(r);
     return r;
 }
+
+// link d + 1 of site x (d the same for all lanes)
+template <typename T>
+__device__ __forceinline__ M3<T> chunk_load_link(const T *__restrict__ p, size_t n2, size_t x, int d) {
+    T v[kLinkVals];
+#pragma unroll
+    for (int k = 0; k < kLinkVals; k += 16 / (int)sizeof(T)) chunk_ld16(p, n2, x, kLinkVals * d + k, v + k);
+    return link_from_rows(v);
+}
+
+// an algebra vector: the 8 values k0..k0+7 (k0 a multiple of 16 / sizeof(T),
+// the same for all lanes)
 template <typename T>
 __device__ __forceinline__ void chunk_load_a(const T *__restrict__ p, size_t n2, size_t x, int k0, T *v) {
 #pragma unroll
