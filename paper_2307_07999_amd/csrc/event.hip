@@ -81,7 +81,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     };
     for (int b = 0; b < 2; b++) L.field[b] = take(kStateVals * n2 * ts);
     L.F = take((size_t)kSiteRec * n2 * ts);
-    for (int b = 0; b < 2; b++) L.part[b] = take((size_t)L.slots * ((kPartRec + 3) * ts + 12));
+    for (int b = 0; b < 2; b++) L.part[b] = take((size_t)L.slots * ((part_rec(ts) + 3) * ts + 12));
     for (int b = 0; b < 2; b++) L.id[b] = take((size_t)L.slots * sizeof(int32_t));
     for (int b = 0; b < 2; b++) L.sort_keys[b] = take((size_t)L.slots * sizeof(uint32_t));
     for (int b = 0; b < 2; b++) L.sort_vals[b] = take((size_t)L.slots * sizeof(int32_t));
@@ -178,7 +178,7 @@ struct gl_event {
         p.species = p.cy + c;
         T *t = (T *)(b + 12 * c);   // 16-byte aligned: c is a multiple of kPushBlock
         p.st = t;
-        p.px0 = t + kPartRec * c;
+        p.px0 = t + kPartRec<T> * c;
         p.py0 = p.px0 + c;
         p.pz0 = p.py0 + c;
         p.cap = c;
@@ -582,9 +582,9 @@ gl_status set_particles_t(gl_event *ev, int64_t n, const int32_t *cell, const do
     const int64_t c = ev->L.slots;
     std::vector<int32_t> cx(c, 0), cy(c, 0), sp(c, -1), id(c, -1);
     // the record planes followed by px0, py0, pz0 (contiguous on the device)
-    std::vector<T> f((kPartRec + 3) * (size_t)c, T(0));
+    std::vector<T> f((kPartRec<T> + 3) * (size_t)c, T(0));
     auto rec = [&](int k, int64_t i) -> T & { return f[chunk_index<T>((size_t)c, k, (size_t)i)]; };
-    T *f0 = f.data() + kPartRec * (size_t)c;
+    T *f0 = f.data() + kPartRec<T> * (size_t)c;
     for (int64_t i = 0; i < n; i++) {
         id[i] = (int32_t)i;
         cx[i] = cell[i];
@@ -616,9 +616,9 @@ gl_status get_particles_t(gl_event *ev, int64_t n, int32_t *cell, double *off, d
                           double *Q, double *p0, int32_t *species) {
     const int64_t c = ev->L.slots;
     std::vector<int32_t> cx(c), cy(c), sp(c), id(c);
-    std::vector<T> f((kPartRec + 3) * (size_t)c);
+    std::vector<T> f((kPartRec<T> + 3) * (size_t)c);
     auto rec = [&](int k, int64_t j) { return (double)f[chunk_index<T>((size_t)c, k, (size_t)j)]; };
-    const T *f0 = f.data() + kPartRec * (size_t)c;
+    const T *f0 = f.data() + kPartRec<T> * (size_t)c;
     PartPtrs<T> P = ev->parts<T>();
     if (c > 0) {
         HIP_TRY(hipMemcpyAsync(id.data(), ev->ids(), c * 4, hipMemcpyDeviceToHost, ev->stream));

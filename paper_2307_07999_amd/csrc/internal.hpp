@@ -48,16 +48,20 @@ struct FieldPtrs {
 };
 
 // Particle arrays, capacity cap (padded per species to kPushBlock).  The
-// state the push reads and writes every step is one record of kPartRec
-// values per slot in chunked planes over the slots (value k of slot i at
-// element ((k / NV) cap + i) NV + k mod NV): offsets within the cell, the
-// rapidity, p_x, p_y, P_eta = tau^2 p^eta and the colour charge Q^a.
-constexpr int kPartRec = 16;
-constexpr int kOx = 0, kOy = 1, kEta = 2, kPx = 3, kPy = 4, kPeta = 5, kQ = 6;   // 14, 15 unused
+// state the push reads and writes every step is one record of
+// kPartRec<T> values per slot in chunked planes over the slots (value k of
+// slot i at element ((k / NV) cap + i) NV + k mod NV): offsets within the
+// cell, the rapidity, p_x, p_y, P_eta = tau^2 p^eta and the colour charge
+// Q^a, 14 values: seven whole chunks in FP64; FP32 pads them to four chunks
+// (values 14, 15 unused).
+constexpr int kOx = 0, kOy = 1, kEta = 2, kPx = 3, kPy = 4, kPeta = 5, kQ = 6;
+constexpr int part_rec(size_t value_bytes) { return value_bytes == 8 ? 14 : 16; }
+template <typename T>
+constexpr int kPartRec = part_rec(sizeof(T));
 template <typename T>
 struct PartPtrs {
     int32_t *cx, *cy;
-    T *st;               // [kPartRec] record per slot, chunked planes
+    T *st;               // [kPartRec<T>] record per slot, chunked planes
     T *px0, *py0, *pz0;  // momenta at formation (pz0 in the lab frame)
     int32_t *species;    // -1 for padding
     int64_t cap;

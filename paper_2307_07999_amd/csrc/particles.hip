@@ -115,9 +115,9 @@ k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, 
     int cx = (int)fx, cy = (int)fy;
     P.cx[j] = cx >= N ? cx - N : cx;
     P.cy[j] = cy >= N ? cy - N : cy;
-    T r[kPartRec];
+    T r[kPartRec<T>];
 #pragma unroll
-    for (int k = 0; k < kPartRec; k++) r[k] = T(0);
+    for (int k = 0; k < kPartRec<T>; k++) r[k] = T(0);
     r[kOx] = (T)(X - fx);
     r[kOy] = (T)(Y - fy);
     w = draw(seed, (uint32_t)i, 1u, stream);
@@ -195,7 +195,7 @@ k_particles_init(int N, PartPtrs<T> P, int64_t slot0, int64_t n, uint64_t seed, 
 #pragma unroll
     for (int a = 0; a < 8; a++) r[kQ + a] = (T)q[a];
 #pragma unroll
-    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16(P.st, (size_t)P.cap, (size_t)j, k, r + k);
+    for (int k = 0; k < kPartRec<T>; k += 16 / (int)sizeof(T)) chunk_st16(P.st, (size_t)P.cap, (size_t)j, k, r + k);
 }
 
 // Per-species partial sums of the squared momenta at formation (p_x0^2,

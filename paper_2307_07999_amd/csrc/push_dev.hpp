@@ -27,9 +27,9 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
     const int s = el_ld_i32<CP>(P.species, i);
     int cx = el_ld_i32<CP>(P.cx, i), cy = el_ld_i32<CP>(P.cy, i);
     // the state record in 16-byte loads
-    T r[kPartRec];
+    T r[kPartRec<T>];
 #pragma unroll
-    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_ld16<CP>(P.st, (size_t)P.cap, (size_t)i, k, r + k);
+    for (int k = 0; k < kPartRec<T>; k += 16 / (int)sizeof(T)) chunk_ld16<CP>(P.st, (size_t)P.cap, (size_t)i, k, r + k);
     T q[8];
 #pragma unroll
     for (int a = 0; a < 8; a++) q[a] = r[kQ + a];
@@ -114,7 +114,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 #pragma unroll
         for (int a = 0; a < 8; a++) r[kQ + a] = q[a];
 #pragma unroll
-        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16<CP>(W.st, (size_t)W.cap, (size_t)j, k, r + k);
+        for (int k = 0; k < kPartRec<T>; k += 16 / (int)sizeof(T)) chunk_st16<CP>(W.st, (size_t)W.cap, (size_t)j, k, r + k);
         // broadening at tau_{n+1/2}, accumulated in FP64
         const double etab = 0.5 * ((double)eta_old + (double)eta_new);
         // sinh and cosh from one expm1 (exact-to-rounding for small rapidities)
@@ -129,7 +129,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         el_st_i32<CP>(W.cx, j, cx);
         el_st_i32<CP>(W.cy, j, cy);
 #pragma unroll
-        for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) chunk_st16<CP>(W.st, (size_t)W.cap, (size_t)j, k, r + k);
+        for (int k = 0; k < kPartRec<T>; k += 16 / (int)sizeof(T)) chunk_st16<CP>(W.st, (size_t)W.cap, (size_t)j, k, r + k);
     }
     return active ? s : -1;
 }

@@ -138,7 +138,7 @@ __device__ __forceinline__ void permute_one(const PartPtrs<T> &src, const PartPt
     dst.cy[j] = src.cy[i];
     dst.species[j] = src.species[i];
 #pragma unroll
-    for (int k = 0; k < kPartRec; k += 16 / (int)sizeof(T)) {
+    for (int k = 0; k < kPartRec<T>; k += 16 / (int)sizeof(T)) {
         T v[16 / sizeof(T)];
         chunk_ld16(src.st, (size_t)src.cap, (size_t)i, k, v);
         chunk_st16(dst.st, (size_t)dst.cap, (size_t)j, k, v);
