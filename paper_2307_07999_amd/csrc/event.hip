@@ -504,7 +504,8 @@ gl_status copy_out(gl_event *ev, double *host, const void *dev, int K) {
 
 template <typename T>
 gl_status get_site_fields_t(gl_event *ev, double *F) {
-    // planes [6][8][n2]; E_x and E_y are the sums of their two stored halves
+    // planes [6][8][n2]; E_x and E_y add their second halves where those are
+    // stored apart (half_stored)
     const size_t n2 = ev->n2;
     std::vector<T> tmp((size_t)kSiteRec * n2);
     HIP_TRY(hipMemcpyAsync(tmp.data(), ev->ws + ev->L.F, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, ev->stream));
@@ -514,7 +515,8 @@ gl_status get_site_fields_t(gl_event *ev, double *F) {
     for (int k = 0; k < 48; k++)
         for (size_t x = 0; x < n2; x++) F[(size_t)k * n2 + x] = at(k, x);
     for (int k = 0; k < 16; k++)
-        for (size_t x = 0; x < n2; x++) F[(size_t)k * n2 + x] += at(48 + k, x);
+        for (size_t x = 0; x < n2; x++)
+            if (half_stored(k / 8, (int)(x % ev->N), (int)(x / ev->N))) F[(size_t)k * n2 + x] += at(48 + k, x);
     return GL_OK;
 }
 

@@ -70,7 +70,8 @@ k_static_accum(int N, const T *__restrict__ F, double *__restrict__ I, double dt
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 double e = (double)chunk_ld(F, n2, x, 8 * i + a);
-                if (i < 2) e += (double)chunk_ld(F, n2, x, 48 + 8 * i + a);
+                if (i < 2 && half_stored(i, (int)(x % N), (int)(x / N)))
+                    e += (double)chunk_ld(F, n2, x, 48 + 8 * i + a);
                 const double t = pl_ld(I, n2, 8 * i + a, x) + dtau * e;
                 pl_st(I, n2, 8 * i + a, x, t);
                 s += t * t;
@@ -115,9 +116,12 @@ k_lightlike_accum(int N, const T *__restrict__ F, const T *__restrict__ U, doubl
             double f[8], t[8];
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                if (i == 0) f[a] = (double)chunk_ld(F, n2, c, a) + (double)chunk_ld(F, n2, c, 48 + a);
+                if (i == 0)
+                    f[a] = (double)chunk_ld(F, n2, c, a) +
+                           (half_stored(0, ix, iy) ? (double)chunk_ld(F, n2, c, 48 + a) : 0.0);
                 else if (i == 1)
-                    f[a] = ((double)chunk_ld(F, n2, c, 8 + a) + (double)chunk_ld(F, n2, c, 56 + a)) -
+                    f[a] = ((double)chunk_ld(F, n2, c, 8 + a) +
+                            (half_stored(1, ix, iy) ? (double)chunk_ld(F, n2, c, 56 + a) : 0.0)) -
                            (double)chunk_ld(F, n2, c, 40 + a);
                 else f[a] = (double)chunk_ld(F, n2, c, 16 + a) + (double)chunk_ld(F, n2, c, 32 + a);
             }

@@ -186,15 +186,13 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
 }
 
 // E_i^{n+1/2}(x) and U_i^{n+1}(x), i = d + 1, from the force fe and U_i(x) =
-// u; with F, also this site's half of the electric site field (record of
-// site x, slot 8d) and the transported half of x+i (record of site xt, slot
-// 48 + 8d)
+// u; with F, also this site's half of the electric site field (eb) and the
+// half transported to x+i (t), which the caller stores or exchanges
 template <typename T>
 __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const M3<T> &u,
-                                            T *__restrict__ Uout, size_t n2, size_t x, size_t xt, int d,
-                                            const T *fe, T dtau, T s, int reunit, T *__restrict__ F, T inv_tau) {
-    const int fs = 8 * d;
-    T e[8], eb[8];
+                                            T *__restrict__ Uout, size_t n2, size_t x, int d, const T *fe, T dtau,
+                                            T s, int reunit, bool site_fields, T inv_tau, T *eb, T *t) {
+    T e[8];
     chunk_load_n_l<8, kStream<T>>(Ein, n2, x, 8 * d, e);   // E and pi are read once per step
 #pragma unroll
     for (int a = 0; a < 8; a++) {
@@ -213,13 +211,10 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
             uv[2 * (3 * i + j) + 1] = un.im[i][j];
         }
     chunk_store_link_l<kStream<T>>(Uout, n2, x, d, uv);
-    if (F) {
-        T t[8];
+    if (site_fields) {
 #pragma unroll
         for (int a = 0; a < 8; a++) eb[a] = T(0.25) * inv_tau * (eb[a] + e[a]);   // Ebar / (2 tau)
-        store_rec(F, n2, x, fs, eb);
         transport_dn(u, herm_from_alg(eb), t);
-        store_rec(F, n2, xt, 48 + fs, t);
     }
 }
 
@@ -227,7 +222,8 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
 // lanes of a pair (d = 0, 1) share the site (ix, iy) = (x0 + lx, y0 + ly) of
 // the staged tile, and lane d owns direction i = d + 1 (j is the other one).
 // Every thread of the workgroup calls this (active: the site lies on the
-// lattice), since it synchronises the workgroup once.  First the plaquette
+// lattice), since it synchronises the workgroup (once, three times when it
+// writes site fields).  First the plaquette
 // at x is assembled from the halves U_i(x) U_j(x+i) of both lanes and its
 // algebra stored in the tile, with those of the tile's lower and left halo
 // sites (computed by the first threads); then lane d reads the staple
@@ -247,9 +243,10 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
 //   E_z = (pi^{n-1/2} + pi^{n+1/2}) / 2,
 //   B_x = -D_2 phi / tau, B_y = D_1 phi / tau, D_i phi = (Phi_{+i} - Phi_{-i}) / 2,
 //   B_z = -(1/4) (sum of the four plaquettes at x, each transported to x).
-// The second half of E_i belongs to the site x+i; lane d owns the link U_i(x)
-// and Ebar_i(x) it needs, so it stores that half at x+i in slots of its own
-// (48..63) and the push adds the two halves.
+// The second half of E_i at x+i needs U_i(x) and Ebar_i(x), which lane d
+// owns: it hands that half to the lane of x+i through LDS, which adds it to
+// its own, or, at the sites of half_stored, stores it in x+i's slots 48..63
+// for the readers to add.
 template <typename T, int SX, int SY>
 __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, const FieldPtrs<T> &in,
                                                 const FieldPtrs<T> &out, T *__restrict__ F, int x0, int y0, int lx,
@@ -307,61 +304,92 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
         tl.put_plaq(Tl::pidx(hx, hy), v);
     }
     __syncthreads();
-    if (!active) return;
-
-    const M3<T> ui = tl.m(li, rx);   // U_i(x)
-    T fe[8], cl[8];
-    {
-        // staple: U_j^dag(y) [P(y)]_X U_j(y)
-        T pa[8], t[8];
-        tl.plaq(Tl::pidx(lx + 1 - d, ly + d), pa);
-        transport_dn(tl.m(lj, ry), herm_from_alg(pa), t);
+    // this lane's half of E_i at x and the half it transports to x+i
+    T eb[8], tr[8];
+    if (active) {
+        const M3<T> ui = tl.m(li, rx);   // U_i(x)
+        T fe[8], cl[8];
+        {
+            // staple: U_j^dag(y) [P(y)]_X U_j(y)
+            T pa[8], t[8];
+            tl.plaq(Tl::pidx(lx + 1 - d, ly + d), pa);
+            transport_dn(tl.m(lj, ry), herm_from_alg(pa), t);
 #pragma unroll
-        for (int a = 0; a < 8; a++) {
-            fe[a] = -tau * sgn * (px[a] - t[a]);
-            cl[a] = px[a] + (t[a] + pair_swap(t[a]));
+            for (int a = 0; a < 8; a++) {
+                fe[a] = -tau * sgn * (px[a] - t[a]);
+                cl[a] = px[a] + (t[a] + pair_swap(t[a]));
+            }
         }
+        if (F) {
+            // fourth clover plaquette P(z), moved to x along z -> z+1 -> x, i.e.
+            // by C = U_1(z) U_2(z+1)
+            T pa[8], t[8];
+            tl.plaq(Tl::pidx(lx, ly), pa);
+            transport_dn(mul(tl.m(0, rz), tl.m(1, rz + 1)), herm_from_alg(pa), t);
+#pragma unroll
+            for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
+            store_half(F, n2, x, 40, t, d);   // B_z
+        }
+        // scalar couplings: Phi_{+i} in the E_i force, all four in the pi force
+        T fpi[8];
+        {
+            T c[8], pf[8], pb[8];
+            transport_nd(ui, herm_from_alg(php), pf);   // Phi_{+i}
+            alg_comm(ph, pf, c);                        // -i[phi, Phi_{+i}]
+            transport_dn(tl.m(li, rmi), herm_from_alg(phm), pb);   // Phi_{-i}
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                fe[a] = fma(inv_tau, c[a], fe[a]);
+                const T l = pf[a] + pb[a];
+                fpi[a] = inv_tau * ((l + pair_swap(l)) - T(4) * ph[a]);
+                pf[a] = T(0.5) * sgn * inv_tau * (pf[a] - pb[a]);
+            }
+            // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
+            if (F) store_rec(F, n2, x, 32 - 8 * d, pf);
+        }
+        update_link(in.E, out.E, ui, out.U, n2, x, d, fe, dtau, dtau / tau_h, reunit, F != nullptr, inv_tau, eb, tr);
+        // pi, phi and E_z: lane d takes colour components 4d..4d+3
+        T pv[4], pn[4], phn[4], ez[4];
+        chunk_load_n_l<4, kStream<T>>(in.pi, n2, x, 4 * d, pv);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            pn[k] = pv[k] + dtau * (d0 ? fpi[k] : fpi[4 + k]);
+            phn[k] = (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn[k];
+            ez[k] = T(0.5) * (pv[k] + pn[k]);
+        }
+        chunk_store_n_l<4, kStream<T>>(out.pi, n2, x, 4 * d, pn);
+        chunk_store_n_l<4, kStream<T>>(out.phi, n2, x, 4 * d, phn);
+        if (F) chunk_store_n_l<4>(F, n2, x, 16 + 4 * d, ez);
     }
     if (F) {
-        // fourth clover plaquette P(z), moved to x along z -> z+1 -> x, i.e.
-        // by C = U_1(z) U_2(z+1)
-        T pa[8], t[8];
-        tl.plaq(Tl::pidx(lx, ly), pa);
-        transport_dn(mul(tl.m(0, rz), tl.m(1, rz + 1)), herm_from_alg(pa), t);
+        // E_i site fields: the half transported from x - i is added here when
+        // that link is in this workgroup, else stored apart (half_stored).
+        // The exchange reuses the tile's LDS once every lane is done with it.
+        static_assert(SX % kHalfX == 0 && SY % kHalfY == 0, "tile shape breaks the E_i half rule");
+        T *ex = reinterpret_cast<T *>(&tl.c[0]);   // [2][8][SX * SY]
+        constexpr int S = SX * SY;
+        static_assert(16 * S * sizeof(T) <= sizeof(tl.c), "exchange larger than the link tile");
+        __syncthreads();
+        if (active) {
+            const int ixt = d0 ? ixp : ix, iyt = d0 ? iy : iyp;
+            if (half_stored(d, ixt, iyt)) {
+                store_rec(F, n2, xpi, 48 + 8 * d, tr);
+            } else {   // x+i lies in this tile (the rule keeps x+i off tile edges)
+                const int st = (lx + (d0 ? 1 : 0)) + SX * (ly + (d0 ? 0 : 1));
 #pragma unroll
-        for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
-        store_half(F, n2, x, 40, t, d);   // B_z
-    }
-    // scalar couplings: Phi_{+i} in the E_i force, all four in the pi force
-    T fpi[8];
-    {
-        T c[8], pf[8], pb[8];
-        transport_nd(ui, herm_from_alg(php), pf);   // Phi_{+i}
-        alg_comm(ph, pf, c);                        // -i[phi, Phi_{+i}]
-        transport_dn(tl.m(li, rmi), herm_from_alg(phm), pb);   // Phi_{-i}
-#pragma unroll
-        for (int a = 0; a < 8; a++) {
-            fe[a] = fma(inv_tau, c[a], fe[a]);
-            const T l = pf[a] + pb[a];
-            fpi[a] = inv_tau * ((l + pair_swap(l)) - T(4) * ph[a]);
-            pf[a] = T(0.5) * sgn * inv_tau * (pf[a] - pb[a]);
+                for (int a = 0; a < 8; a++) ex[(d * 8 + a) * S + st] = tr[a];
+            }
         }
-        // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
-        if (F) store_rec(F, n2, x, 32 - 8 * d, pf);
-    }
-    update_link(in.E, out.E, ui, out.U, n2, x, xpi, d, fe, dtau, dtau / tau_h, reunit, F, inv_tau);
-    // pi, phi and E_z: lane d takes colour components 4d..4d+3
-    T pv[4], pn[4], phn[4], ez[4];
-    chunk_load_n_l<4, kStream<T>>(in.pi, n2, x, 4 * d, pv);
+        __syncthreads();
+        if (active) {
+            if (!half_stored(d, ix, iy)) {
+                const int so = lx + SX * ly;
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        pn[k] = pv[k] + dtau * (d0 ? fpi[k] : fpi[4 + k]);
-        phn[k] = (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn[k];
-        ez[k] = T(0.5) * (pv[k] + pn[k]);
+                for (int a = 0; a < 8; a++) eb[a] = eb[a] + ex[(d * 8 + a) * S + so];
+            }
+            store_rec(F, n2, x, 8 * d, eb);
+        }
     }
-    chunk_store_n_l<4, kStream<T>>(out.pi, n2, x, 4 * d, pn);
-    chunk_store_n_l<4, kStream<T>>(out.phi, n2, x, 4 * d, phn);
-    if (F) chunk_store_n_l<4>(F, n2, x, 16 + 4 * d, ez);
 }
 
 }  // namespace gl

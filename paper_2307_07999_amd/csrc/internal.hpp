@@ -10,11 +10,22 @@ constexpr int kMaxSpecies = 16;
 constexpr int kPushBlock = 256;   // particles per push workgroup
 // site-field record of kSiteRec reals per site in chunked planes (16-byte
 // chunks of consecutive values, one chunk plane per chunk index over all
-// sites): slots of 8 reals Ex, Ey, Ez, Bx, By, Bz (local frame) and the
-// transported halves of Ex, Ey stored at their site (E_i = slot i + slot
-// 6 + i).  A particle reads its cell's record in 16-byte loads, and the
-// field step's lanes store neighbouring chunks.
+// sites): slots of 8 reals Ex, Ey, Ez, Bx, By, Bz (local frame), then two
+// slots for the second halves of Ex and Ey.  E_i at a site is the sum of
+// the half from the link U_i(x) and the half transported from U_i(x - i).
+// Where both links fall in one field-step workgroup the step adds them and
+// stores the sum in slot i; at the sites of half_stored (a fixed lattice
+// rule that every tile shape respects) the half from x - i is stored apart
+// in slot 6 + i, and readers add it: E_i = slot i + slot 6 + i there, slot
+// i elsewhere (slot 6 + i is not written).  Either way it is the same sum
+// of the same two halves.  A particle reads its cell's record in 16-byte
+// loads, and the field step's lanes store neighbouring chunks.
 constexpr int kSiteRec = 64;
+constexpr int kHalfX = 16, kHalfY = 2;   // tile widths and heights are multiples of these
+// whether site (ix, iy) keeps the half of E_{d+1} from x - (d+1) apart
+__host__ __device__ __forceinline__ bool half_stored(int d, int ix, int iy) {
+    return d == 0 ? ix % kHalfX == 0 : iy % kHalfY == 0;
+}
 
 // distance between consecutive planes of a lattice quantity, in elements
 // (packed: a padded pitch against L2 set aliasing of the power-of-two planes

@@ -41,18 +41,41 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const T tau = dtau * (T)n, th = dtau * ((T)n + T(0.5));
         const T m = tab.mass[s];
         const size_t x = (size_t)cx + (size_t)N * cy;
-        // the cell's whole site-field record, in 16-byte loads
+        // the cell's site-field record, in 16-byte loads: the six fields,
+        // and the second half of E_x or E_y where it is stored apart (zero
+        // elsewhere).  FP64 loads those halves only where they are stored,
+        // which spares a fifth of the gathered lines; FP32, whose site
+        // fields stay in the last-level cache, loads them everywhere and
+        // selects, without the divergent branch (push 43.3 against 41.9 us)
+        constexpr int NV = 16 / (int)sizeof(T);
         T rec[kSiteRec];
 #pragma unroll
-        for (int j = 0; j < kSiteRec; j += 16 / (int)sizeof(T)) chunk_ld16(F, n2, x, j, rec + j);
+        for (int j = 0; j < 48; j += NV) chunk_ld16(F, n2, x, j, rec + j);
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const bool stored = half_stored(d, cx, cy);
+            if constexpr (sizeof(T) == 8) {
+                if (stored) {
+#pragma unroll
+                    for (int j = 0; j < 8; j += NV) chunk_ld16(F, n2, x, 48 + 8 * d + j, rec + 48 + 8 * d + j);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; j++) rec[48 + 8 * d + j] = T(0);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; j += NV) chunk_ld16(F, n2, x, 48 + 8 * d + j, rec + 48 + 8 * d + j);
+#pragma unroll
+                for (int j = 0; j < 8; j++) rec[48 + 8 * d + j] = stored ? rec[48 + 8 * d + j] : T(0);
+            }
+        }
         T e[3], b[3], ph[8];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             T se = T(0), sb = T(0);
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                se = fma(q[a], rec[8 * k + a], se);
-                if (k < 2) se = fma(q[a], rec[48 + 8 * k + a], se);
+                se = fma(q[a], k < 2 ? rec[8 * k + a] + rec[48 + 8 * k + a] : rec[8 * k + a], se);
                 sb = fma(q[a], rec[8 * (3 + k) + a], sb);
             }
             e[k] = se;
