@@ -145,6 +145,10 @@ struct gl_event {
     // within a run the particles move to their sorted slots while being
     // pushed; every call returns with none pending
     bool perm_pending = false;
+    // the particle set changed since the last sort and formation sums: both
+    // are taken once, before the next push (settle_particles), so that
+    // adding several species sorts once
+    bool set_changed = false;
     int32_t sort_every = 16;    // re-sort particles by cell every this many pushes (0: never)
     int64_t since_sort = 0;
     bool stat_on = false;       // static-quark accumulation running
@@ -402,8 +406,23 @@ gl_status sort_particles(gl_event *ev);
 
 // the push, then a sort when one is due: with defer, only the sorted order,
 // which the next push applies
+// the sort by cell and the formation sums of a changed particle set.  A
+// stable sort gives the same order as sorting after each added species (each
+// added block follows the earlier ones, particles in creation order).
+gl_status settle_particles(gl_event *ev) {
+    if (!ev->set_changed) return GL_OK;
+    gl_status s = sort_particles(ev);
+    if (s) return s;
+    s = p0_sums(ev);
+    if (s) return s;
+    ev->set_changed = false;
+    return GL_OK;
+}
+
 gl_status do_push(gl_event *ev, bool defer = false) {
-    gl_status s = ev->fp64() ? push<double>(ev) : push<float>(ev);
+    gl_status s = settle_particles(ev);
+    if (s) return s;
+    s = ev->fp64() ? push<double>(ev) : push<float>(ev);
     if (s) return s;
     if (ev->sort_every > 0 && ev->since_sort >= ev->sort_every && ev->slots_used > 0) {
         if (defer) return ev->fp64() ? sort_order_t<double>(ev) : sort_order_t<float>(ev);
@@ -825,10 +844,7 @@ gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uin
     s = ev->fp64() ? init_particles<double>(ev, si, sid, seed, slot0, end)
                    : init_particles<float>(ev, si, sid, seed, slot0, end);
     if (s) return s;
-    s = sort_particles(ev);
-    if (s) return s;
-    s = p0_sums(ev);
-    if (s) return s;
+    ev->set_changed = true;   // sorted, with its formation sums, before the next push
     if (species_id) *species_id = sid;
     return GL_OK;
 }
@@ -1137,9 +1153,8 @@ gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_des
     gl_status s = ev->fp64() ? set_particles_t<double>(ev, n, cell, off, eta, p, Q, p0, species)
                              : set_particles_t<float>(ev, n, cell, off, eta, p, Q, p0, species);
     if (s) return s;
-    s = sort_particles(ev);
-    if (s) return s;
-    return p0_sums(ev);
+    ev->set_changed = true;
+    return GL_OK;
 }
 
 gl_status gl_set_sort_period(gl_event *ev, int32_t every) {
@@ -1576,6 +1591,14 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
     b->stiles = z.stiles;
     b->ctl = z.ctl;
     for (auto *ev : b->evs) {
+        // the batch reads each event's current particle buffer and formation
+        // sums: take a pending sort first (on the event's stream; the batch
+        // runs after those streams)
+        gl_status st = settle_particles(ev);
+        if (st) {
+            delete b;
+            return st;
+        }
         b->cur0.push_back(ev->cur);
         b->pbuf0.push_back(ev->pbuf);
         b->any_particles |= ev->slots_used > 0;
