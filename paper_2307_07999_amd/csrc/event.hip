@@ -768,10 +768,12 @@ static gl_status wilson_lines(gl_event *ev, int n_sheets, double m_ir_GeV, doubl
                     HIP_TRY(launch_charges_to_planes(
                         ev->stream, N, rho_dev + ((size_t)nuc * n_sheets + sh0 + k) * 8 * ev->n2,
                         planes + (size_t)k * 4 * ev->n2));
+                HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes, cnt, tab));
             } else {
-                HIP_TRY(launch_mv_charges(ev->stream, N, sigma, seed, nuc, sh0, cnt, planes));
+                // the forward row pass draws the charges itself
+                const MvDraw mv{sigma, seed, nuc, sh0};
+                HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes, cnt, tab, &mv));
             }
-            HIP_TRY(launch_poisson(ev->stream, N, m2, uv2, planes, cnt, tab));
             HIP_TRY(launch_wilson_accum(ev->stream, N, planes, cnt, V[nuc]));
         }
     }

@@ -26,21 +26,25 @@
 namespace gl {
 
 // ---- 1. charges ---------------------------------------------------------------
+// colours 2j, 2j + 1 of the charge of one sheet at site x: one counter-based
+// draw, two normal deviates, scaled by sigma
+__device__ __forceinline__ double2 mv_charge_pair(const MvDraw &mv, int sheet, int j, size_t x) {
+    U4 w = draw(mv.seed, (uint32_t)x, (uint32_t)(4 * sheet + j), (uint32_t)mv.nucleus);
+    double g0, g1;
+    box_muller(w, g0, g1);
+    return make_double2(mv.sigma * g0, mv.sigma * g1);
+}
+
 // sheets sheet0 + blockIdx.y of one nucleus into planes [sheet][4][n2]
 __global__ void __launch_bounds__(256)
-k_mv_charges(int N, double sigma, uint64_t seed, int nucleus, int sheet0, double2 *planes) {
+k_mv_charges(int N, MvDraw mv, double2 *planes) {
     size_t n2 = (size_t)N * N;
     size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= n2) return;
-    const int sheet = sheet0 + (int)blockIdx.y;
+    const int sheet = mv.sheet0 + (int)blockIdx.y;
     double2 *pl = planes + (size_t)blockIdx.y * 4 * n2;
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        U4 w = draw(seed, (uint32_t)x, (uint32_t)(4 * sheet + j), (uint32_t)nucleus);
-        double g0, g1;
-        box_muller(w, g0, g1);
-        pl[(size_t)j * n2 + x] = make_double2(sigma * g0, sigma * g1);
-    }
+    for (int j = 0; j < 4; j++) pl[(size_t)j * n2 + x] = mv_charge_pair(mv, sheet, j, x);
 }
 
 __global__ void __launch_bounds__(256)
@@ -212,14 +216,19 @@ k_fft_tables(int N, double2 *__restrict__ tw, double *__restrict__ s2) {
 // the twiddles exp(-2 pi i j / N) copied from the solve's table into LDS.  Loads
 // and stores walk the C lines together, so a column workgroup reads C
 // consecutive values of each row.  sign = -1 forward, +1 inverse
-// (unnormalised).  POISSON (columns only, after the forward row pass): the
-// forward column transform, the multiplication of mode (kx, ky) by
-// 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m2)) (zero above uv2 > 0)
-// and the inverse column transform, in one pass.
-template <bool POISSON>
+// (unnormalised).  MODE kFftPoisson (columns only, after the forward row
+// pass): the forward column transform, the multiplication of mode (kx, ky)
+// by 1 / (N^2 (4 sin^2(pi kx/N) + 4 sin^2(pi ky/N) + m2)) (zero above
+// uv2 > 0) and the inverse column transform, in one pass.  MODE kFftDraw
+// (forward rows): the input lines are the MV charges, drawn here instead of
+// being written to the planes by a pass of their own and read back.
+constexpr int kFftLines = 0, kFftPoisson = 1, kFftDraw = 2;
+template <int MODE>
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int groups_per_plane, int sign,
-            Radices rs, double m2, double uv2, const double2 *__restrict__ tw_tab, const double *__restrict__ s2_tab) {
+            Radices rs, double m2, double uv2, const double2 *__restrict__ tw_tab, const double *__restrict__ s2_tab,
+            MvDraw mv) {
+    constexpr bool POISSON = MODE == kFftPoisson;
     // dynamic LDS sized for this N: the lines, then tw[N], then (POISSON) s2[N]
     extern __shared__ double2 lds[];
     double2 *buf = lds, *tw = lds + kFftElems;
@@ -237,7 +246,8 @@ k_fft_lines(double2 *data, int N, int C, int cols, size_t plane_stride, int grou
     for (int i = threadIdx.x; i < C * N; i += kFftThreads) {
         const int line = cols ? i % C : i / N, k = cols ? i / C : i % N;
         const size_t addr = cols ? (size_t)k * N + (l0 + line) : (size_t)(l0 + line) * N + k;
-        buf[line * N + k] = base[addr];
+        if constexpr (MODE == kFftDraw) buf[line * N + k] = mv_charge_pair(mv, mv.sheet0 + plane / 4, plane % 4, addr);
+        else buf[line * N + k] = base[addr];
     }
     __syncthreads();
     if (POISSON) {
@@ -600,8 +610,9 @@ static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n +
 
 hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed, int nucleus,
                              int sheet0, int n_sheets, double2 *planes) {
-    hipLaunchKernelGGL(k_mv_charges, dim3(blocks_for((size_t)N * N, 256), n_sheets), dim3(256), 0, st, N,
-                       sigma, seed, nucleus, sheet0, planes);
+    const MvDraw mv{sigma, seed, nucleus, sheet0};
+    hipLaunchKernelGGL(k_mv_charges, dim3(blocks_for((size_t)N * N, 256), n_sheets), dim3(256), 0, st, N, mv,
+                       planes);
     return hipGetLastError();
 }
 
@@ -623,25 +634,31 @@ hipError_t launch_fft_tables(hipStream_t st, int N, double2 *tab) {
 
 // Poisson solve of n_sheets x 4 planes: forward row transforms, the fused
 // column pass (forward, kernel, inverse) and inverse row transforms; tab
-// holds the tables of launch_fft_tables for this N
+// holds the tables of launch_fft_tables for this N.  With draw, the forward
+// row pass draws the MV charges itself (the planes' input is not read).
 hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets,
-                          const double2 *tab) {
+                          const double2 *tab, const MvDraw *draw) {
     Radices rs;
     if (N > kFftMaxN || !radices_of(N, rs)) return hipErrorInvalidValue;
     const size_t n2 = (size_t)N * N;
     const int C = fft_lines_per_group(N), groups = N / C, n_planes = 4 * n_sheets;
     const double *s2 = (const double *)(tab + kFftMaxN);
     const size_t lds_lines = (kFftElems + (size_t)N) * sizeof(double2), lds_poisson = lds_lines + N * sizeof(double);
-    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes, N, C,
-                       0, n2, groups, -1, rs, m2, uv2, tab, s2);
+    const MvDraw mv = draw ? *draw : MvDraw{0.0, 0, 0, 0};
+    if (draw)
+        hipLaunchKernelGGL(k_fft_lines<kFftDraw>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes,
+                           N, C, 0, n2, groups, -1, rs, m2, uv2, tab, s2, mv);
+    else
+        hipLaunchKernelGGL(k_fft_lines<kFftLines>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes,
+                           N, C, 0, n2, groups, -1, rs, m2, uv2, tab, s2, mv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fft_lines<true>, dim3(n_planes * groups), dim3(kFftThreads), lds_poisson, st, planes, N,
-                       C, 1, n2, groups, -1, rs, m2, uv2, tab, s2);
+    hipLaunchKernelGGL(k_fft_lines<kFftPoisson>, dim3(n_planes * groups), dim3(kFftThreads), lds_poisson, st,
+                       planes, N, C, 1, n2, groups, -1, rs, m2, uv2, tab, s2, mv);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fft_lines<false>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes, N, C,
-                       0, n2, groups, +1, rs, m2, uv2, tab, s2);
+    hipLaunchKernelGGL(k_fft_lines<kFftLines>, dim3(n_planes * groups), dim3(kFftThreads), lds_lines, st, planes,
+                       N, C, 0, n2, groups, +1, rs, m2, uv2, tab, s2, mv);
     return hipGetLastError();
 }
 

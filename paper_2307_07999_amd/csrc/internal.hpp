@@ -151,6 +151,14 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
 
 // initial conditions (always FP64 internally)
 constexpr int kSheetChunk = 8;   // MV sheets per initialisation launch
+// the MV charges of one nucleus drawn for sheets sheet0.. (seeded, counter
+// based): colours 2j, 2j + 1 of sheet s at site x from one draw
+struct MvDraw {
+    double sigma;
+    uint64_t seed;
+    int nucleus;
+    int sheet0;
+};
 hipError_t launch_mv_charges(hipStream_t st, int N, double sigma, uint64_t seed, int nucleus,
                              int sheet0, int n_sheets, double2 *planes /* [n_sheets][4][n2] */);
 hipError_t launch_charges_to_planes(hipStream_t st, int N, const double *rho /* [8][n2] */,
@@ -160,7 +168,7 @@ hipError_t launch_planes_to_charges(hipStream_t st, int N, const double2 *planes
 constexpr size_t kFftTableBytes = 1024 * (sizeof(double2) + sizeof(double));
 hipError_t launch_fft_tables(hipStream_t st, int N, double2 *tab);
 hipError_t launch_poisson(hipStream_t st, int N, double m2, double uv2, double2 *planes, int n_sheets,
-                          const double2 *tab);
+                          const double2 *tab, const MvDraw *draw = nullptr);
 hipError_t launch_wilson_init(hipStream_t st, int N, double *V);
 // dipole correlator D[0..rmax] of a Wilson line; partials [(rmax+1)][ceil(N^2/256)]
 hipError_t launch_dipole(hipStream_t st, int N, const double *V, int rmax, double *partials, double *D);
