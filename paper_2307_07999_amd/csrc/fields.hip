@@ -53,7 +53,8 @@ k_field_step(int N, FieldPtrs<T> in, FieldPtrs<T> out, T *__restrict__ F, T tau,
 }
 
 // Static quarks (Sec. 2, Eq. (4)): I_i^a(x) += dtau E_i^a(x, tau_n) from the
-// site fields at tau_n (E_x and E_y as their two stored halves), FP64, and
+// site fields at tau_n (E_x and E_y adding the half stored apart where
+// half_stored holds), FP64, and
 // per workgroup the sums over its sites of (1/2) sum_a (I_i^a)^2 for
 // i = x, y, z with the site count, added in a fixed order.
 template <typename T>

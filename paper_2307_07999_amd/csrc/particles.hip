@@ -2,8 +2,9 @@
 // of Wong's equations (Eq. (2)) and the FP64 momentum-broadening sums.
 //
 // Push (one thread per particle, reading the site-field record F^n of its
-// cell -- the six local-frame fields, E_x and E_y as two stored halves, in
-// 16-byte chunks -- and phi^n from the field state; the particles are kept
+// cell -- the six local-frame fields, E_x and E_y plus the half stored apart
+// where half_stored holds, in 16-byte chunks -- and phi^n from the field
+// state; the particles are kept
 // sorted by cell so that a wave's gathers hit neighbouring addresses):
 //   e_k = Q^a E_k^a, b_k = Q^a B_k^a in the local frame at tau_n
 //   Boris kick of dp/dtau = e + v x b on (p_x, p_y, P_eta/tau_n), P_eta = tau^2 p^eta
