@@ -404,8 +404,6 @@ gl_status do_field_step(gl_event *ev, bool sf) {
 }
 gl_status sort_particles(gl_event *ev);
 
-// the push, then a sort when one is due: with defer, only the sorted order,
-// which the next push applies
 // the sort by cell and the formation sums of a changed particle set.  A
 // stable sort gives the same order as sorting after each added species (each
 // added block follows the earlier ones, particles in creation order).
@@ -419,6 +417,8 @@ gl_status settle_particles(gl_event *ev) {
     return GL_OK;
 }
 
+// the push, then a sort when one is due: with defer, only the sorted order,
+// which the next push applies
 gl_status do_push(gl_event *ev, bool defer = false) {
     gl_status s = settle_particles(ev);
     if (s) return s;

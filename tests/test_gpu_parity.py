@@ -103,6 +103,27 @@ def test_field_steps_match_oracle(gl, orc, N):
         assert np.abs(g - w).max() < 1e-12
 
 
+@pytest.mark.parametrize("prec,tol", [(64, 1e-12), (32, 2e-5)])
+def test_site_fields_on_a_ragged_lattice(gl, orc, prec, tol):
+    """Site fields at N = 40: the field-step tiles end inside the lattice in
+    both directions, and E_x adds the half transported from x - 1 within
+    the workgroup except at x = 0, 16, 32, where it is stored apart and
+    added by the reader (E_y likewise at even y).  FP64 and FP32 against the
+    oracle; a few particles make the step write the site fields."""
+    N = 40
+    U, E, phi, pi = si.random_state(700 + prec, N, link_kind="near", eps=0.5)
+    s = orc.State(N)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 3
+    ev = _event(gl, N, prec=prec, max_particles=64)
+    ev.set_state(*H.state_oracle_to_soa(s), 3)
+    ev.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, 16, 5)
+    ev.evolve_fields(1)
+    F = orc.field_step(s, 0.125, want_F=True)
+    want = np.transpose(F, (1, 2, 0))
+    got = ev.site_fields()
+    assert np.abs(got - want).max() < tol * max(1.0, np.abs(want).max())
+
+
 def _oracle_particles(orc, N, seed, specs):
     parts = []
     for sid, (kind, p0, n) in enumerate(specs):
