@@ -210,7 +210,9 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
             uv[2 * (3 * i + j)] = un.re[i][j];
             uv[2 * (3 * i + j) + 1] = un.im[i][j];
         }
-    chunk_store_link_l<kStream<T>>(Uout, n2, x, d, uv);
+    // the new links stay cached: the next step stages them, halo included,
+    // into its tiles (streaming them cost the FP64 step 4.5 us)
+    chunk_store_link_l(Uout, n2, x, d, uv);
     if (site_fields) {
 #pragma unroll
         for (int a = 0; a < 8; a++) eb[a] = T(0.25) * inv_tau * (eb[a] + e[a]);   // Ebar / (2 tau)

@@ -496,9 +496,11 @@ constexpr int kLinkVals = 12;            // stored values of a link (its first t
 // kStream<T> is the policy of such streamed arrays in precision T: in FP64
 // the working set of a step (field state, site fields, particles: over
 // 400 MB at 512^2) overflows the 256 MB last-level cache, and streaming the
-// particle records and the new field state keeps the gathered site fields
-// cached (push 113 -> 94 us); in FP32 it all fits, and the hint only sends
-// the next kernel's inputs to HBM (step 89 -> 100 us), so FP32 uses none.
+// particle records and most of the new field state (E, phi, pi; the links,
+// which the next step stages with their halo, stay cached) keeps the
+// gathered site fields cached (push 113 -> 94 us); in FP32 it all fits, and
+// the hint only sends the next kernel's inputs to HBM (step 89 -> 100 us),
+// so FP32 uses none.
 constexpr int kNonTemporal = 2;
 template <typename T>
 constexpr int kStream = sizeof(T) == 8 ? kNonTemporal : 0;
