@@ -41,8 +41,10 @@ __device__ __forceinline__ void batch_field_tile(LinkTile<T, TX, TY> &tile, cons
     // every thread takes part (the step synchronises the workgroup)
     const bool active = x0 + lx < e.N && y0 + ly < e.N;
     const int reunit = e.reunit_every > 0 && (n % e.reunit_every) == e.reunit_every - 1;
-    field_step_link(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, x0, y0, lx, ly,
-                    threadIdx.x & 1, tid, active, tau, dtau, tau_h, reunit);
+    // a batch's working set overflows the last-level cache in either
+    // precision: its streamed arrays take the non-temporal hint
+    field_step_link<T, TX, TY, true>(tile, e.N, e.f[fpar], e.f[fpar ^ 1], e.n_species > 0 ? e.F : nullptr, x0, y0,
+                                     lx, ly, threadIdx.x & 1, tid, active, tau, dtau, tau_h, reunit);
 }
 
 template <typename T, int TX, int TY>
@@ -79,7 +81,8 @@ __device__ __forceinline__ void batch_push_block(const BatchEv<T> &e, int2 w, in
     const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int s = -1;
-    if (i < e.n_slots) s = push_particle<T>(e.N, e.P[ppar], i, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+    if (i < e.n_slots)
+        s = push_particle<T, false, true>(e.N, e.P[ppar], i, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
     block_species_reduce(s, acc, e.n_species, e.partials + (size_t)w.y * e.n_species * 4);
 }
 

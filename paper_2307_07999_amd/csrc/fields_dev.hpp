@@ -188,18 +188,18 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
 // E_i^{n+1/2}(x) and U_i^{n+1}(x), i = d + 1, from the force fe and U_i(x) =
 // u; with F, also this site's half of the electric site field (eb) and the
 // half transported to x+i (t), which the caller stores or exchanges
-template <typename T>
+template <typename T, bool ST>
 __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const M3<T> &u,
                                             T *__restrict__ Uout, size_t n2, size_t x, int d, const T *fe, T dtau,
                                             T s, int reunit, bool site_fields, T inv_tau, T *eb, T *t) {
     T e[8];
-    chunk_load_n_l<8, kStream<T>>(Ein, n2, x, 8 * d, e);   // E and pi are read once per step
+    chunk_load_n_l<8, stream_policy(ST)>(Ein, n2, x, 8 * d, e);   // E and pi are read once per step
 #pragma unroll
     for (int a = 0; a < 8; a++) {
         eb[a] = e[a];
         e[a] += dtau * fe[a];
     }
-    chunk_store_n_l<8, kStream<T>>(Eout, n2, x, 8 * d, e);   // the new state is streamed
+    chunk_store_n_l<8, stream_policy(ST)>(Eout, n2, x, 8 * d, e);   // the new state is streamed (ST)
     M3<T> un = mul(expi_alg(e, s), u);
     if (reunit) un = reunitarize(un);
     T uv[18];
@@ -249,7 +249,7 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
 // owns: it hands that half to the lane of x+i through LDS, which adds it to
 // its own, or, at the sites of half_stored, stores it in x+i's slots 48..63
 // for the readers to add.
-template <typename T, int SX, int SY>
+template <typename T, int SX, int SY, bool ST = kStreamed<T>>
 __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, const FieldPtrs<T> &in,
                                                 const FieldPtrs<T> &out, T *__restrict__ F, int x0, int y0, int lx,
                                                 int ly, int d, int tid, bool active, T tau, T dtau, T tau_h,
@@ -349,18 +349,19 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
             if (F) store_rec(F, n2, x, 32 - 8 * d, pf);
         }
-        update_link(in.E, out.E, ui, out.U, n2, x, d, fe, dtau, dtau / tau_h, reunit, F != nullptr, inv_tau, eb, tr);
+        update_link<T, ST>(in.E, out.E, ui, out.U, n2, x, d, fe, dtau, dtau / tau_h, reunit, F != nullptr, inv_tau, eb,
+                           tr);
         // pi, phi and E_z: lane d takes colour components 4d..4d+3
         T pv[4], pn[4], phn[4], ez[4];
-        chunk_load_n_l<4, kStream<T>>(in.pi, n2, x, 4 * d, pv);
+        chunk_load_n_l<4, stream_policy(ST)>(in.pi, n2, x, 4 * d, pv);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             pn[k] = pv[k] + dtau * (d0 ? fpi[k] : fpi[4 + k]);
             phn[k] = (d0 ? ph[k] : ph[4 + k]) + dtau * tau_h * pn[k];
             ez[k] = T(0.5) * (pv[k] + pn[k]);
         }
-        chunk_store_n_l<4, kStream<T>>(out.pi, n2, x, 4 * d, pn);
-        chunk_store_n_l<4, kStream<T>>(out.phi, n2, x, 4 * d, phn);
+        chunk_store_n_l<4, stream_policy(ST)>(out.pi, n2, x, 4 * d, pn);
+        chunk_store_n_l<4, stream_policy(ST)>(out.phi, n2, x, 4 * d, phn);
         if (F) chunk_store_n_l<4>(F, n2, x, 16 + 4 * d, ez);
     }
     if (F) {

@@ -17,13 +17,13 @@ namespace gl {
 // formation.  Loads are grouped so that a wave makes three dependent trips
 // to memory: the particle state (all of it, before the activity test), the
 // site fields and phi of its cell, and the links of both crossings together.
-template <typename T, bool MOVE = false>
+template <typename T, bool MOVE = false, bool ST = kStreamed<T>>
 __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const PartPtrs<T> &W, int64_t j,
                                              const FieldPtrs<T> &f, const T *__restrict__ F,
                                              const SpeciesTab<T> &tab, int n, T dtau, double *acc) {
     const size_t n2 = plane_pitch(N);
     acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
-    constexpr int CP = kStream<T>;   // the particle arrays are streamed
+    constexpr int CP = stream_policy(ST);   // the particle arrays are streamed (ST)
     const int s = el_ld_i32<CP>(P.species, i);
     int cx = el_ld_i32<CP>(P.cx, i), cy = el_ld_i32<CP>(P.cy, i);
     // the state record in 16-byte loads

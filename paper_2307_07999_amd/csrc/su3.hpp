@@ -493,17 +493,20 @@ constexpr int kLinkVals = 12;            // stored values of a link (its first t
 // cache-policy operand of a buffer access: the non-temporal hint, for data
 // read or written once per kernel and not again until much other traffic
 // has passed (it then leaves the caches to data that is reused).
-// kStream<T> is the policy of such streamed arrays in precision T: in FP64
-// the working set of a step (field state, site fields, particles: over
-// 400 MB at 512^2) overflows the 256 MB last-level cache, and streaming the
-// particle records and most of the new field state (E, phi, pi; the links,
-// which the next step stages with their halo, stay cached) keeps the
-// gathered site fields cached (push 113 -> 94 us); in FP32 it all fits, and
-// the hint only sends the next kernel's inputs to HBM (step 89 -> 100 us),
-// so FP32 uses none.
+// stream_policy(ST) is the policy of such streamed arrays: the hint when
+// the kernels' working set overflows the 256 MB last-level cache (ST), none
+// when it fits.  A single FP64 event (field state, site fields, particles:
+// over 400 MB per step at 512^2) overflows it: streaming the particle
+// records and most of the new field state (E, phi, pi; the links, which the
+// next step stages with their halo, stay cached) keeps the gathered site
+// fields cached (push 113 -> 94 us).  A single FP32 event fits, and the hint
+// only sends the next kernel's inputs to HBM (step 89 -> 100 us).  A batch
+// of events overflows it in either precision (FP32 64-event batch 986 ->
+// 969 ms).  kStreamed<T> is the single-event choice.
 constexpr int kNonTemporal = 2;
+constexpr int stream_policy(bool streamed) { return streamed ? kNonTemporal : 0; }
 template <typename T>
-constexpr int kStream = sizeof(T) == 8 ? kNonTemporal : 0;
+constexpr bool kStreamed = sizeof(T) == 8;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7FFFFFFF, kBufConfig);
