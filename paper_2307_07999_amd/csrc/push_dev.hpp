@@ -43,10 +43,12 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const size_t x = (size_t)cx + (size_t)N * cy;
         // the cell's site-field record, in 16-byte loads: the six fields,
         // and the second half of E_x or E_y where it is stored apart (zero
-        // elsewhere).  FP64 loads those halves only where they are stored,
-        // which spares a fifth of the gathered lines; FP32, whose site
-        // fields stay in the last-level cache, loads them everywhere and
-        // selects, without the divergent branch (push 43.3 against 41.9 us)
+        // elsewhere).  Where the working set overflows the last-level cache
+        // (ST: single FP64 events, batches) those halves are loaded only
+        // where they are stored, which spares a fifth of the gathered lines;
+        // a single FP32 event, whose site fields stay cached, loads them
+        // everywhere and selects, without the divergent branch (push 43.3
+        // against 41.9 us)
         constexpr int NV = 16 / (int)sizeof(T);
         T rec[kSiteRec];
 #pragma unroll
@@ -54,7 +56,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
 #pragma unroll
         for (int d = 0; d < 2; d++) {
             const bool stored = half_stored(d, cx, cy);
-            if constexpr (sizeof(T) == 8) {
+            if constexpr (ST) {
                 if (stored) {
 #pragma unroll
                     for (int j = 0; j < 8; j += NV) chunk_ld16(F, n2, x, 48 + 8 * d + j, rec + 48 + 8 * d + j);
