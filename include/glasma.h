@@ -165,7 +165,11 @@ gl_status gl_rates_from_series(const double *series, int32_t rows, double dtau,
 /* Diagnostics of the current state (FP64 reductions on the device). */
 gl_status gl_diagnostics(gl_event *ev, gl_diag *out);
 
-/* Host <-> device state transfer in the layouts above (tests, checkpoints). */
+/* Host <-> device state transfer in the layouts above (tests, checkpoints).
+ * The device keeps the first two rows of each link and rebuilds the third as
+ * the complex conjugate of their cross product (exact for SU(3)):
+ * gl_set_state expects SU(3) links and stores rows 0 and 1 of each;
+ * gl_get_state returns all 18 values with the third row so rebuilt. */
 gl_status gl_set_state(gl_event *ev, const double *U, const double *E, const double *phi,
                        const double *pi, int64_t n);
 gl_status gl_get_state(gl_event *ev, double *U, double *E, double *phi, double *pi,
