@@ -73,7 +73,9 @@ typedef struct {
     int32_t precision;      /* 64 (FP64 fields/particles) or 32 (FP32 fields/particles, FP64 sums) */
     int32_t reunit_every;   /* FP32 only: re-unitarise links when n % reunit_every == reunit_every-1; 0 = never */
     int32_t max_steps;      /* capacity of the broadening series (rows) */
-    int64_t max_particles;  /* particle capacity over all species (padding included by the library) */
+    int64_t max_particles;  /* particle capacity over all species (padding included by the library);
+                               at most 19173888 (FP64) or 33554176 (FP32): the particle record
+                               is addressed with 32-bit byte offsets; GL_EINVAL above */
     int32_t static_correlator; /* nonzero: reserve the static-quark accumulators (gl_static_start) */
     int32_t lightlike_correlator; /* nonzero: reserve the lightlike-jet accumulators (gl_lightlike_start) */
 } gl_lattice_desc;

@@ -59,18 +59,27 @@ bool valid_N_for_fft(int N) {
     return m == 1;
 }
 
+// largest particle capacity whose record planes stay below 2^31 bytes
+// (the buffer range of the device accesses), in whole push blocks
+int64_t max_particles_for(int precision) {
+    const int64_t rec = (int64_t)part_rec(precision == 64 ? 8 : 4) * (precision == 64 ? 8 : 4);
+    return ((((int64_t)1 << 31) - 256) / rec) / kPushBlock * kPushBlock;
+}
+
 gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     if (!d) return fail(GL_EINVAL, "null lattice description");
     if (d->N < 2 || d->N > 1024) return fail(GL_EINVAL, "N must be in [2, 1024]");
     if (!(d->L_fm > 0) || !(d->dtau_over_a > 0) || d->dtau_over_a > 0.5)
         return fail(GL_EINVAL, "L_fm must be > 0 and 0 < dtau_over_a <= 0.5");
     if (d->precision != 64 && d->precision != 32) return fail(GL_EINVAL, "precision must be 64 or 32");
-    // particle arrays are indexed with 32-bit byte offsets on the device
-    if (d->max_particles > ((int64_t)1 << 28) - ((int64_t)kPushBlock << 5))
-        return fail(GL_EINVAL, "max_particles must be below 2^28 - 8192");
     if (d->max_steps < 0 || d->max_particles < 0 || d->reunit_every < 0)
         return fail(GL_EINVAL, "negative capacity");
     const size_t n2 = (size_t)d->N * d->N, ts = d->precision == 64 ? 8 : 4;
+    // particle arrays are addressed with 32-bit byte offsets on the device;
+    // the widest is the particle record, whose chunk planes span all slots
+    if (d->max_particles > max_particles_for(d->precision))
+        return fail(GL_EINVAL, "max_particles above the 32-bit particle-record range (" +
+                                   std::to_string(max_particles_for(d->precision)) + " at this precision)");
     L.slots = (d->max_particles + kPushBlock - 1) / kPushBlock * kPushBlock;
     if (d->max_particles == 0) L.slots = 0;
     size_t off = 0;

@@ -484,9 +484,10 @@ __device__ __forceinline__ T row_sum(T v) {
 // Arrays are read and written through buffer resources: the array base lives
 // in scalar registers, the lane's byte offset is one 32-bit vector register
 // and the plane offset a scalar, so the many plane accesses of a site cost no
-// per-lane 64-bit address arithmetic.  Lattice planes hold at most 2^20 sites
-// and particle arrays at most 2^28 entries, so every byte offset fits in 32
-// bits.  Offsets x may include a whole number of planes (a lane-dependent
+// per-lane 64-bit address arithmetic.  Lattice planes hold at most 2^20 sites,
+// and the particle capacity is capped so that the widest particle array (the
+// record, in chunk planes over all slots) stays below 2^31 bytes, so every
+// byte offset fits in 32 bits.  Offsets x may include a whole number of planes (a lane-dependent
 // choice of planes).
 constexpr int kBufConfig = 0x00020000;   // raw 32-bit data, gfx9-family layout
 constexpr int kLinkVals = 12;            // stored values of a link (its first two rows)

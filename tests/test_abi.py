@@ -44,6 +44,19 @@ def test_required_bytes_and_validation(gl):
         assert e.value.status == -1
 
 
+@pytest.mark.parametrize("prec,rec_bytes", [(64, 14 * 8), (32, 16 * 4)])
+def test_particle_capacity_stays_within_32_bit_record_offsets(gl, prec, rec_bytes):
+    # the record of every slot spans rec_bytes of chunk planes over all slots;
+    # its byte offsets must stay below 2^31
+    top = ((2**31 - 256) // rec_bytes) // 256 * 256
+    assert top * rec_bytes < 2**31
+    assert gl.required_bytes(16, 2.0, precision=prec, max_particles=top) > top * rec_bytes
+    for bad in (top + 1, 2**28 - 8192):
+        with pytest.raises(gl.GlasmaError) as e:
+            gl.required_bytes(16, 2.0, precision=prec, max_particles=bad)
+        assert e.value.status == -1
+
+
 def test_event_create_checks_workspace_without_touching_device(gl):
     from paper_2307_07999_amd import glasma as G
     d = G.LatticeDesc(16, 2.0, 0.125, 64, 16, 32, 0)
