@@ -24,10 +24,10 @@ def gl():
     return g
 
 
-def _sites(seed, k):
+def _sites(seed, k, n=N):
     g = np.random.default_rng(seed)
-    edge = [0, N - 1, N * (N - 1), N * N - 1, N // 2, N * 7 + N - 1, N * (N - 1) + 5]
-    return np.array(sorted(set(edge) | set(g.integers(0, N * N, k).tolist())), np.int32)
+    edge = [0, n - 1, n * (n - 1), n * n - 1, n // 2, n * 7 + n - 1, n * (n - 1) + 5]
+    return np.array(sorted(set(edge) | set(g.integers(0, n * n, k).tolist())), np.int32)
 
 
 SPECIES = [(1.27, 0.0, 0), (1.27, 2.0, 0), (1.27, 5.0, 0), (4.18, 0.0, 0), (4.18, 2.0, 0),
@@ -47,6 +47,35 @@ def test_field_step_and_site_fields_sampled(gl, orc, prec):
     Ug, Eg, phig, pig, n = ev.get_state()
     Fg = ev.site_fields()
     sites = _sites(prec, 300)
+    Un, En, phin, pin, F = orc.field_step_sites(s, 0.125, sites)
+    tol = 1e-12 if prec == 64 else 2e-5
+    assert np.abs(Ug[:, :, sites] - np.transpose(Un, (1, 2, 0))).max() < tol
+    assert np.abs(Eg[:, :, sites] - np.transpose(En, (1, 2, 0))).max() < tol
+    assert np.abs(phig[:, sites] - phin.T).max() < tol
+    assert np.abs(pig[:, sites] - pin.T).max() < tol
+    scale = max(1.0, np.abs(F).max())
+    assert np.abs(Fg[:, :, sites] - np.transpose(F, (1, 2, 0))).max() < tol * scale
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_field_step_sampled_on_the_largest_lattice(gl, orc, prec):
+    """N = 1024, the largest lattice the library accepts: 2^20 sites, the
+    largest byte offsets of the field planes and of the site-field record.
+    Sampled sites of one field step with site fields, the lattice's last
+    row and column included."""
+    n = 1024
+    U, E, phi, pi = si.random_state(1024 + prec, n, link_kind="near", eps=0.3, e_scale=0.1,
+                                    phi_scale=0.1, pi_scale=0.1)
+    s = orc.State(n)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
+    ev = gl.Event(n, 20.0, 0.125, precision=prec, max_steps=8, max_particles=1000)
+    ev.set_state(*H.state_oracle_to_soa(s), 40)
+    ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 1000, 3)     # so that site fields are made
+    ev.evolve_fields(1)
+    Ug, Eg, phig, pig, steps = ev.get_state()
+    assert steps == 41
+    Fg = ev.site_fields()
+    sites = _sites(prec + 1, 300, n)
     Un, En, phin, pin, F = orc.field_step_sites(s, 0.125, sites)
     tol = 1e-12 if prec == 64 else 2e-5
     assert np.abs(Ug[:, :, sites] - np.transpose(Un, (1, 2, 0))).max() < tol

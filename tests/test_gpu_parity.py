@@ -199,6 +199,56 @@ def test_site_fields_and_one_push_match_oracle(gl, orc):
         assert np.abs(got[k] - w[k]).max() < 1e-12, k
 
 
+@pytest.mark.parametrize("prec,tol,stol", [(64, 1e-12, 1e-9), (32, 2e-4, 1e-3)])
+def test_single_particles_through_a_sort_period_match_oracle(gl, orc, prec, tol, stol):
+    """The smallest ensembles: one heavy quark and one jet, each alone in its
+    push workgroup (255 padding lanes), through 20 coupled steps of gl_run,
+    so that the sort that falls due at step 16 and the push that applies it
+    run too."""
+    N = 24
+    cfg = dict(H.C1, N=N, L=3.0)
+    s, P, ev, mass, nform = _setup_coupled(gl, orc, N, prec, 17, [(0, 1.27, 2.0, 1), (1, 0.0, 10.0, 1)], cfg)
+    steps = 20
+    ev.run(steps)
+    rows = []
+    for _ in range(steps):
+        U0, phi0, n = s.U.copy(), s.phi.copy(), s.n
+        F = orc.field_step(s, 0.125, want_F=True)
+        rows.append(orc.particle_step(N, n, 0.125, U0, phi0, F, P, mass, nform))
+    got = ev.get_particles()
+    w = H.particles_oracle_to_gpu(P)
+    assert np.array_equal(got["cell"], w["cell"])
+    for k in ("off", "eta", "p", "Q"):
+        assert np.abs(got[k] - w[k]).max() < tol, k
+    # series rows: the count of formed particles exactly (the quark forms at
+    # its formation step, the jet at once), the momentum sums to tolerance
+    ser, want = ev.series()[:, :2, :], np.array(rows)[:, :2, :]
+    assert ser.shape == want.shape == (steps, 2, 4)
+    assert np.array_equal(ser[:, :, 3], want[:, :, 3])
+    assert want[0, 0, 3] == 0 and want[-1, 0, 3] == 1 and np.all(want[:, 1, 3] == 1)
+    assert np.abs(ser[:, :, :3] - want[:, :, :3]).max() <= stol * max(1.0, np.abs(want[:, :, :3]).max())
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_run_without_particles_equals_field_steps(gl, prec):
+    """An event with no particles: gl_run is the field leapfrog alone, bitwise
+    the state that gl_evolve_fields reaches, and writes no series rows."""
+    N = 40
+    U, E, phi, pi = si.random_state(41 + prec, N, link_kind="near", eps=0.4)
+    evs = []
+    for _ in range(2):
+        ev = _event(gl, N, prec=prec, max_particles=0, max_steps=16)
+        ev.set_state(si.links_to_soa(U), si.links_to_soa(E), si.alg_to_soa(phi), si.alg_to_soa(pi), 2)
+        evs.append(ev)
+    evs[0].run(7)
+    evs[1].evolve_fields(7)
+    a, b = evs[0].get_state(), evs[1].get_state()
+    assert a[4] == b[4] == 9
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    assert len(evs[0].series()) == 0
+
+
 def test_c1_full_run_matches_oracle(gl, orc):
     """The 32^2 parity configuration end to end: MV init on the device,
     1000 charm quarks, 63 coupled steps to tau = 1 fm, series and kappa."""
