@@ -1,0 +1,61 @@
+"""Host logic of bench.py (CPU only): the workload's step count, the
+algorithmic byte counts the roofline line divides by, the rule that stale
+traffic figures are reported as null, and the single-GPU refusal."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_coupled_steps_of_the_workloads():
+    # dtau = a/8 up to tau = 1 fm, less the first half step of the leapfrog
+    assert bench.coupled_steps(32, 4.0) == 63      # a = 0.125 fm: 64 steps of a/8
+    assert bench.coupled_steps(512, 10.0) == 409   # a = 10/512 fm: ceil(409.6) - 1
+    assert bench.coupled_steps(bench.N, bench.L_FM) == 409
+
+
+@pytest.mark.parametrize("prec,ts", [(64, 8), (32, 4)])
+def test_algorithmic_bytes_follow_the_layouts(prec, ts):
+    b = bench.alg_bytes(prec)
+    link_rows = 2 * (2 * 3 * 2)          # two links, two stored rows of 3 complex entries
+    state = link_rows + 2 * 8 + 8 + 8    # U, E_x and E_y, phi, pi
+    site_fields = 6 * 8                  # E and B, eight colours each
+    assert b["field_step"] == (2 * state + site_fields) * ts
+    record = 2 + 1 + 3 + 8               # offsets in the cell, rapidity, momenta, charge
+    cells, species = 8, 4
+    assert b["push"] == (cells + species + record * ts) + (site_fields + 8) * ts + (cells + record * ts)
+    assert (b["field_step"], b["push"]) == ((1280, 692) if prec == 64 else (640, 356))
+
+
+def test_recorded_traffic_is_near_the_algorithmic_bytes():
+    for prec in (64, 32):
+        t = bench.measured_traffic("field_step", prec)
+        assert t is not None, "traffic figures missing or taken on other kernel sources"
+        alg = bench.alg_bytes(prec)["field_step"] * bench.N * bench.N
+        assert 1.0 <= sum(t) / alg < 1.2
+        p = bench.measured_traffic("push", prec)
+        assert p is not None and p[0] > 0 and p[1] > 0
+
+
+def test_traffic_from_other_kernel_sources_is_null(tmp_path, monkeypatch):
+    text = open(bench.TRAFFIC_FILE).read()
+    assert "source hash: `%s`" % bench.kernel_source_hash() in text
+    stale = tmp_path / "traffic.md"
+    stale.write_text(text.replace(bench.kernel_source_hash(), "0123456789abcdef"))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
+    assert bench.measured_traffic("field_step", 64) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic("field_step", 64) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
