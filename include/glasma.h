@@ -74,8 +74,8 @@ typedef struct {
     int32_t reunit_every;   /* FP32 only: re-unitarise links when n % reunit_every == reunit_every-1; 0 = never */
     int32_t max_steps;      /* capacity of the broadening series (rows) */
     int64_t max_particles;  /* particle capacity over all species (padding included by the library);
-                               at most 19173888 (FP64) or 33554176 (FP32): the particle record
-                               is addressed with 32-bit byte offsets; GL_EINVAL above */
+                               at most gl_max_particles(precision), 19173888 (FP64) or 33554176
+                               (FP32); GL_EINVAL above */
     int32_t static_correlator; /* nonzero: reserve the static-quark accumulators (gl_static_start) */
     int32_t lightlike_correlator; /* nonzero: reserve the lightlike-jet accumulators (gl_lightlike_start) */
 } gl_lattice_desc;
@@ -114,6 +114,11 @@ typedef struct {
 
 /* Workspace size for an event.  Pure function. */
 gl_status gl_required_bytes(const gl_lattice_desc *desc, size_t *bytes);
+
+/* Largest max_particles an event of this precision (64 or 32) accepts: the
+ * particle record, in 16-byte chunk planes over all slots, must stay within
+ * 32-bit byte offsets.  Pure function; GL_EINVAL for another precision. */
+gl_status gl_max_particles(int32_t precision, int64_t *max_particles);
 
 /* Create an event on a caller-owned workspace and stream (hipStream_t). */
 gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t bytes,

@@ -716,6 +716,13 @@ const char *gl_status_string(gl_status s) {
     }
 }
 
+gl_status gl_max_particles(int32_t precision, int64_t *max_particles) {
+    if (precision != 64 && precision != 32) return fail(GL_EINVAL, "precision must be 64 or 32");
+    if (!max_particles) return fail(GL_EINVAL, "null output");
+    *max_particles = max_particles_for(precision);
+    return GL_OK;
+}
+
 gl_status gl_required_bytes(const gl_lattice_desc *desc, size_t *bytes) {
     Layout L;
     gl_status s = make_layout(desc, L);

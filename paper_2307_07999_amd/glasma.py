@@ -95,6 +95,7 @@ _SIGS = {
     "gl_batch_config": [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "gl_batch_info": [_VP, _I32, _I32, _I32, _I32, _I32],
     "gl_batch_run": [_VP, ctypes.c_int32],
+    "gl_max_particles": [ctypes.c_int32, _I64],
 }
 
 _lib = None
@@ -150,6 +151,13 @@ def required_bytes(N, L_fm, dtau_over_a=0.125, precision=64, reunit_every=16, ma
     d = LatticeDesc(N, L_fm, dtau_over_a, precision, reunit_every, max_steps, max_particles)
     out = ctypes.c_size_t(0)
     check(lib().gl_required_bytes(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
+
+
+def max_particles(precision=64):
+    """Largest particle capacity an event of this precision accepts."""
+    out = ctypes.c_int64(0)
+    check(lib().gl_max_particles(precision, ctypes.byref(out)))
     return out.value
 
 

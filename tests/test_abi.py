@@ -50,11 +50,14 @@ def test_particle_capacity_stays_within_32_bit_record_offsets(gl, prec, rec_byte
     # its byte offsets must stay below 2^31
     top = ((2**31 - 256) // rec_bytes) // 256 * 256
     assert top * rec_bytes < 2**31
+    assert gl.max_particles(prec) == top
     assert gl.required_bytes(16, 2.0, precision=prec, max_particles=top) > top * rec_bytes
     for bad in (top + 1, 2**28 - 8192):
         with pytest.raises(gl.GlasmaError) as e:
             gl.required_bytes(16, 2.0, precision=prec, max_particles=bad)
         assert e.value.status == -1
+    with pytest.raises(gl.GlasmaError):
+        gl.max_particles(16)
 
 
 def test_event_create_checks_workspace_without_touching_device(gl):
