@@ -108,7 +108,8 @@ typedef struct {
     double gauss_rel;        /* gauss_max / max |E^a|                   */
     double unitarity_max;    /* max |U U^dag - 1| entry                 */
     double energy[4];        /* (E_T, E_L, B_T, B_L) per unit rapidity, lattice units, at the stored times */
-    double casimir2_dev;     /* max |Q^aQ^a - 4| over active particles  */
+    double casimir2_dev;     /* max |Q^aQ^a - 4| over the particles     */
+    double casimir3_dev;     /* max |d_abc Q^aQ^bQ^c - 10/3| over the particles */
     int32_t nonfinite;       /* 1 if any NaN/Inf in the fields          */
 } gl_diag;
 
@@ -169,8 +170,44 @@ gl_status gl_series(gl_event *ev, double *out, int32_t cap_rows, int32_t *n_rows
 gl_status gl_rates_from_series(const double *series, int32_t rows, double dtau,
                                double *rates);
 
-/* Diagnostics of the current state (FP64 reductions on the device). */
+/* Diagnostics of the current state (FP64 reductions on the device): the
+ * Gauss-law residual, unitarity, the energy terms, and the two Casimirs of
+ * the particle charges, which Eq. (2) conserves (Sec. 1 "Probes in Glasma":
+ * q2 = Q^aQ^a = 4 and q3 = d_abc Q^aQ^bQ^c = 10/3 for <Q^aQ^b> = delta^ab/2,
+ * <Q^aQ^bQ^c> = d^abc/4).  GL_ENUMERIC, with *out filled, when a field value
+ * is not finite. */
 gl_status gl_diagnostics(gl_event *ev, gl_diag *out);
+
+/* Failure detection inside gl_run.  With period K >= 1 every K-th step (and
+ * the last step of the call) checks the whole field state for non-finite
+ * values on the device, and the series rows the call wrote are checked at
+ * its end; gl_run then synchronises the stream and returns GL_ENUMERIC,
+ * naming the first step at which a non-finite value was seen, if any was.
+ * The run itself is not cut short (the device does not stop), so the state
+ * at return is that of the full call.  0 (default) switches the checks off. */
+gl_status gl_set_check_period(gl_event *ev, int32_t every);
+
+/* Iteration cap and residual tolerance of the matching Newton solve of the
+ * initial condition (defaults 100 and 1e-13; max_iter >= 1, tol > 0).  A link
+ * whose residual is not below tol after max_iter iterations makes
+ * gl_init_glasma return GL_ENOTCONV. */
+gl_status gl_set_match_params(gl_event *ev, int32_t max_iter, double tol);
+
+/* Checkpoint and restore (bitwise resume).  gl_checkpoint writes, to a file
+ * of the host, everything a later call needs to continue the event exactly
+ * as if it had not stopped: the field state (and, when a particle step is
+ * due, the site fields and the state at tau_n that the push reads), the particles in their device order with their ids,
+ * the species table, the broadening series and formation sums, the sort
+ * phase, and the static-quark and lightlike-jet accumulators with their
+ * series when running.  Not saved: the Wilson lines of the initial
+ * condition (gl_get_wilson_line, gl_dipole need a new gl_init_glasma) and
+ * the kernel-timing state.  gl_restore reads such a file into an event
+ * created with an identical gl_lattice_desc (GL_EINVAL otherwise, or for a
+ * file that is not a checkpoint of this format); the event's previous
+ * contents are replaced.  Both synchronise the stream.  GL_ESTATE for an
+ * uninitialised event (checkpoint) or an event held by a batch (restore). */
+gl_status gl_checkpoint(gl_event *ev, const char *path);
+gl_status gl_restore(gl_event *ev, const char *path);
 
 /* Host <-> device state transfer in the layouts above (tests, checkpoints).
  * The device keeps the first two rows of each link and rebuilds the third as
@@ -289,10 +326,15 @@ gl_status gl_sync(gl_event *ev);
  * captured once into a hipGraph (graph_steps steps, default 32 = two particle
  * sort periods, so that the ping-pong parities return) and replayed; steps
  * that do not fill a graph run as ordinary launches.  The batch snapshots the
- * events: do not add particles to or step its events individually while the
- * batch exists (gl_batch_run keeps their step index, buffers and series up
- * to date, so they can be read and used again afterwards).  The caller owns
- * the batch workspace (gl_batch_required_bytes, 256-byte aligned). */
+ * events, so while it exists it holds them: the calls that step, initialise
+ * or change an event (gl_init_glasma*, gl_add_species, gl_set_particles,
+ * gl_set_state, gl_restore, gl_evolve_fields, gl_push_particles, gl_run,
+ * gl_set_sort_period, gl_static_start, gl_lightlike_start) return GL_ESTATE
+ * for a held event, and an event can be held by one batch at a time.  The
+ * getters work (gl_batch_run keeps the step index, buffers and series of its
+ * events up to date); gl_batch_destroy releases the events, which can then
+ * be used again.  Destroy the batch before its events.  The caller owns the
+ * batch workspace (gl_batch_required_bytes, 256-byte aligned). */
 typedef struct gl_batch gl_batch;
 gl_status gl_batch_required_bytes(gl_event *const *evs, int32_t n_events, size_t *bytes);
 gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspace, size_t bytes,

@@ -71,8 +71,7 @@ def forward(p, Xs, shape, bf16=False):
     return Zs, Hs
 
 
-def loss_and_grads(p, Xs, Ys, shape, bf16=False):
-    """Standardised targets Ys.  Returns (loss, flat gradient)."""
+def _backward(p, Xs, Ys, shape, bf16, magnitudes):
     Ws, bs = unpack(p, *shape)
     r = bf16_round if bf16 else (lambda v: v)
     Zs, Hs = forward(p, Xs, shape, bf16)
@@ -81,10 +80,35 @@ def loss_and_grads(p, Xs, Ys, shape, bf16=False):
     loss = np.sum((out - Ys) ** 2) / n
     dz = 2.0 * (out - Ys) / n
     gW, gb = [None] * len(Ws), [None] * len(Ws)
+    mag = np.abs if magnitudes else (lambda v: v)
     for l in range(len(Ws) - 1, -1, -1):
-        gW[l] = r(dz).T @ Hs[l]
-        gb[l] = dz.sum(axis=0)
+        gW[l] = mag(r(dz)).T @ mag(Hs[l])
+        gb[l] = mag(dz).sum(axis=0)
         if l > 0:
             dh = r(dz) @ r(Ws[l])
             dz = dh * dsilu(Zs[l - 1])
     return loss, pack(gW, gb)
+
+
+def loss_and_grads(p, Xs, Ys, shape, bf16=False):
+    """Standardised targets Ys.  Returns (loss, flat gradient)."""
+    return _backward(p, Xs, Ys, shape, bf16, False)
+
+
+def grad_scales(p, Xs, Ys, shape, bf16=False):
+    """Per parameter, the sum of the magnitudes of the terms that make up its
+    gradient (|dZ|^T |H| for a weight, sum |dZ| for a bias), from the same
+    forward and backward pass as loss_and_grads: the condition of each sum.
+    Changing every term by a relative u moves the element by at most u times
+    this, so rounding the BF16 operands differently (one BF16 ulp, u = 2^-8)
+    or accumulating in another order stays within a small multiple of it."""
+    return _backward(p, Xs, Ys, shape, bf16, True)[1]
+
+
+def output_scales(p, Xs, shape, bf16=False):
+    """Per sample and output, |W_L| |h_{L-1}| + |b_L|: the condition of the
+    last layer's sum (standardised units), the same role as grad_scales."""
+    Ws, bs = unpack(p, *shape)
+    r = bf16_round if bf16 else (lambda v: v)
+    _, Hs = forward(p, Xs, shape, bf16)
+    return np.abs(Hs[-1]) @ np.abs(r(Ws[-1])).T + np.abs(bs[-1])

@@ -102,7 +102,7 @@ gl_status make_layout(const gl_lattice_desc *d, Layout &L) {
     L.p0sum = take((size_t)kMaxSpecies * 4 * sizeof(double));
     L.n_diag_blocks = (size_t)((d->N + 31) / 32) * ((d->N + 7) / 8);
     size_t cas_blocks = (size_t)std::max<int64_t>(1, (L.slots + 255) / 256);
-    L.diag = take(std::max(L.n_diag_blocks * 8, cas_blocks) * sizeof(double));
+    L.diag = take(std::max(L.n_diag_blocks * 8, 2 * cas_blocks) * sizeof(double));
     L.VA = take(18 * n2 * sizeof(double));
     L.VB = take(18 * n2 * sizeof(double));
     L.planes = take((size_t)kSheetChunk * 4 * n2 * sizeof(double2));
@@ -166,6 +166,10 @@ struct gl_event {
     bool ll_on = false;         // lightlike-jet accumulation running
     int64_t ll_n0 = 0;          // first accumulated field step
     int64_t ll_rows = 0;
+    gl_batch *owner = nullptr;  // the batch that holds the event (its mutators refuse)
+    int32_t match_max_iter = 100;
+    double match_tol = 1e-13;
+    int32_t check_every = 0;    // finite-value checks inside gl_run every this many steps (0: off)
 
     // kernel timing: pairs of events per launch, grouped by kernel class
     int32_t prof = 0;                       // time every prof-th launch of each class (0: off)
@@ -230,6 +234,13 @@ namespace {
 
 gl_status check_ev(gl_event *ev) {
     if (!ev) return fail(GL_EINVAL, "null event");
+    return GL_OK;
+}
+
+// the calls that step, initialise or change an event refuse while a batch holds it
+gl_status check_free(gl_event *ev) {
+    if (!ev) return fail(GL_EINVAL, "null event");
+    if (ev->owner) return fail(GL_ESTATE, "the event is held by a batch (destroy the batch first)");
     return GL_OK;
 }
 
@@ -408,6 +419,33 @@ gl_status p0_sums(gl_event *ev) {
     return GL_OK;
 }
 
+// failure detection: the whole field state at the current step
+gl_status check_state(gl_event *ev, int *first_bad) {
+    const int64_t n = (int64_t)kStateVals * ev->n2;
+    const int step = (int)std::min<int64_t>(ev->n, 0x7F7F7F7E);
+    if (ev->fp64())
+        HIP_TRY(launch_check_finite<double>(ev->stream, ev->fields<double>(ev->cur).U, n, n, step, first_bad));
+    else
+        HIP_TRY(launch_check_finite<float>(ev->stream, ev->fields<float>(ev->cur).U, n, n, step, first_bad));
+    return GL_OK;
+}
+
+// the series rows [row0, row_end) the call wrote (row r holds the particle
+// step r + 1 -> r + 2), then the verdict of all checks of the call
+gl_status check_report(gl_event *ev, int *first_bad, int64_t row0, int64_t row_end) {
+    const int64_t vals = (int64_t)kMaxSpecies * 4;
+    if (row_end > row0)
+        HIP_TRY(launch_check_finite<double>(ev->stream, ev->series() + row0 * vals, (row_end - row0) * vals, vals,
+                                            (int)(row0 + 2), first_bad));
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, first_bad, sizeof(int), hipMemcpyDeviceToHost, ev->stream));
+    HIP_TRY(hipStreamSynchronize(ev->stream));
+    if (h != 0x7F7F7F7F)
+        return fail(GL_ENUMERIC, "non-finite values in the fields or the broadening sums at step n = " +
+                                     std::to_string(h));
+    return GL_OK;
+}
+
 gl_status do_field_step(gl_event *ev, bool sf) {
     return ev->fp64() ? field_step<double>(ev, sf) : field_step<float>(ev, sf);
 }
@@ -482,7 +520,8 @@ gl_status finish_init(gl_event *ev) {
     int *status = (int *)(ev->ws + ev->L.status);
     HIP_TRY(hipMemsetAsync(status, 0, sizeof(int), ev->stream));
     HIP_TRY(launch_match_pi0(ev->stream, ev->N, (double *)(ev->ws + ev->L.VA), (double *)(ev->ws + ev->L.VB),
-                             (double *)(ev->ws + ev->L.U0), (double *)(ev->ws + ev->L.pi0), status, 100, 1e-13));
+                             (double *)(ev->ws + ev->L.U0), (double *)(ev->ws + ev->L.pi0), status,
+                             ev->match_max_iter, ev->match_tol));
     ev->cur = 0;
     HIP_TRY(launch_first_half_step<T>(ev->stream, ev->N, (double *)(ev->ws + ev->L.U0),
                                       (double *)(ev->ws + ev->L.pi0), ev->fields<T>(0), ev->dtau));
@@ -830,7 +869,8 @@ static double qs_from_dipole(const std::vector<double> &D, double a_gev) {
 }
 
 gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed) {
-    if (check_ev(ev) || !mv) return fail(GL_EINVAL, "null argument");
+    if (!mv) return fail(GL_EINVAL, "null argument");
+    if (gl_status s = check_free(ev)) return s;
     if (mv->n_sheets < 1) return fail(GL_EINVAL, "n_sheets must be >= 1");
     if (!(mv->g2mu_GeV >= 0)) return fail(GL_EINVAL, "g2mu must be >= 0");
     if (!(mv->uv_cut_GeV >= 0)) return fail(GL_EINVAL, "uv_cut_GeV must be >= 0");
@@ -839,13 +879,15 @@ gl_status gl_init_glasma(gl_event *ev, const gl_mv_desc *mv, uint64_t seed) {
 }
 
 gl_status gl_init_glasma_from_charges(gl_event *ev, const double *rho_dev, int32_t n_sheets, double m_ir_GeV) {
-    if (check_ev(ev) || !rho_dev) return fail(GL_EINVAL, "null argument");
+    if (!rho_dev) return fail(GL_EINVAL, "null argument");
+    if (gl_status s = check_free(ev)) return s;
     if (n_sheets < 1) return fail(GL_EINVAL, "n_sheets must be >= 1");
     return init_common(ev, n_sheets, m_ir_GeV, 0.0, rho_dev, 0.0, 0);
 }
 
 gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uint64_t seed, int32_t *species_id) {
-    if (check_ev(ev) || !sp) return fail(GL_EINVAL, "null argument");
+    if (!sp) return fail(GL_EINVAL, "null argument");
+    if (gl_status s = check_free(ev)) return s;
     if (n < 1) return fail(GL_EINVAL, "n must be >= 1");
     if ((int)ev->species.size() >= kMaxSpecies) return fail(GL_EINVAL, "too many species");
     if (ev->push_due) return fail(GL_ESTATE, "a particle step is due");
@@ -868,7 +910,7 @@ gl_status gl_add_species(gl_event *ev, const gl_species_desc *sp, int64_t n, uin
 }
 
 gl_status gl_evolve_fields(gl_event *ev, int32_t n_steps) {
-    if (check_ev(ev)) return GL_EINVAL;
+    if (gl_status s = check_free(ev)) return s;
     if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
     if (n_steps < 0) return fail(GL_EINVAL, "n_steps must be >= 0");
     bool has_particles = ev->slots_used > 0;
@@ -883,7 +925,7 @@ gl_status gl_evolve_fields(gl_event *ev, int32_t n_steps) {
 }
 
 gl_status gl_push_particles(gl_event *ev) {
-    if (check_ev(ev)) return GL_EINVAL;
+    if (gl_status s = check_free(ev)) return s;
     if (!ev->push_due) return fail(GL_ESTATE, "no particle step is due: call gl_evolve_fields(ev, 1) first");
     gl_status s = do_push(ev);
     if (s) return s;
@@ -891,29 +933,39 @@ gl_status gl_push_particles(gl_event *ev) {
 }
 
 gl_status gl_run(gl_event *ev, int32_t n_steps) {
-    if (check_ev(ev)) return GL_EINVAL;
+    if (gl_status s = check_free(ev)) return s;
     if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
     if (ev->push_due) return fail(GL_ESTATE, "a particle step is due");
     if (n_steps < 0) return fail(GL_EINVAL, "n_steps must be >= 0");
     bool has_particles = ev->slots_used > 0;
     if (has_particles && ev->n - 1 + n_steps > ev->desc.max_steps)
         return fail(GL_EINVAL, "series capacity (max_steps) too small for this run");
+    // this call writes the series rows [n - 1, n - 1 + n_steps) (row r: the
+    // particle step r + 1 -> r + 2)
+    const int64_t row0 = ev->n - 1, row_end = has_particles ? row0 + n_steps : row0;
+    int *first_bad = (int *)(ev->ws + ev->L.status) + 1;
+    const bool checks = ev->check_every > 0 && n_steps > 0;
+    if (checks) HIP_TRY(hipMemsetAsync(first_bad, 0x7F, sizeof(int), ev->stream));
     gl_status s = GL_OK;
     for (int32_t k = 0; k < n_steps && !s; k++) {
         s = do_field_step(ev, has_particles);
-        if (s || !has_particles) continue;
-        ev->push_due = true;
-        s = do_push(ev, true);
+        if (!s && has_particles) {
+            ev->push_due = true;
+            s = do_push(ev, true);
+        }
+        if (!s && checks && ((k + 1) % ev->check_every == 0 || k + 1 == n_steps)) s = check_state(ev, first_bad);
     }
     // no sort is left pending, also after an error
     const gl_status sp = apply_pending_sort(ev);
     if (s) return s;
     if (sp) return sp;
-    return flush_series(ev);
+    s = flush_series(ev);
+    if (s || !checks) return s;
+    return check_report(ev, first_bad, row0, row_end);
 }
 
 gl_status gl_static_start(gl_event *ev, double tau_start_fm) {
-    if (check_ev(ev)) return GL_EINVAL;
+    if (gl_status s = check_free(ev)) return s;
     if (!ev->desc.static_correlator) return fail(GL_ESTATE, "event created without static_correlator");
     if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
     if (!(tau_start_fm >= 0)) return fail(GL_EINVAL, "tau_start_fm must be >= 0");
@@ -960,7 +1012,7 @@ gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *
 }
 
 gl_status gl_lightlike_start(gl_event *ev, double tau_start_fm) {
-    if (check_ev(ev)) return GL_EINVAL;
+    if (gl_status s = check_free(ev)) return s;
     if (!ev->desc.lightlike_correlator) return fail(GL_ESTATE, "event created without lightlike_correlator");
     if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
     if (!(tau_start_fm >= 0)) return fail(GL_EINVAL, "tau_start_fm must be >= 0");
@@ -1102,14 +1154,18 @@ gl_status gl_diagnostics(gl_event *ev, gl_diag *out) {
     for (int k = 0; k < 4; k++) out->energy[k] = v[3 + k];
     out->nonfinite = v[7] > 0 ? 1 : 0;
     out->casimir2_dev = 0.0;
+    out->casimir3_dev = 0.0;
     if (ev->slots_used > 0) {
         int cb = 0;
         if (ev->fp64()) HIP_TRY(launch_casimir<double>(ev->stream, ev->parts<double>(), ev->slots_used, part, &cb));
         else HIP_TRY(launch_casimir<float>(ev->stream, ev->parts<float>(), ev->slots_used, part, &cb));
-        std::vector<double> c(cb);
-        HIP_TRY(hipMemcpyAsync(c.data(), part, cb * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
+        std::vector<double> c((size_t)2 * cb);
+        HIP_TRY(hipMemcpyAsync(c.data(), part, c.size() * sizeof(double), hipMemcpyDeviceToHost, ev->stream));
         HIP_TRY(hipStreamSynchronize(ev->stream));
-        for (double x : c) out->casimir2_dev = std::max(out->casimir2_dev, x);
+        for (int b = 0; b < cb; b++) {
+            out->casimir2_dev = std::max(out->casimir2_dev, c[2 * b]);
+            out->casimir3_dev = std::max(out->casimir3_dev, c[2 * b + 1]);
+        }
     }
     if (out->nonfinite) return fail(GL_ENUMERIC, "non-finite values in the fields");
     return GL_OK;
@@ -1117,10 +1173,16 @@ gl_status gl_diagnostics(gl_event *ev, gl_diag *out) {
 
 gl_status gl_set_state(gl_event *ev, const double *U, const double *E, const double *phi, const double *pi,
                        int64_t n) {
-    if (check_ev(ev) || !U || !E || !phi || !pi) return fail(GL_EINVAL, "null argument");
+    if (!U || !E || !phi || !pi) return fail(GL_EINVAL, "null argument");
+    if (gl_status s = check_free(ev)) return s;
     if (n < 1) return fail(GL_EINVAL, "time index must be >= 1");
     gl_status s = ev->fp64() ? set_state_t<double>(ev, U, E, phi, pi) : set_state_t<float>(ev, U, E, phi, pi);
     if (s) return s;
+    // a new history: the series rows before the first push read as zero
+    if (ev->desc.max_steps > 0)
+        HIP_TRY(hipMemsetAsync(ev->series(), 0, (size_t)ev->desc.max_steps * kMaxSpecies * 4 * sizeof(double),
+                               ev->stream));
+    ev->rows = 0;
     ev->n = n;
     ev->ready = true;
     ev->push_due = false;
@@ -1145,8 +1207,8 @@ gl_status gl_get_site_fields(gl_event *ev, double *F) {
 gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_desc *sp, int64_t n,
                            const int32_t *cell, const double *off, const double *eta, const double *p,
                            const double *Q, const double *p0, const int32_t *species) {
-    if (check_ev(ev) || !sp || !cell || !off || !eta || !p || !Q || !p0 || !species)
-        return fail(GL_EINVAL, "null argument");
+    if (!sp || !cell || !off || !eta || !p || !Q || !p0 || !species) return fail(GL_EINVAL, "null argument");
+    if (gl_status s = check_free(ev)) return s;
     if (n_species < 1 || n_species > kMaxSpecies || n < 1) return fail(GL_EINVAL, "bad counts");
     if (ev->push_due) return fail(GL_ESTATE, "a particle step is due");
     std::vector<int64_t> count(n_species, 0);
@@ -1176,9 +1238,24 @@ gl_status gl_set_particles(gl_event *ev, int32_t n_species, const gl_species_des
 }
 
 gl_status gl_set_sort_period(gl_event *ev, int32_t every) {
-    if (check_ev(ev)) return GL_EINVAL;
+    if (gl_status s = check_free(ev)) return s;
     if (every < 0) return fail(GL_EINVAL, "sort period must be >= 0");
     ev->sort_every = every;
+    return GL_OK;
+}
+
+gl_status gl_set_check_period(gl_event *ev, int32_t every) {
+    if (check_ev(ev)) return GL_EINVAL;
+    if (every < 0) return fail(GL_EINVAL, "check period must be >= 0");
+    ev->check_every = every;
+    return GL_OK;
+}
+
+gl_status gl_set_match_params(gl_event *ev, int32_t max_iter, double tol) {
+    if (gl_status s = check_free(ev)) return s;
+    if (max_iter < 1 || !(tol > 0)) return fail(GL_EINVAL, "max_iter must be >= 1 and tol > 0");
+    ev->match_max_iter = max_iter;
+    ev->match_tol = tol;
     return GL_OK;
 }
 
@@ -1306,6 +1383,210 @@ gl_status gl_event_info(gl_event *ev, double *a_fm, double *dtau_lat, int64_t *n
 gl_status gl_sync(gl_event *ev) {
     if (check_ev(ev)) return GL_EINVAL;
     HIP_TRY(hipStreamSynchronize(ev->stream));
+    return GL_OK;
+}
+
+}  // extern "C"
+
+// ---- checkpoint / restore -----------------------------------------------------
+// File: magic, format version, sizeof(gl_lattice_desc), the descriptor, the
+// runtime scalars, the species table, then tagged device blobs (tag, bytes,
+// raw device bytes).  The blob list follows from the descriptor and the
+// scalars, so a restore rebuilds it after reading them and checks each tag
+// and size.  Raw device bytes in the device order keep the resumed run
+// bitwise identical (the reductions follow the particles' slots).
+namespace {
+
+const char kCkptMagic[8] = {'G', 'L', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptScalars {
+    int64_t n, rows, slots_used, since_sort, stat_n0, stat_rows, ll_n0, ll_rows;
+    int32_t cur, pbuf, push_due, set_changed, sort_every, stat_on, ll_on, match_max_iter, check_every, n_species;
+    double match_tol;
+};
+
+struct CkptSpecies {
+    gl_species_desc desc;
+    int64_t n;
+    int32_t nform, pad;
+    double mass_lat, p0_lat, tau_form_fm;
+};
+
+struct Blob {
+    uint64_t tag;
+    char *dev;
+    size_t bytes;
+};
+
+std::vector<Blob> ckpt_blobs(gl_event *ev) {
+    const size_t ts = ev->fp64() ? 8 : 4, n2 = ev->n2, row = (size_t)kMaxSpecies * 4 * sizeof(double);
+    std::vector<Blob> b;
+    b.push_back({1, ev->ws + ev->L.field[ev->cur], (size_t)kStateVals * n2 * ts});
+    if (ev->push_due) {
+        // the pending push reads the site fields and the state at tau_n (links
+        // for the crossings, phi for the eta rotation), the other buffer
+        b.push_back({2, ev->ws + ev->L.F, (size_t)kSiteRec * n2 * ts});
+        b.push_back({11, ev->ws + ev->L.field[1 - ev->cur], (size_t)kStateVals * n2 * ts});
+    }
+    if (ev->L.slots > 0) {
+        b.push_back({3, ev->ws + ev->L.part[ev->pbuf], (size_t)ev->L.slots * ((part_rec(ts) + 3) * ts + 12)});
+        b.push_back({4, (char *)ev->ids(), (size_t)ev->L.slots * sizeof(int32_t)});
+    }
+    b.push_back({5, (char *)ev->series(), (size_t)ev->rows * row});
+    b.push_back({6, (char *)ev->p0sum(), row});
+    if (ev->stat_on) {
+        b.push_back({7, ev->ws + ev->L.stat, 24 * n2 * sizeof(double)});
+        b.push_back({8, (char *)ev->stat_series(), (size_t)ev->stat_rows * row});
+    }
+    if (ev->ll_on) {
+        b.push_back({9, ev->ws + ev->L.ll, 42 * n2 * sizeof(double)});
+        b.push_back({10, (char *)ev->ll_series(), (size_t)ev->ll_rows * row});
+    }
+    return b;
+}
+
+struct FileCloser {
+    std::FILE *f;
+    ~FileCloser() {
+        if (f) std::fclose(f);
+    }
+};
+
+bool same_desc(const gl_lattice_desc &a, const gl_lattice_desc &b) {
+    return a.N == b.N && a.L_fm == b.L_fm && a.dtau_over_a == b.dtau_over_a && a.precision == b.precision &&
+           a.reunit_every == b.reunit_every && a.max_steps == b.max_steps && a.max_particles == b.max_particles &&
+           a.static_correlator == b.static_correlator && a.lightlike_correlator == b.lightlike_correlator;
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_checkpoint(gl_event *ev, const char *path) {
+    if (check_ev(ev) || !path) return fail(GL_EINVAL, "null argument");
+    if (!ev->ready) return fail(GL_ESTATE, "fields not initialised");
+    if (ev->pend != 0 || ev->perm_pending) return fail(GL_ESTATE, "the event has deferred device work pending");
+    FileCloser fc{std::fopen(path, "wb")};
+    if (!fc.f) return fail(GL_EINVAL, std::string("cannot open ") + path + " for writing");
+    CkptScalars c{};
+    c.n = ev->n;
+    c.rows = ev->rows;
+    c.slots_used = ev->slots_used;
+    c.since_sort = ev->since_sort;
+    c.stat_n0 = ev->stat_n0;
+    c.stat_rows = ev->stat_rows;
+    c.ll_n0 = ev->ll_n0;
+    c.ll_rows = ev->ll_rows;
+    c.cur = ev->cur;
+    c.pbuf = ev->pbuf;
+    c.push_due = ev->push_due;
+    c.set_changed = ev->set_changed;
+    c.sort_every = ev->sort_every;
+    c.stat_on = ev->stat_on;
+    c.ll_on = ev->ll_on;
+    c.match_max_iter = ev->match_max_iter;
+    c.check_every = ev->check_every;
+    c.n_species = (int32_t)ev->species.size();
+    c.match_tol = ev->match_tol;
+    std::vector<CkptSpecies> sp(ev->species.size());
+    for (size_t k = 0; k < sp.size(); k++) {
+        const SpeciesInfo &si = ev->species[k];
+        sp[k] = CkptSpecies{si.desc, si.n, si.nform, 0, si.mass_lat, si.p0_lat, si.tau_form_fm};
+    }
+    const uint32_t head[2] = {kCkptVersion, (uint32_t)sizeof(gl_lattice_desc)};
+    bool ok = std::fwrite(kCkptMagic, 1, 8, fc.f) == 8 && std::fwrite(head, sizeof(head), 1, fc.f) == 1 &&
+              std::fwrite(&ev->desc, sizeof(ev->desc), 1, fc.f) == 1 && std::fwrite(&c, sizeof(c), 1, fc.f) == 1 &&
+              (sp.empty() || std::fwrite(sp.data(), sizeof(CkptSpecies), sp.size(), fc.f) == sp.size());
+    std::vector<char> host;
+    for (const Blob &b : ckpt_blobs(ev)) {
+        if (!ok) break;
+        host.resize(b.bytes);
+        if (b.bytes) {
+            HIP_TRY(hipMemcpyAsync(host.data(), b.dev, b.bytes, hipMemcpyDeviceToHost, ev->stream));
+            HIP_TRY(hipStreamSynchronize(ev->stream));
+        }
+        const uint64_t hb[2] = {b.tag, (uint64_t)b.bytes};
+        ok = std::fwrite(hb, sizeof(hb), 1, fc.f) == 1 && (b.bytes == 0 || std::fwrite(host.data(), 1, b.bytes, fc.f) == b.bytes);
+    }
+    if (!ok || std::fflush(fc.f) != 0) return fail(GL_EINVAL, std::string("write to ") + path + " failed");
+    return GL_OK;
+}
+
+gl_status gl_restore(gl_event *ev, const char *path) {
+    if (!path) return fail(GL_EINVAL, "null argument");
+    if (gl_status s = check_free(ev)) return s;
+    FileCloser fc{std::fopen(path, "rb")};
+    if (!fc.f) return fail(GL_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t head[2];
+    gl_lattice_desc d;
+    CkptScalars c;
+    if (std::fread(magic, 1, 8, fc.f) != 8 || std::memcmp(magic, kCkptMagic, 8) != 0 ||
+        std::fread(head, sizeof(head), 1, fc.f) != 1 || head[0] != kCkptVersion ||
+        head[1] != sizeof(gl_lattice_desc) || std::fread(&d, sizeof(d), 1, fc.f) != 1 ||
+        std::fread(&c, sizeof(c), 1, fc.f) != 1)
+        return fail(GL_EINVAL, std::string(path) + " is not a checkpoint of this format");
+    if (!same_desc(d, ev->desc)) return fail(GL_EINVAL, "the checkpoint's lattice description differs from the event's");
+    if (c.n_species < 0 || c.n_species > kMaxSpecies || c.cur < 0 || c.cur > 1 || c.pbuf < 0 || c.pbuf > 1 ||
+        c.rows < 0 || c.rows > std::max(0, d.max_steps) || c.stat_rows < 0 || c.stat_rows > std::max(0, d.max_steps) ||
+        c.ll_rows < 0 || c.ll_rows > std::max(0, d.max_steps) || c.slots_used < 0 || c.slots_used > ev->L.slots ||
+        (c.stat_on && !d.static_correlator) || (c.ll_on && !d.lightlike_correlator))
+        return fail(GL_EINVAL, std::string(path) + ": inconsistent checkpoint");
+    std::vector<CkptSpecies> sp(c.n_species);
+    if (!sp.empty() && std::fread(sp.data(), sizeof(CkptSpecies), sp.size(), fc.f) != sp.size())
+        return fail(GL_EINVAL, std::string(path) + " is truncated");
+    // the event takes the checkpoint's scalars, then its blobs
+    ev->n = c.n;
+    ev->rows = c.rows;
+    ev->slots_used = c.slots_used;
+    ev->since_sort = c.since_sort;
+    ev->stat_n0 = c.stat_n0;
+    ev->stat_rows = c.stat_rows;
+    ev->ll_n0 = c.ll_n0;
+    ev->ll_rows = c.ll_rows;
+    ev->cur = c.cur;
+    ev->pbuf = c.pbuf;
+    ev->push_due = c.push_due != 0;
+    ev->set_changed = c.set_changed != 0;
+    ev->sort_every = c.sort_every;
+    ev->stat_on = c.stat_on != 0;
+    ev->ll_on = c.ll_on != 0;
+    ev->match_max_iter = c.match_max_iter;
+    ev->match_tol = c.match_tol;
+    ev->check_every = c.check_every;
+    ev->pend = 0;
+    ev->pend_row0 = 0;
+    ev->perm_pending = false;
+    ev->ready = false;   // until every blob is in
+    ev->species.clear();
+    for (const CkptSpecies &k : sp) {
+        SpeciesInfo si;
+        si.desc = k.desc;
+        si.n = k.n;
+        si.nform = k.nform;
+        si.mass_lat = k.mass_lat;
+        si.p0_lat = k.p0_lat;
+        si.tau_form_fm = k.tau_form_fm;
+        ev->species.push_back(si);
+    }
+    // series rows past the saved ones read as zero, as in a fresh run
+    const size_t row = (size_t)kMaxSpecies * 4 * sizeof(double), cap_rows = (size_t)std::max(1, d.max_steps);
+    HIP_TRY(hipMemsetAsync(ev->series(), 0, cap_rows * row, ev->stream));
+    if (d.static_correlator) HIP_TRY(hipMemsetAsync(ev->stat_series(), 0, cap_rows * row, ev->stream));
+    if (d.lightlike_correlator) HIP_TRY(hipMemsetAsync(ev->ll_series(), 0, cap_rows * row, ev->stream));
+    std::vector<char> host;
+    for (const Blob &b : ckpt_blobs(ev)) {
+        uint64_t hb[2];
+        if (std::fread(hb, sizeof(hb), 1, fc.f) != 1 || hb[0] != b.tag || hb[1] != b.bytes)
+            return fail(GL_EINVAL, std::string(path) + ": unexpected section");
+        host.resize(b.bytes);
+        if (b.bytes == 0) continue;
+        if (std::fread(host.data(), 1, b.bytes, fc.f) != b.bytes) return fail(GL_EINVAL, std::string(path) + " is truncated");
+        HIP_TRY(hipMemcpyAsync(b.dev, host.data(), b.bytes, hipMemcpyHostToDevice, ev->stream));
+        HIP_TRY(hipStreamSynchronize(ev->stream));
+    }
+    ev->ready = true;
     return GL_OK;
 }
 
@@ -1588,6 +1869,7 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
         gl_event *ev = evs[e];
         if (!ev->ready) return fail(GL_ESTATE, "every event must be initialised");
         if (ev->push_due) return fail(GL_ESTATE, "an event has a particle step due");
+        if (ev->owner) return fail(GL_ESTATE, "an event is already held by another batch");
         if (ev->desc.precision != e0->desc.precision || ev->dtau != e0->dtau || ev->n != e0->n)
             return fail(GL_EINVAL, "events of a batch share precision, dtau and the step index");
         for (int f = 0; f < e; f++)
@@ -1667,6 +1949,7 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
         hipMemcpyAsync(b->ws + b->ctl, &c, sizeof(c), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return cleanup(fail(GL_EDEVICE, "table upload failed"));
+    for (auto *ev : b->evs) ev->owner = b;
     *out = b;
     return GL_OK;
 }
@@ -1674,6 +1957,8 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
 void gl_batch_destroy(gl_batch *b) {
     if (!b) return;
     batch_drop_graphs(b);
+    for (auto *ev : b->evs)
+        if (ev->owner == b) ev->owner = nullptr;
     delete b;
 }
 

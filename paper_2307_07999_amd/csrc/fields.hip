@@ -26,6 +26,8 @@
 // band of rows (xcd_remap): the neighbour reads of the stencil then hit the
 // L2 of the XCD that owns the tile instead of refetching halo lines from
 // memory.
+#include <algorithm>
+
 #include "fields_dev.hpp"
 
 namespace gl {
@@ -273,6 +275,43 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
     }
 }
 
+// Failure detection: values [0, n) of a flat array, grouped in steps of
+// vals_per_step consecutive values (step step0 + i / vals_per_step), are
+// tested for NaN and Inf, and a lane holding one lowers *first_bad to its
+// step.  Grid-stride; one 16-byte vector of V values per lane and pass.
+template <typename V, typename T, int NV>
+__global__ void __launch_bounds__(256)
+k_check_finite(const T *__restrict__ a, int64_t n, int64_t vals_per_step, int step0, int *first_bad) {
+    const int64_t nv = n / NV;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += stride) {
+        const V w = reinterpret_cast<const V *>(a)[v];
+        const T *e = reinterpret_cast<const T *>(&w);
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < NV; k++) bad |= !isfinite(e[k]);
+        if (bad) atomicMin(first_bad, step0 + (int)(v * NV / vals_per_step));
+    }
+    // a tail shorter than one vector
+    const int64_t t = nv * NV + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n && !isfinite(a[t])) atomicMin(first_bad, step0 + (int)(t / vals_per_step));
+}
+
+template <typename T>
+hipError_t launch_check_finite(hipStream_t st, const T *a, int64_t n, int64_t vals_per_step, int step0,
+                               int *first_bad) {
+    if (n <= 0) return hipSuccess;
+    constexpr int NV = 16 / (int)sizeof(T);
+    const int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, (n / NV + 255) / 256));
+    if (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_check_finite<double2, double, 2>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const double *)a, n, vals_per_step, step0, first_bad);
+    else
+        hipLaunchKernelGGL((k_check_finite<float4, float, 4>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const float *)a, n, vals_per_step, step0, first_bad);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F, double tau,
                              double dtau, int reunit) {
@@ -313,6 +352,7 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
     template hipError_t launch_field_step<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, T *,    \
                                              double, double, int);                           \
     template hipError_t launch_diag<T>(hipStream_t, int, FieldPtrs<T>, double, double *, int *);     \
+    template hipError_t launch_check_finite<T>(hipStream_t, const T *, int64_t, int64_t, int, int *);   \
     template hipError_t launch_static_accum<T>(hipStream_t, int, const T *, double *, double, double *, int *); \
     template hipError_t launch_lightlike_accum<T>(hipStream_t, int, const T *, const T *, double *, double *, \
                                                   int64_t, double, double *, int *);

@@ -148,6 +148,11 @@ hipError_t launch_lightlike_accum(hipStream_t st, int N, const T *F, const T *U,
 template <typename T>
 hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double *partials,
                        int *n_blocks_out);
+// lowers *first_bad to step0 + i / vals_per_step for every non-finite value i
+// of a [0, n) (16-byte aligned; the int is not reset here)
+template <typename T>
+hipError_t launch_check_finite(hipStream_t st, const T *a, int64_t n, int64_t vals_per_step, int step0,
+                               int *first_bad);
 
 // initial conditions (always FP64 internally)
 constexpr int kSheetChunk = 8;   // MV sheets per initialisation launch
@@ -176,6 +181,8 @@ hipError_t launch_wilson_accum(hipStream_t st, int N, const double2 *planes, int
 hipError_t launch_match_pi0(hipStream_t st, int N, const double *VA, const double *VB,
                            double *U0 /* [2][18][n2] FP64 */, double *pi0 /* [8][n2] */,
                            int *status, int max_iter, double tol);
+// per workgroup max |q2 - 4| and max |q3 - 10/3| of the particles' charges:
+// partials [blocks][2]
 template <typename T>
 hipError_t launch_casimir(hipStream_t st, PartPtrs<T> p, int64_t n_slots, double *partials,
                           int *n_blocks_out);

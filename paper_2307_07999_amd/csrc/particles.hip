@@ -231,28 +231,44 @@ hipError_t launch_p0_sums(hipStream_t st, PartPtrs<T> p, int64_t n_slots, int n_
     return launch_series_reduce(st, partials, (int)blocks, n_species, out, nullptr);
 }
 
-// max |Q^a Q^a - 4| per workgroup over particles (padding excluded)
+// per workgroup, over the particles (padding excluded): max |q2 - 4| and
+// max |q3 - 10/3| of the Casimirs q2 = Q^aQ^a = 2 Tr Q^2 and
+// q3 = d_abc Q^aQ^bQ^c = 4 Tr Q^3 (the f_abc part of Tr T^aT^bT^c cancels in
+// the symmetric contraction), which Eq. (2) conserves
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_casimir(PartPtrs<T> P, int64_t n_slots, double *partials) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double v = 0.0;
+    double v2 = 0.0, v3 = 0.0;
     if (i < n_slots && P.species[i] >= 0) {
-        double q2 = 0.0;
+        double q[8], q2 = 0.0;
 #pragma unroll
         for (int a = 0; a < 8; a++) {
-            double q = chunk_ld(P.st, (size_t)P.cap, (size_t)i, kQ + a);
-            q2 += q * q;
+            q[a] = chunk_ld(P.st, (size_t)P.cap, (size_t)i, kQ + a);
+            q2 += q[a] * q[a];
         }
-        v = fabs(q2 - 4.0);
-        if (!isfinite(v)) v = 1e300;
+        const M3<double> Qm = herm_from_alg(q);
+        const double q3 = 4.0 * re_tr_mul(mul(Qm, Qm), Qm);
+        v2 = fabs(q2 - 4.0);
+        v3 = fabs(q3 - 10.0 / 3.0);
+        if (!isfinite(v2)) v2 = 1e300;
+        if (!isfinite(v3)) v3 = 1e300;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    for (int off = 32; off > 0; off >>= 1) {
+        v2 = fmax(v2, __shfl_xor(v2, off, 64));
+        v3 = fmax(v3, __shfl_xor(v3, off, 64));
+    }
+    __shared__ double red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = v2;
+        red[1][threadIdx.x >> 6] = v3;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (threadIdx.x < 2) {
+        const int k = threadIdx.x;
+        partials[2 * blockIdx.x + k] = fmax(fmax(red[k][0], red[k][1]), fmax(red[k][2], red[k][3]));
+    }
 }
 
 template <typename T>

@@ -45,7 +45,8 @@ class SpeciesDesc(ctypes.Structure):
 class Diag(ctypes.Structure):
     _fields_ = [("gauss_max", ctypes.c_double), ("gauss_rel", ctypes.c_double),
                 ("unitarity_max", ctypes.c_double), ("energy", ctypes.c_double * 4),
-                ("casimir2_dev", ctypes.c_double), ("nonfinite", ctypes.c_int32)]
+                ("casimir2_dev", ctypes.c_double), ("casimir3_dev", ctypes.c_double),
+                ("nonfinite", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -96,6 +97,10 @@ _SIGS = {
     "gl_batch_info": [_VP, _I32, _I32, _I32, _I32, _I32],
     "gl_batch_run": [_VP, ctypes.c_int32],
     "gl_max_particles": [ctypes.c_int32, _I64],
+    "gl_set_check_period": [_VP, ctypes.c_int32],
+    "gl_set_match_params": [_VP, ctypes.c_int32, ctypes.c_double],
+    "gl_checkpoint": [_VP, ctypes.c_char_p],
+    "gl_restore": [_VP, ctypes.c_char_p],
 }
 
 _lib = None
@@ -213,9 +218,17 @@ class Event:
         return check(lib().gl_init_glasma(self._h, ctypes.byref(mv), seed))
 
     def init_glasma_from_charges(self, rho, m_ir_GeV):
-        """rho: torch float64 device tensor [2, n_sheets, 8, N*N] (lattice units)."""
-        assert rho.dtype == self.torch.float64 and rho.is_contiguous() and rho.device.type == "cuda"
-        return check(lib().gl_init_glasma_from_charges(self._h, _VP(rho.data_ptr()), rho.shape[1], m_ir_GeV))
+        """rho: contiguous torch float64 device tensor [2, n_sheets, 8, N*N] or
+        [2, n_sheets, 8, N, N] (lattice units); the library reads all of it."""
+        if rho.dtype != self.torch.float64 or not rho.is_contiguous() or rho.device.type != "cuda":
+            raise ValueError("rho must be a contiguous float64 tensor on the GPU")
+        N = self.N
+        shape = tuple(rho.shape)
+        if not (len(shape) in (4, 5) and shape[0] == 2 and shape[1] >= 1 and shape[2] == 8 and
+                shape[3:] in ((N * N,), (N, N))):
+            raise ValueError("rho must have shape (2, n_sheets, 8, %d) or (2, n_sheets, 8, %d, %d), got %s"
+                             % (N * N, N, N, shape))
+        return check(lib().gl_init_glasma_from_charges(self._h, _VP(rho.data_ptr()), shape[1], m_ir_GeV))
 
     def add_species(self, mass_GeV, p0_GeV, kind, n, seed, tau_form_fm=-1.0):
         sp = SpeciesDesc(mass_GeV, p0_GeV, kind, tau_form_fm)
@@ -311,8 +324,21 @@ class Event:
         if st not in (GL_OK, GL_ENUMERIC):
             check(st)
         return dict(gauss_max=d.gauss_max, gauss_rel=d.gauss_rel, unitarity_max=d.unitarity_max,
-                    energy=list(d.energy), casimir2_dev=d.casimir2_dev, nonfinite=d.nonfinite,
-                    status=st)
+                    energy=list(d.energy), casimir2_dev=d.casimir2_dev, casimir3_dev=d.casimir3_dev,
+                    nonfinite=d.nonfinite, status=st)
+
+    def set_check_period(self, every):
+        """Finite-value checks inside run() every `every` steps (0: off)."""
+        return check(lib().gl_set_check_period(self._h, every))
+
+    def set_match_params(self, max_iter, tol):
+        return check(lib().gl_set_match_params(self._h, max_iter, tol))
+
+    def checkpoint(self, path):
+        return check(lib().gl_checkpoint(self._h, os.fsencode(path)))
+
+    def restore(self, path):
+        return check(lib().gl_restore(self._h, os.fsencode(path)))
 
     # ---- host transfers (tests, checkpoints) ---------------------------------
     def set_state(self, U, E, phi, pi, n):

@@ -59,7 +59,8 @@ def test_batch_equals_single_events(gl, prec, shape, mult):
             ps, pb = s.get_particles(), t.get_particles()
             for k in ("cell", "p", "Q"):
                 assert np.array_equal(ps[k], pb[k])
-    # the events keep working on their own after the batch
+    # the events keep working on their own once the batch releases them
+    b.close()
     for t, (N, npart) in zip(batched, SIZES):
         if npart:
             t.evolve_fields(1)
@@ -77,7 +78,53 @@ def test_autotune_cache_roundtrip(gl, tmp_path):
     (key, val), = data.items()
     assert key.startswith("gfx") and "|p32|" in key
     assert val == [first["shape"], first["grid_mult"]]
+    b.close()
     b2 = gl.Batch(evs)
     b2.autotune(path)
     assert b2.info() == first
     b2.run(4)
+
+
+def test_batched_event_matches_oracle(gl, orc):
+    """One event of a mixed batch against the oracle directly: the 32^2
+    configuration (MV init, 1000 charm quarks, 63 coupled steps to 1 fm) runs
+    in a batch beside a 48^2 and a 64^2 event with quarks and jets, and its
+    series and final state must match orc.run as a single event does (the
+    batched kernels hold the same arithmetic; 1e-9 relative over the chaotic
+    63-step evolution)."""
+    cfg = H.C1
+    N = cfg["N"]
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    steps = H.n_steps(cfg)
+    ev = gl.Event(N, cfg["L"], 0.125, precision=64, max_steps=steps, max_particles=1000)
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
+    sid = ev.add_species(1.27, 0.0, gl.KIND_HEAVY_QUARK, 1000, cfg["seed"])
+    nform, mass = ev.species_info(sid)
+    others = []
+    for k, (Nk, npart) in enumerate(((48, 900), (64, 2000))):
+        o = gl.Event(Nk, Nk * 0.125, 0.125, precision=64, max_steps=steps, max_particles=npart)
+        o.init_glasma(1.0, 0.2, 1, 500 + k)
+        o.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, npart // 2, 600 + k)
+        o.add_species(0.0, 10.0, gl.KIND_JET, npart - npart // 2, 700 + k)
+        others.append(o)
+    b = gl.Batch([others[0], ev, others[1]])
+    b.config(shape=2, grid_mult=0, sort_every=16, graph_steps=32)
+    b.run(steps)
+    b.stream.synchronize()
+    st, P, ser_o, rc = orc.run(N, sigma, m2, 1, cfg["seed"], 0.125, steps,
+                               [dict(kind=0, mass=mass, p0=0.0, nform=nform, n=1000)])
+    assert rc == 0
+    ser = ev.series()[:, :1, :]
+    assert ser.shape == ser_o.shape
+    assert np.array_equal(ser[:, 0, 3], ser_o[:, 0, 3])
+    for c in range(3):
+        err = H.rel_err(ser[:, 0, c], ser_o[:, 0, c])
+        print("batched event vs oracle, series component %d: %.2e" % (c, err))
+        assert err < 1e-9
+    U, E, phi, pi, n = ev.get_state()
+    assert n == 1 + steps
+    for g, w in zip((U, E, phi, pi), H.state_oracle_to_soa(st)):
+        assert H.rel_err(g, w) < 1e-9
+    parts = ev.get_particles()
+    assert np.array_equal(parts["cell"], np.ascontiguousarray(P.cell.T))
+    b.close()

@@ -82,3 +82,46 @@ def test_training_reduces_loss_and_fits(gl):
     pred = net.infer(Xt.astype(np.float32)).cpu().numpy()
     err = np.abs(pred - Yt).max(axis=0) / np.abs(Yt).max(axis=0)
     assert np.all(err < 0.1), err
+
+
+def test_forward_and_gradients_match_oracle_elementwise(gl):
+    """Every output and every gradient element within a bound derived from
+    BF16 rounding: the device and the oracle round the same operands to BF16,
+    but their FP32 and FP64 accumulations can land on the two sides of a BF16
+    rounding boundary, which changes an operand by one BF16 ulp (2^-8
+    relative).  An element then moves by at most 2^-8 times the sum of the
+    magnitudes of its terms (oracle.grad_scales, oracle.output_scales), so
+    |device - oracle| <= 2^-8 * scale per element, plus an FP32 floor."""
+    n = 384
+    net = gl.MLP(*SHAPE, max_batch=512, max_samples=4096, seed=11)
+    net.set_scaling(LO, HI, MU, SD)
+    p = net.params().astype(np.float64)
+    X, Y = _data(n, 12)
+    Xs = M.scale_inputs(X.astype(np.float32), LO.astype(np.float32), HI.astype(np.float32))
+    # forward
+    got = net.infer(X.astype(np.float32)).cpu().numpy()
+    Zs, _ = M.forward(p, Xs, SHAPE, bf16=True)
+    want = Zs[-1] * SD + MU
+    scale = M.output_scales(p, Xs, SHAPE, bf16=True) * SD
+    rf = np.abs(got - want) / (scale + 1e-30)
+    # gradients
+    g, loss = net.grads(X.astype(np.float32), Y.astype(np.float32))
+    Ys = (Y.astype(np.float32) - MU) / SD
+    _, go = M.loss_and_grads(p, Xs, Ys, SHAPE, bf16=True)
+    A = M.grad_scales(p, Xs, Ys, SHAPE, bf16=True)
+    rg = np.abs(g - go) / (A + 1e-30)
+    L, din, dout = M.dims(*SHAPE)
+    off, parts = 0, []
+    for l in range(L):
+        k = din[l] * dout[l]
+        parts.append(("W%d" % (l + 1), rg[off:off + k]))
+        off += k
+    for l in range(L):
+        parts.append(("b%d" % (l + 1), rg[off:off + dout[l]]))
+        off += dout[l]
+    print("forward: max |dev - orc| / scale = %.2e" % rf.max())
+    for name, r in parts:
+        print("%s: max |dev - orc| / scale = %.2e (median %.1e)" % (name, r.max(), np.median(r)))
+    u = 2.0 ** -8
+    assert rf.max() < u
+    assert rg.max() < u

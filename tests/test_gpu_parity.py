@@ -518,3 +518,108 @@ def test_paper_scale_g2mu_gives_qs_2_gev(gl):
     ev.close()
     print("calibrated g2mu %.4f GeV (Q_s %.4f GeV)" % (g, q))
     assert abs(g - bench.G2MU) < 5e-3
+
+
+def test_energy_diagnostics_match_oracle(gl, orc):
+    """gl_diagnostics' energy terms (E_T, E_L, B_T, B_L per unit rapidity)
+    against the oracle's energy of the same state, right after the MV
+    initial condition and after 20 field steps."""
+    cfg = H.C1
+    N = cfg["N"]
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    ev = _event(gl, N, cfg["L"])
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], cfg["sheets"], cfg["seed"])
+    s, rc, _ = orc.init_glasma(N, sigma, m2, cfg["sheets"], cfg["seed"], 0.125)
+    for k in (0, 20):
+        if k:
+            ev.evolve_fields(k)
+            for _ in range(k):
+                orc.field_step(s, 0.125)
+        got = np.array(ev.diagnostics()["energy"])
+        want = orc.energy(s, s.n * 0.125)
+        print("energy at n=%d: %s vs %s" % (s.n, got, want))
+        # E_T vanishes at n = 1 (E^{1/2} = 0); the other terms start non-zero
+        assert np.all(want[1:] > 0) and (k == 0 or want[0] > 0)
+        assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+
+
+def test_observable_rows_match_oracle(gl, orc):
+    """The rows of gl_broadening (GeV^2), gl_kappa and gl_qhat (GeV^2/fm)
+    against the oracle's series turned into means and central differences and
+    converted with the lattice spacing: heavy quarks (kappa_T, kappa_L and
+    tau - tau_form) and jets (qhat_y, qhat_z), with the rows before formation
+    left out."""
+    N = 24
+    cfg = dict(H.C1, N=N, L=3.0)
+    a_fm, a_gev, sigma, m2 = H.lattice(cfg)
+    steps = 30
+    ev = _event(gl, N, cfg["L"], max_particles=1200, max_steps=steps)
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], 1, cfg["seed"])
+    q = ev.add_species(4.18, 2.0, gl.KIND_HEAVY_QUARK, 600, cfg["seed"])
+    j = ev.add_species(0.0, 5.0, gl.KIND_JET, 600, cfg["seed"])
+    ev.run(steps)
+    sp = [dict(kind=0, mass=ev.species_info(q)[1], p0=2.0 * a_gev, nform=ev.species_info(q)[0], n=600),
+          dict(kind=1, mass=0.0, p0=5.0 * a_gev, nform=ev.species_info(j)[0], n=600)]
+    _, _, ser_o, rc = orc.run(N, sigma, m2, 1, cfg["seed"], 0.125, steps, sp)
+    assert rc == 0
+    f2, fk = orc.to_physical(a_fm)
+    dt_fm = 0.125 * a_fm
+    for sid in (q, j):
+        mean, act = orc.mean_broadening(ser_o[:, sid])
+        ks = np.nonzero(act)[0]
+        br = ev.broadening(sid)
+        assert len(br) == len(ks) > 0
+        assert np.abs(br[:, 0] - (ks + 1.5) * dt_fm).max() < 1e-14
+        assert H.rel_err(br[:, 1:4], mean[ks] * f2) < 1e-9
+        assert np.array_equal(br[:, 4], ser_o[ks, sid, 3])
+        kk, rates = orc.coefficients(ser_o[:, sid], 0.125)
+        if sid == q:
+            rows = ev.kappa(sid)
+            nform = ev.species_info(sid)[0]
+            assert ks[0] == nform - 1          # the first active row is the formation step
+            tau_form = 0.1973269804 / (2 * math.hypot(4.18, 2.0))
+            assert np.abs(rows[:, 1] - (rows[:, 0] - tau_form)).max() < 1e-14
+            assert H.rel_err(rows[:, 2], (rates[:, 0] + rates[:, 1]) * fk) < 1e-9
+            assert H.rel_err(rows[:, 3], rates[:, 2] * fk) < 1e-9
+        else:
+            rows = ev.qhat(sid)
+            assert H.rel_err(rows[:, 1], rates[:, 1] * fk) < 1e-9
+            assert H.rel_err(rows[:, 2], rates[:, 2] * fk) < 1e-9
+        assert len(rows) == len(kk)
+        assert np.abs(rows[:, 0] - (kk + 1) * dt_fm).max() < 1e-14
+
+
+def test_fp32_reunitarisation_runs_and_repairs(gl):
+    """FP32 links re-unitarised when n mod 16 = 15: right after that step
+    (n = 16) the links are unitary to FP32 rounding, and more so than the
+    same run without it, whose rounding drift accumulates over 15 link
+    updates.  FP32 keeps the Gauss law to FP32 rounding either way; an FP64
+    event ignores the setting."""
+    cfg = H.C1
+    N = cfg["N"]
+    out = {}
+    for reunit in (16, 0):
+        ev = _event(gl, N, cfg["L"], prec=32, reunit=reunit)
+        ev.init_glasma(cfg["g2mu"], cfg["m_ir"], 1, cfg["seed"])
+        ev.evolve_fields(15)
+        assert ev.info()[2] == 16
+        d = ev.diagnostics()
+        ev.evolve_fields(16)
+        d2 = ev.diagnostics()
+        out[reunit] = (d, d2)
+        print("FP32 reunit_every=%d: unitarity at n=16 %.2e, n=32 %.2e; gauss_rel %.2e, %.2e"
+              % (reunit, d["unitarity_max"], d2["unitarity_max"], d["gauss_rel"], d2["gauss_rel"]))
+    (w16, w32), (n16, n32) = out[16], out[0]
+    assert w16["unitarity_max"] < 1e-6 and w32["unitarity_max"] < 1e-6
+    assert w16["unitarity_max"] < n16["unitarity_max"]
+    assert w32["unitarity_max"] < n32["unitarity_max"]
+    for d in (w16, w32, n16, n32):
+        assert d["gauss_rel"] < 1e-5 and d["nonfinite"] == 0
+    ev = _event(gl, N, cfg["L"], prec=64, reunit=16)
+    ev.init_glasma(cfg["g2mu"], cfg["m_ir"], 1, cfg["seed"])
+    ev.evolve_fields(15)
+    e0 = _event(gl, N, cfg["L"], prec=64, reunit=0)
+    e0.init_glasma(cfg["g2mu"], cfg["m_ir"], 1, cfg["seed"])
+    e0.evolve_fields(15)
+    for x, y in zip(ev.get_state()[:4], e0.get_state()[:4]):
+        assert np.array_equal(x, y)
