@@ -386,6 +386,19 @@ gl_status gl_mlp_set_output_power(gl_mlp *m, int32_t col, const float *powers);
 gl_status gl_mlp_train(gl_mlp *m, const float *X, const float *Y, int64_t n, int32_t epochs,
                        int32_t batch, float lr, uint64_t seed, float *loss_per_epoch);
 gl_status gl_mlp_infer(gl_mlp *m, const float *X, float *Y, int64_t n);
+/* Inference that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same outputs as gl_mlp_infer, bit for bit, with its
+ * staging and activation buffers in a fixed 4 MiB device array of the library
+ * instead of the model's workspace.  X [n][n_in], Y [n][n_out] are device
+ * FP32 arrays of the caller; rows go through in passes of as many as fit
+ * (about 4000 at width 256).  The device of the model's stream must be the
+ * current device; the array's address on that device is looked up on the
+ * first call there.  Every call on one device uses that device's one array,
+ * so calls that overlap on a device (concurrent streams or threads) race.
+ * GL_EINVAL for a network too wide for 64 rows to fit (width above about
+ * 16 000) or a stream of another device; launches only, no allocation. */
+gl_status gl_mlp_infer_noalloc(gl_mlp *m, const float *X, float *Y, int64_t n);
 /* One forward/backward pass on n <= max_batch samples (no update): gradients
  * of the standardised MSE to host grads [n_params], loss to *loss. */
 gl_status gl_mlp_grads(gl_mlp *m, const float *X, const float *Y, int32_t n, float *grads,

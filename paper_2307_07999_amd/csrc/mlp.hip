@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -543,6 +544,102 @@ gl_status gl_mlp_infer(gl_mlp *m, const float *X, float *Y, int64_t n) {
         hipLaunchKernelGGL(k_unscale, dim3(nb((int64_t)b * m->d.n_out, 256)), dim3(256), 0, m->st, m->Z[m->L - 1], b,
                            m->d.n_out, m->sc + 2 * m->d.n_in, X + off * m->d.n_in, m->d.n_in, m->pcol,
                            Y + off * m->d.n_out);
+        MHIP(hipGetLastError());
+    }
+    return GL_OK;
+}
+
+}  // extern "C"
+
+// ---- inference without allocation ---------------------------------------------
+// gl_mlp_infer_noalloc stages its rows in a fixed device array of this file
+// instead of the model's workspace: the scaled inputs (BF16), two BF16
+// activation buffers used in turn by the hidden layers, and the last layer's
+// FP32 output, for as many rows per pass as fit.  Each device holds its own
+// copy of the array until the process ends; calls on one device share it.
+constexpr size_t kInferScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char infer_scratch[kInferScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kScratchDevices] = {};   // device address of infer_scratch, per device
+
+// the address of this device's copy of the array, looked up once per device
+// with that device current (the symbol's name is a host-side stand-in)
+gl_status infer_scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kScratchDevices) return mfail(GL_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(infer_scratch));
+        if (e != hipSuccess || !p)
+            return mfail(GL_EDEVICE, std::string("hipGetSymbolAddress(infer_scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return GL_OK;
+}
+
+// rows per pass that fit the array: inputs n_in BF16, two activation
+// buffers of width BF16, outputs n_out FP32 per row, each buffer 256-aligned
+int64_t infer_rows_per_pass(const gl_mlp *m) {
+    const int64_t per_row = 2 * (int64_t)m->d.n_in + 2 * 2 * (int64_t)m->d.width + 4 * (int64_t)m->d.n_out;
+    const int64_t rows = ((int64_t)kInferScratchBytes - 4 * 256) / per_row;
+    return rows / 64 * 64;
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_mlp_infer_noalloc(gl_mlp *m, const float *X, float *Y, int64_t n) {
+    if (!m || !X || !Y) return mfail(GL_EINVAL, "null argument");
+    if (n < 0) return mfail(GL_EINVAL, "n must be >= 0");
+    const int64_t R = infer_rows_per_pass(m);
+    if (R < 64)
+        return mfail(GL_EINVAL, "network too wide for the inference scratch of " +
+                                    std::to_string(kInferScratchBytes) + " bytes: 64 rows of inputs, two activation "
+                                    "buffers and outputs must fit (width <= " +
+                                    std::to_string(((int64_t)kInferScratchBytes - 1024) / 64 / 4 - 2) + " or so)");
+    if (n == 0) return GL_OK;
+    // the device of the model's stream must be current: the scratch address
+    // is taken per device
+    int dev = -1;
+    MHIP(hipGetDevice(&dev));
+    hipDevice_t sdev = dev;
+    if (m->st) MHIP(hipStreamGetDevice(m->st, &sdev));
+    if (sdev != dev) return mfail(GL_EINVAL, "the device of the model's stream is not the current device");
+    void *base = nullptr;
+    if (gl_status s = infer_scratch_address(dev, &base)) return s;
+    char *sp = (char *)base;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        char *p = sp + off;
+        off = al(off + bytes);
+        return p;
+    };
+    bf16 *Xb = (bf16 *)carve((size_t)R * m->d.n_in * 2);
+    bf16 *Hs[2] = {(bf16 *)carve((size_t)R * m->d.width * 2), (bf16 *)carve((size_t)R * m->d.width * 2)};
+    float *Z = (float *)carve((size_t)R * m->d.n_out * 4);
+    if (off > kInferScratchBytes) return mfail(GL_EINVAL, "inference scratch layout exceeds the array");
+    for (int64_t r0 = 0; r0 < n; r0 += R) {
+        const int b = (int)std::min<int64_t>(R, n - r0);
+        hipLaunchKernelGGL(k_prep, dim3(nb(b, 256)), dim3(256), 0, m->st, X, (const float *)nullptr,
+                           (const int32_t *)nullptr, r0, b, m->d.n_in, m->d.n_out, m->sc, m->pcol, Xb,
+                           (float *)nullptr);
+        MHIP(hipGetLastError());
+        const bf16 *in = Xb;
+        for (int l = 0; l < m->L; l++) {
+            const bool last = l == m->L - 1;
+            MHIP((gemm<false, true>(m->st, in, m->din[l], m->Wb + m->woff[l], m->din[l], b, m->dout[l], m->din[l],
+                                    m->P + m->boff[l], last ? Z : nullptr, m->dout[l], last ? nullptr : Hs[l & 1],
+                                    m->dout[l], 1)));
+            in = Hs[l & 1];
+        }
+        hipLaunchKernelGGL(k_unscale, dim3(nb((int64_t)b * m->d.n_out, 256)), dim3(256), 0, m->st, Z, b, m->d.n_out,
+                           m->sc + 2 * m->d.n_in, X + r0 * m->d.n_in, m->d.n_in, m->pcol, Y + r0 * m->d.n_out);
         MHIP(hipGetLastError());
     }
     return GL_OK;

@@ -495,6 +495,7 @@ def _mlp_declare(L):
         "gl_mlp_train": [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                          ctypes.c_uint64, _F],
         "gl_mlp_infer": [_VP, _VP, _VP, ctypes.c_int64],
+        "gl_mlp_infer_noalloc": [_VP, _VP, _VP, ctypes.c_int64],
         "gl_mlp_grads": [_VP, _VP, _VP, ctypes.c_int32, _F, _F],
         "gl_mlp_params": [_VP, _F, _F, _I64],
     }
@@ -576,6 +577,15 @@ class MLP:
         Xd = X if hasattr(X, "data_ptr") else self._dev(X, self.n_in)
         Yd = self.torch.empty((Xd.shape[0], self.n_out), dtype=self.torch.float32, device=self.device)
         _mlp_check(lib().gl_mlp_infer(self._h, _VP(Xd.data_ptr()), _VP(Yd.data_ptr()), Xd.shape[0]))
+        return Yd
+
+    def infer_noalloc(self, X, Y=None):
+        """Inference through gl_mlp_infer_noalloc (no device allocation in the
+        library; Y, if given, is the caller's output tensor)."""
+        Xd = X if hasattr(X, "data_ptr") else self._dev(X, self.n_in)
+        Yd = Y if Y is not None else self.torch.empty((Xd.shape[0], self.n_out), dtype=self.torch.float32,
+                                                      device=self.device)
+        _mlp_check(lib().gl_mlp_infer_noalloc(self._h, _VP(Xd.data_ptr()), _VP(Yd.data_ptr()), Xd.shape[0]))
         return Yd
 
     def grads(self, X, Y):
