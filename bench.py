@@ -124,6 +124,35 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
             "finite": finite}
 
 
+def scan_bench(n_events=16, n_per=N_PER, precision=64):
+    """The paper's scans (Sec. 2, Figs. 1 and 2) at the 512^2 scale: beauty
+    quarks at p_T0 in {0, 2, 5, 10} GeV and jets at p_x in {1, 2, 5, 10} GeV for
+    m in {1.27, 4.18} GeV, n_per particles per point, with the static and
+    lightlike correlators, over n_events MV events; jackknife errors over the
+    events.  Reports the wall time and, per point, the peak of the total
+    coefficient (kappa_T + kappa_L or qhat_y + qhat_z) with its error and
+    time after formation, and the anisotropy 0.3 fm after formation."""
+    from paper_2307_07999_amd import scan
+    res = scan.run_scan(n_events=n_events, N=N, L_fm=L_FM, sheets=SHEETS, g2mu=G2MU, m_ir=M_IR, n_per=n_per,
+                        precision=precision)
+    summ = scan.summary(res)
+
+    def short(v):
+        pk = v["peak"]
+        return {"peak_total_GeV2_per_fm": [round(pk["total"], 3), round(pk["err"], 3)],
+                "peak_dtau_fm": round(pk["dtau_fm"], 4),
+                "ratio_B_over_A_at_0.3fm": None if v["ratio_at_0.3fm"] is None else
+                [round(x, 4) for x in v["ratio_at_0.3fm"]]}
+    return {"events": n_events, "particles_per_point": n_per, "points": len(res["points"]),
+            "precision": precision, "coupled_steps": res["coupled_steps"], "wall_s": res["wall_s"],
+            "s_per_event": res["s_per_event"], "particle_steps_per_s": res["particle_steps_per_s"],
+            "results": {k: short(v) for k, v in summ.items()},
+            "paper_context": {"kappa_total_peak_GeV2_per_fm": scan.PAPER_KAPPA_PEAK,
+                              "kappa_peak_dtau_fm": scan.PAPER_KAPPA_PEAK_DTAU,
+                              "qhat_total_peak_GeV2_per_fm": scan.PAPER_QHAT_PEAK,
+                              "qhat_peak_tau_fm": scan.PAPER_QHAT_PEAK_TAU}}
+
+
 def surrogate_bench(mode):
     """Surrogate vs solver: the protocol of paper_2307_07999_amd.surrogate
     (solver-generated training data, BF16 network trained on the GPU,
@@ -258,6 +287,38 @@ def copy_calibration(mib):
                       "launches": 3}))
 
 
+STREAM_KINDS = ("copy", "read", "write")
+
+
+def stream_ceiling(mib=1024, reps=10):
+    """The bandwidth the library's own streaming kernels reach (gl_stream_probe):
+    a copy, a read and a write of mib MiB in 16-byte accesses, over its access
+    patterns and grid sizes; GB/s counts the bytes read plus written.  The best
+    of each kind is the ceiling a kernel of this library can be held against."""
+    import torch
+    import paper_2307_07999_amd as g
+    g.lib()
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    rows, best = [], {}
+    for kind, name in enumerate(STREAM_KINDS):
+        moved = nbytes * (2 if kind == 0 else 1)
+        for variant in range(6):
+            for blocks in (2048, 8192, 32768):
+                ms = g.glasma.stream_probe(kind, variant, blocks, src.data_ptr(), dst.data_ptr(), nbytes,
+                                           nbytes, reps, stream)
+                gbs = moved / (ms * 1e-3) / 1e9
+                rows.append({"kind": name, "variant": variant, "blocks": blocks, "ms": ms, "GBps": gbs})
+                if gbs > best.get(name, {}).get("GBps", 0.0):
+                    best[name] = {"GBps": gbs, "variant": variant, "blocks": blocks}
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"MiB": mib, "reps": reps, "best": best, "all": rows}
+
+
 def summarize(path, command):
     """Markdown summary of a rocprofv3 output directory: per-kernel durations
     (kernel_stats.csv) and mean per-dispatch counter values
@@ -300,8 +361,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-event batched FP32 workload")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache for the batch")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the paper's scans (16 events of 12 scan points at 512^2)")
     ap.add_argument("--surrogate", default="full", choices=("quick", "full", "off"),
                     help="surrogate-vs-solver section: reduced protocol, full protocol or none")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="only measure the streaming ceiling (copy/read/write kernels of the library) and exit")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--summarize", nargs=2, metavar=("DIR", "COMMAND"),
@@ -317,6 +382,9 @@ def main():
         return
     if args.copy_calib:
         copy_calibration(args.copy_calib)
+        return
+    if args.ceiling:
+        print(json.dumps(stream_ceiling()))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "
@@ -405,6 +473,8 @@ def main():
     }
     if not args.no_batch:
         out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache)
+    if not args.no_scan:
+        out["scan"] = scan_bench()
     if args.surrogate != "off":
         out["surrogate"] = surrogate_bench(args.surrogate)
     if not args.no_cpu_baseline:

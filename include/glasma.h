@@ -170,6 +170,28 @@ gl_status gl_series(gl_event *ev, double *out, int32_t cap_rows, int32_t *n_rows
 gl_status gl_rates_from_series(const double *series, int32_t rows, double dtau,
                                double *rates);
 
+/* Event statistics of the broadening (Sec. 2: <dp_i^2> is averaged over the
+ * particle trajectories and over Glasma events; the paper's scans are
+ * curves of it and of its derivative with that averaging).  series holds,
+ * for each of n_events >= 2 events, the raw series of one species as
+ * gl_series gives it, [n_events][rows][4] = (sum dpx^2, sum dpy^2, sum dpz^2,
+ * n_active) in lattice units, on the same time grid (row k: tau_{k+1+1/2}).
+ * The components are A = dp_x^2 + dp_y^2 (transverse) and B = dp_z^2
+ * (longitudinal) for kind GL_KIND_HEAVY_QUARK, A = dp_y^2 and B = dp_z^2 for
+ * GL_KIND_JET (a jet along x).  Per row with active particles, out [cap][14]
+ * receives (tau_{k+1+1/2} [fm], tau_{k+1} [fm], <A>, err, <B>, err, <B>/<A>,
+ * err, d<A>/dtau, err, d<B>/dtau, err, d<A + B>/dtau, err): the broadenings
+ * in GeV^2 pooled over all events (sum over events of the sums over their
+ * count), the anisotropy ratio, the rates kappa_T, kappa_L (heavy quarks) or
+ * qhat_y, qhat_z (jets) in GeV^2/fm as the central difference of gl_kappa /
+ * gl_qhat, and the total rate (the paper's total kappa or qhat); each
+ * with its delete-one jackknife error sqrt((n-1)/n sum_i (f_(i) - mean f_(.))^2)
+ * over the events.  out may be null to query n_rows.  dtau_fm and a_fm: the
+ * step and lattice spacing in fm.  GL_EINVAL for bad arguments or events
+ * whose active rows differ.  Host-only. */
+gl_status gl_scan_statistics(const double *series, int32_t n_events, int32_t rows, int32_t kind, double dtau_fm,
+                             double a_fm, double *out, int32_t cap, int32_t *n_rows);
+
 /* Diagnostics of the current state (FP64 reductions on the device): the
  * Gauss-law residual, unitarity, the energy terms, and the two Casimirs of
  * the particle charges, which Eq. (2) conserves (Sec. 1 "Probes in Glasma":
@@ -406,6 +428,25 @@ gl_status gl_mlp_grads(gl_mlp *m, const float *X, const float *Y, int32_t n, flo
 /* Read (get) and/or write (set) the FP32 parameters (host arrays). */
 gl_status gl_mlp_params(gl_mlp *m, float *get, const float *set, int64_t *n_params);
 const char *gl_mlp_last_error(void);
+
+/* ---- measurement ---------------------------------------------------------------
+ * The bandwidth a kernel of this library reaches on the device, as the
+ * ceiling next to the 8 TB/s peak for the roofline fractions: reps timed
+ * launches (after one untimed) of a streaming kernel over caller device
+ * buffers in 16-byte accesses, kind 0 copy src -> dst, 1 read src (the
+ * workgroups write one 16-byte word each to dst), 2 write dst (a fill); blocks
+ * workgroups of 256 lanes.  variant (0 .. GL_STREAM_VARIANTS-1): 0 one vector
+ * per lane and pass, interleaved workgroups; 1 four vectors per lane; 2 the
+ * same non-temporal; 3 four vectors, each workgroup one contiguous share; 4
+ * the same non-temporal; 5 eight vectors, non-temporal.  bytes: the size
+ * streamed (a multiple of 16, 16-byte aligned buffers); dst_bytes: the size
+ * of dst (at least bytes, or 16 * blocks for a read).  *ms_avg receives the
+ * mean milliseconds per launch (HIP events on stream).  Errors: GL_EINVAL,
+ * GL_EDEVICE (message from gl_stream_last_error). */
+#define GL_STREAM_VARIANTS 6
+gl_status gl_stream_probe(int32_t kind, int32_t variant, int32_t blocks, const void *src, void *dst, size_t bytes,
+                          size_t dst_bytes, int32_t reps, void *stream, double *ms_avg);
+const char *gl_stream_last_error(void);
 
 const char *gl_status_string(gl_status s);
 const char *gl_last_error(void);

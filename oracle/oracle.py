@@ -461,3 +461,66 @@ def to_physical(a_fm):
     """Factors turning lattice <dp^2> into GeV^2 and lattice rates into GeV^2/fm."""
     a_gev = a_fm / HBARC_GEV_FM
     return 1.0 / a_gev ** 2, 1.0 / (a_gev ** 2 * a_fm)
+
+
+def scan_statistics(series_events, kind, dtau_fm, a_fm):
+    """Event statistics of one species' broadening over several Glasma events
+    (Sec. 2: <dp_i^2> averaged over the particle trajectories and over
+    events), written out plainly.  series_events [E][rows][4] holds each
+    event's raw series (sums of dp_x^2, dp_y^2, dp_z^2 and the count, lattice
+    units).  Components: A = dp_x^2 + dp_y^2, B = dp_z^2 for heavy quarks
+    (kind 0); A = dp_y^2, B = dp_z^2 for jets along x (kind 1).  For every row
+    with active particles: the pooled means <A>, <B> (GeV^2), their ratio, the
+    rates of Eq. (3) as central differences on the half-step grid and their
+    sum, the total rate (GeV^2/fm), each from all events and from every sample that leaves one
+    event out; the error is the delete-one jackknife (Quenouille, Tukey)
+    sqrt((E-1)/E sum_i (f_(i) - mean_i f_(i))^2).  Returns rows (tau_{k+3/2},
+    tau_{k+1}, <A>, err, <B>, err, <B>/<A>, err, rate A, err, rate B, err,
+    total rate, err)."""
+    S = np.asarray(series_events, np.float64)
+    E, rows = S.shape[0], S.shape[1]
+    a_gev = a_fm / HBARC_GEV_FM
+    f2 = 1.0 / a_gev ** 2
+    fk = f2 / a_fm
+    dtau_lat = dtau_fm / a_fm
+
+    def components(e, k):
+        if kind == 0:
+            return S[e, k, 0] + S[e, k, 1], S[e, k, 2]
+        return S[e, k, 1], S[e, k, 2]
+
+    def pooled(k, skip):
+        sa = sb = n = 0.0
+        for e in range(E):
+            if e == skip:
+                continue
+            a, b = components(e, k)
+            sa += a
+            sb += b
+            n += S[e, k, 3]
+        if n > 0:
+            return sa / n, sb / n, True
+        return 0.0, 0.0, False
+
+    def observables(k, skip):
+        A, B, _ = pooled(k, skip)
+        Ap, Bp, prev = pooled(k - 1, skip) if k > 0 else (0.0, 0.0, False)
+        if not prev:
+            Ap = Bp = 0.0
+        ratio = B / A if A != 0 else 0.0
+        ra, rb = (A - Ap) / dtau_lat * fk, (B - Bp) / dtau_lat * fk
+        return [A * f2, B * f2, ratio, ra, rb, ra + rb]
+
+    out = []
+    for k in range(rows):
+        if not any(S[e, k, 3] > 0 for e in range(E)):
+            continue
+        full = observables(k, None)
+        loo = [observables(k, i) for i in range(E)]
+        row = [(k + 1.5) * dtau_fm, (k + 1) * dtau_fm]
+        for j in range(6):
+            mean = sum(f[j] for f in loo) / E
+            var = sum((f[j] - mean) ** 2 for f in loo) * (E - 1) / E
+            row += [full[j], var ** 0.5]
+        out.append(row)
+    return np.array(out).reshape(-1, 14)

@@ -1067,6 +1067,81 @@ gl_status gl_rates_from_series(const double *series, int32_t rows, double dtau, 
     return GL_OK;
 }
 
+gl_status gl_scan_statistics(const double *series, int32_t n_events, int32_t rows, int32_t kind, double dtau_fm,
+                             double a_fm, double *out, int32_t cap, int32_t *n_rows) {
+    if (!series || !n_rows || n_events < 2 || rows < 0 || (kind != GL_KIND_HEAVY_QUARK && kind != GL_KIND_JET) ||
+        !(dtau_fm > 0) || !(a_fm > 0))
+        return fail(GL_EINVAL, "bad argument (at least two events, kind heavy quark or jet, dtau and a > 0)");
+    const int E = n_events;
+    const double a_gev = a_fm / kHbarC, f2 = 1.0 / (a_gev * a_gev), fk = f2 / a_fm;
+    const double dtau_lat = dtau_fm / a_fm;
+    auto at = [&](int e, int k, int c) { return series[((size_t)e * rows + k) * 4 + c]; };
+    // the two components: (dp_x^2 + dp_y^2, dp_z^2) for heavy quarks, (dp_y^2, dp_z^2) for jets
+    auto comp = [&](int e, int k, int j) {
+        if (j == 1) return at(e, k, 2);
+        return kind == GL_KIND_HEAVY_QUARK ? at(e, k, 0) + at(e, k, 1) : at(e, k, 1);
+    };
+    // pooled sums of a row over all events, and over all but event i (i < 0: none left out)
+    auto pooled = [&](int k, int skip, double *A, double *B) {
+        double sa = 0, sb = 0, n = 0;
+        for (int e = 0; e < E; e++) {
+            if (e == skip) continue;
+            sa += comp(e, k, 0);
+            sb += comp(e, k, 1);
+            n += at(e, k, 3);
+        }
+        *A = n > 0 ? sa / n : 0.0;
+        *B = n > 0 ? sb / n : 0.0;
+        return n > 0;
+    };
+    // the observables of row k from one (leave-one-out) sample: <A>, <B>,
+    // <B>/<A>, dA/dtau, dB/dtau and the total rate d(A + B)/dtau
+    auto observables = [&](int k, int skip, double *v) {
+        double A = 0, B = 0, Ap = 0, Bp = 0;
+        pooled(k, skip, &A, &B);
+        const bool prev = k > 0 && pooled(k - 1, skip, &Ap, &Bp);
+        v[0] = A * f2;
+        v[1] = B * f2;
+        v[2] = A != 0 ? B / A : 0.0;
+        v[3] = (A - (prev ? Ap : 0.0)) / dtau_lat * fk;
+        v[4] = (B - (prev ? Bp : 0.0)) / dtau_lat * fk;
+        v[5] = v[3] + v[4];
+    };
+    int32_t r = 0;
+    for (int k = 0; k < rows; k++) {
+        int active = 0;
+        for (int e = 0; e < E; e++) active += at(e, k, 3) > 0 ? 1 : 0;
+        if (active == 0) continue;
+        if (active != E) return fail(GL_EINVAL, "the events disagree on which rows hold active particles");
+        if (out) {
+            if (r >= cap) return fail(GL_EINVAL, "output too small");
+            constexpr int NO = 6;
+            double full[NO], jk[NO] = {0, 0, 0, 0, 0, 0}, sq[NO] = {0, 0, 0, 0, 0, 0};
+            observables(k, -1, full);
+            std::vector<double> loo((size_t)E * NO);
+            for (int i = 0; i < E; i++) {
+                observables(k, i, &loo[(size_t)i * NO]);
+                for (int j = 0; j < NO; j++) jk[j] += loo[(size_t)i * NO + j] / E;
+            }
+            for (int i = 0; i < E; i++)
+                for (int j = 0; j < NO; j++) {
+                    const double d = loo[(size_t)i * NO + j] - jk[j];
+                    sq[j] += d * d;
+                }
+            double *o = out + (size_t)r * 14;
+            o[0] = (k + 1.5) * dtau_fm;
+            o[1] = (k + 1) * dtau_fm;
+            for (int j = 0; j < NO; j++) {
+                o[2 + 2 * j] = full[j];
+                o[3 + 2 * j] = std::sqrt((double)(E - 1) / E * sq[j]);
+            }
+        }
+        r++;
+    }
+    *n_rows = r;
+    return GL_OK;
+}
+
 gl_status gl_broadening(gl_event *ev, int32_t species, double *out, int32_t cap, int32_t *n_rows) {
     if (check_ev(ev) || !n_rows) return fail(GL_EINVAL, "null argument");
     std::vector<double> s4;

@@ -97,6 +97,8 @@ _SIGS = {
     "gl_batch_info": [_VP, _I32, _I32, _I32, _I32, _I32],
     "gl_batch_run": [_VP, ctypes.c_int32],
     "gl_max_particles": [ctypes.c_int32, _I64],
+    "gl_scan_statistics": [_D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                           _D, ctypes.c_int32, _I32],
     "gl_set_check_period": [_VP, ctypes.c_int32],
     "gl_set_match_params": [_VP, ctypes.c_int32, ctypes.c_double],
     "gl_checkpoint": [_VP, ctypes.c_char_p],
@@ -164,6 +166,40 @@ def max_particles(precision=64):
     out = ctypes.c_int64(0)
     check(lib().gl_max_particles(precision, ctypes.byref(out)))
     return out.value
+
+
+def stream_probe(kind, variant, blocks, src_ptr, dst_ptr, nbytes, dst_bytes, reps, stream_handle):
+    """Mean milliseconds per launch of the library's streaming kernel
+    (gl_stream_probe: kind 0 copy, 1 read, 2 write) over device buffers."""
+    L = lib()
+    if not getattr(L, "_stream_declared", False):
+        L.gl_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, ctypes.c_size_t,
+                                      ctypes.c_size_t, ctypes.c_int32, _VP, _D]
+        L.gl_stream_probe.restype = ctypes.c_int32
+        L.gl_stream_last_error.argtypes = []
+        L.gl_stream_last_error.restype = ctypes.c_char_p
+        L._stream_declared = True
+    ms = ctypes.c_double(0)
+    st = L.gl_stream_probe(kind, variant, blocks, _VP(src_ptr), _VP(dst_ptr), nbytes, dst_bytes, reps,
+                           _VP(stream_handle), ctypes.byref(ms))
+    if st != GL_OK:
+        raise GlasmaError(st, L.gl_stream_last_error().decode())
+    return ms.value
+
+
+def scan_statistics(series, kind, dtau_fm, a_fm):
+    """Event statistics of one species' series from several events (see
+    gl_scan_statistics): series [n_events, rows, 4] -> rows of (tau_half,
+    tau, <A>, err, <B>, err, <B>/<A>, err, rate A, err, rate B, err, total
+    rate, err)."""
+    s = np.ascontiguousarray(series, np.float64)
+    assert s.ndim == 3 and s.shape[2] == 4
+    n = ctypes.c_int32(0)
+    check(lib().gl_scan_statistics(_d(s), s.shape[0], s.shape[1], kind, dtau_fm, a_fm, None, 0, ctypes.byref(n)))
+    out = np.zeros((max(n.value, 1), 14))
+    check(lib().gl_scan_statistics(_d(s), s.shape[0], s.shape[1], kind, dtau_fm, a_fm, _d(out), n.value,
+                                   ctypes.byref(n)))
+    return out[:n.value]
 
 
 def rates_from_series(series_s, dtau):
