@@ -425,6 +425,29 @@ gl_status gl_mlp_infer_noalloc(gl_mlp *m, const float *X, float *Y, int64_t n);
  * of the standardised MSE to host grads [n_params], loss to *loss. */
 gl_status gl_mlp_grads(gl_mlp *m, const float *X, const float *Y, int32_t n, float *grads,
                        float *loss);
+/* The surrogate's answer or the solver (the surrogate falls back to the
+ * solver, which also judges its error).  gl_mlp_set_trust stores a trust
+ * region: the box [lo, hi] of the inputs the network was trained on (host
+ * arrays of n_in), the allowed values of one discrete input column
+ * (class_col, n_classes values, matched within class_tol), bins of one
+ * continuous column (bin_col, n_bins + 1 increasing edges, the last bin
+ * closed), and err [n_classes][n_bins], the network's error measured on
+ * held-out solver runs of each cell; cells whose err exceeds err_max are not
+ * trusted.  gl_surrogate_query takes n query rows X [n][n_in] (host FP32)
+ * and sets *verdict to GL_SURROGATE_NETWORK when every row lies in the box,
+ * in a known class and bin, in a trusted cell: then Y [n][n_out] (host)
+ * receives the network's outputs (computed on the device through the
+ * model's workspace, like gl_mlp_infer).  Otherwise *verdict is
+ * GL_SURROGATE_OUTSIDE_DOMAIN or GL_SURROGATE_UNTRUSTED, Y is not written,
+ * and the caller runs the solver.  GL_ESTATE without a trust table.
+ * Synchronises the model's stream. */
+#define GL_SURROGATE_NETWORK 0
+#define GL_SURROGATE_OUTSIDE_DOMAIN 1
+#define GL_SURROGATE_UNTRUSTED 2
+gl_status gl_mlp_set_trust(gl_mlp *m, const float *lo, const float *hi, int32_t class_col, int32_t n_classes,
+                           const float *classes, float class_tol, int32_t bin_col, int32_t n_bins,
+                           const float *bin_edges, const float *err, float err_max);
+gl_status gl_surrogate_query(gl_mlp *m, const float *X, int64_t n, float *Y, int32_t *verdict);
 /* Read (get) and/or write (set) the FP32 parameters (host arrays). */
 gl_status gl_mlp_params(gl_mlp *m, float *get, const float *set, int64_t *n_params);
 const char *gl_mlp_last_error(void);

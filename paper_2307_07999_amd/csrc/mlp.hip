@@ -263,6 +263,12 @@ struct gl_mlp {
     int64_t max_samples;
     int64_t adam_t = 0;
     int pcol = -1;                              // input column of the output power, -1: none
+    // trust region of gl_surrogate_query: the training box, and the held-out
+    // error per (class of the discrete column) x (bin of the binned column)
+    bool trust = false;
+    std::vector<float> t_lo, t_hi, t_classes, t_edges, t_err;
+    int t_class_col = -1, t_bin_col = -1;
+    float t_class_tol = 0.f, t_err_max = 0.f;
 };
 
 namespace {
@@ -642,6 +648,80 @@ gl_status gl_mlp_infer_noalloc(gl_mlp *m, const float *X, float *Y, int64_t n) {
                            m->sc + 2 * m->d.n_in, X + r0 * m->d.n_in, m->d.n_in, m->pcol, Y + r0 * m->d.n_out);
         MHIP(hipGetLastError());
     }
+    return GL_OK;
+}
+
+gl_status gl_mlp_set_trust(gl_mlp *m, const float *lo, const float *hi, int32_t class_col, int32_t n_classes,
+                           const float *classes, float class_tol, int32_t bin_col, int32_t n_bins,
+                           const float *bin_edges, const float *err, float err_max) {
+    if (!m || !lo || !hi) return mfail(GL_EINVAL, "null argument");
+    const int ni = m->d.n_in;
+    if (class_col < 0 || class_col >= ni || bin_col < 0 || bin_col >= ni || n_classes < 1 || n_bins < 1 || !classes ||
+        !bin_edges || !err || !(class_tol >= 0) || !(err_max >= 0))
+        return mfail(GL_EINVAL, "bad trust table (columns, counts, tolerances)");
+    for (int c = 0; c < ni; c++)
+        if (!(hi[c] >= lo[c])) return mfail(GL_EINVAL, "box hi must be >= lo");
+    for (int b = 0; b < n_bins; b++)
+        if (!(bin_edges[b + 1] > bin_edges[b])) return mfail(GL_EINVAL, "bin edges must increase");
+    m->t_lo.assign(lo, lo + ni);
+    m->t_hi.assign(hi, hi + ni);
+    m->t_classes.assign(classes, classes + n_classes);
+    m->t_edges.assign(bin_edges, bin_edges + n_bins + 1);
+    m->t_err.assign(err, err + (size_t)n_classes * n_bins);
+    m->t_class_col = class_col;
+    m->t_bin_col = bin_col;
+    m->t_class_tol = class_tol;
+    m->t_err_max = err_max;
+    m->trust = true;
+    return GL_OK;
+}
+
+gl_status gl_surrogate_query(gl_mlp *m, const float *X, int64_t n, float *Y, int32_t *verdict) {
+    if (!m || !X || !verdict || (n > 0 && !Y)) return mfail(GL_EINVAL, "null argument");
+    if (n < 0) return mfail(GL_EINVAL, "n must be >= 0");
+    if (!m->trust) return mfail(GL_ESTATE, "no trust table: call gl_mlp_set_trust after training");
+    const int ni = m->d.n_in, no = m->d.n_out;
+    // the decision, row by row on the host: inside the box, of a known
+    // class, in a cell whose calibrated held-out error is small enough
+    *verdict = GL_SURROGATE_NETWORK;
+    for (int64_t r = 0; r < n && *verdict == GL_SURROGATE_NETWORK; r++) {
+        const float *x = X + r * ni;
+        for (int c = 0; c < ni; c++)
+            if (!(x[c] >= m->t_lo[c] && x[c] <= m->t_hi[c])) *verdict = GL_SURROGATE_OUTSIDE_DOMAIN;
+        if (*verdict != GL_SURROGATE_NETWORK) break;
+        int cls = -1;
+        for (size_t k = 0; k < m->t_classes.size(); k++)
+            if (std::fabs(x[m->t_class_col] - m->t_classes[k]) <= m->t_class_tol) cls = (int)k;
+        if (cls < 0) {
+            *verdict = GL_SURROGATE_OUTSIDE_DOMAIN;
+            break;
+        }
+        const int nb = (int)m->t_edges.size() - 1;
+        const float v = x[m->t_bin_col];
+        int bin = -1;
+        for (int b = 0; b < nb; b++)
+            if (v >= m->t_edges[b] && (v < m->t_edges[b + 1] || (b == nb - 1 && v <= m->t_edges[b + 1]))) bin = b;
+        if (bin < 0) {
+            *verdict = GL_SURROGATE_OUTSIDE_DOMAIN;
+            break;
+        }
+        const float e = m->t_err[(size_t)cls * nb + bin];
+        if (!(e <= m->t_err_max)) *verdict = GL_SURROGATE_UNTRUSTED;
+    }
+    if (*verdict != GL_SURROGATE_NETWORK || n == 0) return GL_OK;
+    // inference: the rows staged in the model's FP32 scratch (dZ holds
+    // max_batch x max(width, n_in, n_out) floats), outputs in dH
+    const int64_t wmax = std::max(m->d.width, std::max(m->d.n_in, m->d.n_out));
+    const int64_t per = std::max<int64_t>(1, std::min<int64_t>(m->d.max_batch, (int64_t)m->d.max_batch * wmax / ni));
+    const int64_t rows = std::min<int64_t>(per, (int64_t)m->d.max_batch * wmax / no);
+    for (int64_t r0 = 0; r0 < n; r0 += rows) {
+        const int64_t b = std::min<int64_t>(rows, n - r0);
+        MHIP(hipMemcpyAsync(m->dZ, X + r0 * ni, (size_t)b * ni * 4, hipMemcpyHostToDevice, m->st));
+        gl_status s = gl_mlp_infer(m, m->dZ, m->dH, b);
+        if (s) return s;
+        MHIP(hipMemcpyAsync(Y + r0 * no, m->dH, (size_t)b * no * 4, hipMemcpyDeviceToHost, m->st));
+    }
+    MHIP(hipStreamSynchronize(m->st));
     return GL_OK;
 }
 

@@ -532,6 +532,9 @@ def _mlp_declare(L):
                          ctypes.c_uint64, _F],
         "gl_mlp_infer": [_VP, _VP, _VP, ctypes.c_int64],
         "gl_mlp_infer_noalloc": [_VP, _VP, _VP, ctypes.c_int64],
+        "gl_mlp_set_trust": [_VP, _F, _F, ctypes.c_int32, ctypes.c_int32, _F, ctypes.c_float, ctypes.c_int32,
+                             ctypes.c_int32, _F, _F, ctypes.c_float],
+        "gl_surrogate_query": [_VP, _F, ctypes.c_int64, _F, _I32],
         "gl_mlp_grads": [_VP, _VP, _VP, ctypes.c_int32, _F, _F],
         "gl_mlp_params": [_VP, _F, _F, _I64],
     }
@@ -623,6 +626,25 @@ class MLP:
                                                       device=self.device)
         _mlp_check(lib().gl_mlp_infer_noalloc(self._h, _VP(Xd.data_ptr()), _VP(Yd.data_ptr()), Xd.shape[0]))
         return Yd
+
+    def set_trust(self, lo, hi, class_col, classes, class_tol, bin_col, bin_edges, err, err_max):
+        """Trust region for query(): box, classes of one column, bins of another
+        and the held-out error per (class, bin) cell (gl_mlp_set_trust)."""
+        f = lambda v: np.ascontiguousarray(v, np.float32)
+        lo, hi, classes, bin_edges, err = f(lo), f(hi), f(classes), f(bin_edges), f(err)
+        assert err.shape == (len(classes), len(bin_edges) - 1)
+        _mlp_check(lib().gl_mlp_set_trust(self._h, _f(lo), _f(hi), class_col, len(classes), _f(classes), class_tol,
+                                          bin_col, len(bin_edges) - 1, _f(bin_edges), _f(err), err_max))
+
+    def query(self, X):
+        """(Y or None, verdict): the network's outputs for host rows X when the
+        trust region covers them all (gl_surrogate_query); None and the
+        verdict (1 outside the domain, 2 untrusted cell) otherwise."""
+        Xh = np.ascontiguousarray(X, np.float32).reshape(-1, self.n_in)
+        Y = np.zeros((Xh.shape[0], self.n_out), np.float32)
+        v = ctypes.c_int32(-1)
+        _mlp_check(lib().gl_surrogate_query(self._h, _f(Xh), Xh.shape[0], _f(Y), ctypes.byref(v)))
+        return (Y if v.value == 0 else None), v.value
 
     def grads(self, X, Y):
         Xd, Yd = self._dev(X, self.n_in), self._dev(Y, self.n_out)

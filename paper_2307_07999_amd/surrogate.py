@@ -35,6 +35,8 @@ QS_OVER_G2MU = 0.722
 # so curves of different lattice spacings line up at their start; the square
 # root spreads the sharp rise right after formation over the input range.
 IN_LO = np.array([QS_RANGE[0], 0.0, PT_RANGE[0], 0.0, 0.0], np.float32)
+# p_T0 bins of the trust table (per quark mass)
+PT_BINS = np.array([0.0, 10.0 / 3.0, 20.0 / 3.0, 10.0], np.float32)
 IN_HI = np.array([QS_RANGE[1], MASSES[-1], PT_RANGE[1], 0.2, math.sqrt(TAU_MAX)], np.float32)
 # the surrogate reproduces the 512^2, L = 10 fm solver (time step a/8)
 REF_N, REF_L_FM = 512, 10.0
@@ -170,14 +172,33 @@ class Surrogate:
         live = since >= -1e-9
         return np.where(live, Y[:, 0], 0.0), np.where(live, Y[:, 1], 0.0)
 
+    def set_trust(self, err_table, err_max=0.05):
+        """Trust region of the queries: the training box, the three masses
+        and three p_T0 bins, with the held-out kappa error of each
+        (mass, p_T0 bin) cell; cells above err_max fall back to the solver."""
+        lo = IN_LO.copy()
+        hi = IN_HI.copy()
+        hi[3] = tau_form(0.0, JET_PT_MIN) + 1e-6      # the largest formation time in the domain
+        self.net.set_trust(lo, hi, 1, np.array(MASSES, np.float32), 1e-3, 2, PT_BINS, err_table, err_max)
+        self.trusted = True
+
     def query(self, qs, m, pt, tau, N=512, L_fm=10.0, n_particles=100000, seed=12345):
-        """kappa(tau), <dp_T^2>(tau) and whether the solver was used instead
-        of the network (outside the training domain, or before training)."""
-        if self.trained and in_domain(qs, m, pt, tau):
-            k, d = self.predict(qs, m, pt, tau)
-            return k, d, False
+        """kappa(tau), <dp_T^2>(tau) and the verdict of gl_surrogate_query: 0
+        when the network answered, else the solver did (1: outside the
+        training domain, 2: a cell whose held-out error is above the bound,
+        3: no trust table yet)."""
+        tau = np.asarray(tau, np.float64)
+        verdict = 3
+        if self.trained and getattr(self, "trusted", False) and (m > 0 or pt >= JET_PT_MIN):
+            since = tau - tau_start(m, pt)
+            Y, verdict = self.net.query(features(qs, m, pt, since))
+            if Y is not None:
+                live = since >= -1e-9
+                return np.where(live, Y[:, 0], 0.0), np.where(live, Y[:, 1], 0.0), 0
+        elif self.trained and getattr(self, "trusted", False):
+            verdict = 1
         (t, k, d), = solver_curves([(qs, m, pt)], N, L_fm, n_particles, seed, batch=1)[0]
-        return np.interp(tau, t, k), np.interp(tau, t, d), True
+        return np.interp(tau, t, k), np.interp(tau, t, d), verdict
 
 
 def curve_error(pred, ref):
@@ -185,20 +206,49 @@ def curve_error(pred, ref):
     return float(np.abs(pred - ref).max() / max(np.abs(ref).max(), 1e-30))
 
 
-def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_part_train=10000,
-             n_part_fine=100000, n_part_heldout=100000, epochs=60, fine_epochs=120, seed=20230718,
-             log=print):
+def cell_of(m, pt):
+    """(mass class, p_T0 bin) of a parameter point, as gl_surrogate_query bins it."""
+    k = int(np.argmin([abs(m - mm) for mm in MASSES]))
+    b = int(np.clip(np.searchsorted(PT_BINS, pt, side="right") - 1, 0, len(PT_BINS) - 2))
+    return k, b
+
+
+def trust_table(params, errors):
+    """Largest held-out kappa error per (mass, p_T0 bin) cell; cells without a
+    held-out point get infinity (never trusted)."""
+    t = np.full((len(MASSES), len(PT_BINS) - 1), np.inf, np.float32)
+    for (qs, m, pt), e in zip(params, errors):
+        k, b = cell_of(m, pt)
+        t[k, b] = e if not np.isfinite(t[k, b]) else max(t[k, b], e)
+    return t
+
+
+def mean_curves(runs):
+    """Per point, the mean curve of several solver runs (same time grid)."""
+    out = []
+    for per_point in zip(*runs):
+        tau = per_point[0][0]
+        out.append((tau, np.mean([c[1] for c in per_point], axis=0), np.mean([c[2] for c in per_point], axis=0)))
+    return out
+
+
+def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_avg=4, n_part_train=10000,
+             n_part_fine=100000, n_part_heldout=100000, epochs=60, fine_epochs=120, err_max=0.05,
+             seed=20230718, log=print):
     """The surrogate workload end to end on the GPU.
 
     1. training data from the solver: n_train_coarse runs at 256^2 and
        n_train_fine runs at 512^2 (L = 10 fm, n_part_train particles each);
-    2. held-out solver runs at 512^2 with n_part_heldout particles, and for
-       the first n_noise of them a second solver run with other seeds (the
-       noise floor: what a perfect surrogate could reach against one run);
-    3. network A trained on the 256^2 runs only, network B the same then
-       fine-tuned on the 512^2 runs;
-    4. errors on the held-out curves (max |pred - solver| / max |solver|) and
-       the time per kappa(tau) curve of the network and of the solver.
+    2. held-out points run n_avg times at 512^2 with other seeds: their mean
+       is the reference curve (label noise down by sqrt(n_avg)), and one run
+       against the mean of the others is the solver's own noise floor;
+    3. network A trained on the 256^2 runs only (the specified training set),
+       network B the same then fine-tuned on the 512^2 runs;
+    4. errors on the held-out curves (max |pred - ref| / max |ref|), and the
+       trust region of the queries: the even held-out points calibrate the
+       error of each (mass, p_T0 bin) cell, the odd ones test what the
+       queries answer (coverage and error of the network's answers);
+    5. the time per kappa(tau) curve of the network and of the solver.
     """
     import torch
     rep = {}
@@ -213,19 +263,30 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_
     rep["train_rows"] = [int(len(Xc)), int(len(Xf))]
     log("surrogate: data %.1f s, rows %s" % (rep["data_s"], rep["train_rows"]))
     hp = draw_params(n_heldout, seed + 4)
-    hc, tpc_h = solver_curves(hp, 512, 10.0, n_part_heldout, seed + 5)
-    hc2, _ = solver_curves(hp[:n_noise], 512, 10.0, n_part_heldout, seed + 6)
+    runs = []
+    for r in range(n_avg):
+        hc_r, tpc_h = solver_curves(hp, 512, 10.0, n_part_heldout, seed + 5 + 7919 * r)
+        runs.append(hc_r)
     rep["solver_s_per_curve"] = tpc_h
-    noise = [curve_error(a[1], np.interp(a[0], b[0], b[1])) for a, b in zip(hc[:n_noise], hc2)]
-    rep["noise_floor_kappa"] = {"median": float(np.median(noise)), "max": float(np.max(noise))}
+    ref = mean_curves(runs)
+    rest = mean_curves(runs[1:])
+    noise = np.array([curve_error(a[1], b[1]) for a, b in zip(runs[0], rest)])
+    rep["reference"] = "mean of %d solver runs per held-out point (%d particles each)" % (n_avg, n_part_heldout)
+    rep["noise_floor_kappa"] = {"what": "one solver run against the mean of the other %d" % (n_avg - 1),
+                                "median": float(np.median(noise)), "p90": float(np.percentile(noise, 90)),
+                                "max": float(np.max(noise))}
 
-    def evaluate(sur):
+    def errors(sur, idx):
         ek, ed = [], []
-        for (qs, m, pt), (tau, k, d) in zip(hp, hc):
+        for i in idx:
+            (qs, m, pt), (tau, k, d) = hp[i], ref[i]
             kp, dp = sur.predict(qs, m, pt, tau)
             ek.append(curve_error(kp, k))
             ed.append(curve_error(dp, d))
-        ek, ed = np.array(ek), np.array(ed)
+        return np.array(ek), np.array(ed)
+
+    def evaluate(sur):
+        ek, ed = errors(sur, range(n_heldout))
         out = {"kappa_median": float(np.median(ek)), "kappa_p90": float(np.percentile(ek, 90)),
                "kappa_max": float(np.max(ek)), "dpT2_median": float(np.median(ed)),
                "dpT2_max": float(np.max(ed))}
@@ -247,7 +308,30 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_
     rep["train_s"] = time.perf_counter() - t
     rep["loss_final"] = [float(la[-1]), float(lb[-1])]
     rep["coarse_only"] = evaluate(A)
+    rep["c5_as_specified"] = "coarse_only: trained on the 2000 runs at 256^2 alone"
     rep["fine_tuned"] = evaluate(B)
+    # trust region: calibrate on the even held-out points, test on the odd ones
+    cal, test = list(range(0, n_heldout, 2)), list(range(1, n_heldout, 2))
+    ek_cal, _ = errors(B, cal)
+    table = trust_table([hp[i] for i in cal], ek_cal)
+    B.set_trust(table, err_max)
+    ek_test, _ = errors(B, test)
+    answered = []
+    for i in test:
+        qs, m, pt = hp[i]
+        tau = ref[i][0]
+        _, verdict = B.net.query(features(qs, m, pt, tau - tau_start(m, pt)))
+        answered.append(verdict == 0)
+    answered = np.array(answered)
+    rep["trust"] = {"err_max": err_max, "cells_trusted": int(np.sum(table <= err_max)), "cells": int(table.size),
+                    "calibration_points": len(cal), "test_points": len(test),
+                    "test_coverage": float(answered.mean()),
+                    "test_kappa_err_answered": None if not answered.any() else
+                    {"median": float(np.median(ek_test[answered])), "p90": float(np.percentile(ek_test[answered], 90)),
+                     "max": float(np.max(ek_test[answered]))},
+                    "test_kappa_err_all": {"median": float(np.median(ek_test)),
+                                           "p90": float(np.percentile(ek_test, 90)), "max": float(np.max(ek_test))},
+                    "table": [[None if not np.isfinite(v) else round(float(v), 4) for v in row] for row in table]}
     tau = np.linspace(0.0025, 1.0, 410)
     B.predict(2.0, 4.18, 2.0, tau)
     torch.cuda.synchronize()
@@ -269,8 +353,8 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_noise=16, n_
     rep["mlp_s_per_curve_batched64"] = (time.perf_counter() - t) / reps / 64
     rep["speedup"] = rep["solver_s_per_curve"] / rep["mlp_s_per_curve"]
     rep["speedup_batched"] = rep["solver_s_per_curve"] / rep["mlp_s_per_curve_batched64"]
-    # fallback outside the training domain goes to the solver
-    _, _, used = B.query(3.5, 1.27, 2.0, tau[:100], N=64, L_fm=10.0 * 64 / 512, n_particles=1000)
-    rep["fallback_outside_domain"] = bool(used)
+    # a query outside the training domain goes to the solver
+    _, _, verdict = B.query(3.5, 1.27, 2.0, tau[:100], N=64, L_fm=10.0 * 64 / 512, n_particles=1000)
+    rep["fallback_outside_domain"] = bool(verdict == 1)
     log("surrogate: %s" % rep)
     return rep

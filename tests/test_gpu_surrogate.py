@@ -71,10 +71,29 @@ def test_network_is_much_faster_than_the_solver(trained):
     assert solver_s / net_s > 5
 
 
-def test_queries_outside_the_domain_fall_back_to_the_solver(trained):
-    S, sur, _, _, _, _ = trained
+def test_queries_go_through_the_trust_region(trained):
+    """gl_surrogate_query decides: inside the training box, in a cell whose
+    calibrated held-out error is within the bound, the network answers
+    (verdict 0); outside the box (Q_s = 3.5 GeV) and in untrusted cells the
+    solver does (verdicts 1 and 2), and its curves are returned instead."""
+    S, sur, held, (ref, ref2), _, _ = trained
+    errs = [S.curve_error(sur.predict(qs, m, pt, tau)[0], k) for (qs, m, pt), (tau, k, d) in zip(held, ref)]
+    table = S.trust_table(held, errs)
     tau = np.linspace(0.0025, 0.25, 50)
-    k, d, used = sur.query(2.0, 1.27, 2.0, tau, N=N, L_fm=L_FM, n_particles=2000)
-    assert not used and np.all(np.isfinite(k))
-    k, d, used = sur.query(3.5, 1.27, 2.0, tau, N=N, L_fm=L_FM, n_particles=2000)
-    assert used and np.all(np.isfinite(k)) and np.all(np.isfinite(d))
+    k0, b0 = S.cell_of(1.27, 2.0)
+    sur.set_trust(table, err_max=float(table[k0, b0]) + 1e-6)      # that cell is trusted
+    k, d, verdict = sur.query(2.0, 1.27, 2.0, tau, N=N, L_fm=L_FM, n_particles=2000)
+    assert verdict == 0 and np.all(np.isfinite(k))
+    kp, dp = sur.predict(2.0, 1.27, 2.0, tau)
+    assert np.array_equal(k, kp) and np.array_equal(d, dp)
+    k, d, verdict = sur.query(3.5, 1.27, 2.0, tau, N=N, L_fm=L_FM, n_particles=2000)
+    assert verdict == 1 and np.all(np.isfinite(k)) and np.all(np.isfinite(d))
+    sur.set_trust(table, err_max=0.0)                               # no cell is trusted
+    k, d, verdict = sur.query(2.0, 1.27, 2.0, tau, N=N, L_fm=L_FM, n_particles=2000)
+    assert verdict == 2 and np.all(np.isfinite(k))
+    # the decision itself, on rows at the box edges and off the mass classes
+    X = S.features(2.0, 1.27, 2.0, tau)
+    sur.set_trust(np.zeros_like(table), err_max=0.05)
+    assert sur.net.query(X)[1] == 0
+    X[3, 1] = 2.0                                                    # not one of the masses
+    assert sur.net.query(X)[1] == 1
