@@ -61,6 +61,22 @@ def alg_bytes(prec):
     }
 
 
+def kernel_rates(prec, avg_us, units, ab):
+    """Per dominant kernel: algorithmic GB/s (algorithmic bytes over the live
+    HIP-event duration) and counted GB/s (the HBM bytes of the counter runs
+    over the same duration, None when those are stale), each also as a
+    fraction of the 8 TB/s peak."""
+    out = {}
+    for name in ("field_step", "push"):
+        t = avg_us[name] * 1e-6
+        alg = ab[name] * units[name] / t / 1e9
+        tr = measured_traffic(name, prec)
+        cnt = None if tr is None else (tr[0] + tr[1]) / t / 1e9
+        out[name] = {"avg_us": avg_us[name], "alg_GBps": alg, "alg_frac": alg / PEAK_HBM_GBS,
+                     "counted_GBps": cnt, "counted_frac": None if cnt is None else cnt / PEAK_HBM_GBS}
+    return out
+
+
 def run_event(g, torch, prec, n_per, steps, prof=False):
     ev = g.Event(N, L_FM, DTAU, precision=prec, reunit_every=16, max_steps=steps,
                  max_particles=n_per * len(SPECIES))
@@ -111,6 +127,11 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
     ab = alg_bytes(32)
     step_bytes = sites * ab["field_step"] + npart * ab["push"]
     finite = all(e.diagnostics()["nonfinite"] == 0 for e in evs)
+    counted = {}
+    for kern, alg in (("batch_field", sites * ab["field_step"]), ("batch_push", npart * ab["push"])):
+        tr = measured_traffic(kern, 32)
+        counted[kern] = {"alg_bytes_per_launch": alg,
+                         "counted_bytes_per_launch": None if tr is None else tr[0] + tr[1]}
     b.close()
     for e in evs:
         e.close()
@@ -121,7 +142,7 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
             "alg_GBps": step_bytes * steps / t_run / 1e9,
             "frac_hbm": step_bytes * steps / t_run / 1e9 / PEAK_HBM_GBS,
             "tile": cfg["tile"], "grid_mult": cfg["grid_mult"], "graph_steps": cfg["graph_steps"],
-            "finite": finite}
+            "hbm_traffic": counted, "finite": finite}
 
 
 def scan_bench(n_events=16, n_per=N_PER, precision=64):
@@ -285,7 +306,8 @@ def measured_traffic(kernel, prec):
             m = re.search(r"`([0-9a-f]+)`", ln)
             src = m.group(1) if m else None
         cells = [c.strip() for c in ln.strip().strip("|").split("|")]
-        if len(cells) >= 4 and cells[0] in ("field_step", "push") and cells[1] in ("32", "64"):
+        if len(cells) >= 4 and cells[0] in ("field_step", "push", "batch_field", "batch_push") and \
+                cells[1] in ("32", "64"):
             rows[(cells[0], int(cells[1]))] = (float(cells[2]), float(cells[3]))
     if src != kernel_source_hash():
         return None
@@ -298,6 +320,15 @@ def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     1 GiB copy (bench.py --copy-calib 1024)."""
     import csv
     import glob
+
+    def counts(d, counter):
+        n = {}
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                if r["Counter_Name"] == counter:
+                    name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                    n[name] = n.get(name, 0) + 1
+        return n
 
     def means(d, counter):
         acc = {}
@@ -320,7 +351,15 @@ def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     w = means(write_dir, "WRITE_SIZE")
     tname = "double" if prec == 64 else "float"
     print("fetch factor %.4f, write factor %.4f (bytes per KiB counted, from the copy)" % (kf, kw))
-    for kern, short in (("gl::k_field_step<%s>" % tname, "field_step"), ("gl::k_push<%s>" % tname, "push")):
+    kerns = [("gl::k_field_step<%s>" % tname, "field_step"), ("gl::k_push<%s>" % tname, "push")]
+    # the batched kernels of the 64-event FP32 workload, when the run had them
+    # (the field kernel of the tile shape the autotuner picked: most launches)
+    bf = [k for k in f if k.startswith("gl::k_batch_field_flat<%s" % tname)]
+    if bf:
+        kerns.append((max(bf, key=lambda k: counts(fetch_dir, "FETCH_SIZE").get(k, 0)), "batch_field"))
+    if "gl::k_batch_push_flat<%s>" % tname in f:
+        kerns.append(("gl::k_batch_push_flat<%s>" % tname, "batch_push"))
+    for kern, short in kerns:
         print("| %s | %d | %.0f | %.0f |" % (short, prec, f[kern] * 1024 * kf, w[kern] * 1024 * kw))
     print("source hash: `%s`" % kernel_source_hash())
 
@@ -520,6 +559,7 @@ def main():
         "particle_steps_per_s": particle_steps / wall,
         "kernel_avg_us": avg_us,
         "finite": bool(kappa_ok),
+        "kernels": kernel_rates(args.precision, avg_us, units, ab),
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": None if tr is None else tr[0] + tr[1],
