@@ -310,6 +310,11 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_avg=4, n_par
     rep["coarse_only"] = evaluate(A)
     rep["c5_as_specified"] = "coarse_only: trained on the 2000 runs at 256^2 alone"
     rep["fine_tuned"] = evaluate(B)
+    ek_all, _ = errors(B, range(n_heldout))
+    worst = np.argsort(ek_all)[::-1][:3]
+    rep["fine_tuned_worst"] = [{"qs_GeV": round(hp[i][0], 3), "m_GeV": hp[i][1], "pT0_GeV": round(hp[i][2], 3),
+                                "kappa_err": round(float(ek_all[i]), 4), "cell": list(cell_of(hp[i][1], hp[i][2])),
+                                "noise_of_one_run": round(float(noise[i]), 4)} for i in worst]
     # trust region: calibrate on the even held-out points, test on the odd ones
     cal, test = list(range(0, n_heldout, 2)), list(range(1, n_heldout, 2))
     ek_cal, _ = errors(B, cal)
