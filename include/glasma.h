@@ -375,8 +375,18 @@ gl_status gl_batch_config(gl_batch *b, int32_t shape, int32_t grid_mult, int32_t
                           int32_t graph_steps);
 gl_status gl_batch_info(gl_batch *b, int32_t *shape, int32_t *tile_x, int32_t *tile_y,
                         int32_t *grid_mult, int32_t *graph_steps);
-/* n_steps coupled steps of every event of the batch. */
+/* n_steps coupled steps of every event of the batch.  Failure handling: an
+ * event whose broadening series turns non-finite at a step (a NaN or Inf
+ * momentum, or fields gone non-finite where its particles are) is masked
+ * from that step on: its field and particle work is skipped and its state
+ * and series after that step are not meaningful, while the other events
+ * run on unaffected.  At the end of the call every event's field state is
+ * checked as well, and the call synchronises the batch stream and returns
+ * GL_ENUMERIC if any event failed (gl_batch_status names them). */
 gl_status gl_batch_run(gl_batch *b, int32_t n_steps);
+/* Per event of the batch (in creation order), the first step at which it
+ * failed, or -1. */
+gl_status gl_batch_status(gl_batch *b, int32_t *fail_step);
 
 /* ---- learned surrogate ------------------------------------------------------
  * Fully connected network n_in -> width (x depth hidden layers, SiLU) -> n_out

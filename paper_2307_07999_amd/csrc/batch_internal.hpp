@@ -22,7 +22,11 @@ struct BatchEv {
     SortScratch sort;      // the event's radix-sort scratch
     int64_t sort_tiles;    // sort tiles over n_slots
     int32_t *ids[2];       // particle ids, alternating with P
+    int32_t *fail;         // first step at which the event failed (kNotFailed: none); failed events are skipped
 };
+
+constexpr int32_t kNotFailed = 0x7F7F7F7F;   // the value of bytes 0x7F, as hipMemsetAsync writes it
+constexpr int64_t kCheckChunk = 65536;       // state values per entry of the batch's finite-value check
 
 struct BatchCtl {
     int64_t n;             // common step index of all events
@@ -42,5 +46,11 @@ hipError_t launch_batch_sort(hipStream_t st, const BatchEv<T> *evs, int n_events
 template <typename T>
 hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *blocks, int64_t total, int fpar,
                              int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events);
+// every event's field state at parity fpar checked for NaN/Inf in chunks of
+// kCheckChunk values ((event, chunk) entries); a failing event's fail slot
+// is lowered to the current step
+template <typename T>
+hipError_t launch_batch_check(hipStream_t st, const BatchEv<T> *evs, const int2 *entries, int64_t total, int fpar,
+                              const BatchCtl *ctl);
 
 }  // namespace gl

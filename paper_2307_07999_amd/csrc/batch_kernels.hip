@@ -57,6 +57,7 @@ k_batch_field(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ tiles
     int64_t stride, end;
     for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
         const int2 w = tiles[t];
+        if (*evs[w.x].fail != kNotFailed) continue;   // a failed event is masked (uniform per workgroup)
         __syncthreads();   // the previous tile's reads are done
         batch_field_tile(tile, evs[w.x], w, fpar, n, tau, dtau, tau_h);
     }
@@ -73,6 +74,7 @@ k_batch_field_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ 
     const int64_t n = ctl->n;
     const T tau = dtau * (T)n, tau_h = dtau * ((T)n + T(0.5));
     const int2 w = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    if (*evs[w.x].fail != kNotFailed) return;   // a failed event is masked (uniform per workgroup)
     batch_field_tile(tile, evs[w.x], w, fpar, n, tau, dtau, tau_h);
 }
 
@@ -94,6 +96,7 @@ k_batch_push(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks
     int64_t stride, end;
     for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
         const int2 w = blocks[t];
+        if (*evs[w.x].fail != kNotFailed) continue;
         batch_push_block(evs[w.x], w, fpar, ppar, n, dtau);
     }
 }
@@ -103,6 +106,7 @@ __global__ void __launch_bounds__(kPushBlock)
 k_batch_push_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks, int64_t total, int fpar,
                   int ppar, const BatchCtl *__restrict__ ctl, T dtau) {
     const int2 w = blocks[xcd_remap(blockIdx.x, gridDim.x)];
+    if (*evs[w.x].fail != kNotFailed) return;
     batch_push_block(evs[w.x], w, fpar, ppar, (int)ctl->n, dtau);
 }
 
@@ -116,6 +120,10 @@ k_batch_reduce(const BatchEv<T> *__restrict__ evs, const BatchCtl *__restrict__ 
     if (s >= e.n_species) return;
     const int64_t row = ctl->n - 1;
     if (row < 0 || row >= e.max_steps) return;
+    // masked since an earlier step: that push skipped the event, its partial
+    // rows are stale.  Blocks of this launch lower fail to n + 1 at most, so
+    // the test reads the same for every thread of the workgroup.
+    if (*e.fail <= ctl->n) return;
     const int nb = (int)(e.n_slots / kPushBlock);
     __shared__ double red[256][4];
     double acc[4] = {0, 0, 0, 0};
@@ -135,7 +143,25 @@ k_batch_reduce(const BatchEv<T> *__restrict__ evs, const BatchCtl *__restrict__ 
         double v = red[0][threadIdx.x];
         if (threadIdx.x < 3 && red[0][3] > 0.0) v -= e.p0sum[s * 4 + threadIdx.x];
         e.series[((size_t)row * kMaxSpecies + s) * 4 + threadIdx.x] = v;
+        // a non-finite sum fails the event at the step this push reached (n + 1)
+        if (!isfinite(v)) atomicMin(e.fail, (int32_t)(ctl->n + 1 < kNotFailed ? ctl->n + 1 : kNotFailed - 1));
     }
+}
+
+// the batch's finite-value check: entry (event, chunk) tests values
+// [chunk * kCheckChunk, ...) of the event's whole field state at parity fpar
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_batch_check(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ entries, int fpar,
+              const BatchCtl *__restrict__ ctl) {
+    const int2 w = entries[blockIdx.x];
+    const BatchEv<T> &e = evs[w.x];
+    const int64_t nvals = (int64_t)kStateVals * e.N * e.N;
+    const int64_t lo = (int64_t)w.y * kCheckChunk, hi = lo + kCheckChunk < nvals ? lo + kCheckChunk : nvals;
+    const T *a = e.f[fpar].U;   // the state's arrays lie contiguous from U on
+    bool bad = false;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) bad |= !isfinite(a[i]);
+    if (bad) atomicMin(e.fail, (int32_t)(ctl->n < kNotFailed ? ctl->n : kNotFailed - 1));
 }
 
 __global__ void k_batch_advance(BatchCtl *ctl) {
@@ -183,7 +209,17 @@ hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_batch_check(hipStream_t st, const BatchEv<T> *evs, const int2 *entries, int64_t total, int fpar,
+                              const BatchCtl *ctl) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_check<T>, dim3((unsigned)total), dim3(256), 0, st, evs, entries, fpar, ctl);
+    return hipGetLastError();
+}
+
 #define GL_INST(T)                                                                                          \
+    template hipError_t launch_batch_check<T>(hipStream_t, const BatchEv<T> *, const int2 *, int64_t, int,      \
+                                              const BatchCtl *);                                             \
     template hipError_t launch_batch_fields<T>(hipStream_t, int, const BatchEv<T> *, const int2 *, int64_t, int, \
                                                const BatchCtl *, double, int);                               \
     template hipError_t launch_batch_push<T>(hipStream_t, const BatchEv<T> *, const int2 *, int64_t, int, int,  \

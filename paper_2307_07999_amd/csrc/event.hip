@@ -1683,8 +1683,8 @@ struct gl_batch {
     double dtau = 0.125;
     hipStream_t stream = nullptr;
     char *ws = nullptr;
-    size_t desc = 0, tiles[kBatchShapes] = {0, 0, 0}, pblocks = 0, stiles = 0, ctl = 0;
-    int64_t total_tiles[kBatchShapes] = {0, 0, 0}, total_pblocks = 0, total_stiles = 0;
+    size_t desc = 0, tiles[kBatchShapes] = {0, 0, 0}, pblocks = 0, stiles = 0, ctl = 0, fail = 0, checks = 0;
+    int64_t total_tiles[kBatchShapes] = {0, 0, 0}, total_pblocks = 0, total_stiles = 0, total_checks = 0;
     int shape = 0, grid_mult = 4, cus = 256;
     int fpar = 0, ppar = 0;
     int64_t since_sort = 0;
@@ -1698,9 +1698,12 @@ struct gl_batch {
 namespace {
 
 struct BatchSizes {
-    size_t desc, tiles[kBatchShapes], pblocks, stiles, ctl, total;
-    int64_t n_tiles[kBatchShapes], n_pblocks, n_stiles;
+    size_t desc, tiles[kBatchShapes], pblocks, stiles, ctl, fail, checks, total;
+    int64_t n_tiles[kBatchShapes], n_pblocks, n_stiles, n_checks;
 };
+
+// (event, chunk) entries of the finite-value check over the events' states
+int64_t check_chunks(const gl_event *ev) { return ((int64_t)kStateVals * ev->n2 + kCheckChunk - 1) / kCheckChunk; }
 
 const int kShapeTX[kBatchShapes] = {32, 64, 16}, kShapeTY[kBatchShapes] = {4, 2, 8};
 
@@ -1729,6 +1732,10 @@ gl_status batch_sizes(gl_event *const *evs, int n, BatchSizes &z) {
     for (int e = 0; e < n; e++) z.n_stiles += evs[e]->slots_used > 0 ? sort_tiles(evs[e]->slots_used) : 0;
     z.stiles = take((size_t)std::max<int64_t>(1, z.n_stiles) * sizeof(int2));
     z.ctl = take(sizeof(BatchCtl));
+    z.fail = take((size_t)n * sizeof(int32_t));
+    z.n_checks = 0;
+    for (int e = 0; e < n; e++) z.n_checks += check_chunks(evs[e]);
+    z.checks = take((size_t)z.n_checks * sizeof(int2));
     z.total = off;
     return GL_OK;
 }
@@ -1755,6 +1762,7 @@ BatchEv<T> batch_desc(const gl_batch *b, int e) {
     d.sort_tiles = ev->slots_used > 0 ? sort_tiles(ev->slots_used) : 0;
     d.ids[0] = ev->ids(b->pbuf0[e]);
     d.ids[1] = ev->ids(1 - b->pbuf0[e]);
+    d.fail = (int32_t *)(b->ws + b->fail) + e;
     return d;
 }
 
@@ -1965,6 +1973,9 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
     b->pblocks = z.pblocks;
     b->stiles = z.stiles;
     b->ctl = z.ctl;
+    b->fail = z.fail;
+    b->checks = z.checks;
+    b->total_checks = z.n_checks;
     for (auto *ev : b->evs) {
         // the batch reads each event's current particle buffer and formation
         // sums: take a pending sort first (on the event's stream; the batch
@@ -2017,6 +2028,13 @@ gl_status gl_batch_create(gl_event *const *evs, int32_t n_events, void *workspac
     if (!stl.empty() && hipMemcpyAsync(b->ws + b->stiles, stl.data(), stl.size() * sizeof(int2), hipMemcpyHostToDevice,
                                        b->stream) != hipSuccess)
         return cleanup(fail(GL_EDEVICE, "sort table upload failed"));
+    std::vector<int2> chk;
+    for (int e = 0; e < n_events; e++)
+        for (int64_t j = 0; j < check_chunks(evs[e]); j++) chk.push_back(make_int2(e, (int)j));
+    if (hipMemsetAsync(b->ws + b->fail, 0x7F, (size_t)n_events * sizeof(int32_t), b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->ws + b->checks, chk.data(), chk.size() * sizeof(int2), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return cleanup(fail(GL_EDEVICE, "failure table upload failed"));
     BatchCtl c;
     c.n = e0->n;
     if ((!pb.empty() && hipMemcpyAsync(b->ws + b->pblocks, pb.data(), pb.size() * sizeof(int2), hipMemcpyHostToDevice,
@@ -2116,11 +2134,32 @@ gl_status gl_batch_run(gl_batch *b, int32_t n_steps) {
         left--;
     }
     batch_sync_events(b, n_steps);
-    for (auto *ev : b->evs)
-        if (ev->stream != b->stream) {
-            HIP_TRY(hipStreamSynchronize(b->stream));
-            break;
-        }
+    // the events' states, checked once per call (their series every step)
+    const BatchCtl *ctl = (const BatchCtl *)(b->ws + b->ctl);
+    if (b->fp64)
+        HIP_TRY(launch_batch_check<double>(b->stream, (const BatchEv<double> *)(b->ws + b->desc),
+                                           (const int2 *)(b->ws + b->checks), b->total_checks, b->fpar, ctl));
+    else
+        HIP_TRY(launch_batch_check<float>(b->stream, (const BatchEv<float> *)(b->ws + b->desc),
+                                          (const int2 *)(b->ws + b->checks), b->total_checks, b->fpar, ctl));
+    std::vector<int32_t> f(b->evs.size());
+    HIP_TRY(hipMemcpyAsync(f.data(), b->ws + b->fail, f.size() * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::string bad;
+    for (size_t e = 0; e < f.size(); e++)
+        if (f[e] != kNotFailed) bad += (bad.empty() ? "" : ", ") + std::to_string(e) + " at step " + std::to_string(f[e]);
+    if (!bad.empty())
+        return fail(GL_ENUMERIC, "non-finite values in batch event(s) " + bad +
+                                     " (masked from that step on; gl_batch_status lists them)");
+    return GL_OK;
+}
+
+gl_status gl_batch_status(gl_batch *b, int32_t *fail_step) {
+    if (!b || !fail_step) return fail(GL_EINVAL, "null argument");
+    std::vector<int32_t> f(b->evs.size());
+    HIP_TRY(hipMemcpyAsync(f.data(), b->ws + b->fail, f.size() * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t e = 0; e < f.size(); e++) fail_step[e] = f[e] == kNotFailed ? -1 : f[e];
     return GL_OK;
 }
 

@@ -96,6 +96,7 @@ _SIGS = {
     "gl_batch_config": [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "gl_batch_info": [_VP, _I32, _I32, _I32, _I32, _I32],
     "gl_batch_run": [_VP, ctypes.c_int32],
+    "gl_batch_status": [_VP, _I32],
     "gl_max_particles": [ctypes.c_int32, _I64],
     "gl_scan_statistics": [_D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                            _D, ctypes.c_int32, _I32],
@@ -507,6 +508,12 @@ class Batch:
 
     def run(self, n_steps):
         return check(lib().gl_batch_run(self._h, n_steps))
+
+    def status(self):
+        """Per event, the first step at which it failed (masked), or -1."""
+        out = np.zeros(len(self.events), np.int32)
+        check(lib().gl_batch_status(self._h, _i(out)))
+        return out
 
 
 class MLPDesc(ctypes.Structure):

@@ -128,3 +128,46 @@ def test_batched_event_matches_oracle(gl, orc):
     parts = ev.get_particles()
     assert np.array_equal(parts["cell"], np.ascontiguousarray(P.cell.T))
     b.close()
+
+
+def test_a_failed_event_is_masked_in_a_batch(gl):
+    """One event of a batch gets a NaN momentum (set from the host), another
+    a NaN in E and no particles.  The first is masked from the step of its
+    first push (its series row turns non-finite there), the second is found
+    by the end-of-run check of the field states; gl_batch_run reports
+    GL_ENUMERIC and gl_batch_status the steps, while the healthy events run
+    bitwise as they do alone."""
+    steps = 40
+    def make(k, N, npart):
+        ev = gl.Event(N, N * 0.125, 0.125, precision=64, max_steps=steps + 2, max_particles=max(npart, 1))
+        ev.init_glasma(1.0, 0.2, 1, 900 + k)
+        if npart:
+            ev.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, npart, 910 + k, tau_form_fm=0.0)
+        return ev
+    spec = [(24, 300), (32, 400), (48, 500), (16, 0)]
+    single = [make(k, N, p) for k, (N, p) in enumerate(spec)]
+    batched = [make(k, N, p) for k, (N, p) in enumerate(spec)]
+    d = batched[1].get_particles()
+    d["p"][0, 123] = np.nan
+    batched[1].set_particles([(1.27, 2.0, gl.KIND_HEAVY_QUARK, 0.0)], d["cell"], d["off"], d["eta"], d["p"],
+                             d["Q"], d["p0"], d["species"])
+    U, E, phi, pi, n = batched[3].get_state()
+    E[0, 3, 100] = np.nan
+    batched[3].set_state(U, E, phi, pi, n)
+    for k in (0, 2):
+        single[k].run(steps)
+    b = gl.Batch(batched)
+    b.config(shape=0, grid_mult=0, sort_every=16, graph_steps=32)
+    with pytest.raises(gl.GlasmaError) as e:
+        b.run(steps)
+    assert e.value.status == gl.GL_ENUMERIC
+    st = b.status()
+    print("batch failure steps:", st)
+    assert st[0] == -1 and st[2] == -1
+    assert st[1] == 2                  # the first push, 1 -> 2
+    assert st[3] == 1 + steps          # the field state at the end of the call
+    for k in (0, 2):
+        for x, y in zip(single[k].get_state()[:4], batched[k].get_state()[:4]):
+            assert np.array_equal(x, y)
+        assert np.array_equal(single[k].series(), batched[k].series())
+    b.close()
