@@ -171,3 +171,37 @@ def test_a_failed_event_is_masked_in_a_batch(gl):
             assert np.array_equal(x, y)
         assert np.array_equal(single[k].series(), batched[k].series())
     b.close()
+
+
+def test_batch_equals_single_events_at_batched_workload_sizes(gl):
+    """The bitwise batch == single-event check at the sizes of the 64-event
+    FP32 workload: lattices of 128^2, 256^2 and 384^2 at its spacing with
+    1e4 to 1e5 particles of its seven species, 40 steps (a graph of 32 and
+    8 ordinary steps, two sorts), autotuned configuration."""
+    import bench
+    steps = 40
+    a_fm = bench.L_FM / bench.N
+
+    def make(k, N, per):
+        ev = gl.Event(N, N * a_fm, bench.DTAU, precision=32, reunit_every=16, max_steps=steps,
+                      max_particles=per * len(bench.SPECIES))
+        ev.init_glasma(bench.G2MU, bench.M_IR, 4, 5000 + k)
+        for j, (m, p0, kind) in enumerate(bench.SPECIES):
+            ev.add_species(m, p0, kind, per, 6000 + 17 * k + j)
+        return ev
+    spec = [(128, 1500), (256, 4000), (384, 14000)]
+    single = [make(k, N, p) for k, (N, p) in enumerate(spec)]
+    for ev in single:
+        ev.run(steps)
+    batched = [make(k, N, p) for k, (N, p) in enumerate(spec)]
+    b = gl.Batch(batched)
+    b.autotune(None)
+    b.run(steps)
+    for s, t in zip(single, batched):
+        for x, y in zip(s.get_state()[:4], t.get_state()[:4]):
+            assert np.array_equal(x, y)
+        assert np.array_equal(s.series(), t.series())
+        ps, pb = s.get_particles(), t.get_particles()
+        for k in ("cell", "p", "Q"):
+            assert np.array_equal(ps[k], pb[k])
+    b.close()
