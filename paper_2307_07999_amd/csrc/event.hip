@@ -170,6 +170,9 @@ struct gl_event {
     int32_t match_max_iter = 100;
     double match_tol = 1e-13;
     int32_t check_every = 0;    // finite-value checks inside gl_run every this many steps (0: off)
+    int32_t graph_steps = 0;    // gl_run replays blocks of this many steps from a captured graph (0: off)
+    hipGraphExec_t gexec = nullptr;
+    int64_t graph_launches = 0, graph_instantiations = 0;
 
     // kernel timing: pairs of events per launch, grouped by kernel class
     int32_t prof = 0;                       // time every prof-th launch of each class (0: off)
@@ -448,6 +451,58 @@ gl_status check_report(gl_event *ev, int *first_bad, int64_t row0, int64_t row_e
 
 gl_status do_field_step(gl_event *ev, bool sf) {
     return ev->fp64() ? field_step<double>(ev, sf) : field_step<float>(ev, sf);
+}
+gl_status do_push(gl_event *ev, bool defer);
+
+// one coupled step of gl_run: the field step, then the push (a due sort only
+// computes its order; the next push applies it)
+gl_status one_step(gl_event *ev, bool has_particles) {
+    gl_status s = do_field_step(ev, has_particles);
+    if (s || !has_particles) return s;
+    ev->push_due = true;
+    return do_push(ev, true);
+}
+
+// count steps recorded from the stream into a graph with the same launch
+// code and replayed: the graph of the first block is instantiated, later
+// blocks update it in place (same topology, new step-dependent arguments)
+// or instantiate anew.  The host state advances while recording, so a
+// failure here leaves the event uninitialised rather than out of step.
+gl_status graph_block(gl_event *ev, int32_t count, bool has_particles) {
+    HIP_TRY(hipStreamBeginCapture(ev->stream, hipStreamCaptureModeRelaxed));
+    gl_status s = GL_OK;
+    for (int32_t k = 0; k < count && !s; k++) s = one_step(ev, has_particles);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ev->stream, &g);
+    if (s || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        ev->ready = false;
+        return s ? s : fail(GL_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    bool updated = false;
+    if (ev->gexec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult r = hipGraphExecUpdateError;
+        updated = hipGraphExecUpdate(ev->gexec, g, &bad, &r) == hipSuccess && r == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();   // a refused update is expected here; keep it out of later launch checks
+            (void)hipGraphExecDestroy(ev->gexec);
+            ev->gexec = nullptr;
+        }
+    }
+    hipError_t le = hipSuccess;
+    if (!updated) {
+        le = hipGraphInstantiate(&ev->gexec, g, nullptr, nullptr, 0);
+        if (le == hipSuccess) ev->graph_instantiations++;
+    }
+    if (le == hipSuccess) le = hipGraphLaunch(ev->gexec, ev->stream);
+    (void)hipGraphDestroy(g);
+    if (le != hipSuccess) {
+        ev->ready = false;
+        return fail(GL_EDEVICE, std::string("graph replay: ") + hipGetErrorString(le));
+    }
+    ev->graph_launches++;
+    return GL_OK;
 }
 gl_status sort_particles(gl_event *ev);
 
@@ -798,6 +853,7 @@ gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t b
 
 void gl_event_destroy(gl_event *ev) {
     if (!ev) return;
+    if (ev->gexec) (void)hipGraphExecDestroy(ev->gexec);
     for (hipEvent_t e : ev->ev_pool) (void)hipEventDestroy(e);
     delete ev;
 }
@@ -946,14 +1002,20 @@ gl_status gl_run(gl_event *ev, int32_t n_steps) {
     int *first_bad = (int *)(ev->ws + ev->L.status) + 1;
     const bool checks = ev->check_every > 0 && n_steps > 0;
     if (checks) HIP_TRY(hipMemsetAsync(first_bad, 0x7F, sizeof(int), ev->stream));
-    gl_status s = GL_OK;
-    for (int32_t k = 0; k < n_steps && !s; k++) {
-        s = do_field_step(ev, has_particles);
-        if (!s && has_particles) {
-            ev->push_due = true;
-            s = do_push(ev, true);
+    // a changed particle set is sorted and summed once, before any recording
+    gl_status s = has_particles ? settle_particles(ev) : GL_OK;
+    // whole blocks of graph_steps from captured graphs (not while kernels are
+    // timed or checked: those keep direct launches), the rest launched directly
+    const bool graphs = ev->graph_steps > 0 && ev->prof == 0 && !checks;
+    for (int32_t k = 0; k < n_steps && !s;) {
+        if (graphs && n_steps - k >= ev->graph_steps) {
+            s = graph_block(ev, ev->graph_steps, has_particles);
+            k += ev->graph_steps;
+            continue;
         }
-        if (!s && checks && ((k + 1) % ev->check_every == 0 || k + 1 == n_steps)) s = check_state(ev, first_bad);
+        s = one_step(ev, has_particles);
+        k++;
+        if (!s && checks && (k % ev->check_every == 0 || k == n_steps)) s = check_state(ev, first_bad);
     }
     // no sort is left pending, also after an error
     const gl_status sp = apply_pending_sort(ev);
@@ -1316,6 +1378,25 @@ gl_status gl_set_sort_period(gl_event *ev, int32_t every) {
     if (gl_status s = check_free(ev)) return s;
     if (every < 0) return fail(GL_EINVAL, "sort period must be >= 0");
     ev->sort_every = every;
+    return GL_OK;
+}
+
+gl_status gl_set_graph_steps(gl_event *ev, int32_t steps) {
+    if (gl_status s = check_free(ev)) return s;
+    if (steps < 0) return fail(GL_EINVAL, "graph_steps must be >= 0");
+    if (steps > 0 && !ev->stream) return fail(GL_EINVAL, "graph replay needs a stream other than the null stream");
+    ev->graph_steps = steps;
+    if (steps == 0 && ev->gexec) {
+        (void)hipGraphExecDestroy(ev->gexec);
+        ev->gexec = nullptr;
+    }
+    return GL_OK;
+}
+
+gl_status gl_graph_stats(const gl_event *ev, int64_t *launches, int64_t *instantiations) {
+    if (!ev || !launches || !instantiations) return fail(GL_EINVAL, "null argument");
+    *launches = ev->graph_launches;
+    *instantiations = ev->graph_instantiations;
     return GL_OK;
 }
 

@@ -101,6 +101,8 @@ _SIGS = {
     "gl_scan_statistics": [_D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                            _D, ctypes.c_int32, _I32],
     "gl_set_check_period": [_VP, ctypes.c_int32],
+    "gl_set_graph_steps": [_VP, ctypes.c_int32],
+    "gl_graph_stats": [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gl_set_match_params": [_VP, ctypes.c_int32, ctypes.c_double],
     "gl_checkpoint": [_VP, ctypes.c_char_p],
     "gl_restore": [_VP, ctypes.c_char_p],
@@ -367,6 +369,17 @@ class Event:
     def set_check_period(self, every):
         """Finite-value checks inside run() every `every` steps (0: off)."""
         return check(lib().gl_set_check_period(self._h, every))
+
+    def set_graph_steps(self, steps):
+        """run() replays whole blocks of `steps` steps from a captured HIP
+        graph (0: direct launches); needs a non-null stream."""
+        return check(lib().gl_set_graph_steps(self._h, steps))
+
+    def graph_stats(self):
+        """(graphs launched, graphs instantiated) by run() so far."""
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(lib().gl_graph_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def set_match_params(self, max_iter, tol):
         return check(lib().gl_set_match_params(self._h, max_iter, tol))

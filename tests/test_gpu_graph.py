@@ -1,0 +1,95 @@
+"""gl_run with its steps replayed from captured HIP graphs against the same
+run launched step by step: both must give the same fields, particles and
+series bit for bit, over several calls (graphs updated in place and
+re-instantiated), a remainder launched directly, and with the correlators on."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_07999_amd as g
+    g.lib()
+    return g
+
+
+def _event(gl, prec, stream):
+    ev = gl.Event(32, 4.0, 0.125, precision=prec, max_steps=200, max_particles=3000, stream=stream,
+                  static_correlator=True, lightlike_correlator=True)
+    ev.init_glasma(1.0, 0.2, 2, 91)
+    ev.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, 1200, 92)
+    ev.add_species(0.0, 10.0, gl.KIND_JET, 1300, 93)
+    ev.static_start(0.02)
+    ev.lightlike_start(0.05)
+    return ev
+
+
+def _snapshot(ev):
+    return dict(state=ev.get_state(), parts=ev.get_particles(), series=ev.series(),
+                static=ev.static_broadening(), lightlike=ev.lightlike_broadening())
+
+
+def _assert_bitwise(a, b):
+    for x, y in zip(a["state"], b["state"]):
+        assert np.array_equal(x, y)
+    for k in a["parts"]:
+        assert np.array_equal(a["parts"][k], b["parts"][k]), k
+    for k in ("series", "static", "lightlike"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_graph_replay_equals_direct_launches(gl, prec):
+    import torch
+    s_direct, s_graph = torch.cuda.Stream(), torch.cuda.Stream()
+    ref, ev = _event(gl, prec, s_direct), _event(gl, prec, s_graph)
+    ev.set_graph_steps(32)
+    # 40 = one graph + 8 direct steps; 64 = two graphs at another phase of the
+    # sort and flush cadence; 16 and 24 replay graphs of another length
+    for n, G in ((40, 32), (64, 32), (16, 16), (24, 8)):
+        ev.set_graph_steps(G)
+        ref.run(n)
+        ev.run(n)
+        torch.cuda.synchronize()
+        _assert_bitwise(_snapshot(ref), _snapshot(ev))
+    launches, inst = ev.graph_stats()
+    assert launches == 1 + 2 + 1 + 3
+    assert 1 <= inst <= launches
+    print("graphs launched %d, instantiated %d" % (launches, inst))
+    ev.set_graph_steps(0)            # frees the graph; direct from here on
+    ref.run(5)
+    ev.run(5)
+    torch.cuda.synchronize()
+    _assert_bitwise(_snapshot(ref), _snapshot(ev))
+    assert ev.graph_stats()[0] == launches
+    ref.close()
+    ev.close()
+
+
+def test_graph_replay_is_off_while_checking_and_needs_a_stream(gl):
+    import torch
+    s = torch.cuda.Stream()
+    ev = _event(gl, 64, s)
+    ev.set_graph_steps(16)
+    ev.set_check_period(8)
+    ev.run(32)                       # checked steps are launched directly
+    assert ev.graph_stats()[0] == 0
+    ev.set_check_period(0)
+    ev.run(32)
+    assert ev.graph_stats()[0] == 2
+    with pytest.raises(gl.GlasmaError) as e:
+        ev.set_graph_steps(-1)
+    assert e.value.status == gl.GL_EINVAL
+    ev.close()
+    null = torch.cuda.default_stream()
+    if null.cuda_stream == 0:
+        ev = gl.Event(16, 2.0, 0.125, precision=64, max_steps=4, stream=null)
+        with pytest.raises(gl.GlasmaError) as e:
+            ev.set_graph_steps(8)
+        assert e.value.status == gl.GL_EINVAL
+        ev.close()
