@@ -54,12 +54,15 @@ k_push_permuted(int N, PartPtrs<T> P, PartPtrs<T> W, const int32_t *__restrict__
     int s = -1;
     if (j < n_slots) {
         const int64_t i = perm[j];
-        s = push_particle<T, true>(N, P, i, W, j, f, F, tab, n, dtau, acc);
+        // the fields that only move go first, so that nothing of them stays
+        // live through the push
         W.species[j] = P.species[i];
         W.px0[j] = P.px0[i];
         W.py0[j] = P.py0[i];
         W.pz0[j] = P.pz0[i];
         id_dst[j] = id_src[i];
+        __builtin_amdgcn_sched_barrier(0);
+        s = push_particle<T, true>(N, P, i, W, j, f, F, tab, n, dtau, acc);
     }
     block_species_reduce(s, acc, n_species, partials + (size_t)blk * n_species * 4);
 }

@@ -14,9 +14,9 @@ namespace gl {
 // species of an active particle (-1 otherwise) and in acc its squared
 // momenta p_x^2, p_y^2, p_z^2 (lab frame) at tau_{n+1/2} and a count of 1;
 // the series reduction subtracts the species' sums of the squared momenta at
-// formation.  Loads are grouped so that a wave makes three dependent trips
-// to memory: the particle state (all of it, before the activity test), the
-// site fields and phi of its cell, and the links of both crossings together.
+// formation.  A wave makes four dependent trips to memory: the particle
+// state (all of it, before the activity test), the site fields and phi of its
+// cell, and the link of each crossing.
 template <typename T, bool MOVE = false, bool ST = kStreamed<T>>
 __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_t i, const PartPtrs<T> &W, int64_t j,
                                              const FieldPtrs<T> &f, const T *__restrict__ F,
@@ -109,23 +109,33 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         oy += dtau * pl[1] / ptau;
         const T deta = dtau * peta / (th * th * ptau);
         const T eta_new = eta_old + deta;
-        // cells crossed, x first then y; the links of both crossings are
-        // loaded before either transport
+        // cells crossed, x first then y
         const int sx = ox >= T(0.5) ? 1 : (ox < T(-0.5) ? -1 : 0);
         const int sy = oy >= T(0.5) ? 1 : (oy < T(-0.5) ? -1 : 0);
         const int cxm = cx == 0 ? N - 1 : cx - 1, cym = cy == 0 ? N - 1 : cy - 1;
         const int cx1 = sx > 0 ? (cx + 1 == N ? 0 : cx + 1) : (sx < 0 ? cxm : cx);
         const int cy1 = sy > 0 ? (cy + 1 == N ? 0 : cy + 1) : (sy < 0 ? cym : cy);
-        M3<T> ux, uy;
-        if (sx != 0) ux = chunk_load_link(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy, 0);
-        if (sy != 0) uy = chunk_load_link(f.U, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym), 1);
         // colour rotation along eta with phi^n at the old cell: Q <- W Q W^dag
         transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
-        // crossings: Q <- U^dag Q U forward, U Q U^dag backward
-        if (sx > 0) transport_dn(ux, herm_from_alg(q), q);
-        else if (sx < 0) transport_nd(ux, herm_from_alg(q), q);
-        if (sy > 0) transport_dn(uy, herm_from_alg(q), q);
-        else if (sy < 0) transport_nd(uy, herm_from_alg(q), q);
+        // crossings: Q <- U^dag Q U forward, U Q U^dag backward.  Each link is
+        // loaded when its transport is due (the scheduling barriers keep the
+        // compiler from hoisting the loads): holding both links through the
+        // exponential took the FP64 push to 214 VGPRs and two waves per SIMD;
+        // loaded one after the other it fits 168 VGPRs and three waves, and
+        // the extra trip to memory costs less than the lost occupancy (FP64
+        // push 83.1 -> 74.0 us at 512^2 with 7e5 particles)
+        __builtin_amdgcn_sched_barrier(0);
+        if (sx != 0) {
+            const M3<T> ux = chunk_load_link(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy, 0);
+            if (sx > 0) transport_dn(ux, herm_from_alg(q), q);
+            else transport_nd(ux, herm_from_alg(q), q);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (sy != 0) {
+            const M3<T> uy = chunk_load_link(f.U, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym), 1);
+            if (sy > 0) transport_dn(uy, herm_from_alg(q), q);
+            else transport_nd(uy, herm_from_alg(q), q);
+        }
         ox -= (T)sx;
         oy -= (T)sy;
         el_st_i32<CP>(W.cx, j, cx1);
