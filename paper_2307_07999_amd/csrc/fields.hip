@@ -128,7 +128,7 @@ k_lightlike_accum(int N, const T *__restrict__ F, const T *__restrict__ U, doubl
                            (double)chunk_ld(F, n2, c, 40 + a);
                 else f[a] = (double)chunk_ld(F, n2, c, 16 + a) + (double)chunk_ld(F, n2, c, 32 + a);
             }
-            transport_nd(w, herm_from_alg(f), t);
+            transport_nd(w, f, t);
             double s = 0.0;
 #pragma unroll
             for (int a = 0; a < 8; a++) {
@@ -190,8 +190,8 @@ k_diag(int N, FieldPtrs<T> f, T tau, double *__restrict__ partials) {
         chunk_load_a(f.pi, n2, nb.x, 0, p);
         M3<T> u1m = chunk_load_link(f.U, n2, nb.xm1, 0), u2m = chunk_load_link(f.U, n2, nb.xm2, 1);
         T t1[8], t2[8];
-        transport_dn(u1m, herm_from_alg(e1m), t1);
-        transport_dn(u2m, herm_from_alg(e2m), t2);
+        transport_dn(u1m, e1m, t1);
+        transport_dn(u2m, e2m, t2);
         M3<T> PH = herm_from_alg(ph), PI = herm_from_alg(p);
         M3<T> c = sub(mul(PH, PI), mul(PI, PH));   // [phi, pi]; i[phi,pi] hermitian
         M3<T> ic;

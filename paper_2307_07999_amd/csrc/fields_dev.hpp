@@ -8,6 +8,10 @@
 
 namespace gl {
 
+// the field step's transports use the hermitian-aware products in FP64 only
+template <typename T>
+constexpr bool kHermFS = sizeof(T) == 8;
+
 // values slot..slot+7 of the site-field record of site x
 template <typename T>
 __device__ __forceinline__ void store_rec(T *__restrict__ F, size_t n2, size_t x, int slot, const T *v) {
@@ -216,7 +220,7 @@ __device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__rest
     if (site_fields) {
 #pragma unroll
         for (int a = 0; a < 8; a++) eb[a] = T(0.25) * inv_tau * (eb[a] + e[a]);   // Ebar / (2 tau)
-        transport_dn(u, herm_from_alg(eb), t);
+        transport_dn<kHermFS<T>>(u, eb, t);
     }
 }
 
@@ -315,7 +319,7 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             // staple: U_j^dag(y) [P(y)]_X U_j(y)
             T pa[8], t[8];
             tl.plaq(Tl::pidx(lx + 1 - d, ly + d), pa);
-            transport_dn(tl.m(lj, ry), herm_from_alg(pa), t);
+            transport_dn<kHermFS<T>>(tl.m(lj, ry), pa, t);
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 fe[a] = -tau * sgn * (px[a] - t[a]);
@@ -327,7 +331,7 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             // by C = U_1(z) U_2(z+1)
             T pa[8], t[8];
             tl.plaq(Tl::pidx(lx, ly), pa);
-            transport_dn(mul(tl.m(0, rz), tl.m(1, rz + 1)), herm_from_alg(pa), t);
+            transport_dn<kHermFS<T>>(mul(tl.m(0, rz), tl.m(1, rz + 1)), pa, t);
 #pragma unroll
             for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
             store_half(F, n2, x, 40, t, d);   // B_z
@@ -336,9 +340,9 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
         T fpi[8];
         {
             T c[8], pf[8], pb[8];
-            transport_nd(ui, herm_from_alg(php), pf);   // Phi_{+i}
+            transport_nd<kHermFS<T>>(ui, php, pf);   // Phi_{+i}
             alg_comm(ph, pf, c);                        // -i[phi, Phi_{+i}]
-            transport_dn(tl.m(li, rmi), herm_from_alg(phm), pb);   // Phi_{-i}
+            transport_dn<kHermFS<T>>(tl.m(li, rmi), phm, pb);   // Phi_{-i}
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 fe[a] = fma(inv_tau, c[a], fe[a]);

@@ -133,7 +133,7 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         const int cx1 = sx > 0 ? (cx + 1 == N ? 0 : cx + 1) : (sx < 0 ? cxm : cx);
         const int cy1 = sy > 0 ? (cy + 1 == N ? 0 : cy + 1) : (sy < 0 ? cym : cy);
         // colour rotation along eta with phi^n at the old cell: Q <- W Q W^dag
-        transport_nd(expi_alg(ph, -deta), herm_from_alg(q), q);
+        transport_nd(expi_alg(ph, -deta), q, q);
         // crossings: Q <- U^dag Q U forward, U Q U^dag backward.  Each link is
         // loaded when its transport is due (the scheduling barriers keep the
         // compiler from hoisting the loads): holding both links through the
@@ -144,14 +144,14 @@ __device__ __forceinline__ int push_particle(int N, const PartPtrs<T> &P, int64_
         __builtin_amdgcn_sched_barrier(0);
         if (sx != 0) {
             const M3<T> ux = chunk_load_link(f.U, n2, (size_t)(sx > 0 ? cx : cxm) + (size_t)N * cy, 0);
-            if (sx > 0) transport_dn(ux, herm_from_alg(q), q);
-            else transport_nd(ux, herm_from_alg(q), q);
+            if (sx > 0) transport_dn(ux, q, q);
+            else transport_nd(ux, q, q);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (sy != 0) {
             const M3<T> uy = chunk_load_link(f.U, n2, (size_t)cx1 + (size_t)N * (sy > 0 ? cy : cym), 1);
-            if (sy > 0) transport_dn(uy, herm_from_alg(q), q);
-            else transport_nd(uy, herm_from_alg(q), q);
+            if (sy > 0) transport_dn(uy, q, q);
+            else transport_nd(uy, q, q);
         }
         ox -= (T)sx;
         oy -= (T)sy;

@@ -441,14 +441,66 @@ __device__ __forceinline__ M3<T> reunitarize(const M3<T> &m) {
     return r;
 }
 
-// U^dag X U and U X U^dag of a hermitian X, returned as algebra components
+// Products with a hermitian X = x^a T^a as herm_from_alg builds it, whose
+// diagonal is real: the terms with its (zero) imaginary diagonal are left out,
+// and the others are summed in the order of mul.  Without fast-math the
+// compiler keeps an FMA by a zero, so mul would spend 18 of its 108 FMAs on
+// them.
 template <typename T>
-__device__ __forceinline__ void transport_dn(const M3<T> &U, const M3<T> &X, T *out) {
-    alg_herm_dn(U, mul(X, U), out);
+__device__ __forceinline__ M3<T> mul_herm_u(const M3<T> &X, const M3<T> &b) {   // X b
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                sr = fma(X.re[i][k], b.re[k][j], sr);
+                if (k != i) sr = fma(-X.im[i][k], b.im[k][j], sr);
+                si = fma(X.re[i][k], b.im[k][j], si);
+                if (k != i) si = fma(X.im[i][k], b.re[k][j], si);
+            }
+            r.re[i][j] = sr;
+            r.im[i][j] = si;
+        }
+    return r;
 }
 template <typename T>
-__device__ __forceinline__ void transport_nd(const M3<T> &U, const M3<T> &X, T *out) {
-    alg_herm_nd(mul(U, X), U, out);
+__device__ __forceinline__ M3<T> mul_u_herm(const M3<T> &a, const M3<T> &X) {   // a X
+    M3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                sr = fma(a.re[i][k], X.re[k][j], sr);
+                if (k != j) sr = fma(-a.im[i][k], X.im[k][j], sr);
+                if (k != j) si = fma(a.re[i][k], X.im[k][j], si);
+                si = fma(a.im[i][k], X.re[k][j], si);
+            }
+            r.re[i][j] = sr;
+            r.im[i][j] = si;
+        }
+    return r;
+}
+
+// U^dag X U and U X U^dag of the hermitian X = x^a T^a, returned as algebra
+// components.  HERM = false takes the general product (the same sums, with
+// the zero terms): in the FP32 field step the shorter product changed the
+// register allocation into more spills (batch FP32 field kernel 1 -> 8 dwords,
+// 64-event batch 0.920 -> 0.930 s), so that kernel keeps it.
+template <bool HERM = true, typename T>
+__device__ __forceinline__ void transport_dn(const M3<T> &U, const T *x, T *out) {
+    if constexpr (HERM) alg_herm_dn(U, mul_herm_u(herm_from_alg(x), U), out);
+    else alg_herm_dn(U, mul(herm_from_alg(x), U), out);
+}
+template <bool HERM = true, typename T>
+__device__ __forceinline__ void transport_nd(const M3<T> &U, const T *x, T *out) {
+    if constexpr (HERM) alg_herm_nd(mul_u_herm(U, herm_from_alg(x)), U, out);
+    else alg_herm_nd(mul(U, herm_from_alg(x)), U, out);
 }
 
 // ---- lane exchanges within a wave (DPP, no LDS traffic) -------------------
