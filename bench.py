@@ -90,6 +90,61 @@ def one_event(ev, g, n_per, steps):
     ev.run(steps)
 
 
+# profile classes of the library's kernel timing (1 is unused: the site
+# fields are fused into the field step); class 4 is the push that applies a
+# sort, once per sort period
+PROFILE_CLASSES = {0: "field_step", 2: "push", 4: "push_applying_sort"}
+
+
+def timed_events(g, torch, prec, n_per, steps, k, warmup):
+    """W untimed warm-up events, then K whole events timed together with
+    their kernel durations from HIP events on the library's stream over the
+    same region.  Returns (wall s, ms per profile class, launches per class,
+    all finite)."""
+    ev = run_event(g, torch, prec, n_per, steps)
+    for _ in range(warmup):
+        one_event(ev, g, n_per, steps)
+        ev.close()
+        ev = run_event(g, torch, prec, n_per, steps)
+    ev.close()
+    torch.cuda.synchronize()
+    evs = [run_event(g, torch, prec, n_per, steps) for _ in range(k)]
+    for e in evs:
+        e.profile(True, period=PROFILE_PERIOD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in evs:
+        one_event(e, g, n_per, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [0.0] * 5
+    cnt = [0] * 5
+    for e in evs:
+        m, c = e.profile_read()
+        for j in range(5):
+            ms[j] += m[j]
+            cnt[j] += int(c[j])
+    finite = True
+    for e in evs:
+        finite &= e.diagnostics()["nonfinite"] == 0
+    for e in evs:
+        e.close()
+    return wall, ms, cnt, bool(finite)
+
+
+def fp32_event(g, torch, n_per, steps, k):
+    """The FP32 twin of the headline event (FP32 links, fields and
+    particles, FP64 sums): one warm-up event, then K timed events, with the
+    per-kernel algorithmic and counted HBM rates."""
+    wall, ms, cnt, finite = timed_events(g, torch, 32, n_per, steps, k, 1)
+    n_part = n_per * len(SPECIES)
+    avg_us = {PROFILE_CLASSES[j]: 1e3 * ms[j] / max(cnt[j], 1) for j in PROFILE_CLASSES}
+    units = {"field_step": N * N, "push": n_part}
+    return {"events": k, "ms_per_event": 1e3 * wall / k, "site_updates_per_s": N * N * steps * k / wall,
+            "particle_steps_per_s": n_part * steps * k / wall, "kernel_avg_us": avg_us,
+            "kernels": kernel_rates(32, avg_us, units, alg_bytes(32)), "finite": finite}
+
+
 def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
     """64 MV events with N uniform on {128, 256, 384, 512} at fixed a = 10/512 fm
     and log-uniform 1e4..1e6 particles each (charm and beauty at p_T0 in
@@ -454,6 +509,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-event batched FP32 workload")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache for the batch")
+    ap.add_argument("--no-fp32-event", action="store_true",
+                    help="skip the FP32 twin of the headline event (reported beside the FP64 line)")
     ap.add_argument("--no-scan", action="store_true",
                     help="skip the paper's scans (16 events of 12 scan points at 512^2)")
     ap.add_argument("--surrogate", default="full", choices=("quick", "full", "off"),
@@ -492,49 +549,16 @@ def main():
     torch.cuda.set_device(dev)
     steps = coupled_steps(N, L_FM)
     n_per = args.particles_per_species
-    ev = run_event(g, torch, args.precision, n_per, steps)
-    for _ in range(args.warmup):
-        one_event(ev, g, n_per, steps)
-        ev.close()
-        ev = run_event(g, torch, args.precision, n_per, steps)
-    torch.cuda.synchronize()
-
-    # timed region: K whole events; kernel durations from HIP events on the
-    # library's stream over the same region
-    evs = [run_event(g, torch, args.precision, n_per, steps) for _ in range(args.steps)]
-    for e in evs:
-        e.profile(True, period=PROFILE_PERIOD)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e in evs:
-        one_event(e, g, n_per, steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = [0.0] * 5
-    cnt = [0] * 5
-    for e in evs:
-        m, c = e.profile_read()
-        for k in range(5):
-            ms[k] += m[k]
-            cnt[k] += int(c[k])
-    kappa_ok = True
-    for e in evs:
-        d = e.diagnostics()
-        kappa_ok &= d["nonfinite"] == 0
-    for e in evs:
-        e.close()
+    wall, ms, cnt, kappa_ok = timed_events(g, torch, args.precision, n_per, steps, args.steps, args.warmup)
 
     n_part = n_per * len(SPECIES)
     site_updates = N * N * steps * args.steps
     particle_steps = n_part * steps * args.steps
     ab = alg_bytes(args.precision)
-    # profile classes (1 is unused: the site fields are fused into the field
-    # step); class 4 is the push that applies a sort, once per sort period
-    names = {0: "field_step", 2: "push", 4: "push_applying_sort"}
-    avg_us = {names[k]: 1e3 * ms[k] / max(cnt[k], 1) for k in names}
+    avg_us = {PROFILE_CLASSES[k]: 1e3 * ms[k] / max(cnt[k], 1) for k in PROFILE_CLASSES}
     units = {"field_step": N * N, "push": n_part}
     dom = max((0, 2), key=lambda k: ms[k])
-    dname = names[dom]
+    dname = PROFILE_CLASSES[dom]
     achieved = ab[dname] * units[dname] / (avg_us[dname] * 1e-6) / 1e9
     tr = measured_traffic(dname, args.precision)
     traffic = None if tr is None else (tr[0] + tr[1]) / (avg_us[dname] * 1e-6) / 1e9
@@ -565,6 +589,8 @@ def main():
                      "traffic_bytes_per_launch": None if tr is None else tr[0] + tr[1],
                      "alg_bytes_per_unit": ab[dname], "units_per_launch": units[dname]},
     }
+    if args.precision == 64 and not args.no_fp32_event:
+        out["fp32_event"] = fp32_event(g, torch, n_per, steps, args.steps)
     if not args.no_batch:
         out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache)
     if not args.no_scan:
