@@ -211,18 +211,20 @@ gl_status gl_set_check_period(gl_event *ev, int32_t every);
 
 /* Graph replay inside gl_run.  With G >= 1 gl_run records each whole block of
  * G coupled steps from the event's stream into a HIP graph and launches that
- * graph; the first block instantiates it, later blocks update it in place
- * when the launches match and instantiate anew when they do not (a block
- * whose sort or series flush falls elsewhere).  Steps left over (fewer than
+ * graph.  Blocks alternate between two executable graphs: the one due waits
+ * on the host for its previous launch (two blocks back) to finish, then is
+ * updated in place when the launches match or instantiated anew when they do
+ * not (a block whose sort or series flush falls elsewhere).  Steps left over (fewer than
  * G) are launched directly, and so is every step while kernel timing
  * (gl_profile_enable) or the finite checks are on.  The launches and their
  * results are those of direct stepping, bit for bit.  Needs an event created
  * on a stream other than the null stream (GL_EINVAL otherwise).  0 (default)
- * launches every step directly and frees the graph.  A recording or launch
+ * launches every step directly and frees the graphs (after the stream is done
+ * with them).  A recording or launch
  * error returns GL_EDEVICE and leaves the event uninitialised. */
 gl_status gl_set_graph_steps(gl_event *ev, int32_t steps);
 /* Graphs launched by gl_run since the event was created, and how many of them
- * had to be instantiated (the rest updated the previous one in place). */
+ * had to be instantiated (the rest updated one of the two in place). */
 gl_status gl_graph_stats(const gl_event *ev, int64_t *launches, int64_t *instantiations);
 
 /* Iteration cap and residual tolerance of the matching Newton solve of the

@@ -171,7 +171,12 @@ struct gl_event {
     double match_tol = 1e-13;
     int32_t check_every = 0;    // finite-value checks inside gl_run every this many steps (0: off)
     int32_t graph_steps = 0;    // gl_run replays blocks of this many steps from a captured graph (0: off)
-    hipGraphExec_t gexec = nullptr;
+    // two executable graphs used in turn, each with the event recorded after
+    // its last launch: one is updated or replaced only once that launch is
+    // done, while the other's may still run
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipEvent_t gdone[2] = {nullptr, nullptr};
+    int gslot = 0;
     int64_t graph_launches = 0, graph_instantiations = 0;
 
     // kernel timing: pairs of events per launch, grouped by kernel class
@@ -463,12 +468,25 @@ gl_status one_step(gl_event *ev, bool has_particles) {
     return do_push(ev, true);
 }
 
+// the executable graphs of gl_run, after the stream has finished with them
+void free_graphs(gl_event *ev) {
+    if (!ev->gexec[0] && !ev->gexec[1]) return;
+    (void)hipStreamSynchronize(ev->stream);
+    for (int k = 0; k < 2; k++) {
+        if (ev->gexec[k]) (void)hipGraphExecDestroy(ev->gexec[k]);
+        ev->gexec[k] = nullptr;
+    }
+}
+
 // count steps recorded from the stream into a graph with the same launch
-// code and replayed: the graph of the first block is instantiated, later
-// blocks update it in place (same topology, new step-dependent arguments)
-// or instantiate anew.  The host state advances while recording, so a
-// failure here leaves the event uninitialised rather than out of step.
+// code and replayed.  Blocks alternate between two executable graphs; the
+// one due is first waited for (its previous launch, two blocks back), then
+// updated in place (same topology, new step-dependent arguments) or
+// instantiated anew.  The host state advances while recording, so a failure
+// here leaves the event uninitialised rather than out of step.
 gl_status graph_block(gl_event *ev, int32_t count, bool has_particles) {
+    const int slot = ev->gslot;
+    if (!ev->gdone[slot]) HIP_TRY(hipEventCreateWithFlags(&ev->gdone[slot], hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(ev->stream, hipStreamCaptureModeRelaxed));
     gl_status s = GL_OK;
     for (int32_t k = 0; k < count && !s; k++) s = one_step(ev, has_particles);
@@ -480,27 +498,33 @@ gl_status graph_block(gl_event *ev, int32_t count, bool has_particles) {
         return s ? s : fail(GL_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     }
     bool updated = false;
-    if (ev->gexec) {
-        hipGraphNode_t bad = nullptr;
-        hipGraphExecUpdateResult r = hipGraphExecUpdateError;
-        updated = hipGraphExecUpdate(ev->gexec, g, &bad, &r) == hipSuccess && r == hipGraphExecUpdateSuccess;
-        if (!updated) {
-            (void)hipGetLastError();   // a refused update is expected here; keep it out of later launch checks
-            (void)hipGraphExecDestroy(ev->gexec);
-            ev->gexec = nullptr;
+    hipError_t le = hipSuccess;
+    hipGraphExec_t &x = ev->gexec[slot];
+    if (x) {
+        le = hipEventSynchronize(ev->gdone[slot]);   // its previous launch is done
+        if (le == hipSuccess) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult r = hipGraphExecUpdateError;
+            updated = hipGraphExecUpdate(x, g, &bad, &r) == hipSuccess && r == hipGraphExecUpdateSuccess;
+            if (!updated) {
+                (void)hipGetLastError();   // a refused update is expected here; keep it out of later launch checks
+                (void)hipGraphExecDestroy(x);
+                x = nullptr;
+            }
         }
     }
-    hipError_t le = hipSuccess;
-    if (!updated) {
-        le = hipGraphInstantiate(&ev->gexec, g, nullptr, nullptr, 0);
+    if (le == hipSuccess && !updated) {
+        le = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
         if (le == hipSuccess) ev->graph_instantiations++;
     }
-    if (le == hipSuccess) le = hipGraphLaunch(ev->gexec, ev->stream);
+    if (le == hipSuccess) le = hipGraphLaunch(x, ev->stream);
+    if (le == hipSuccess) le = hipEventRecord(ev->gdone[slot], ev->stream);
     (void)hipGraphDestroy(g);
     if (le != hipSuccess) {
         ev->ready = false;
         return fail(GL_EDEVICE, std::string("graph replay: ") + hipGetErrorString(le));
     }
+    ev->gslot = slot ^ 1;
     ev->graph_launches++;
     return GL_OK;
 }
@@ -853,7 +877,9 @@ gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t b
 
 void gl_event_destroy(gl_event *ev) {
     if (!ev) return;
-    if (ev->gexec) (void)hipGraphExecDestroy(ev->gexec);
+    free_graphs(ev);
+    for (hipEvent_t e : ev->gdone)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev->ev_pool) (void)hipEventDestroy(e);
     delete ev;
 }
@@ -1386,10 +1412,7 @@ gl_status gl_set_graph_steps(gl_event *ev, int32_t steps) {
     if (steps < 0) return fail(GL_EINVAL, "graph_steps must be >= 0");
     if (steps > 0 && !ev->stream) return fail(GL_EINVAL, "graph replay needs a stream other than the null stream");
     ev->graph_steps = steps;
-    if (steps == 0 && ev->gexec) {
-        (void)hipGraphExecDestroy(ev->gexec);
-        ev->gexec = nullptr;
-    }
+    if (steps == 0) free_graphs(ev);
     return GL_OK;
 }
 
