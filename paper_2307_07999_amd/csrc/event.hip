@@ -1892,7 +1892,10 @@ gl_status batch_step(gl_batch *b) {
 
 gl_status batch_step_any(gl_batch *b) { return b->fp64 ? batch_step<double>(b) : batch_step<float>(b); }
 
+// the batch's graphs, after the stream has finished with them (a launch may
+// still be in flight when the batch is reconfigured or destroyed)
 void batch_drop_graphs(gl_batch *b) {
+    if (!b->graphs.empty()) (void)hipStreamSynchronize(b->stream);
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
     for (auto &g : b->graph_defs) (void)hipGraphDestroy(g.second);
     b->graphs.clear();
