@@ -6,6 +6,7 @@ library must be built (``python paper_2307_07999_amd/build.py``); loading
 fails loudly otherwise.
 """
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -151,6 +152,14 @@ def _i(a):
     return a.ctypes.data_as(_I32)
 
 
+def _keep_until_done(torch, ws, stream, device):
+    """A workspace allocated on the current stream but used on another one
+    is not handed out again before that stream's work queued at its release
+    has finished."""
+    if stream.cuda_stream != torch.cuda.current_stream(device).cuda_stream:
+        ws.record_stream(stream)
+
+
 def lattice_spacing(N, L_fm):
     a_fm = L_fm / N
     return a_fm, a_fm / HBARC_GEV_FM
@@ -231,6 +240,7 @@ class Event:
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _keep_until_done(torch, self._ws, self.stream, self.device)
         h = _VP()
         check(lib().gl_event_create(ctypes.byref(self.desc), _VP(self._ws_ptr), self.nbytes,
                                     _VP(self.stream.cuda_stream), ctypes.byref(h)))
@@ -241,9 +251,13 @@ class Event:
         self.species = []
 
     def close(self):
+        held = getattr(self, "_held_by", None)
+        if held is not None and held() is not None and getattr(held(), "_h", None):
+            raise GlasmaError(GL_ESTATE, "the event is held by a batch: close the batch first")
         if getattr(self, "_h", None):
             lib().gl_event_destroy(self._h)
             self._h = None
+            self._ws = None
 
     def __del__(self):
         try:
@@ -491,15 +505,19 @@ class Batch:
         # a stream of its own (default priority): the legacy default stream
         # cannot be captured into a graph
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        _keep_until_done(torch, self._ws, self.stream, dev)
         h = _VP()
         check(lib().gl_batch_create(arr, len(self.events), _VP(ptr), nbytes.value,
                                     _VP(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
+        for e in self.events:
+            e._held_by = weakref.ref(self)
 
     def close(self):
         if getattr(self, "_h", None):
             lib().gl_batch_destroy(self._h)
             self._h = None
+            self._ws = None
 
     def __del__(self):
         try:
@@ -591,6 +609,7 @@ class MLP:
         self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
         ptr = (self._ws.data_ptr() + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _keep_until_done(torch, self._ws, self.stream, self.device)
         h = _VP()
         _mlp_check(L.gl_mlp_create(ctypes.byref(self.desc), max_samples, _VP(ptr), nbytes.value,
                                    _VP(self.stream.cuda_stream), seed, ctypes.byref(h)))
@@ -604,6 +623,7 @@ class MLP:
         if getattr(self, "_h", None):
             lib().gl_mlp_destroy(self._h)
             self._h = None
+            self._ws = None
 
     def __del__(self):
         try:

@@ -225,6 +225,9 @@ def test_batch_holds_its_events(gl):
     assert e.value.status == gl.GL_ESTATE
     assert ev.series().shape[0] == 3          # the getters work
     ev.diagnostics()
+    with pytest.raises(gl.GlasmaError) as e:
+        ev.close()                  # the batch still uses its memory
+    assert e.value.status == gl.GL_ESTATE
     b.close()
     ev.run(2)
     assert ev.info()[2] == n + 2
