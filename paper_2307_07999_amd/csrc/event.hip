@@ -878,6 +878,8 @@ gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t b
 void gl_event_destroy(gl_event *ev) {
     if (!ev) return;
     free_graphs(ev);
+    // timing events may still be pending on the stream
+    if (!ev->ev_pool.empty()) (void)hipStreamSynchronize(ev->stream);
     for (hipEvent_t e : ev->gdone)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev->ev_pool) (void)hipEventDestroy(e);
