@@ -124,6 +124,11 @@ gl_status gl_max_particles(int32_t precision, int64_t *max_particles);
 /* Create an event on a caller-owned workspace and stream (hipStream_t). */
 gl_status gl_event_create(const gl_lattice_desc *desc, void *workspace, size_t bytes,
                           void *stream, gl_event **out);
+/* Free the event's host state (and its graphs and timing events, after the
+ * stream is done with them).  Work already queued on the stream may still
+ * read and write the workspace: the caller frees the workspace only after
+ * that work has completed (synchronise the stream, or order the release after
+ * it).  An event held by a batch is destroyed only after the batch. */
 void gl_event_destroy(gl_event *ev);
 
 /* MV sources -> Glasma (Sec. 1): charges drawn on the device from Philox4x32-10
