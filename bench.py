@@ -127,22 +127,55 @@ def timed_events(g, torch, prec, n_per, steps, k, warmup):
     finite = True
     for e in evs:
         finite &= e.diagnostics()["nonfinite"] == 0
+    obs = observables(evs[-1])
     for e in evs:
         e.close()
-    return wall, ms, cnt, bool(finite)
+    return wall, ms, cnt, bool(finite), obs
 
 
-def fp32_event(g, torch, n_per, steps, k):
+def observables(ev):
+    """Per species of an event, the curves the paper plots (library rows):
+    <dp_T^2> or <dp_y^2>, <dp_z^2>, and kappa_T, kappa_L (heavy quarks) or
+    qhat_y, qhat_z (jets)."""
+    out = []
+    for s, (_, _, kind) in enumerate(SPECIES):
+        b = ev.broadening(s)
+        if kind == 0:
+            k = ev.kappa(s)
+            out.append({"dpT2": b[:, 1] + b[:, 2], "dpz2": b[:, 3], "rate_T": k[:, 2], "rate_L": k[:, 3]})
+        else:
+            q = ev.qhat(s)
+            out.append({"dpy2": b[:, 2], "dpz2": b[:, 3], "rate_y": q[:, 1], "rate_z": q[:, 2]})
+    return out
+
+
+def observable_errors(got, want):
+    """Largest over species of max |got - want| / max |want| per curve."""
+    import numpy as np
+    err = {}
+    for g_, w_ in zip(got, want):
+        for key in w_:
+            a, b = np.asarray(g_[key]), np.asarray(w_[key])
+            n = min(len(a), len(b))
+            scale = np.abs(b[:n]).max() if n else 0.0
+            e = float(np.abs(a[:n] - b[:n]).max() / scale) if n and scale > 0 else 0.0
+            err[key] = max(err.get(key, 0.0), e)
+    return err
+
+
+def fp32_event(g, torch, n_per, steps, k, obs64):
     """The FP32 twin of the headline event (FP32 links, fields and
-    particles, FP64 sums): one warm-up event, then K timed events, with the
-    per-kernel algorithmic and counted HBM rates."""
-    wall, ms, cnt, finite = timed_events(g, torch, 32, n_per, steps, k, 1)
+    particles, FP64 sums; the same charges and particles): one warm-up event,
+    then K timed events, with the per-kernel algorithmic and counted HBM rates
+    and the error of its observables against the FP64 event's."""
+    wall, ms, cnt, finite, obs = timed_events(g, torch, 32, n_per, steps, k, 1)
     n_part = n_per * len(SPECIES)
     avg_us = {PROFILE_CLASSES[j]: 1e3 * ms[j] / max(cnt[j], 1) for j in PROFILE_CLASSES}
     units = {"field_step": N * N, "push": n_part}
     return {"events": k, "ms_per_event": 1e3 * wall / k, "site_updates_per_s": N * N * steps * k / wall,
             "particle_steps_per_s": n_part * steps * k / wall, "kernel_avg_us": avg_us,
-            "kernels": kernel_rates(32, avg_us, units, alg_bytes(32)), "finite": finite}
+            "kernels": kernel_rates(32, avg_us, units, alg_bytes(32)), "finite": finite,
+            "observable_rel_err_vs_fp64": observable_errors(obs, obs64)}
 
 
 def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
@@ -549,7 +582,7 @@ def main():
     torch.cuda.set_device(dev)
     steps = coupled_steps(N, L_FM)
     n_per = args.particles_per_species
-    wall, ms, cnt, kappa_ok = timed_events(g, torch, args.precision, n_per, steps, args.steps, args.warmup)
+    wall, ms, cnt, kappa_ok, obs = timed_events(g, torch, args.precision, n_per, steps, args.steps, args.warmup)
 
     n_part = n_per * len(SPECIES)
     site_updates = N * N * steps * args.steps
@@ -590,7 +623,7 @@ def main():
                      "alg_bytes_per_unit": ab[dname], "units_per_launch": units[dname]},
     }
     if args.precision == 64 and not args.no_fp32_event:
-        out["fp32_event"] = fp32_event(g, torch, n_per, steps, args.steps)
+        out["fp32_event"] = fp32_event(g, torch, n_per, steps, args.steps, obs)
     if not args.no_batch:
         out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache)
     if not args.no_scan:
