@@ -63,3 +63,17 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_observable_errors_are_per_curve_maxima_over_species():
+    """The FP32 twin's deviation: per curve, max |got - want| / max |want|,
+    the largest over species, over the rows both curves have."""
+    import numpy as np
+    want = [{"a": np.array([1.0, 2.0, 4.0]), "b": np.array([0.0, -2.0])},
+            {"a": np.array([10.0, 10.0])}]
+    got = [{"a": np.array([1.0, 2.1, 4.0, 99.0]), "b": np.array([0.0, -2.0])},
+           {"a": np.array([10.0, 9.0])}]
+    err = bench.observable_errors(got, want)
+    assert err["a"] == pytest.approx(max(0.1 / 4.0, 1.0 / 10.0))
+    assert err["b"] == 0.0
+    assert bench.observable_errors([{"c": np.zeros(3)}], [{"c": np.zeros(3)}]) == {"c": 0.0}
