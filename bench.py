@@ -128,9 +128,13 @@ def timed_events(g, torch, prec, n_per, steps, k, warmup):
     for e in evs:
         finite &= e.diagnostics()["nonfinite"] == 0
     obs = observables(evs[-1])
+    # the timed events share every seed: their curves must agree bit for bit
+    import numpy as np
+    first = observables(evs[0])
+    repeat = all(np.array_equal(a[k], b[k]) for a, b in zip(first, obs) for k in a)
     for e in evs:
         e.close()
-    return wall, ms, cnt, bool(finite), obs
+    return wall, ms, cnt, bool(finite), obs, bool(repeat)
 
 
 def observables(ev):
@@ -168,13 +172,14 @@ def fp32_event(g, torch, n_per, steps, k, obs64):
     particles, FP64 sums; the same charges and particles): one warm-up event,
     then K timed events, with the per-kernel algorithmic and counted HBM rates
     and the error of its observables against the FP64 event's."""
-    wall, ms, cnt, finite, obs = timed_events(g, torch, 32, n_per, steps, k, 1)
+    wall, ms, cnt, finite, obs, repeat = timed_events(g, torch, 32, n_per, steps, k, 1)
     n_part = n_per * len(SPECIES)
     avg_us = {PROFILE_CLASSES[j]: 1e3 * ms[j] / max(cnt[j], 1) for j in PROFILE_CLASSES}
     units = {"field_step": N * N, "push": n_part}
     return {"events": k, "ms_per_event": 1e3 * wall / k, "site_updates_per_s": N * N * steps * k / wall,
             "particle_steps_per_s": n_part * steps * k / wall, "kernel_avg_us": avg_us,
             "kernels": kernel_rates(32, avg_us, units, alg_bytes(32)), "finite": finite,
+            "bitwise_repeatable": repeat,
             "observable_rel_err_vs_fp64": observable_errors(obs, obs64)}
 
 
@@ -582,7 +587,8 @@ def main():
     torch.cuda.set_device(dev)
     steps = coupled_steps(N, L_FM)
     n_per = args.particles_per_species
-    wall, ms, cnt, kappa_ok, obs = timed_events(g, torch, args.precision, n_per, steps, args.steps, args.warmup)
+    wall, ms, cnt, kappa_ok, obs, repeat = timed_events(g, torch, args.precision, n_per, steps, args.steps,
+                                                        args.warmup)
 
     n_part = n_per * len(SPECIES)
     site_updates = N * N * steps * args.steps
@@ -616,6 +622,7 @@ def main():
         "particle_steps_per_s": particle_steps / wall,
         "kernel_avg_us": avg_us,
         "finite": bool(kappa_ok),
+        "bitwise_repeatable": repeat,
         "kernels": kernel_rates(args.precision, avg_us, units, ab),
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
