@@ -117,3 +117,55 @@ def test_push_sampled_paper_scale(gl, orc):
     for k in ("off", "eta", "p", "Q"):
         assert np.abs(getattr(A, k) - getattr(P, k)).max() < 1e-12, k
     assert ser[:, 3].sum() == 3000
+
+
+def _pick(d, idx):
+    return {k: (v[:, idx] if v.ndim == 2 else v[idx]) for k, v in d.items()}
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_push_at_the_particle_capacity(gl, orc, prec):
+    """The largest ensemble an event takes, whose record planes end just
+    below 2^31 bytes (the limit of the 32-bit buffer offsets): one coupled
+    step on a 64^2 lattice.  FP64: 3000 particles, the last-created ones among
+    them (the highest slots before the sort), recomputed by the oracle to
+    1e-12.  FP32: every particle formed and counted, charges on their Casimir
+    shells, the state finite."""
+    n_lat, l_lat = 64, 8.0
+    cap = gl.max_particles(prec)
+    n = cap // 256 * 256
+    U, E, phi, pi = si.random_state(514, n_lat, link_kind="near", eps=0.3, e_scale=0.1,
+                                    phi_scale=0.1, pi_scale=0.1)
+    s = orc.State(n_lat)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
+    ev = gl.Event(n_lat, l_lat, 0.125, precision=prec, max_steps=48, max_particles=cap)
+    ev.set_state(*H.state_oracle_to_soa(s), 40)
+    ev.add_species(1.27, 2.0, gl.KIND_HEAVY_QUARK, n, 1234)
+    mass, nform = ev.species_info(0)[1], ev.species_info(0)[0]
+    print("capacity %d, particles %d (FP%d)" % (cap, n, prec))
+    if prec == 64:
+        g = np.random.default_rng(6)
+        pick = np.unique(np.concatenate([np.arange(n - 100, n), g.choice(n, 2900, replace=False)]))
+        before = _pick(ev.get_particles(), pick)
+    ev.evolve_fields(1)
+    ev.push_particles()
+    ser = ev.series()
+    assert ser[-1, 0, 3] == n                     # every particle pushed and counted
+    d = ev.diagnostics()
+    assert d["nonfinite"] == 0
+    assert d["casimir2_dev"] < (1e-12 if prec == 64 else 1e-4)
+    assert d["casimir3_dev"] < (1e-12 if prec == 64 else 1e-4)
+    if prec == 64:
+        after = _pick(ev.get_particles(), pick)
+        P = H.particles_gpu_to_oracle(orc, before)
+        cells = np.unique(P.cell[:, 0] + n_lat * P.cell[:, 1]).astype(np.int32)
+        _, _, _, _, Fs = orc.field_step_sites(s, 0.125, cells)
+        Ffull = np.zeros((n_lat * n_lat, 6, 8))
+        Ffull[cells] = Fs
+        so = orc.particle_step(n_lat, 40, 0.125, s.U, s.phi, Ffull, P, [mass], [nform])
+        A = H.particles_gpu_to_oracle(orc, after)
+        assert np.array_equal(A.cell, P.cell)
+        for k in ("off", "eta", "p", "Q"):
+            assert np.abs(getattr(A, k) - getattr(P, k)).max() < 1e-12, k
+        assert so[:, 3].sum() == len(pick)
+    ev.close()
