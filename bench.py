@@ -245,7 +245,9 @@ def scan_bench(n_events=16, n_per=N_PER, precision=64):
     lightlike correlators, over n_events MV events; jackknife errors over the
     events.  Reports the wall time and, per point, the peak of the total
     coefficient (kappa_T + kappa_L or qhat_y + qhat_z) with its error and
-    time after formation, and the anisotropy 0.3 fm after formation."""
+    time after formation, the anisotropy 0.3 fm after formation, the lowest
+    longitudinal rate after the peak (kappa_L or qhat_z, with its time) and
+    the transverse rate at tau_max."""
     from paper_2307_07999_amd import scan
     res = scan.run_scan(n_events=n_events, N=N, L_fm=L_FM, sheets=SHEETS, g2mu=G2MU, m_ir=M_IR, n_per=n_per,
                         precision=precision)
@@ -256,7 +258,10 @@ def scan_bench(n_events=16, n_per=N_PER, precision=64):
         return {"peak_total_GeV2_per_fm": [round(pk["total"], 3), round(pk["err"], 3)],
                 "peak_dtau_fm": round(pk["dtau_fm"], 4),
                 "ratio_B_over_A_at_0.3fm": None if v["ratio_at_0.3fm"] is None else
-                [round(x, 4) for x in v["ratio_at_0.3fm"]]}
+                [round(x, 4) for x in v["ratio_at_0.3fm"]],
+                "min_rate_B_after_peak_GeV2_per_fm": [round(x, 3) for x in v["late"]["rate_B_min"]],
+                "min_rate_B_dtau_fm": round(v["late"]["rate_B_min_dtau_fm"], 4),
+                "rate_A_end_GeV2_per_fm": [round(x, 3) for x in v["late"]["rate_A_end"]]}
     return {"events": n_events, "particles_per_point": n_per, "points": len(res["points"]),
             "precision": precision, "coupled_steps": res["coupled_steps"], "wall_s": res["wall_s"],
             "s_per_event": res["s_per_event"], "particle_steps_per_s": res["particle_steps_per_s"],

@@ -4,7 +4,9 @@ quarks" and "Jets", Figs. 1 and 2).
 * Heavy quarks (Fig. 1): beauty quarks with initial transverse momentum
   p_T(tau_form) in {0, 2, 5, 10} GeV, formed at tau_form = 1/(2 m_T):
   <dp_T^2>, <dp_L^2>, their ratio and kappa_T, kappa_L against
-  delta tau = tau - tau_form, beside static quarks (Eq. (4)).
+  delta tau = tau - tau_form, beside static quarks (Eq. (4)) started at
+  the formation step of the beauty quarks at rest, so that the static and
+  dynamical curves share the delta tau axis.
 * Jets (Fig. 2): quarks formed at tau_form = 0 moving along x with
   p_x(tau_form) in {1, 2, 5, 10} GeV for several masses, labelled by p_x / m:
   <dp_y^2>, <dp_z^2>, their ratio and qhat_y, qhat_z, beside lightlike jets
@@ -63,8 +65,9 @@ def _correlator_series(rows, a_fm, n_rows):
 def run_scan(n_events=16, N=512, L_fm=10.0, sheets=50, g2mu=2.767, m_ir=0.2, n_per=100000, precision=64,
              seed=2307079995, tau_max=1.0, keep_events=False):
     """Run the scan: n_events MV events, each with every scan point as a
-    species of n_per particles and both correlators from tau = 0, coupled to
-    tau_max.  Event e draws its charges and particles with seed + e.
+    species of n_per particles, the lightlike correlator from tau = 0 (the
+    jets' formation) and the static one from the formation step of the
+    beauty quarks at rest, coupled to tau_max.  Event e draws its charges and particles with seed + e.
     Returns a dict with the per-event raw series, the statistics of every
     point and correlator (gl_scan_statistics rows) and the wall time."""
     import torch
@@ -80,7 +83,11 @@ def run_scan(n_events=16, N=512, L_fm=10.0, sheets=50, g2mu=2.767, m_ir=0.2, n_p
         ev.init_glasma(g2mu, m_ir, sheets, seed + e)
         for (_, kind, m, p0, tf) in pts:
             ev.add_species(m, p0, kind, n_per, seed + e, tau_form_fm=tf)
-        ev.static_start(0.0)
+        # Eq. (4) integrates from the static quarks' start; the figure sets
+        # it on the delta tau axis of the dynamical quarks, so it starts on
+        # the formation step of the beauty quarks with p_T0 = 0 (point 0)
+        n_static = ev.species_info(0)[0]
+        ev.static_start(n_static * 0.125 * a_fm)
         ev.lightlike_start(0.0)
         ev.run(steps)
         ser = ev.series()
@@ -98,7 +105,8 @@ def run_scan(n_events=16, N=512, L_fm=10.0, sheets=50, g2mu=2.767, m_ir=0.2, n_p
            "particles_per_point": n_per, "precision": precision, "coupled_steps": steps,
            "points": [p[0] for p in pts], "wall_s": wall, "s_per_event": wall / n_events,
            "particle_steps_per_s": n_events * n_per * len(pts) * steps / wall,
-           "stats": [], "static": None, "lightlike": None}
+           "stats": [], "static": None, "lightlike": None,
+           "static_start_fm": n_static * dt_fm}
     for k, (label, kind, m, p0, tf) in enumerate(pts):
         out["stats"].append(G.scan_statistics(series[:, :, k, :], kind, dt_fm, a_fm))
     out["nform"] = nforms
@@ -128,23 +136,41 @@ def _at(rows, tau, col):
     return [float(rows[i, col]), float(rows[i, col + 1])]
 
 
+def _late(rows, tau0):
+    """After the peak of the total rate: the lowest longitudinal rate
+    d<B>/dtau (kappa_L or qhat_z; value, error, delta tau after tau0) and
+    both rates at the last row (value, error)."""
+    if len(rows) == 0:
+        return None
+    i = int(np.argmax(rows[:, 12]))
+    j = i + int(np.argmin(rows[i:, 10]))
+    return {"rate_B_min": [float(rows[j, 10]), float(rows[j, 11])], "rate_B_min_dtau_fm": float(rows[j, 1] - tau0),
+            "rate_A_end": [float(rows[-1, 8]), float(rows[-1, 9])],
+            "rate_B_end": [float(rows[-1, 10]), float(rows[-1, 11])]}
+
+
+def _curve(rows, tau0):
+    return {"peak": _peak(rows, tau0), "ratio_at_0.3fm": _at(rows, tau0 + 0.3, 6),
+            "A_end": _at(rows, rows[-1, 0], 2) if len(rows) else None,
+            "B_end": _at(rows, rows[-1, 0], 4) if len(rows) else None,
+            "late": _late(rows, tau0)}
+
+
 def summary(res):
     """Per scan point: the peak of the total rate (value, jackknife error,
     delta tau after the start), the anisotropy <B>/<A> at delta tau = 0.3 fm
-    (the end of the Glasma stage the paper names) and the broadenings at the
-    last step; the same for the two correlators."""
+    (the end of the Glasma stage the paper names), the broadenings at the
+    last step and the late rates (the lowest longitudinal rate after the
+    peak, both rates at the last step: the paper reports kappa_T and qhat_y
+    levelling off at zero while kappa_L and qhat_z turn negative); the same
+    for the two correlators, timed from their own starts."""
     pts = scan_points()
     out = {}
     for k, (label, kind, m, p0, tf) in enumerate(pts):
-        rows = res["stats"][k]
         # delta tau counts from the formation time itself (the particles
         # start at the first step at or after it)
         tau0 = tf if tf >= 0 else G.HBARC_GEV_FM / (2.0 * math.hypot(m, p0))
-        out[label] = {"peak": _peak(rows, tau0), "ratio_at_0.3fm": _at(rows, tau0 + 0.3, 6),
-                      "A_end": _at(rows, rows[-1, 0], 2) if len(rows) else None,
-                      "B_end": _at(rows, rows[-1, 0], 4) if len(rows) else None}
-    for name in ("static", "lightlike"):
-        rows = res[name]
-        out[name] = {"peak": _peak(rows, 0.0), "ratio_at_0.3fm": _at(rows, 0.3, 6),
-                     "A_end": _at(rows, rows[-1, 0], 2), "B_end": _at(rows, rows[-1, 0], 4)}
+        out[label] = _curve(res["stats"][k], tau0)
+    for name, tau0 in (("static", res["static_start_fm"]), ("lightlike", 0.0)):
+        out[name] = _curve(res[name], tau0)
     return out

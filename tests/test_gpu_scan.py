@@ -36,11 +36,13 @@ def test_scan_event_equals_a_single_event_run(scan):
     ev.init_glasma(CFG["g2mu"], CFG["m_ir"], CFG["sheets"], CFG["seed"] + e)
     for (_, kind, m, p0, tf) in S.scan_points():
         ev.add_species(m, p0, kind, CFG["n_per"], CFG["seed"] + e, tau_form_fm=tf)
-    ev.static_start(0.0)
+    a_fm = CFG["L_fm"] / CFG["N"]
+    # static quarks start on the formation step of the beauty quarks at rest
+    assert res["static_start_fm"] == res["nform"][0] * 0.125 * a_fm
+    ev.static_start(res["static_start_fm"])
     ev.lightlike_start(0.0)
     ev.run(steps)
     assert np.array_equal(ev.series()[:, :12, :], res["series"][e])
-    a_fm = CFG["L_fm"] / CFG["N"]
     assert np.array_equal(S._correlator_series(ev.static_broadening(), a_fm, steps), res["static_series"][e])
     assert np.array_equal(S._correlator_series(ev.lightlike_broadening(), a_fm, steps), res["lightlike_series"][e])
 
@@ -49,7 +51,9 @@ def test_scan_event_matches_oracle(scan, orc):
     """Event 0: the oracle runs the same MV draw and the twelve species
     (beauty quarks at four p_T, jets at four p_x for two masses) to the same
     time; series to 1e-9 relative per species (chaotic growth over the run)
-    and both correlators, which the oracle computes from its own fields."""
+    and both correlators, which the oracle computes from its own fields (the
+    static one from the beauty quarks' formation step, the lightlike one from
+    the first step)."""
     S, res = scan
     N, L = CFG["N"], CFG["L_fm"]
     a_fm = L / N
@@ -69,7 +73,7 @@ def test_scan_event_matches_oracle(scan, orc):
         assert H.rel_err(got[:, k, :3], ser_o[:, k, :3]) < 1e-9, k
     s, rc, _ = orc.init_glasma(N, sigma, m2, CFG["sheets"], CFG["seed"], 0.125)
     s2 = s.copy()
-    stat = orc.static_series(s, 0.125, steps, n0=1)
+    stat = orc.static_series(s, 0.125, steps, n0=res["nform"][0])
     ll = orc.lightlike_series(s2, 0.125, steps, n0=1)
     assert H.rel_err(res["static_series"][0], stat) < 1e-9
     assert H.rel_err(res["lightlike_series"][0], ll) < 1e-9
