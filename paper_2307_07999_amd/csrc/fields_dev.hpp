@@ -11,6 +11,12 @@ namespace gl {
 // the field step's transports use the hermitian-aware products in FP64 only
 template <typename T>
 constexpr bool kHermFS = sizeof(T) == 8;
+// FP64: E_i(x) and the pi half are loaded before the scalar couplings and
+// arrive while those are computed (the step waited on them: 79.6 -> 74.5 us
+// at 512^2).  FP32 loads them where they are used: held over the couplings
+// its registers would spill (38.4 -> 41.9 us).
+template <typename T>
+constexpr bool kEarlyEP = sizeof(T) == 8;
 
 // values slot..slot+7 of the site-field record of site x
 template <typename T>
@@ -189,17 +195,18 @@ __device__ __forceinline__ void stage_tile(LinkTile<T, SX, SY> &t, int N, const 
     }
 }
 
-// E_i^{n+1/2}(x) and U_i^{n+1}(x), i = d + 1, from the force fe and U_i(x) =
-// u; with F, also this site's half of the electric site field (eb) and the
-// half transported to x+i (t), which the caller stores or exchanges
+// E_i^{n+1/2}(x) and U_i^{n+1}(x), i = d + 1, from E_i^{n-1/2}(x) = ein, the
+// force fe and U_i(x) = u; with F, also this site's half of the electric
+// site field (eb) and the half transported to x+i (t), which the caller
+// stores or exchanges
 template <typename T, bool ST>
-__device__ __forceinline__ void update_link(const T *__restrict__ Ein, T *__restrict__ Eout, const M3<T> &u,
+__device__ __forceinline__ void update_link(const T *ein, T *__restrict__ Eout, const M3<T> &u,
                                             T *__restrict__ Uout, size_t n2, size_t x, int d, const T *fe, T dtau,
                                             T s, int reunit, bool site_fields, T inv_tau, T *eb, T *t) {
     T e[8];
-    chunk_load_n_l<8, stream_policy(ST)>(Ein, n2, x, 8 * d, e);   // E and pi are read once per step
 #pragma unroll
     for (int a = 0; a < 8; a++) {
+        e[a] = ein[a];
         eb[a] = e[a];
         e[a] += dtau * fe[a];
     }
@@ -336,6 +343,12 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
             store_half(F, n2, x, 40, t, d);   // B_z
         }
+        // E_i(x) and this lane's half of pi, read once per step (streamed)
+        T ein[8], pv[4];
+        if constexpr (kEarlyEP<T>) {
+            chunk_load_n_l<8, stream_policy(ST)>(in.E, n2, x, 8 * d, ein);
+            chunk_load_n_l<4, stream_policy(ST)>(in.pi, n2, x, 4 * d, pv);
+        }
         // scalar couplings: Phi_{+i} in the E_i force, all four in the pi force
         T fpi[8];
         {
@@ -353,11 +366,12 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             // B_y = D_1 phi / tau (lane 0, slot 32), B_x = -D_2 phi / tau (lane 1, slot 24)
             if (F) store_rec(F, n2, x, 32 - 8 * d, pf);
         }
-        update_link<T, ST>(in.E, out.E, ui, out.U, n2, x, d, fe, dtau, dtau / tau_h, reunit, F != nullptr, inv_tau, eb,
+        if constexpr (!kEarlyEP<T>) chunk_load_n_l<8, stream_policy(ST)>(in.E, n2, x, 8 * d, ein);
+        update_link<T, ST>(ein, out.E, ui, out.U, n2, x, d, fe, dtau, dtau / tau_h, reunit, F != nullptr, inv_tau, eb,
                            tr);
         // pi, phi and E_z: lane d takes colour components 4d..4d+3
-        T pv[4], pn[4], phn[4], ez[4];
-        chunk_load_n_l<4, stream_policy(ST)>(in.pi, n2, x, 4 * d, pv);
+        T pn[4], phn[4], ez[4];
+        if constexpr (!kEarlyEP<T>) chunk_load_n_l<4, stream_policy(ST)>(in.pi, n2, x, 4 * d, pv);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             pn[k] = pv[k] + dtau * (d0 ? fpi[k] : fpi[4 + k]);
