@@ -343,10 +343,13 @@ gl_status gl_static_broadening(gl_event *ev, double *out, int32_t cap, int32_t *
 gl_status gl_lightlike_start(gl_event *ev, double tau_start_fm);
 gl_status gl_lightlike_broadening(gl_event *ev, double *out, int32_t cap, int32_t *n_rows);
 
-/* Kernel timing with HIP events recorded on the event's stream around the
- * launches of the hot-path kernels: period 0 switches it off, period p >= 1
+/* Kernel timing with HIP events: period 0 switches it off, period p >= 1
  * times every p-th launch of each kernel class (a sample, so that the event
- * records barely perturb the run).  gl_profile_read synchronises
+ * records barely perturb the run).  The single-kernel classes (0, 2, 4) take
+ * the events with the launch itself (hipExtLaunchKernelGGL), at the kernel's
+ * start and end, which times the kernel alone; classes 1 and 3 record them
+ * on the event's stream around the launch, which also counts the dispatch
+ * gap before it.  gl_profile_read synchronises
  * the stream and returns, per kernel class (0 field step, which also writes
  * the site fields when the event has particles or correlators, 1 static
  * quark and lightlike jet accumulation, 2 particle push, 3 series

@@ -255,7 +255,9 @@ gl_status check_free(gl_event *ev) {
 // start/stop marks around one launch of kernel class k (no-ops when disabled
 // and for the launches between samples)
 constexpr size_t kNoMark = ~(size_t)0;
-gl_status prof_begin(gl_event *ev, int k, size_t *idx) {
+// a pair of pooled events for a sampled launch of class k (kNoMark: this
+// launch is not sampled)
+gl_status prof_take(gl_event *ev, int k, size_t *idx) {
     *idx = kNoMark;
     if (ev->prof <= 0 || (ev->prof_count[k]++ % ev->prof) != 0) return GL_OK;
     while (ev->ev_pool.size() < ev->ev_used + 2) {
@@ -266,7 +268,26 @@ gl_status prof_begin(gl_event *ev, int k, size_t *idx) {
     *idx = ev->ev_used;
     ev->ev_used += 2;
     ev->prof_marks.push_back({k, *idx});
+    return GL_OK;
+}
+
+// events recorded on the stream around a launch (classes of more than one
+// kernel or of launchers without a KernelTimer)
+gl_status prof_begin(gl_event *ev, int k, size_t *idx) {
+    gl_status s = prof_take(ev, k, idx);
+    if (s || *idx == kNoMark) return s;
     HIP_TRY(hipEventRecord(ev->ev_pool[*idx], ev->stream));
+    return GL_OK;
+}
+
+// events the launch of a single kernel records at its start and end
+gl_status prof_timer(gl_event *ev, int k, KernelTimer *kt) {
+    *kt = KernelTimer{};
+    size_t idx = kNoMark;
+    gl_status s = prof_take(ev, k, &idx);
+    if (s || idx == kNoMark) return s;
+    kt->start = ev->ev_pool[idx];
+    kt->stop = ev->ev_pool[idx + 1];
     return GL_OK;
 }
 
@@ -285,6 +306,14 @@ gl_status prof_end(gl_event *ev, size_t idx) {
         ps_ = prof_end(ev, pidx_);                              \
         if (ps_) return ps_;                                    \
     } while (0)
+// a single-kernel launch that takes the KernelTimer kt_ of its sample
+#define PROF_KERNEL(ev, k, call)                                \
+    do {                                                        \
+        KernelTimer kt_;                                        \
+        gl_status ps_ = prof_timer(ev, k, &kt_);                \
+        if (ps_) return ps_;                                    \
+        HIP_TRY(call);                                          \
+    } while (0)
 
 // one field step n -> n+1; site fields F^n in the same pass when the event
 // has particles
@@ -298,9 +327,9 @@ gl_status field_step(gl_event *ev, bool site_fields) {
         reunit = 1;
     const bool stat = ev->stat_on && ev->n >= ev->stat_n0 && ev->n - 1 < ev->desc.max_steps;
     const bool ll = ev->ll_on && ev->n >= ev->ll_n0 && ev->n - 1 < ev->desc.max_steps;
-    PROF(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
-                                      site_fields || stat || ll ? (T *)(ev->ws + ev->L.F) : nullptr, tau,
-                                      ev->dtau, reunit)));
+    PROF_KERNEL(ev, 0, (launch_field_step<T>(ev->stream, ev->N, ev->fields<T>(ev->cur), ev->fields<T>(nxt),
+                                             site_fields || stat || ll ? (T *)(ev->ws + ev->L.F) : nullptr, tau,
+                                             ev->dtau, reunit, kt_)));
     if (stat) {
         // static quarks: accumulate the site fields at tau_n, series row n - 1 (time tau_{n+1/2})
         int nb = 0;
@@ -348,17 +377,17 @@ gl_status push(gl_event *ev) {
     if (ev->pend == 0) ev->pend_row0 = row;
     if (ev->perm_pending) {
         const int nb = 1 - ev->pbuf;
-        PROF(ev, 4, (launch_push_permuted<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->parts<T>(nb),
-                                             sort_perm(ev->scratch()), ev->ids(ev->pbuf), ev->ids(nb),
-                                             ev->slots_used, ev->fields<T>(1 - ev->cur),
-                                             (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev,
-                                             ev->dtau, ev->partials(ev->pend))));
+        PROF_KERNEL(ev, 4, (launch_push_permuted<T>(ev->stream, ev->N, ev->parts<T>(ev->pbuf), ev->parts<T>(nb),
+                                                    sort_perm(ev->scratch()), ev->ids(ev->pbuf), ev->ids(nb),
+                                                    ev->slots_used, ev->fields<T>(1 - ev->cur),
+                                                    (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev,
+                                                    ev->dtau, ev->partials(ev->pend), kt_)));
         ev->pbuf = nb;
         ev->perm_pending = false;
     } else {
-        PROF(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used, ev->fields<T>(1 - ev->cur),
-                                    (const T *)(ev->ws + ev->L.F), ev->tab<T>(), ns, (int)n_prev, ev->dtau,
-                                    ev->partials(ev->pend))));
+        PROF_KERNEL(ev, 2, (launch_push<T>(ev->stream, ev->N, ev->parts<T>(), ev->slots_used,
+                                           ev->fields<T>(1 - ev->cur), (const T *)(ev->ws + ev->L.F), ev->tab<T>(),
+                                           ns, (int)n_prev, ev->dtau, ev->partials(ev->pend), kt_)));
     }
     ev->pend++;
     if (ev->pend == kReduceSlots) {

@@ -314,10 +314,10 @@ hipError_t launch_check_finite(hipStream_t st, const T *a, int64_t n, int64_t va
 
 template <typename T>
 hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F, double tau,
-                             double dtau, int reunit) {
+                             double dtau, int reunit, const KernelTimer &kt) {
     dim3 grid(((N + SX - 1) / SX) * ((N + SY - 1) / SY)), block(2 * SX, SY);
-    hipLaunchKernelGGL(k_field_step<T>, grid, block, 0, st, N, in, out, F, (T)tau, (T)dtau,
-                       (T)(tau + 0.5 * dtau), reunit);
+    GL_LAUNCH_TIMED(kt, k_field_step<T>, grid, block, 0, st, N, in, out, F, (T)tau, (T)dtau, (T)(tau + 0.5 * dtau),
+                    reunit);
     return hipGetLastError();
 }
 
@@ -350,7 +350,7 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
 
 #define GL_INST(T)                                                                           \
     template hipError_t launch_field_step<T>(hipStream_t, int, FieldPtrs<T>, FieldPtrs<T>, T *,    \
-                                             double, double, int);                           \
+                                             double, double, int, const KernelTimer &);      \
     template hipError_t launch_diag<T>(hipStream_t, int, FieldPtrs<T>, double, double *, int *);     \
     template hipError_t launch_check_finite<T>(hipStream_t, const T *, int64_t, int64_t, int, int *);   \
     template hipError_t launch_static_accum<T>(hipStream_t, int, const T *, double *, double, double *, int *); \

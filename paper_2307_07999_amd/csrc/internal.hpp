@@ -1,6 +1,7 @@
 // internal.hpp -- device-side data descriptions shared by the kernels and the
 // runtime of the Glasma + colored-particle-in-cell library (not installed).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -106,14 +107,35 @@ struct SpeciesTab {
 };
 
 // ---- launchers (stream-ordered, no synchronisation) --------------------------
+// Events that a launch records itself at its kernel's start and end
+// (hipExtLaunchKernelGGL): the kernel's own duration, without the dispatch
+// gap that events recorded on the stream around a launch also cover.  Both
+// null: an ordinary launch.
+struct KernelTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+#define GL_LAUNCH_TIMED(kt, kernel, grid, block, shmem, st, ...)                                        \
+    do {                                                                                                \
+        if ((kt).start)                                                                                 \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, (kt).start, (kt).stop, 0u, __VA_ARGS__); \
+        else                                                                                            \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                            \
+    } while (0)
+// a launch with nothing to do still closes its sample (an empty interval)
+inline hipError_t timer_skip(hipStream_t st, const KernelTimer &kt) {
+    if (!kt.start) return hipSuccess;
+    hipError_t e = hipEventRecord(kt.start, st);
+    return e != hipSuccess ? e : hipEventRecord(kt.stop, st);
+}
+
 // F: site-field records at tau_n in chunked planes, written when non-null
 template <typename T>
 hipError_t launch_field_step(hipStream_t st, int N, FieldPtrs<T> in, FieldPtrs<T> out, T *F,
-                             double tau, double dtau, int reunit);
+                             double tau, double dtau, int reunit, const KernelTimer &kt);
 template <typename T>
 hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
                        const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
-                       double *partials);
+                       double *partials, const KernelTimer &kt);
 // the push of particles still to be moved by a sort permutation: position j
 // is pushed from slot perm[j] of p and written, with the particle's other
 // arrays and id, to slot j of dst
@@ -121,7 +143,7 @@ template <typename T>
 hipError_t launch_push_permuted(hipStream_t st, int N, PartPtrs<T> p, PartPtrs<T> dst, const int32_t *perm,
                                 const int32_t *id_src, int32_t *id_dst, int64_t n_slots, FieldPtrs<T> f,
                                 const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
-                                double *partials);
+                                double *partials, const KernelTimer &kt);
 hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, int32_t base);
 // fixed-order sum of per-workgroup partial rows into a series row; a
 // non-null sub [kMaxSpecies][4] is subtracted from the first three terms of

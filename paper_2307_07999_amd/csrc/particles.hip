@@ -298,11 +298,12 @@ hipError_t launch_iota(hipStream_t st, int32_t *id, int64_t n, int64_t n_valid, 
 
 template <typename T>
 hipError_t launch_push(hipStream_t st, int N, PartPtrs<T> p, int64_t n_slots, FieldPtrs<T> f,
-                       const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau, double *partials) {
-    if (n_slots <= 0) return hipSuccess;
+                       const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau, double *partials,
+                       const KernelTimer &kt) {
+    if (n_slots <= 0) return timer_skip(st, kt);
     unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
-    hipLaunchKernelGGL(k_push<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, n_slots, f, F, tab,
-                       n_species, n, (T)dtau, partials);
+    GL_LAUNCH_TIMED(kt, k_push<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, n_slots, f, F, tab, n_species, n,
+                    (T)dtau, partials);
     return hipGetLastError();
 }
 
@@ -310,11 +311,11 @@ template <typename T>
 hipError_t launch_push_permuted(hipStream_t st, int N, PartPtrs<T> p, PartPtrs<T> dst, const int32_t *perm,
                                 const int32_t *id_src, int32_t *id_dst, int64_t n_slots, FieldPtrs<T> f,
                                 const T *F, SpeciesTab<T> tab, int n_species, int n, double dtau,
-                                double *partials) {
-    if (n_slots <= 0) return hipSuccess;
+                                double *partials, const KernelTimer &kt) {
+    if (n_slots <= 0) return timer_skip(st, kt);
     unsigned blocks = (unsigned)((n_slots + kPushBlock - 1) / kPushBlock);
-    hipLaunchKernelGGL(k_push_permuted<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, dst, perm, id_src, id_dst,
-                       n_slots, f, F, tab, n_species, n, (T)dtau, partials);
+    GL_LAUNCH_TIMED(kt, k_push_permuted<T>, dim3(blocks), dim3(kPushBlock), 0, st, N, p, dst, perm, id_src, id_dst,
+                    n_slots, f, F, tab, n_species, n, (T)dtau, partials);
     return hipGetLastError();
 }
 
@@ -345,11 +346,12 @@ hipError_t launch_particles_init(hipStream_t st, int N, PartPtrs<T> p, int64_t s
 
 #define GL_INST(T)                                                                               \
     template hipError_t launch_push<T>(hipStream_t, int, PartPtrs<T>, int64_t, FieldPtrs<T>,      \
-                                       const T *, SpeciesTab<T>, int, int, double, double *);    \
+                                       const T *, SpeciesTab<T>, int, int, double, double *,     \
+                                       const KernelTimer &);                                     \
     template hipError_t launch_push_permuted<T>(hipStream_t, int, PartPtrs<T>, PartPtrs<T>,       \
                                                 const int32_t *, const int32_t *, int32_t *,     \
                                                 int64_t, FieldPtrs<T>, const T *, SpeciesTab<T>, \
-                                                int, int, double, double *);                     \
+                                                int, int, double, double *, const KernelTimer &); \
     template hipError_t launch_particles_init<T>(hipStream_t, int, PartPtrs<T>, int64_t, int64_t, \
                                                  uint64_t, int, int, double);                    \
     template hipError_t launch_casimir<T>(hipStream_t, PartPtrs<T>, int64_t, double *, int *);             \
