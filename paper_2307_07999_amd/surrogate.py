@@ -232,7 +232,7 @@ def mean_curves(runs):
     return out
 
 
-def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_avg=4, n_part_train=10000,
+def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=192, n_avg=4, n_part_train=10000,
              n_part_fine=100000, n_part_heldout=100000, epochs=60, fine_epochs=120, err_max=0.05,
              seed=20230718, log=print):
     """The surrogate workload end to end on the GPU.
@@ -246,8 +246,9 @@ def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=64, n_avg=4, n_par
        network B the same then fine-tuned on the 512^2 runs;
     4. errors on the held-out curves (max |pred - ref| / max |ref|), and the
        trust region of the queries: the even held-out points calibrate the
-       error of each (mass, p_T0 bin) cell, the odd ones test what the
-       queries answer (coverage and error of the network's answers);
+       error of each (mass, p_T0 bin) cell (about ten per cell, so that a
+       cell's largest error is seen), the odd ones test what the queries
+       answer (coverage and error of the network's answers);
     5. the time per kappa(tau) curve of the network and of the solver.
     """
     import torch
