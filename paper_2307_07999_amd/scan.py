@@ -71,6 +71,8 @@ def run_scan(n_events=16, N=512, L_fm=10.0, sheets=50, g2mu=2.767, m_ir=0.2, n_p
     Returns a dict with the per-event raw series, the statistics of every
     point and correlator (gl_scan_statistics rows) and the wall time."""
     import torch
+    if n_events < 2:
+        raise ValueError("the jackknife errors need n_events >= 2")
     pts = scan_points()
     a_fm = L_fm / N
     steps = int(math.ceil(tau_max / (0.125 * a_fm) - 1e-9)) - 1

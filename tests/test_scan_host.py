@@ -64,3 +64,10 @@ def test_static_quarks_start_with_the_beauty_quarks_at_rest():
     formation step the static correlator takes as its start."""
     label, kind, m, p0, tf = S.scan_points()[0]
     assert kind == G.KIND_HEAVY_QUARK and m == S.BEAUTY_GEV and p0 == 0.0 and tf < 0
+
+
+def test_run_scan_refuses_fewer_than_two_events():
+    """The jackknife over events needs two; the check comes before any device work."""
+    import pytest
+    with pytest.raises(ValueError):
+        S.run_scan(n_events=1)
