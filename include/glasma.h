@@ -247,9 +247,11 @@ gl_status gl_set_match_params(gl_event *ev, int32_t max_iter, double tol);
  * series when running.  Not saved: the Wilson lines of the initial
  * condition (gl_get_wilson_line, gl_dipole need a new gl_init_glasma) and
  * the kernel-timing state.  gl_restore reads such a file into an event
- * created with an identical gl_lattice_desc (GL_EINVAL otherwise, or for a
- * file that is not a checkpoint of this format); the event's previous
- * contents are replaced.  Both synchronise the stream.  GL_ESTATE for an
+ * created with an identical gl_lattice_desc (GL_EINVAL otherwise, for a
+ * file that is not a checkpoint of this format or is truncated, and for one
+ * whose step counters, cadences or species counts are out of range or do not
+ * fill the used particle slots; after such a refusal the event is left
+ * uninitialised); the event's previous contents are replaced.  Both synchronise the stream.  GL_ESTATE for an
  * uninitialised event (checkpoint) or an event held by a batch (restore). */
 gl_status gl_checkpoint(gl_event *ev, const char *path);
 gl_status gl_restore(gl_event *ev, const char *path);

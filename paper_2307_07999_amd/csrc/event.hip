@@ -1741,11 +1741,23 @@ gl_status gl_restore(gl_event *ev, const char *path) {
     if (c.n_species < 0 || c.n_species > kMaxSpecies || c.cur < 0 || c.cur > 1 || c.pbuf < 0 || c.pbuf > 1 ||
         c.rows < 0 || c.rows > std::max(0, d.max_steps) || c.stat_rows < 0 || c.stat_rows > std::max(0, d.max_steps) ||
         c.ll_rows < 0 || c.ll_rows > std::max(0, d.max_steps) || c.slots_used < 0 || c.slots_used > ev->L.slots ||
-        (c.stat_on && !d.static_correlator) || (c.ll_on && !d.lightlike_correlator))
+        (c.stat_on && !d.static_correlator) || (c.ll_on && !d.lightlike_correlator) || c.n < 0 ||
+        c.since_sort < 0 || c.sort_every < 0 || c.check_every < 0 || c.match_max_iter < 1 || !(c.match_tol > 0) ||
+        c.stat_n0 < 0 || c.ll_n0 < 0 || (c.push_due != 0 && c.push_due != 1) || (c.set_changed != 0 && c.set_changed != 1))
         return fail(GL_EINVAL, std::string(path) + ": inconsistent checkpoint");
     std::vector<CkptSpecies> sp(c.n_species);
     if (!sp.empty() && std::fread(sp.data(), sizeof(CkptSpecies), sp.size(), fc.f) != sp.size())
         return fail(GL_EINVAL, std::string(path) + " is truncated");
+    // the particles fill [0, total) of whole push blocks, species by species
+    int64_t total = 0;
+    for (const CkptSpecies &k : sp) {
+        if (k.n < 0 || k.n > ev->L.slots || k.nform < 1 || !(k.mass_lat >= 0) ||
+            (k.desc.kind != GL_KIND_HEAVY_QUARK && k.desc.kind != GL_KIND_JET))
+            return fail(GL_EINVAL, std::string(path) + ": inconsistent species record");
+        total += k.n;
+    }
+    if ((total + kPushBlock - 1) / kPushBlock * kPushBlock != c.slots_used)
+        return fail(GL_EINVAL, std::string(path) + ": species counts do not fill the used slots");
     // the event takes the checkpoint's scalars, then its blobs
     ev->n = c.n;
     ev->rows = c.rows;

@@ -122,6 +122,24 @@ def test_restore_refuses_other_lattices_and_junk(gl, tmp_path):
     with pytest.raises(gl.GlasmaError) as e:
         same.run(1)                 # not initialised by the failed restore
     assert e.value.status == gl.GL_ESTATE
+    # a well-formed file whose scalars or species counts are out of range
+    import ctypes
+    scal = 16 + ctypes.sizeof(gl.glasma.LatticeDesc)     # magic, version words, lattice description
+    assert int(np.frombuffer(data, np.int64, 1, scal)[0]) == a.info()[2]   # the step index comes first
+    bad = bytearray(data)
+    bad[scal:scal + 8] = np.int64(-5).tobytes()
+    (tmp_path / "neg.ckpt").write_bytes(bytes(bad))
+    with pytest.raises(gl.GlasmaError) as e:
+        same.restore(str(tmp_path / "neg.ckpt"))
+    assert e.value.status == gl.GL_EINVAL and "inconsistent" in str(e.value)
+    words = np.frombuffer(data, np.int64, (len(data) - scal) // 8, scal)
+    k = scal + 8 * int(np.nonzero(words == 1200)[0][0])   # the first species' count
+    bad = bytearray(data)
+    bad[k:k + 8] = np.int64(5000).tobytes()
+    (tmp_path / "count.ckpt").write_bytes(bytes(bad))
+    with pytest.raises(gl.GlasmaError) as e:
+        same.restore(str(tmp_path / "count.ckpt"))
+    assert e.value.status == gl.GL_EINVAL and "species" in str(e.value)
 
 
 def test_nan_set_from_the_host_is_reported(gl):
