@@ -397,8 +397,11 @@ void gl_batch_destroy(gl_batch *b);
  * holds this batch's key (device, precision, lattice sizes, particle count);
  * the choice is written back to cache_json.  cache_json may be NULL. */
 gl_status gl_batch_autotune(gl_batch *b, const char *cache_json);
-/* Set the configuration by hand (sort_every 0: never sort; graph_steps 0: no
- * graph; graph_steps must be even and a multiple of 2*sort_every). */
+/* Set the configuration by hand (grid_mult as above, at most 64; sort_every
+ * 0: never sort; graph_steps 0: no graph; graph_steps must be even and a
+ * multiple of 2*sort_every).  GL_EINVAL otherwise.  A cached choice that
+ * gl_batch_autotune finds out of its own range (shape, grid_mult above 8) is
+ * ignored and the batch timed again. */
 gl_status gl_batch_config(gl_batch *b, int32_t shape, int32_t grid_mult, int32_t sort_every,
                           int32_t graph_steps);
 gl_status gl_batch_info(gl_batch *b, int32_t *shape, int32_t *tile_x, int32_t *tile_y,

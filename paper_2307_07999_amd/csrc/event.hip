@@ -1994,6 +1994,9 @@ std::string batch_key(const gl_batch *b) {
     return k.str();
 }
 
+// the largest grid multiple the tuner tries (workgroups per CU of a persistent launch)
+constexpr int kMaxGridMult = 8;
+
 bool cache_lookup(const char *path, const std::string &key, int *shape, int *mult) {
     if (!path) return false;
     std::ifstream f(path);
@@ -2003,8 +2006,9 @@ bool cache_lookup(const char *path, const std::string &key, int *shape, int *mul
     std::string s = ss.str(), pat = "\"" + key + "\": [";
     size_t p = s.find(pat);
     if (p == std::string::npos) return false;
+    // an entry out of the tuner's own range is ignored (the batch is timed again)
     return std::sscanf(s.c_str() + p + pat.size(), "%d, %d", shape, mult) == 2 && *shape >= 0 &&
-           *shape < kBatchShapes && *mult >= 0;
+           *shape < kBatchShapes && *mult >= 0 && *mult <= kMaxGridMult;
 }
 
 void cache_store(const char *path, const std::string &key, int shape, int mult) {
@@ -2235,7 +2239,7 @@ gl_status gl_batch_autotune(gl_batch *b, const char *cache_json) {
 
 gl_status gl_batch_config(gl_batch *b, int32_t shape, int32_t grid_mult, int32_t sort_every, int32_t graph_steps) {
     if (!b) return fail(GL_EINVAL, "null batch");
-    if (shape < 0 || shape >= kBatchShapes || grid_mult < 0 || sort_every < 0 || graph_steps < 0)
+    if (shape < 0 || shape >= kBatchShapes || grid_mult < 0 || grid_mult > 64 || sort_every < 0 || graph_steps < 0)
         return fail(GL_EINVAL, "bad batch configuration");
     if (graph_steps > 0 && sort_every > 0 && graph_steps % (2 * sort_every) != 0)
         return fail(GL_EINVAL, "graph_steps must be a multiple of 2*sort_every");

@@ -83,6 +83,18 @@ def test_autotune_cache_roundtrip(gl, tmp_path):
     b2.autotune(path)
     assert b2.info() == first
     b2.run(4)
+    b2.close()
+    # an entry out of the tuner's range is ignored: the batch is timed again
+    # and the entry replaced; a hand configuration out of range is refused
+    json.dump({key: [first["shape"], 100]}, open(path, "w"))
+    b3 = gl.Batch(evs)
+    b3.autotune(path)
+    assert b3.info()["grid_mult"] <= 8
+    assert json.load(open(path))[key] == [b3.info()["shape"], b3.info()["grid_mult"]]
+    with pytest.raises(gl.GlasmaError) as e:
+        b3.config(shape=0, grid_mult=65, sort_every=16, graph_steps=32)
+    assert e.value.status == gl.GL_EINVAL
+    b3.close()
 
 
 def test_batched_event_matches_oracle(gl, orc):
