@@ -142,13 +142,21 @@ def check(status):
     return status
 
 
+def _need(ok, what):
+    # argument checks that stay on under python -O: the C side trusts these sizes
+    if not ok:
+        raise ValueError(what)
+
+
 def _d(a):
-    assert a.dtype == np.float64 and a.flags.c_contiguous
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous float64 array")
     return a.ctypes.data_as(_D)
 
 
 def _i(a):
-    assert a.dtype == np.int32 and a.flags.c_contiguous
+    if a.dtype != np.int32 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous int32 array")
     return a.ctypes.data_as(_I32)
 
 
@@ -205,7 +213,7 @@ def scan_statistics(series, kind, dtau_fm, a_fm):
     tau, <A>, err, <B>, err, <B>/<A>, err, rate A, err, rate B, err, total
     rate, err)."""
     s = np.ascontiguousarray(series, np.float64)
-    assert s.ndim == 3 and s.shape[2] == 4
+    _need(s.ndim == 3 and s.shape[2] == 4, "series must be [n_events, rows, 4]")
     n = ctypes.c_int32(0)
     check(lib().gl_scan_statistics(_d(s), s.shape[0], s.shape[1], kind, dtau_fm, a_fm, None, 0, ctypes.byref(n)))
     out = np.zeros((max(n.value, 1), 14))
@@ -407,8 +415,8 @@ class Event:
     # ---- host transfers (tests, checkpoints) ---------------------------------
     def set_state(self, U, E, phi, pi, n):
         arrs = [np.ascontiguousarray(a, np.float64) for a in (U, E, phi, pi)]
-        assert arrs[0].size == 36 * self.n2 and arrs[1].size == 16 * self.n2
-        assert arrs[2].size == 8 * self.n2 and arrs[3].size == 8 * self.n2
+        _need(arrs[0].size == 36 * self.n2 and arrs[1].size == 16 * self.n2 and arrs[2].size == 8 * self.n2
+              and arrs[3].size == 8 * self.n2, "U, E, phi, pi must hold 36, 16, 8 and 8 values per site")
         return check(lib().gl_set_state(self._h, *[_d(a) for a in arrs], n))
 
     def get_state(self):
@@ -587,7 +595,8 @@ def _mlp_declare(L):
 
 
 def _f(a):
-    assert a.dtype == np.float32 and a.flags.c_contiguous
+    if a.dtype != np.float32 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous float32 array")
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
@@ -672,7 +681,7 @@ class MLP:
         and the held-out error per (class, bin) cell (gl_mlp_set_trust)."""
         f = lambda v: np.ascontiguousarray(v, np.float32)
         lo, hi, classes, bin_edges, err = f(lo), f(hi), f(classes), f(bin_edges), f(err)
-        assert err.shape == (len(classes), len(bin_edges) - 1)
+        _need(err.shape == (len(classes), len(bin_edges) - 1), "err must be [classes, bins]")
         _mlp_check(lib().gl_mlp_set_trust(self._h, _f(lo), _f(hi), class_col, len(classes), _f(classes), class_tol,
                                           bin_col, len(bin_edges) - 1, _f(bin_edges), _f(err), err_max))
 
@@ -697,7 +706,7 @@ class MLP:
     def params(self, set_to=None):
         if set_to is not None:
             v = np.ascontiguousarray(set_to, np.float32)
-            assert v.size == self.n_params
+            _need(v.size == self.n_params, "set_to must hold every parameter")
             _mlp_check(lib().gl_mlp_params(self._h, None, _f(v), None))
         out = np.zeros(self.n_params, np.float32)
         _mlp_check(lib().gl_mlp_params(self._h, _f(out), None, None))

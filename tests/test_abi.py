@@ -99,3 +99,19 @@ def test_status_strings(gl):
     L = gl.lib()
     for s in range(-6, 1):
         assert L.gl_status_string(s)
+
+
+def test_binding_checks_arguments_without_asserts():
+    """The binding's host-array checks raise real exceptions (they stay on
+    under python -O; the C side trusts the sizes it is given)."""
+    from paper_2307_07999_amd import glasma as G
+    with pytest.raises(TypeError):
+        G._d(np.zeros(4, np.float32))
+    with pytest.raises(TypeError):
+        G._d(np.zeros((4, 4))[:, ::2])            # not contiguous
+    with pytest.raises(TypeError):
+        G._i(np.zeros(4, np.int64))
+    with pytest.raises(TypeError):
+        G._f(np.zeros(4))
+    with pytest.raises(ValueError):
+        G.scan_statistics(np.zeros((2, 5, 3)), G.KIND_HEAVY_QUARK, 0.01, 0.02)
