@@ -65,15 +65,21 @@ def kernel_rates(prec, avg_us, units, ab):
     """Per dominant kernel: algorithmic GB/s (algorithmic bytes over the live
     HIP-event duration) and counted GB/s (the HBM bytes of the counter runs
     over the same duration, None when those are stale), each also as a
-    fraction of the 8 TB/s peak."""
+    fraction of the 8 TB/s peak; and the fraction of the chip's VALU issue
+    rate its instructions take (the SQ-counter count per launch over the same
+    duration against VALU_ISSUE_PEAK, None when the counts are stale): the
+    roofline of a kernel bound by its arithmetic rather than by HBM."""
     out = {}
+    tname = "double" if prec == 64 else "float"
     for name in ("field_step", "push"):
         t = avg_us[name] * 1e-6
         alg = ab[name] * units[name] / t / 1e9
         tr = measured_traffic(name, prec)
         cnt = None if tr is None else (tr[0] + tr[1]) / t / 1e9
+        valu = measured_valu("gl::k_%s<%s>" % (name, tname), prec)
         out[name] = {"avg_us": avg_us[name], "alg_GBps": alg, "alg_frac": alg / PEAK_HBM_GBS,
-                     "counted_GBps": cnt, "counted_frac": None if cnt is None else cnt / PEAK_HBM_GBS}
+                     "counted_GBps": cnt, "counted_frac": None if cnt is None else cnt / PEAK_HBM_GBS,
+                     "valu_issue_frac": None if valu is None else valu / t / VALU_ISSUE_PEAK}
     return out
 
 
@@ -412,6 +418,69 @@ def measured_traffic(kernel, prec):
     return rows.get((kernel, prec))
 
 
+SQ_FILES = {p: os.path.join(ROOT, "profiles", "glasma512_fp%d_sq_counters.md" % p) for p in (64, 32)}
+# wave64 VALU instructions the chip can issue per second: each of the 1024
+# SIMDs (256 CUs x 4) takes one every 4 cycles (64 lanes over 16-wide ALUs,
+# FP32 without packing like FP64), at the 2.4 GHz peak clock
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
+SQ_KERNELS = ("gl::k_field_step<", "gl::k_push<", "gl::k_push_permuted<", "gl::k_batch_field_flat<",
+              "gl::k_batch_push_flat<")
+
+
+def sq_table(prec, pmc_dir):
+    """Rows 'kernel | launches | counter means per launch ... | VALU per wave'
+    of the hot-path kernels from one rocprofv3 --pmc run of SQ counters, and
+    the kernel-source hash they belong to."""
+    import csv
+    import glob
+    acc = {}
+    for fn in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            if not name.startswith(SQ_KERNELS):
+                continue
+            a = acc.setdefault(name, {}).setdefault(r["Counter_Name"], [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+    counters = sorted({c for v in acc.values() for c in v})
+    print("| kernel | launches | " + " | ".join(counters) + " | VALU per wave |")
+    print("|---" * (len(counters) + 3) + "|")
+    for name in sorted(acc, key=lambda k: -acc[k].get("SQ_INSTS_VALU", [0, 1])[0] / acc[k].get("SQ_INSTS_VALU", [0, 1])[1]):
+        m = {c: v[0] / v[1] for c, v in acc[name].items()}
+        waves = m.get("SQ_WAVES")
+        vpw = "%.0f" % (m["SQ_INSTS_VALU"] / waves) if waves and "SQ_INSTS_VALU" in m else "-"
+        launches = max(v[1] for v in acc[name].values())
+        print("| %s | %d | %s | %s |" % (name, launches, " | ".join("%.0f" % m.get(c, float("nan")) for c in counters), vpw))
+    print("source hash: `%s`" % kernel_source_hash())
+
+
+def measured_valu(kernel, prec):
+    """SQ_INSTS_VALU per launch of the kernel whose name starts with kernel
+    (e.g. "gl::k_field_step<double>"), from the committed SQ-counter summary
+    of this precision, or None when missing or taken on other kernel sources."""
+    import re
+    try:
+        lines = open(SQ_FILES[prec]).read().splitlines()
+    except (OSError, KeyError):
+        return None
+    src, col, val = None, None, None
+    for ln in lines:
+        if ln.startswith("source hash:"):
+            m = re.search(r"`([0-9a-f]+)`", ln)
+            src = m.group(1) if m else None
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if cells and cells[0] == "kernel" and "SQ_INSTS_VALU" in cells:
+            col = cells.index("SQ_INSTS_VALU")
+        elif col is not None and cells and cells[0].startswith(kernel) and val is None:
+            try:
+                val = float(cells[col])
+            except (ValueError, IndexError):
+                val = None
+    if src != kernel_source_hash():
+        return None
+    return val
+
+
 def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     """Rows 'kernel | precision | fetch bytes | write bytes' per launch from
     two counter runs, each scaled by what the counter reads for the plain
@@ -566,12 +635,17 @@ def main():
                     help="print a markdown summary of a rocprofv3 output directory and exit")
     ap.add_argument("--traffic", nargs=5, metavar=("PREC", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH", "COPY_WRITE"),
                     help="print the HBM traffic rows of the dominant kernels from counter runs and exit")
+    ap.add_argument("--sq-table", nargs=2, metavar=("PREC", "PMC_DIR"),
+                    help="print the SQ-counter rows of the hot-path kernels from a counter run and exit")
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize)
         return
     if args.traffic:
         traffic_table(int(args.traffic[0]), *args.traffic[1:])
+        return
+    if args.sq_table:
+        sq_table(int(args.sq_table[0]), args.sq_table[1])
         return
     if args.copy_calib:
         copy_calibration(args.copy_calib)

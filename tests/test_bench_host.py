@@ -77,3 +77,42 @@ def test_observable_errors_are_per_curve_maxima_over_species():
     assert err["a"] == pytest.approx(max(0.1 / 4.0, 1.0 / 10.0))
     assert err["b"] == 0.0
     assert bench.observable_errors([{"c": np.zeros(3)}], [{"c": np.zeros(3)}]) == {"c": 0.0}
+
+
+def test_valu_counts_are_read_for_the_current_kernel_sources(tmp_path, monkeypatch):
+    """The committed SQ-counter summaries hold the kernels' VALU instruction
+    counts for the current kernel sources; the issue peak is the chip's (one
+    wave64 instruction per SIMD every 4 cycles at 2.4 GHz); a count taken on
+    other sources, a missing file or a missing row reads as None."""
+    assert bench.VALU_ISSUE_PEAK == 256 * 4 * 2.4e9 / 4
+    for prec, t in ((64, "double"), (32, "float")):
+        fs, push = bench.measured_valu("gl::k_field_step<%s>" % t, prec), bench.measured_valu("gl::k_push<%s>" % t, prec)
+        if fs is None:   # bench then reports the issue fraction as null until the counters are taken again
+            pytest.skip("SQ counts missing or taken on other kernel sources")
+        assert push and fs != push
+        # both kernels run one wave64 per 64 lanes: a few thousand VALU instructions per wave
+        assert 1000 < fs / 8192 < 4000
+    text = open(bench.SQ_FILES[32]).read()
+    stale = tmp_path / "stale.md"
+    stale.write_text(text.replace(bench.kernel_source_hash(), "0123456789abcdef"))
+    monkeypatch.setitem(bench.SQ_FILES, 32, str(stale))
+    assert bench.measured_valu("gl::k_field_step<float>", 32) is None
+    monkeypatch.setitem(bench.SQ_FILES, 32, str(tmp_path / "missing.md"))
+    assert bench.measured_valu("gl::k_field_step<float>", 32) is None
+    monkeypatch.setitem(bench.SQ_FILES, 32, str(bench.SQ_FILES[64]))
+    assert bench.measured_valu("gl::k_field_step<float>", 32) is None   # no such row there
+
+
+def test_issue_fraction_in_the_kernel_rates():
+    """kernel_rates reports each kernel's share of the VALU issue peak from
+    its counted instructions and the measured duration."""
+    ab = bench.alg_bytes(32)
+    units = {"field_step": 512 * 512, "push": 700000}
+    r = bench.kernel_rates(32, {"field_step": 36.6, "push": 37.4}, units, ab)
+    valu = bench.measured_valu("gl::k_field_step<float>", 32)
+    if valu is None:
+        assert r["field_step"]["valu_issue_frac"] is None
+        return
+    want = valu / 36.6e-6 / bench.VALU_ISSUE_PEAK
+    assert abs(r["field_step"]["valu_issue_frac"] - want) < 1e-12
+    assert 0.5 < r["field_step"]["valu_issue_frac"] < 1.0
