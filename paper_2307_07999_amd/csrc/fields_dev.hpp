@@ -8,9 +8,13 @@
 
 namespace gl {
 
-// the field step's transports use the hermitian-aware products in FP64 only
+// The field step's transports use the hermitian-aware products in FP64; in
+// FP32 only the staple's and the clover corner's, which come before the
+// scalar couplings, where registers are free (FP32 field step 38.0 -> 37.3
+// us at 512^2; taken everywhere, FP32 spills one more dword and loses it).
 template <typename T>
 constexpr bool kHermFS = sizeof(T) == 8;
+constexpr bool kHermPlaq = true;
 // FP64: E_i(x) and the pi half are loaded before the scalar couplings and
 // arrive while those are computed (the step waited on them: 79.6 -> 74.5 us
 // at 512^2).  FP32 loads them where they are used: held over the couplings
@@ -326,7 +330,7 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             // staple: U_j^dag(y) [P(y)]_X U_j(y)
             T pa[8], t[8];
             tl.plaq(Tl::pidx(lx + 1 - d, ly + d), pa);
-            transport_dn<kHermFS<T>>(tl.m(lj, ry), pa, t);
+            transport_dn<kHermPlaq>(tl.m(lj, ry), pa, t);
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 fe[a] = -tau * sgn * (px[a] - t[a]);
@@ -338,7 +342,7 @@ __device__ __forceinline__ void field_step_link(LinkTile<T, SX, SY> &tl, int N, 
             // by C = U_1(z) U_2(z+1)
             T pa[8], t[8];
             tl.plaq(Tl::pidx(lx, ly), pa);
-            transport_dn<kHermFS<T>>(mul(tl.m(0, rz), tl.m(1, rz + 1)), pa, t);
+            transport_dn<kHermPlaq>(mul(tl.m(0, rz), tl.m(1, rz + 1)), pa, t);
 #pragma unroll
             for (int a = 0; a < 8; a++) t[a] = T(-0.25) * (cl[a] + t[a]);
             store_half(F, n2, x, 40, t, d);   // B_z
