@@ -232,7 +232,7 @@ def mean_curves(runs):
     return out
 
 
-def protocol(n_train_coarse=2000, n_train_fine=512, n_heldout=192, n_avg=4, n_part_train=10000,
+def protocol(n_train_coarse=2000, n_train_fine=1024, n_heldout=192, n_avg=4, n_part_train=10000,
              n_part_fine=100000, n_part_heldout=100000, epochs=60, fine_epochs=120, err_max=0.05,
              seed=20230718, log=print):
     """The surrogate workload end to end on the GPU.
