@@ -119,6 +119,54 @@ def test_push_sampled_paper_scale(gl, orc):
     assert ser[:, 3].sum() == 3000
 
 
+def test_push_sampled_paper_scale_fp32(gl, orc):
+    """The FP32 push of the same step (7 x 1e5 particles on 512^2): the
+    FP64 oracle recomputes 3000 particles from the FP32 event's own state
+    and particles, read back, so both sides start from the same numbers and
+    differ only by one step of FP32 arithmetic (its site fields included).
+    Offsets, rapidities, momenta and charges agree to 2e-6 of each
+    quantity's largest value (one step: about 2e-7, FP32 rounding).  A crossing may be decided the other way only
+    where the oracle's offset lands within 1e-4 of a cell edge, where both
+    decisions are valid; every other cell agrees exactly."""
+    U, E, phi, pi = si.random_state(513, N, link_kind="near", eps=0.3, e_scale=0.1,
+                                    phi_scale=0.1, pi_scale=0.1)
+    s = orc.State(N)
+    s.U, s.E, s.phi, s.pi, s.n = U, E, phi, pi, 40
+    ev = gl.Event(N, L, 0.125, precision=32, max_steps=64, max_particles=700000)
+    ev.set_state(*H.state_oracle_to_soa(s), 40)
+    for k, (m, p0, kind) in enumerate(SPECIES):
+        ev.add_species(m, p0, kind, 100000, 1000 + k)
+    before = ev.get_particles()
+    mass = [ev.species_info(k)[1] for k in range(len(SPECIES))]
+    nform = [ev.species_info(k)[0] for k in range(len(SPECIES))]
+    U32, E32, phi32, pi32, n32 = ev.get_state()          # the FP32 state the event holds
+    s32 = H.state_soa_to_oracle(orc, U32, E32, phi32, pi32, N, n32)
+    assert n32 == 40
+    ev.evolve_fields(1)
+    ev.push_particles()
+    after = ev.get_particles()
+    g = np.random.default_rng(7)
+    pick = np.sort(g.choice(700000, 3000, replace=False))
+    P = H.particles_gpu_to_oracle(orc, before).subset(pick)
+    cells = np.unique(P.cell[:, 0] + N * P.cell[:, 1]).astype(np.int32)
+    _, _, _, _, Fs = orc.field_step_sites(s32, 0.125, cells)
+    Ffull = np.zeros((N * N, 6, 8))
+    Ffull[cells] = Fs
+    ser = orc.particle_step(N, 40, 0.125, s32.U, s32.phi, Ffull, P, mass, nform)
+    assert ser[:, 3].sum() == 3000
+    A = H.particles_gpu_to_oracle(orc, after).subset(pick)
+    same = np.all(A.cell == P.cell, axis=1)
+    edge = np.min(np.abs(0.5 - np.abs(P.off)), axis=1)
+    print("FP32 push at 512^2: %d of 3000 cells differ" % int((~same).sum()))
+    assert (~same).sum() <= 3 and np.all(edge[~same] < 1e-4)
+    for k in ("off", "eta", "p", "Q"):
+        a, b = getattr(A, k)[same], getattr(P, k)[same]
+        err = np.abs(a - b).max() / np.abs(b).max()
+        print("FP32 push at 512^2, %s: %.2e of its largest value" % (k, err))
+        assert err < 2e-6, k
+    ev.close()
+
+
 def _pick(d, idx):
     return {k: (v[:, idx] if v.ndim == 2 else v[idx]) for k, v in d.items()}
 
