@@ -9,7 +9,11 @@ the broadening series.  Inputs are synthetic (seeded) and generated on the
 device; nothing is read from the host inside the timed region.
 
 Prints ONE JSON line (rank 0).  `value` is lattice site-updates per second of
-the whole job; particle-steps per second is reported beside it.
+the whole job; particle-steps per second is reported beside it.  `roofline`
+is the dominant kernel (the field step) against the HBM peak; `kernels`
+gives the field step and the push each with algorithmic and counted GB/s and
+their share of the chip's VALU issue rate (the roofline of a kernel bound by
+its arithmetic), for the FP64 event and its FP32 twin.
 """
 import argparse
 import json
