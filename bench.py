@@ -10,10 +10,13 @@ device; nothing is read from the host inside the timed region.
 
 Prints ONE JSON line (rank 0).  `value` is lattice site-updates per second of
 the whole job; particle-steps per second is reported beside it.  `roofline`
-is the dominant kernel (the field step) against the HBM peak; `kernels`
-gives the field step and the push each with algorithmic and counted GB/s and
-their share of the chip's VALU issue rate (the roofline of a kernel bound by
-its arithmetic), for the FP64 event and its FP32 twin.
+is the dominant kernel (the field step) against the HBM peak and against
+`stream_ceiling`, the copy rate the library's own streaming kernel reaches on
+this device in the same process; `kernels` gives the field step and the push
+each with its rate alone (site updates/s, particle steps/s), algorithmic and
+counted GB/s as fractions of both, and their share of the chip's VALU issue
+rate (the roofline of a kernel bound by its arithmetic), for the FP64 event
+and its FP32 twin.
 """
 import argparse
 import json
@@ -65,25 +68,33 @@ def alg_bytes(prec):
     }
 
 
-def kernel_rates(prec, avg_us, units, ab):
-    """Per dominant kernel: algorithmic GB/s (algorithmic bytes over the live
-    HIP-event duration) and counted GB/s (the HBM bytes of the counter runs
-    over the same duration, None when those are stale), each also as a
-    fraction of the 8 TB/s peak; and the fraction of the chip's VALU issue
-    rate its instructions take (the SQ-counter count per launch over the same
-    duration against VALU_ISSUE_PEAK, None when the counts are stale): the
-    roofline of a kernel bound by its arithmetic rather than by HBM."""
+def kernel_rates(prec, avg_us, units, ab, ceiling=None):
+    """Per dominant kernel: its rate alone (site updates/s of the field step,
+    particle steps/s of the push, from the live HIP-event duration);
+    algorithmic GB/s (algorithmic bytes over that duration) and counted GB/s
+    (the HBM bytes of the counter runs over the same duration, None when those
+    are stale), each as a fraction of the 8 TB/s peak and, when `ceiling`
+    (GB/s of the library's own copy kernel, measured in the same process) is
+    given, of that ceiling; and the fraction of the chip's VALU issue rate its
+    instructions take (the SQ-counter count per launch over the same duration
+    against VALU_ISSUE_PEAK, None when the counts are stale): the roofline of a
+    kernel bound by its arithmetic rather than by HBM."""
     out = {}
     tname = "double" if prec == 64 else "float"
+    rate_name = {"field_step": "site_updates_per_s", "push": "particle_steps_per_s"}
     for name in ("field_step", "push"):
         t = avg_us[name] * 1e-6
         alg = ab[name] * units[name] / t / 1e9
         tr = measured_traffic(name, prec)
         cnt = None if tr is None else (tr[0] + tr[1]) / t / 1e9
         valu = measured_valu("gl::k_%s<%s>" % (name, tname), prec)
-        out[name] = {"avg_us": avg_us[name], "alg_GBps": alg, "alg_frac": alg / PEAK_HBM_GBS,
+        out[name] = {"avg_us": avg_us[name], rate_name[name]: units[name] / t,
+                     "alg_GBps": alg, "alg_frac": alg / PEAK_HBM_GBS,
                      "counted_GBps": cnt, "counted_frac": None if cnt is None else cnt / PEAK_HBM_GBS,
                      "valu_issue_frac": None if valu is None else valu / t / VALU_ISSUE_PEAK}
+        if ceiling:
+            out[name]["alg_ceiling_frac"] = alg / ceiling
+            out[name]["counted_ceiling_frac"] = None if cnt is None else cnt / ceiling
     return out
 
 
@@ -177,7 +188,7 @@ def observable_errors(got, want):
     return err
 
 
-def fp32_event(g, torch, n_per, steps, k, obs64):
+def fp32_event(g, torch, n_per, steps, k, obs64, ceiling=None):
     """The FP32 twin of the headline event (FP32 links, fields and
     particles, FP64 sums; the same charges and particles): one warm-up event,
     then K timed events, with the per-kernel algorithmic and counted HBM rates
@@ -188,12 +199,12 @@ def fp32_event(g, torch, n_per, steps, k, obs64):
     units = {"field_step": N * N, "push": n_part}
     return {"events": k, "ms_per_event": 1e3 * wall / k, "site_updates_per_s": N * N * steps * k / wall,
             "particle_steps_per_s": n_part * steps * k / wall, "kernel_avg_us": avg_us,
-            "kernels": kernel_rates(32, avg_us, units, alg_bytes(32)), "finite": finite,
+            "kernels": kernel_rates(32, avg_us, units, alg_bytes(32), ceiling), "finite": finite,
             "bitwise_repeatable": repeat,
             "observable_rel_err_vs_fp64": observable_errors(obs, obs64)}
 
 
-def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
+def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None, ceiling=None):
     """64 MV events with N uniform on {128, 256, 384, 512} at fixed a = 10/512 fm
     and log-uniform 1e4..1e6 particles each (charm and beauty at p_T0 in
     {0, 2, 5} GeV, jets at 10 GeV), FP32, stepped as one batch: flattened
@@ -244,6 +255,7 @@ def batch_bench(g, torch, steps, n_events=64, seed=20230718, cache=None):
             "particle_steps_per_s": npart * steps / t_run,
             "alg_GBps": step_bytes * steps / t_run / 1e9,
             "frac_hbm": step_bytes * steps / t_run / 1e9 / PEAK_HBM_GBS,
+            "frac_ceiling": step_bytes * steps / t_run / 1e9 / ceiling if ceiling else None,
             "tile": cfg["tile"], "grid_mult": cfg["grid_mult"], "graph_steps": cfg["graph_steps"],
             "hbm_traffic": counted, "finite": finite}
 
@@ -554,7 +566,7 @@ def copy_calibration(mib):
 STREAM_KINDS = ("copy", "read", "write")
 
 
-def stream_ceiling(mib=1024, reps=10):
+def stream_ceiling(mib=1024, reps=10, kinds=STREAM_KINDS):
     """The bandwidth the library's own streaming kernels reach (gl_stream_probe):
     a copy, a read and a write of mib MiB in 16-byte accesses, over its access
     patterns and grid sizes; GB/s counts the bytes read plus written.  The best
@@ -569,6 +581,8 @@ def stream_ceiling(mib=1024, reps=10):
     torch.cuda.synchronize()
     rows, best = [], {}
     for kind, name in enumerate(STREAM_KINDS):
+        if name not in kinds:
+            continue
         moved = nbytes * (2 if kind == 0 else 1)
         for variant in range(6):
             for blocks in (2048, 8192, 32768):
@@ -673,6 +687,10 @@ def main():
     wall, ms, cnt, kappa_ok, obs, repeat = timed_events(g, torch, args.precision, n_per, steps, args.steps,
                                                         args.warmup)
 
+    # the streaming ceiling of this device, from the library's copy kernel
+    ceil = stream_ceiling(reps=5, kinds=("copy",))["best"]["copy"]
+    ceiling = ceil["GBps"]
+
     n_part = n_per * len(SPECIES)
     site_updates = N * N * steps * args.steps
     particle_steps = n_part * steps * args.steps
@@ -706,16 +724,18 @@ def main():
         "kernel_avg_us": avg_us,
         "finite": bool(kappa_ok),
         "bitwise_repeatable": repeat,
-        "kernels": kernel_rates(args.precision, avg_us, units, ab),
+        "kernels": kernel_rates(args.precision, avg_us, units, ab, ceiling),
+        "stream_ceiling": {"copy_GBps": ceiling, "variant": ceil["variant"], "blocks": ceil["blocks"]},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "ceiling": ceiling, "ceiling_frac": achieved / ceiling,
                      "traffic_bytes_per_launch": None if tr is None else tr[0] + tr[1],
                      "alg_bytes_per_unit": ab[dname], "units_per_launch": units[dname]},
     }
     if args.precision == 64 and not args.no_fp32_event:
-        out["fp32_event"] = fp32_event(g, torch, n_per, steps, args.steps, obs)
+        out["fp32_event"] = fp32_event(g, torch, n_per, steps, args.steps, obs, ceiling)
     if not args.no_batch:
-        out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache)
+        out["batch_fp32"] = batch_bench(g, torch, steps, cache=args.tune_cache, ceiling=ceiling)
     if not args.no_scan:
         out["scan"] = scan_bench()
     if args.surrogate != "off":

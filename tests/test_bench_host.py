@@ -116,3 +116,18 @@ def test_issue_fraction_in_the_kernel_rates():
     want = valu / 36.6e-6 / bench.VALU_ISSUE_PEAK
     assert abs(r["field_step"]["valu_issue_frac"] - want) < 1e-12
     assert 0.5 < r["field_step"]["valu_issue_frac"] < 1.0
+
+
+def test_kernel_rates_alone_and_against_the_ceiling():
+    """Each kernel's rate alone is its units over its duration, and the
+    ceiling fractions are the GB/s over the measured copy rate."""
+    ab = bench.alg_bytes(64)
+    units = {"field_step": 512 * 512, "push": 700000}
+    avg = {"field_step": 68.0, "push": 65.0}
+    r = bench.kernel_rates(64, avg, units, ab, ceiling=6300.0)
+    assert abs(r["field_step"]["site_updates_per_s"] - 512 * 512 / 68.0e-6) < 1.0
+    assert abs(r["push"]["particle_steps_per_s"] - 700000 / 65.0e-6) < 1.0
+    for k in ("field_step", "push"):
+        assert abs(r[k]["alg_ceiling_frac"] - r[k]["alg_GBps"] / 6300.0) < 1e-12
+        assert r[k]["alg_ceiling_frac"] > r[k]["alg_frac"]
+    assert "alg_ceiling_frac" not in bench.kernel_rates(64, avg, units, ab)["push"]
