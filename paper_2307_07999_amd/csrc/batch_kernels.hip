@@ -78,17 +78,46 @@ k_batch_field_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ 
     batch_field_tile(tile, evs[w.x], w, fpar, n, tau, dtau, tau_h);
 }
 
-template <typename T>
+// one block of an event's particles; with PERM, position i takes the particle
+// in slot perm[i] of buffer parity ppar (the pending sort) and the pushed
+// particle goes, with its species, momenta at formation and id, to slot i of
+// parity ppar ^ 1, as the single-event push that applies a sort does
+template <typename T, bool PERM>
 __device__ __forceinline__ void batch_push_block(const BatchEv<T> &e, int2 w, int fpar, int ppar, int n, T dtau) {
     const int64_t i = (int64_t)w.y * kPushBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int s = -1;
-    if (i < e.n_slots)
-        s = push_particle<T, false, true>(e.N, e.P[ppar], i, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+    if (i < e.n_slots) {
+        if constexpr (PERM) {
+            const PartPtrs<T> &P = e.P[ppar], &W = e.P[ppar ^ 1];
+            const int64_t src = e.sort.vals[1][i];
+            // the arrays that only move go first, so that nothing of them
+            // stays live through the push
+            W.species[i] = P.species[src];
+            W.px0[i] = P.px0[src];
+            W.py0[i] = P.py0[src];
+            W.pz0[i] = P.pz0[src];
+            e.ids[ppar ^ 1][i] = e.ids[ppar][src];
+            __builtin_amdgcn_sched_barrier(0);
+            s = push_particle<T, true, true>(e.N, P, src, W, i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+        } else {
+            s = push_particle<T, false, true>(e.N, e.P[ppar], i, e.P[ppar], i, e.f[fpar], e.F, e.tab, n, dtau, acc);
+        }
+    }
     block_species_reduce(s, acc, e.n_species, e.partials + (size_t)w.y * e.n_species * 4);
 }
 
-template <typename T>
+// a masked (failed) event is not pushed, but a pending sort still moves its
+// particles, so that its buffers follow the batch's parity
+template <typename T, bool PERM>
+__device__ __forceinline__ void batch_masked_block(const BatchEv<T> &e, int2 w, int ppar) {
+    if constexpr (PERM) {
+        const int64_t j = (int64_t)w.y * kPushBlock + threadIdx.x;
+        if (j < e.n_slots) permute_one(e.P[ppar], e.P[ppar ^ 1], e.sort.vals[1], j, e.ids[ppar], e.ids[ppar ^ 1]);
+    }
+}
+
+template <typename T, bool PERM>
 __global__ void __launch_bounds__(kPushBlock)
 k_batch_push(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks, int64_t total, int fpar,
              int ppar, const BatchCtl *__restrict__ ctl, T dtau) {
@@ -96,18 +125,24 @@ k_batch_push(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks
     int64_t stride, end;
     for (int64_t t = xcd_first(total, stride, end); t < end; t += stride) {
         const int2 w = blocks[t];
-        if (*evs[w.x].fail != kNotFailed) continue;
-        batch_push_block(evs[w.x], w, fpar, ppar, n, dtau);
+        if (*evs[w.x].fail != kNotFailed) {
+            batch_masked_block<T, PERM>(evs[w.x], w, ppar);
+            continue;
+        }
+        batch_push_block<T, PERM>(evs[w.x], w, fpar, ppar, n, dtau);
     }
 }
 
-template <typename T>
+template <typename T, bool PERM>
 __global__ void __launch_bounds__(kPushBlock)
 k_batch_push_flat(const BatchEv<T> *__restrict__ evs, const int2 *__restrict__ blocks, int64_t total, int fpar,
                   int ppar, const BatchCtl *__restrict__ ctl, T dtau) {
     const int2 w = blocks[xcd_remap(blockIdx.x, gridDim.x)];
-    if (*evs[w.x].fail != kNotFailed) return;
-    batch_push_block(evs[w.x], w, fpar, ppar, (int)ctl->n, dtau);
+    if (*evs[w.x].fail != kNotFailed) {
+        batch_masked_block<T, PERM>(evs[w.x], w, ppar);
+        return;
+    }
+    batch_push_block<T, PERM>(evs[w.x], w, fpar, ppar, (int)ctl->n, dtau);
 }
 
 // one workgroup per (event, species): fixed-order sum of the event's partial
@@ -194,15 +229,23 @@ hipError_t launch_batch_fields(hipStream_t st, int shape, const BatchEv<T> *evs,
 
 template <typename T>
 hipError_t launch_batch_push(hipStream_t st, const BatchEv<T> *evs, const int2 *blocks, int64_t total, int fpar,
-                             int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events) {
+                             int ppar, const BatchCtl *ctl, double dtau, int grid, int n_events, bool permuted) {
     if (total > 0) {
         unsigned g = (unsigned)(grid > 0 && grid < total ? grid : total);
-        if (g == total)
-            hipLaunchKernelGGL(k_batch_push_flat<T>, dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, fpar,
-                               ppar, ctl, (T)dtau);
+#define GL_PUSH(PERM)                                                                                          \
+    {                                                                                                          \
+        if (g == total)                                                                                        \
+            hipLaunchKernelGGL((k_batch_push_flat<T, PERM>), dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, \
+                               fpar, ppar, ctl, (T)dtau);                                                      \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_batch_push<T, PERM>), dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total,   \
+                               fpar, ppar, ctl, (T)dtau);                                                      \
+    }
+        if (permuted)
+            GL_PUSH(true)
         else
-            hipLaunchKernelGGL(k_batch_push<T>, dim3(g), dim3(kPushBlock), 0, st, evs, blocks, total, fpar, ppar,
-                               ctl, (T)dtau);
+            GL_PUSH(false)
+#undef GL_PUSH
         hipLaunchKernelGGL(k_batch_reduce<T>, dim3(n_events, kMaxSpecies), dim3(256), 0, st, evs, ctl);
     }
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, st, (BatchCtl *)ctl);
@@ -223,7 +266,7 @@ hipError_t launch_batch_check(hipStream_t st, const BatchEv<T> *evs, const int2 
     template hipError_t launch_batch_fields<T>(hipStream_t, int, const BatchEv<T> *, const int2 *, int64_t, int, \
                                                const BatchCtl *, double, int);                               \
     template hipError_t launch_batch_push<T>(hipStream_t, const BatchEv<T> *, const int2 *, int64_t, int, int,  \
-                                             const BatchCtl *, double, int, int);
+                                             const BatchCtl *, double, int, int, bool);
 GL_INST(double)
 GL_INST(float)
 #undef GL_INST

@@ -1835,11 +1835,20 @@ struct gl_batch {
     int shape = 0, grid_mult = 4, cus = 256;
     int fpar = 0, ppar = 0;
     int64_t since_sort = 0;
+    bool sort_pending = false;        // a sorted order waits in the events' scratch; the next push applies it
     int sort_every = 16;
-    int graph_steps = 32;             // two sort periods: both parities return
+    int graph_steps = 32;             // two sort periods
     bool any_particles = false;
-    std::map<int, hipGraphExec_t> graphs;
-    std::map<int, hipGraph_t> graph_defs;
+    // captured step loops, keyed by the state they start from, with the
+    // state they leave (the parities and the pending sort)
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t def = nullptr;
+        int fpar = 0, ppar = 0;
+        int64_t since_sort = 0;
+        bool sort_pending = false;
+    };
+    std::map<int, Graph> graphs;
 };
 
 namespace {
@@ -1920,16 +1929,32 @@ gl_status batch_step(gl_batch *b) {
     const BatchCtl *ctl = (const BatchCtl *)(b->ws + b->ctl);
     HIP_TRY(launch_batch_fields<T>(b->stream, b->shape, d, (const int2 *)(b->ws + b->tiles[b->shape]),
                                    b->total_tiles[b->shape], b->fpar, ctl, b->dtau, grid));
+    // a pending sort is applied by this push, which moves the particles to the other buffer
     HIP_TRY(launch_batch_push<T>(b->stream, d, (const int2 *)(b->ws + b->pblocks), b->total_pblocks, b->fpar,
-                                 b->ppar, ctl, b->dtau, grid, (int)b->evs.size()));
+                                 b->ppar, ctl, b->dtau, grid, (int)b->evs.size(), b->sort_pending));
+    if (b->sort_pending) b->ppar ^= 1;
+    b->sort_pending = false;
     b->fpar ^= 1;
     b->since_sort++;
     if (b->any_particles && b->sort_every > 0 && b->since_sort >= b->sort_every) {
         HIP_TRY(launch_batch_sort<T>(b->stream, d, (int)b->evs.size(), (const int2 *)(b->ws + b->pblocks),
-                                     b->total_pblocks, (const int2 *)(b->ws + b->stiles), b->total_stiles, b->ppar));
-        b->ppar ^= 1;
+                                     b->total_pblocks, (const int2 *)(b->ws + b->stiles), b->total_stiles, b->ppar,
+                                     false));
+        b->sort_pending = true;
         b->since_sort = 0;
     }
+    return GL_OK;
+}
+
+// a pending sort applied alone (the particles move to the other buffer), so
+// that none is left when a run returns
+template <typename T>
+gl_status batch_apply_pending(gl_batch *b) {
+    if (!b->sort_pending) return GL_OK;
+    const BatchEv<T> *d = (const BatchEv<T> *)(b->ws + b->desc);
+    HIP_TRY(launch_batch_permute<T>(b->stream, d, (const int2 *)(b->ws + b->pblocks), b->total_pblocks, b->ppar));
+    b->ppar ^= 1;
+    b->sort_pending = false;
     return GL_OK;
 }
 
@@ -1939,37 +1964,53 @@ gl_status batch_step_any(gl_batch *b) { return b->fp64 ? batch_step<double>(b) :
 // still be in flight when the batch is reconfigured or destroyed)
 void batch_drop_graphs(gl_batch *b) {
     if (!b->graphs.empty()) (void)hipStreamSynchronize(b->stream);
-    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
-    for (auto &g : b->graph_defs) (void)hipGraphDestroy(g.second);
+    for (auto &g : b->graphs) {
+        (void)hipGraphExecDestroy(g.second.exec);
+        (void)hipGraphDestroy(g.second.def);
+    }
     b->graphs.clear();
-    b->graph_defs.clear();
 }
 
-// capture graph_steps steps starting at a sort boundary with parities (fpar, ppar)
-gl_status batch_graph(gl_batch *b, hipGraphExec_t *out) {
-    int key = b->fpar * 2 + b->ppar;
+// capture graph_steps steps starting at a sort boundary from the batch's
+// state (parities, pending sort); the graph records the state it leaves
+gl_status batch_graph(gl_batch *b, const gl_batch::Graph **out) {
+    const int key = (b->fpar * 2 + b->ppar) * 2 + (b->sort_pending ? 1 : 0);
     auto it = b->graphs.find(key);
     if (it != b->graphs.end()) {
-        *out = it->second;
+        *out = &it->second;
         return GL_OK;
     }
-    int f0 = b->fpar, p0 = b->ppar;
-    int64_t s0 = b->since_sort;
+    const int f0 = b->fpar, p0 = b->ppar;
+    const int64_t s0 = b->since_sort;
+    const bool q0 = b->sort_pending;
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
     gl_status st = GL_OK;
     for (int k = 0; k < b->graph_steps && st == GL_OK; k++) st = batch_step_any(b);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &g);
+    gl_batch::Graph rec;
+    rec.fpar = b->fpar;
+    rec.ppar = b->ppar;
+    rec.since_sort = b->since_sort;
+    rec.sort_pending = b->sort_pending;
+    // capturing ran nothing: the batch is still where it started
     b->fpar = f0;
     b->ppar = p0;
     b->since_sort = s0;
-    if (st) return st;
+    b->sort_pending = q0;
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
     if (e != hipSuccess) return fail(GL_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     hipGraphExec_t x = nullptr;
-    HIP_TRY(hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
-    b->graph_defs[key] = g;
-    b->graphs[key] = x;
-    *out = x;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(GL_EDEVICE, "hipGraphInstantiate failed");
+    }
+    rec.exec = x;
+    rec.def = g;
+    *out = &(b->graphs[key] = rec);
     return GL_OK;
 }
 
@@ -2275,11 +2316,14 @@ gl_status gl_batch_run(gl_batch *b, int32_t n_steps) {
     while (left > 0) {
         bool aligned = b->since_sort == 0 || !b->any_particles || b->sort_every == 0;
         if (b->graph_steps > 0 && aligned && left >= b->graph_steps) {
-            hipGraphExec_t g;
+            const gl_batch::Graph *g = nullptr;
             gl_status s = batch_graph(b, &g);
             if (s) return s;
-            HIP_TRY(hipGraphLaunch(g, b->stream));
-            // a whole graph returns both parities to where they started
+            HIP_TRY(hipGraphLaunch(g->exec, b->stream));
+            b->fpar = g->fpar;
+            b->ppar = g->ppar;
+            b->since_sort = g->since_sort;
+            b->sort_pending = g->sort_pending;
             left -= b->graph_steps;
             continue;
         }
@@ -2287,6 +2331,9 @@ gl_status gl_batch_run(gl_batch *b, int32_t n_steps) {
         if (s) return s;
         left--;
     }
+    // no sort is left pending when the run returns
+    gl_status ap = b->fp64 ? batch_apply_pending<double>(b) : batch_apply_pending<float>(b);
+    if (ap) return ap;
     batch_sync_events(b, n_steps);
     // the events' states, checked once per call (their series every step)
     const BatchCtl *ctl = (const BatchCtl *)(b->ws + b->ctl);

@@ -128,27 +128,6 @@ __device__ __forceinline__ void radix_scatter_tile(const uint32_t *__restrict__ 
     }
 }
 
-// position j of dst takes every array of slot perm[j] of src
-template <typename T>
-__device__ __forceinline__ void permute_one(const PartPtrs<T> &src, const PartPtrs<T> &dst,
-                                            const int32_t *__restrict__ perm, int64_t j,
-                                            const int32_t *__restrict__ id_src, int32_t *__restrict__ id_dst) {
-    int64_t i = perm[j];
-    dst.cx[j] = src.cx[i];
-    dst.cy[j] = src.cy[i];
-    dst.species[j] = src.species[i];
-#pragma unroll
-    for (int k = 0; k < kPartRec<T>; k += 16 / (int)sizeof(T)) {
-        T v[16 / sizeof(T)];
-        chunk_ld16(src.st, (size_t)src.cap, (size_t)i, k, v);
-        chunk_st16(dst.st, (size_t)dst.cap, (size_t)j, k, v);
-    }
-    dst.px0[j] = src.px0[i];
-    dst.py0[j] = src.py0[i];
-    dst.pz0[j] = src.pz0[i];
-    id_dst[j] = id_src[i];
-}
-
 // ---- single-sort kernels ----------------------------------------------------
 
 template <typename T>
@@ -282,12 +261,14 @@ hipError_t launch_sort_particles(hipStream_t st, int N, PartPtrs<T> src, PartPtr
     return launch_permute<T>(st, src, dst, sort_perm(s), n, id_src, id_dst);
 }
 
-// the sort of every event of a batch by cell, from buffer parity ppar to
-// ppar ^ 1: keys, three digit passes (count, scan, scatter) and the
-// permutation, one launch each for all events
+// the sorted order of every event of a batch by cell, of buffer parity ppar:
+// keys and three digit passes (count, scan, scatter), one launch each for all
+// events, leaving each event's permutation in its sort scratch (vals[1]);
+// with permute, then the permutation itself (ppar to ppar ^ 1), else the next
+// push applies it (launch_batch_push with permuted)
 template <typename T>
 hipError_t launch_batch_sort(hipStream_t st, const BatchEv<T> *evs, int n_events, const int2 *pblocks,
-                             int64_t n_pblocks, const int2 *stiles, int64_t n_stiles, int ppar) {
+                             int64_t n_pblocks, const int2 *stiles, int64_t n_stiles, int ppar, bool permute) {
     if (n_pblocks <= 0 || n_stiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_sort_keys<T>, dim3((unsigned)n_pblocks), dim3(256), 0, st, evs, pblocks, ppar);
     int cur = 0;
@@ -300,6 +281,16 @@ hipError_t launch_batch_sort(hipStream_t st, const BatchEv<T> *evs, int n_events
                            stiles, shift, cur);
         cur ^= 1;
     }
+    if (permute) return launch_batch_permute<T>(st, evs, pblocks, n_pblocks, ppar);
+    return hipGetLastError();
+}
+
+// every event's pending permutation (left by launch_batch_sort) applied alone,
+// buffer parity ppar to ppar ^ 1
+template <typename T>
+hipError_t launch_batch_permute(hipStream_t st, const BatchEv<T> *evs, const int2 *pblocks, int64_t n_pblocks,
+                                int ppar) {
+    if (n_pblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_permute<T>, dim3((unsigned)n_pblocks), dim3(256), 0, st, evs, pblocks, ppar);
     return hipGetLastError();
 }
@@ -311,7 +302,8 @@ hipError_t launch_batch_sort(hipStream_t st, const BatchEv<T> *evs, int n_events
     template hipError_t launch_permute<T>(hipStream_t, PartPtrs<T>, PartPtrs<T>, const int32_t *, int64_t,        \
                                           int32_t *, int32_t *);                                                  \
     template hipError_t launch_batch_sort<T>(hipStream_t, const BatchEv<T> *, int, const int2 *, int64_t,         \
-                                             const int2 *, int64_t, int);
+                                             const int2 *, int64_t, int, bool);                                   \
+    template hipError_t launch_batch_permute<T>(hipStream_t, const BatchEv<T> *, const int2 *, int64_t, int);
 GL_INST(double)
 GL_INST(float)
 #undef GL_INST

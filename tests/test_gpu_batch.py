@@ -67,6 +67,33 @@ def test_batch_equals_single_events(gl, prec, shape, mult):
             t.push_particles()
 
 
+@pytest.mark.parametrize("prec,shape,mult", [(64, 0, 4), (32, 2, 0)])
+def test_batch_graph_windows_and_calls_ending_at_a_sort(gl, prec, shape, mult):
+    """Each sort's order is applied by the next push.  Two graph windows in a
+    row (the second starts with the order of the first one's last sort
+    pending, so the two graphs differ), a call that ends on a sort boundary
+    (the pending order is applied before the call returns), then a short
+    call: bitwise the events run alone."""
+    steps = 64 + 16 + 5
+    single = _make(gl, prec, steps)
+    for ev in single:
+        ev.run(steps)
+    batched = _make(gl, prec, steps)
+    b = gl.Batch(batched)
+    b.config(shape=shape, grid_mult=mult, sort_every=16, graph_steps=32)
+    for k in (64, 16, 5):
+        b.run(k)
+    for s, t, (N, npart) in zip(single, batched, SIZES):
+        for x, y in zip(s.get_state()[:5], t.get_state()[:5]):
+            assert np.array_equal(x, y)
+        if npart:
+            assert np.array_equal(s.series(), t.series())
+            ps, pb = s.get_particles(), t.get_particles()
+            for k in ps:
+                assert np.array_equal(ps[k], pb[k]), k
+    b.close()
+
+
 def test_autotune_cache_roundtrip(gl, tmp_path):
     evs = _make(gl, 32, 4)
     b = gl.Batch(evs)
@@ -182,6 +209,20 @@ def test_a_failed_event_is_masked_in_a_batch(gl):
         for x, y in zip(single[k].get_state()[:4], batched[k].get_state()[:4]):
             assert np.array_equal(x, y)
         assert np.array_equal(single[k].series(), batched[k].series())
+    # the masked event keeps the particles of its one push (1 -> 2); the
+    # sorts at steps 16 and 32 still moved them (a masked event's particles
+    # follow the batch's buffers without a push), so the getters find each
+    # one whole, against the same event stopped after its first push
+    ref = make(1, *spec[1])
+    ref.set_particles([(1.27, 2.0, gl.KIND_HEAVY_QUARK, 0.0)], d["cell"], d["off"], d["eta"], d["p"],
+                      d["Q"], d["p0"], d["species"])
+    try:
+        ref.run(1)
+    except gl.GlasmaError as err:
+        assert err.status == gl.GL_ENUMERIC
+    pr, pb = ref.get_particles(), batched[1].get_particles()
+    for k in pr:
+        assert np.array_equal(pr[k], pb[k], equal_nan=True), k
     b.close()
 
 
