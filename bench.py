@@ -402,6 +402,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "glasma512_hbm_traffic.md")
 KERNEL_SOURCES = ["su3.hpp", "internal.hpp", "fields_dev.hpp", "fields.hip", "push_dev.hpp", "particles.hip"]
 
 
+def kernel_name(raw):
+    """A profiler's kernel name without its return type, anonymous-namespace
+    qualifier and parameter list."""
+    n = raw.replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("(")[0].strip()
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -452,7 +461,7 @@ def sq_table(prec, pmc_dir):
     acc = {}
     for fn in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(fn)):
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            name = kernel_name(r["Kernel_Name"])
             if not name.startswith(SQ_KERNELS):
                 continue
             a = acc.setdefault(name, {}).setdefault(r["Counter_Name"], [0.0, 0])
@@ -509,7 +518,7 @@ def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
         for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(fn)):
                 if r["Counter_Name"] == counter:
-                    name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                    name = kernel_name(r["Kernel_Name"])
                     n[name] = n.get(name, 0) + 1
         return n
 
@@ -519,7 +528,7 @@ def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] != counter:
                     continue
-                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                name = kernel_name(r["Kernel_Name"])
                 a = acc.setdefault(name, [0.0, 0])
                 a[0] += float(r["Counter_Value"])
                 a[1] += 1
@@ -540,8 +549,9 @@ def traffic_table(prec, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     bf = [k for k in f if k.startswith("gl::k_batch_field_flat<%s" % tname)]
     if bf:
         kerns.append((max(bf, key=lambda k: counts(fetch_dir, "FETCH_SIZE").get(k, 0)), "batch_field"))
-    if "gl::k_batch_push_flat<%s>" % tname in f:
-        kerns.append(("gl::k_batch_push_flat<%s>" % tname, "batch_push"))
+    # the batch's plain push (the one that applies a sort's order runs once per period)
+    if "gl::k_batch_push_flat<%s, false>" % tname in f:
+        kerns.append(("gl::k_batch_push_flat<%s, false>" % tname, "batch_push"))
     for kern, short in kerns:
         print("| %s | %d | %.0f | %.0f |" % (short, prec, f[kern] * 1024 * kf, w[kern] * 1024 * kw))
     print("source hash: `%s`" % kernel_source_hash())
@@ -607,7 +617,7 @@ def summarize(path, command):
     for f in sorted(glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True)):
         lines += ["| kernel | calls | avg µs | total ms | % |", "|---|---|---|---|---|"]
         for r in csv.DictReader(open(f)):
-            name = r["Name"].split("(")[0].replace("void ", "")
+            name = kernel_name(r["Name"])
             lines.append("| %s | %s | %.2f | %.2f | %.1f |" % (
                 name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
                 float(r["Percentage"])))
@@ -615,7 +625,7 @@ def summarize(path, command):
     for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
         acc = {}
         for r in csv.DictReader(open(f)):
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            name = kernel_name(r["Kernel_Name"])
             key = (name, r["Counter_Name"])
             a = acc.setdefault(key, [0.0, 0, r.get("VGPR_Count", ""), r.get("Accum_VGPR_Count", "")])
             a[0] += float(r["Counter_Value"])
