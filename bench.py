@@ -399,7 +399,8 @@ def cpu_baseline(budget_s=12.0, max_procs=16):
 # WRITE_SIZE runs (bench.py --traffic), valid for the kernel sources whose
 # hash is recorded beside them; stale figures are reported as null.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "glasma512_hbm_traffic.md")
-KERNEL_SOURCES = ["su3.hpp", "internal.hpp", "fields_dev.hpp", "fields.hip", "push_dev.hpp", "particles.hip"]
+KERNEL_SOURCES = ["su3.hpp", "internal.hpp", "fields_dev.hpp", "fields.hip", "fields_f64.hip", "push_dev.hpp",
+                  "particles.hip"]
 
 
 def kernel_name(raw):
@@ -412,11 +413,15 @@ def kernel_name(raw):
 
 
 def kernel_source_hash():
+    """Hash of the hot kernels' sources and of the compiler flags they are
+    built with (build.py)."""
     import hashlib
+    from paper_2307_07999_amd import build as b
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2307_07999_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(repr((b.COMMON[:-2], sorted((k, v) for k, v in b.PER_SOURCE.items() if k in KERNEL_SOURCES))).encode())
     return h.hexdigest()[:16]
 
 

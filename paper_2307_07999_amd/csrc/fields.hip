@@ -356,8 +356,13 @@ hipError_t launch_diag(hipStream_t st, int N, FieldPtrs<T> f, double tau, double
     template hipError_t launch_static_accum<T>(hipStream_t, int, const T *, double *, double, double *, int *); \
     template hipError_t launch_lightlike_accum<T>(hipStream_t, int, const T *, const T *, double *, double *, \
                                                   int64_t, double, double *, int *);
+// the FP64 instantiations come from fields_f64.hip, which includes this file
+// and is compiled with its own scheduling flag
+#ifdef GL_FIELDS_FP64
 GL_INST(double)
+#else
 GL_INST(float)
+#endif
 #undef GL_INST
 
 }  // namespace gl
