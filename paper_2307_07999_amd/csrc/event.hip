@@ -1845,7 +1845,8 @@ struct gl_batch {
         hipGraphExec_t exec = nullptr;
         hipGraph_t def = nullptr;
         int fpar = 0, ppar = 0;
-        int64_t since_sort = 0;
+        int64_t since_sort = 0;   // steps since the last sort at the end, if the graph sorts
+        bool sorts = false;       // else the count just grows by graph_steps
         bool sort_pending = false;
     };
     std::map<int, Graph> graphs;
@@ -1992,6 +1993,7 @@ gl_status batch_graph(gl_batch *b, const gl_batch::Graph **out) {
     rec.fpar = b->fpar;
     rec.ppar = b->ppar;
     rec.since_sort = b->since_sort;
+    rec.sorts = b->since_sort != s0 + b->graph_steps;
     rec.sort_pending = b->sort_pending;
     // capturing ran nothing: the batch is still where it started
     b->fpar = f0;
@@ -2322,7 +2324,7 @@ gl_status gl_batch_run(gl_batch *b, int32_t n_steps) {
             HIP_TRY(hipGraphLaunch(g->exec, b->stream));
             b->fpar = g->fpar;
             b->ppar = g->ppar;
-            b->since_sort = g->since_sort;
+            b->since_sort = g->sorts ? g->since_sort : b->since_sort + b->graph_steps;
             b->sort_pending = g->sort_pending;
             left -= b->graph_steps;
             continue;
