@@ -30,10 +30,12 @@ _SGPR_SOFFSET = re.compile(r",\s*s\d+(\s|$)")
 
 
 def _asm(src, out_dir):
+    # the flags the library build gives this source, so that the code checked is the code shipped
+    from paper_2307_07999_amd import build
     out = os.path.join(out_dir, os.path.basename(src) + ".s")
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", out, "-I", CSRC, "-I", os.path.join(ROOT, "include"),
-           src]
+           "-packed-fp32-ops"] + build.PER_SOURCE.get(os.path.basename(src), []) + [
+           "--cuda-device-only", "-S", "-o", out, "-I", CSRC, "-I", os.path.join(ROOT, "include"), src]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     return out
