@@ -131,3 +131,15 @@ def test_kernel_rates_alone_and_against_the_ceiling():
         assert abs(r[k]["alg_ceiling_frac"] - r[k]["alg_GBps"] / 6300.0) < 1e-12
         assert r[k]["alg_ceiling_frac"] > r[k]["alg_frac"]
     assert "alg_ceiling_frac" not in bench.kernel_rates(64, avg, units, ab)["push"]
+
+
+def test_per_source_flags_name_existing_sources_and_enter_the_kernel_hash(monkeypatch):
+    """Every per-source flag of the build names a source that exists (a typo
+    would drop the flag silently), and the profiles' kernel hash changes
+    with the flags of the hot kernels' sources."""
+    from paper_2307_07999_amd import build
+    srcs = {os.path.basename(s) for s in build.sources()}
+    assert set(build.PER_SOURCE) <= srcs, set(build.PER_SOURCE) - srcs
+    h0 = bench.kernel_source_hash()
+    monkeypatch.setitem(build.PER_SOURCE, "fields_f64.hip", ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"])
+    assert bench.kernel_source_hash() != h0
