@@ -45,8 +45,11 @@ SEED = 2307079992
 # kernel durations are sampled on every PROFILE_PERIOD-th launch of each
 # kernel over the timed region (HIP events on the library's stream); the
 # period is coprime with the 16-step particle sort cycle so that the samples
-# cover every phase of it (the push is fastest right after a sort)
-PROFILE_PERIOD = 7
+# cover every phase of it (the push is fastest right after a sort).  A
+# sampled launch costs a few microseconds of timing events, so the period is
+# long: every 7th launch cost 0.6 % of the event's wall time, every 17th
+# about 0.25 %, and still gives about 25 samples per kernel and event.
+PROFILE_PERIOD = 17
 
 
 def coupled_steps(N, L, tau_max=1.0):
